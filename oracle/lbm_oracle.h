@@ -1,0 +1,106 @@
+/*
+ * lbm_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 CPU reference of the EOS-based multiphase MRT lattice
+ * Boltzmann time step of He, Qin, Chen & Wen, "Numerical simulation of
+ * pulmonary airway reopening by the EOS-based multiphase lattice Boltzmann
+ * method" (arXiv 2103.08301), Sec. 2.  It exists so that tests can check the
+ * GPU library against an independent, obviously-correct implementation.
+ *
+ * Only tests/, the package's smoke() entry and the bench's CPU-baseline leg
+ * may load this library.  It shares no code, header, table or helper with the
+ * GPU library; neither includes, links or imports the other.
+ *
+ * Every floating-point result is FP64, compiled without FMA contraction.
+ * Grids are row-major with x fastest: field[y][x]; distributions are
+ * f[i][y][x] (structure of arrays), i = 0..8 in the D2Q9 order
+ *   e0=(0,0) e1=(1,0) e2=(0,1) e3=(-1,0) e4=(0,-1)
+ *   e5=(1,1) e6=(-1,1) e7=(-1,-1) e8=(1,-1).
+ */
+#ifndef LBM_ORACLE_H
+#define LBM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_EOS_CS = 0, ORC_EOS_PR = 1 };
+
+/* Status codes (0 = ok). */
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EUNSTABLE = -4 };
+
+typedef struct {
+    int eos;            /* ORC_EOS_CS (Carnahan-Starling) or ORC_EOS_PR (Peng-Robinson, eq. 2.18) */
+    double a, b, R;     /* EOS constants */
+    double omega;       /* PR acentric factor (Sec. 2.2 verification paragraph) */
+    double T_over_Tc;   /* temperature as a fraction of the EOS's critical temperature */
+    double k;           /* proportional coefficient, eqs. 2.13-2.17 */
+    double kappa;       /* gradient coefficient, eqs. 2.3 and 2.17 */
+    double tau;         /* relaxation time; s_v = 1/tau (Sec. 2.1) */
+    double s_e, s_eps, s_q;  /* MRT rates (Sec. 2.1) */
+    double s_j;         /* rate on the momentum rows; <= 0 selects 1/tau */
+    double rho_wall;    /* virtual density in the wall ghost rows; NaN selects rho_l */
+    double dp;          /* pressure drop along x; body force density dp/nx */
+    int x_periodic;     /* 1: periodic in x; 0: extrapolated (zero-gradient) ends */
+    int y_periodic;     /* 1: periodic in y (no walls); 0: halfway bounce-back walls */
+    int check_every;    /* stability check cadence in steps (>= 1) */
+    double v_limit;     /* |v| above this (or a NaN) at a check is an instability */
+} orc_params;
+
+typedef struct {
+    int64_t step;                       /* 1-based index of the step these values belong to */
+    double tau_max[2], tau_min[2];      /* [0] bottom wall, [1] top wall */
+    double p_max[2], p_min[2];
+    int32_t x_tau_max[2], x_tau_min[2]; /* smallest x attaining the extreme */
+    int32_t x_p_max[2], x_p_min[2];
+    double sum_tau2;                    /* sum over both walls and all x of tau_w^2 */
+    double int_peak_tau2;               /* running sum over steps of max_{wall,x} tau_w^2 */
+    double int_tau2;                    /* running sum over steps of sum_tau2 */
+} orc_summary;
+
+typedef struct orc_sim orc_sim;
+
+void   orc_params_default(orc_params* p);
+
+/* Equation of state (Sec. 2.2; eq. 2.18 for PR). */
+int    orc_critical(const orc_params* p, double* rho_c, double* T_c);
+double orc_alpha(const orc_params* p, double T, double T_c);
+double orc_p0(const orc_params* p, double T, double rho);
+double orc_dp0(const orc_params* p, double T, double rho, int order);   /* order 1 or 2 */
+int    orc_coexistence(const orc_params* p, double T, double* rho_g, double* rho_l, double* p_star);
+
+/* Single-node and stencil building blocks, exposed for tests. */
+void   orc_velocities(int i, int* ex, int* ey, double* w);
+void   orc_moment_matrix(double* M81);                    /* row-major 9x9 */
+void   orc_equilibrium(double rho, double ux, double uy, double* feq9);
+void   orc_collide_node(const orc_params* p, const double* f9, double Fx, double Fy,
+                        double* fout9, double* rho, double* vx, double* vy);
+void   orc_grad_field(const double* a, int w, int h, double* gx, double* gy);
+void   orc_lap_field(const double* a, int w, int h, double* lap);
+uint64_t orc_splitmix64(uint64_t seed, uint64_t counter);   /* counter-th output (0-based) */
+
+/* Time stepper. */
+int    orc_create(int nx, int ny, const orc_params* p, orc_sim** out);
+void   orc_destroy(orc_sim* s);
+int    orc_state(const orc_sim* s, double* T, double* Tc, double* rho_g, double* rho_l, double* rho_w);
+int    orc_init_plug(orc_sim* s, double plug_len, double film, double x_center,
+                     double noise_amp, uint64_t seed);
+int    orc_init_density(orc_sim* s, const double* rho);    /* f* = f^eq(rho, 0) */
+void   orc_set_f(orc_sim* s, const double* f);             /* [9][ny][nx], post-collision */
+void   orc_get_f(const orc_sim* s, double* f);
+int    orc_step(orc_sim* s, int64_t n);
+int64_t orc_step_count(const orc_sim* s);
+int64_t orc_unstable_step(const orc_sim* s);
+void   orc_fields(const orc_sim* s, double* rho, double* vx, double* vy);
+void   orc_force(const orc_sim* s, double* Fx, double* Fy);
+void   orc_wall(const orc_sim* s, double* tau_bot, double* tau_top, double* p_bot, double* p_top);
+int64_t orc_history(const orc_sim* s, orc_summary* buf, int64_t cap);
+void   orc_totals(const orc_sim* s, double* mass, double* momx, double* momy);
+int    orc_interface(const orc_sim* s, double* x_rear, double* x_front, int* liquid_columns);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
