@@ -1,0 +1,192 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the EOS-based multiphase
+ * lattice Boltzmann method of He, Qin, Chen & Wen, "Numerical simulation of
+ * pulmonary airway reopening by the EOS-based multiphase lattice Boltzmann
+ * method" (arXiv 2103.08301).
+ *
+ * One call of lbm_step advances a D2Q9 lattice by n time steps.  Each step is
+ * one fused HIP kernel that
+ *   - pull-streams the post-collision distributions (left side of eq. 2.1),
+ *     with halfway bounce-back at the walls and extrapolated or periodic ends
+ *     (Sec. 2.3, airway model),
+ *   - forms the density and the EOS field phi = k^2 p0(rho) - rho c_s^2
+ *     (eqs. 2.12, 2.17, 2.18), with wetting ghost rows of density rho_wall,
+ *   - evaluates the nonideal force F = -grad phi + kappa rho grad(lap rho)
+ *     (eq. 2.17) plus the pressure-drop body force dp/nx along +x,
+ *   - applies the velocity-shift forcing u_eq = u + tau F/rho and
+ *     v = u + F/(2 rho) (Sec. 2.2, last paragraph before "Verification"),
+ *   - relaxes in moment space with the MRT operator of eq. 2.1 and the rates
+ *     printed after it, and stores the new distributions,
+ *   - and, on the two first fluid rows next to each wall, produces the wall
+ *     shear stress and wall pressure (Figs. 3, 5, 8 of the paper) with FP64
+ *     per-step extremes and time integrals.
+ *
+ * Conventions
+ *   - Every call returns lbm_status: 0 on success, a negative code otherwise;
+ *     lbm_last_error(ctx) then holds a message.  A call that fails with
+ *     LBM_EINVAL has no side effects.
+ *   - Host arrays are caller-owned, row-major [ny][nx] with x fastest;
+ *     distributions are [9][ny][nx] in the D2Q9 order
+ *       e0=(0,0) e1=(1,0) e2=(0,1) e3=(-1,0) e4=(0,-1)
+ *       e5=(1,1) e6=(-1,1) e7=(-1,-1) e8=(1,-1).
+ *   - Device memory is caller-owned: the caller allocates lbm_workspace()
+ *     bytes (any allocator; 256-byte alignment) and binds it with lbm_bind()
+ *     together with the HIP stream on which every kernel is launched.  The
+ *     library itself never allocates device memory.
+ *   - Walls lie at y = -1/2 and y = ny - 1/2 (channel width ny); cell centres
+ *     are at integer (x, y).
+ *   - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument; nothing was changed */
+    LBM_ENOMEM = -2,     /* host allocation failed, or the bound workspace is too small */
+    LBM_EDEVICE = -3,    /* a HIP call failed; the message names it */
+    LBM_EUNSTABLE = -4,  /* a stability check found NaN or |v| > v_limit; see lbm_check_state */
+    LBM_ESTATE = -5      /* call out of order (e.g. lbm_step before lbm_bind / lbm_init_*) */
+} lbm_status;
+
+typedef enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 } lbm_eos_kind;
+
+/* Storage of the distributions in device memory and arithmetic of the step:
+   F64: FP64 / FP64.  F32: FP32 / FP32.  F16S, BF16S: f_i - w_i rho0_shift in
+   FP16 / BF16, FP32 arithmetic.  F32D: FP32 storage, FP64 arithmetic.
+   F32S: f_i - w_i rho0_shift in FP32, FP32 arithmetic. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_F32D = 4, LBM_F32S = 5 } lbm_storage;
+
+typedef struct {
+    int eos;             /* lbm_eos_kind. CS: Carnahan-Starling p0 = rho R T (1+h+h^2-h^3)/(1-h)^3 - a rho^2,
+                            h = b rho/4.  PR: eq. 2.18 with the standard alpha(T). */
+    double a, b, R;      /* EOS constants (CS: 1, 4, 1; PR in the paper: 2/49, 2/21, 1) */
+    double omega;        /* PR acentric factor (paper: 0.344 water, 0.011 methane) */
+    double T_over_Tc;    /* temperature as a fraction of the EOS critical temperature,
+                            which the library solves from (a, b, R) */
+    double k;            /* proportional coefficient of eqs. 2.13-2.17 (mesh units: phi = k^2 p0 - rho/3) */
+    double kappa;        /* gradient coefficient of eq. 2.17 (paper: 0.001) */
+    double s_e, s_eps, s_q;  /* MRT rates (paper: 1.64, 1.54, 1.7); s_v = 1/tau */
+    double s_j;          /* momentum-row rate; <= 0 selects 1/tau (so the velocity shift adds exactly F) */
+    double rho_wall;     /* virtual density of the wall ghost rows (wettability); NaN selects rho_l(T) */
+    double dp;           /* pressure drop along +x; uniform body force density dp/nx */
+    int x_periodic;      /* 1: periodic ends; 0: extrapolated (zero-gradient) ends */
+    int y_periodic;      /* 1: no walls, periodic in y (test mode; no wall diagnostics) */
+    int storage;         /* lbm_storage */
+    double rho0_shift;   /* shift of F16S/BF16S storage; NaN selects rho_g(T) */
+    int check_every;     /* stability/interface check cadence in steps (>= 1) */
+    double v_limit;      /* a check fails when |v| exceeds this or a NaN appears */
+    int history_cap;     /* capacity (steps) of the device ring of per-step wall summaries (>= 1) */
+} lbm_params;
+
+/* Per-step wall summary ([0] bottom wall, [1] top wall).  FP64. */
+typedef struct {
+    int64_t step;                        /* 1-based index of the step */
+    double tau_max[2], tau_min[2];       /* wall shear stress extremes over x */
+    double p_max[2], p_min[2];           /* wall pressure extremes over x */
+    int32_t x_tau_max[2], x_tau_min[2];  /* smallest x attaining each extreme */
+    int32_t x_p_max[2], x_p_min[2];
+    double sum_tau2;                     /* sum over both walls and all x of tau_w^2 */
+    double int_peak_tau2;                /* running sum over steps of max over walls and x of tau_w^2 */
+    double int_tau2;                     /* running sum over steps of sum_tau2 */
+} lbm_stress_summary;
+
+/* Result of the latest stability/interface check. */
+typedef struct {
+    int64_t step;            /* step at which the check ran (0 = initial state) */
+    double mass;             /* sum of rho over the grid (FP64) */
+    double momx, momy;       /* sum of rho v (FP64) */
+    double vmax;             /* max |v| */
+    int64_t nan_count;       /* cells whose rho, vx or vy is NaN */
+    double x_rear, x_front;  /* plug interfaces on the centreline; NaN unless exactly one liquid run */
+    int32_t liquid_columns;  /* columns whose minimum density exceeds (rho_g + rho_l)/2 */
+    int64_t rupture_step;    /* first check step with no liquid column; -1 before rupture */
+    int64_t unstable_step;   /* first check step that failed; -1 if none */
+} lbm_check_result;
+
+/* Defaults: Carnahan-Starling a=1, b=4, R=1 at 0.85 Tc, k=1, kappa=0.001, paper MRT
+   rates, rho_wall=rho_l, dp=0, extrapolated ends, walls, FP32 storage, check every
+   1000 steps, v_limit 0.5, history of 4096 steps. */
+void lbm_params_default(lbm_params* p);
+
+/* Validates the parameters, solves the EOS critical point and the Maxwell
+   coexistence densities on the host (paper Sec. 2.2, "Verification") and
+   returns a new context.  No device work.  tau > 1/2; 4 <= nx, ny;
+   (pitch of nx) * ny < 2^31.  T_over_Tc >= 1 is allowed (single phase) but
+   then lbm_init_plug is rejected. */
+lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx** out);
+
+/* Device bytes the caller must allocate and bind (alignment 256). */
+lbm_status lbm_workspace(const lbm_ctx* ctx, size_t* bytes);
+
+/* Binds caller-owned device memory (>= lbm_workspace bytes, 256-aligned) on
+   the current HIP device and the hipStream_t (NULL = default stream) for all
+   later launches.  Rebinding moves no data: initialise again afterwards. */
+lbm_status lbm_bind(lbm_ctx* ctx, void* device_ptr, size_t bytes, void* hip_stream);
+
+/* Temperature, critical temperature, coexistence densities and wall density
+   the context uses (host values, no device work). */
+lbm_status lbm_state(const lbm_ctx* ctx, double* T, double* Tc, double* rho_g, double* rho_l,
+                     double* rho_w);
+
+/* Liquid plug of plug_len cells spanning the channel, centred at x_center
+   (NaN: nx/4 + plug_len/2), and a liquid film of `film` rows on each wall
+   (Sec. 2.3 and Sec. 3.1 of the paper), gas elsewhere, at the Maxwell densities,
+   plus additive uniform noise of amplitude noise_amp: cell (x, y) adds
+   noise_amp (2U - 1), U from the (y nx + x)-th output of SplitMix64(seed).
+   A cell is liquid when x_center - plug_len/2 <= x < x_center + plug_len/2,
+   or y < film, or y >= ny - film.  Distributions start at f_eq(rho, 0).
+   Requires bind; 0 < plug_len <= nx, 0 <= 2 film < ny, T_over_Tc < 1. */
+lbm_status lbm_init_plug(lbm_ctx* ctx, double plug_len, double film, double x_center,
+                         double noise_amp, uint64_t seed);
+
+/* Initial state from a host density field [ny][nx] (all > 0): f = f_eq(rho, 0). */
+lbm_status lbm_init_density(lbm_ctx* ctx, const double* rho);
+
+/* Advances n >= 0 steps on the bound stream.  Returns after the last check of
+   the call has completed on the device (one host synchronisation per check).
+   Returns LBM_EUNSTABLE, and stops, at the first failed check. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Number of steps taken since the last initialisation. */
+lbm_status lbm_step_count(const lbm_ctx* ctx, int64_t* steps);
+
+/* Density and velocity v = u + F/(2 rho) of the last step (after an
+   initialisation: the initial density and zero velocity), copied to caller-owned
+   host arrays [ny][nx] (FP64).  Any pointer may be NULL. */
+lbm_status lbm_fields(lbm_ctx* ctx, double* rho, double* vx, double* vy);
+
+/* Wall shear stress and wall pressure of the last step along both walls
+   (host arrays of nx doubles, any may be NULL) and that step's summary
+   (may be NULL).  Before the first step they are zero. */
+lbm_status lbm_wall_stress(lbm_ctx* ctx, double* tau_bot, double* tau_top, double* p_bot,
+                           double* p_top, lbm_stress_summary* s);
+
+/* The last min(cap, steps, history_cap) per-step summaries, oldest first. */
+lbm_status lbm_stress_history(lbm_ctx* ctx, lbm_stress_summary* buf, int64_t cap, int64_t* n_out);
+
+/* Result of the latest stability/interface check. */
+lbm_status lbm_check_state(const lbm_ctx* ctx, lbm_check_result* out);
+
+/* Post-collision distributions as FP64 host arrays [9][ny][nx]
+   (decoded from the storage type) / replaced from such an array (encoded with
+   round-to-nearest-even).  lbm_set_f keeps the step count and history. */
+lbm_status lbm_get_f(lbm_ctx* ctx, double* f);
+lbm_status lbm_set_f(lbm_ctx* ctx, const double* f);
+
+void lbm_destroy(lbm_ctx* ctx);
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -89,6 +89,7 @@ def lib():
             "orc_grad_field": (None, [_D, C.c_int, C.c_int, _D, _D]),
             "orc_lap_field": (None, [_D, C.c_int, C.c_int, _D]),
             "orc_splitmix64": (C.c_uint64, [C.c_uint64, C.c_uint64]),
+            "orc_threads": (C.c_int, []),
             "orc_create": (C.c_int, [C.c_int, C.c_int, P, C.POINTER(C.c_void_p)]),
             "orc_destroy": (None, [C.c_void_p]),
             "orc_state": (C.c_int, [C.c_void_p, _D, _D, _D, _D, _D]),
@@ -203,6 +204,10 @@ def lap_field(a: np.ndarray):
     out = np.zeros((h - 2, w - 2))
     lib().orc_lap_field(_ptr(a), w, h, _ptr(out))
     return out
+
+
+def threads() -> int:
+    return lib().orc_threads()
 
 
 def splitmix64(seed: int, counter: int) -> int:

@@ -35,6 +35,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* D2Q9 lattice (standard; see the reading above).                          */
@@ -392,6 +395,14 @@ void orc_collide_node(const orc_params* p, const double* f9, double Fx, double F
 /* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the state advances by the   */
 /* odd constant 0x9E3779B97F4A7C15 and each output is a mix of the state.    */
 
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 uint64_t orc_splitmix64(uint64_t seed, uint64_t counter) {
     uint64_t z = seed + (counter + 1u) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -440,7 +451,7 @@ void orc_params_default(orc_params* p) {
     p->x_periodic = 0;
     p->y_periodic = 0;
     p->check_every = 1000;
-    p->v_limit = 0.3;
+    p->v_limit = 0.5;
 }
 
 int orc_create(int nx, int ny, const orc_params* p, orc_sim** out) {

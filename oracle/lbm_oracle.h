@@ -80,6 +80,7 @@ void   orc_collide_node(const orc_params* p, const double* f9, double Fx, double
 void   orc_grad_field(const double* a, int w, int h, double* gx, double* gy);
 void   orc_lap_field(const double* a, int w, int h, double* lap);
 uint64_t orc_splitmix64(uint64_t seed, uint64_t counter);   /* counter-th output (0-based) */
+int    orc_threads(void);                                  /* OpenMP threads a step uses */
 
 /* Time stepper. */
 int    orc_create(int nx, int ny, const orc_params* p, orc_sim** out);

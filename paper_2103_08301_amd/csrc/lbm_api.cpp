@@ -1,0 +1,736 @@
+// lbm_api.cpp -- host side of the C ABI declared in include/lbm.h.
+//
+// Parameter validation, the equation of state (critical point and Maxwell
+// coexistence, paper Sec. 2.2 "Verification"), the plug initial condition
+// (Sec. 2.3 / 3.1), the layout of the caller-owned device workspace, and the
+// launch sequence of lbm_step.  All per-node work runs in lbm_kernels.hip.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.hpp"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Second-order forward-mode automatic differentiation: value, d/drho, d2/drho2.
+
+struct Dual2 {
+    double v, d, dd;
+};
+inline Dual2 operator+(Dual2 a, Dual2 b) { return {a.v + b.v, a.d + b.d, a.dd + b.dd}; }
+inline Dual2 operator-(Dual2 a, Dual2 b) { return {a.v - b.v, a.d - b.d, a.dd - b.dd}; }
+inline Dual2 operator*(Dual2 a, Dual2 b) { return {a.v * b.v, a.d * b.v + a.v * b.d, a.dd * b.v + 2 * a.d * b.d + a.v * b.dd}; }
+inline Dual2 operator*(double s, Dual2 a) { return {s * a.v, s * a.d, s * a.dd}; }
+inline Dual2 operator+(double s, Dual2 a) { return {s + a.v, a.d, a.dd}; }
+inline Dual2 operator-(double s, Dual2 a) { return {s - a.v, -a.d, -a.dd}; }
+inline Dual2 recip(Dual2 a) {
+    const double r = 1.0 / a.v;
+    return {r, -a.d * r * r, (2 * a.d * a.d * r - a.dd) * r * r};
+}
+inline Dual2 operator/(Dual2 a, Dual2 b) { return a * recip(b); }
+
+// p0 = RT * rep(rho) - aA * att(rho)
+struct Eos {
+    int kind;
+    double a, b, R;
+    double Tc, T, alpha;
+
+    Dual2 rep(Dual2 r) const {
+        if (kind == LBM_EOS_CS) {
+            const Dual2 h = (0.25 * b) * r;
+            const Dual2 om = 1.0 - h;
+            return r * (1.0 + h * (1.0 + h * (1.0 - h))) / (om * om * om);
+        }
+        return r / (1.0 - b * r);
+    }
+    Dual2 att(Dual2 r) const {
+        if (kind == LBM_EOS_CS) return r * r;
+        return r * r / (1.0 + b * r * (2.0 - b * r));
+    }
+    double rho_max() const { return kind == LBM_EOS_CS ? 4.0 / b : 1.0 / b; }
+    Dual2 p(double rho) const {
+        const Dual2 r{rho, 1.0, 0.0};
+        return (R * T) * rep(r) - (a * alpha) * att(r);
+    }
+};
+
+double pr_alpha(double omega, double T, double Tc) {
+    const double kw = 0.37464 + 1.54226 * omega - 0.26992 * omega * omega;
+    const double s = 1.0 + kw * (1.0 - std::sqrt(T / Tc));
+    return s * s;
+}
+
+// Critical point: p' = p'' = 0.  With p = T A(rho) + B(rho) (alpha(Tc) = 1),
+// T = -B'/A' and the density solves A' B'' - A'' B' = 0.
+bool critical_point(Eos& e, double& rho_c) {
+    auto cond = [&](double rho) {
+        const Dual2 r{rho, 1.0, 0.0};
+        const Dual2 A = e.R * e.rep(r);
+        const Dual2 B = -e.a * e.att(r);
+        return A.d * B.dd - A.dd * B.d;
+    };
+    const double rmax = e.rho_max();
+    double lo = rmax * 1e-6, flo = cond(lo), hi = 0;
+    bool found = false;
+    for (int k = 1; k <= 4000; ++k) {  // geometric scan up to the excluded-volume limit
+        const double r = rmax * 1e-6 * std::pow(1e6 * 0.999, k / 4000.0);
+        const double fr = cond(r);
+        if ((flo > 0) != (fr > 0)) { hi = r; found = true; break; }
+        lo = r;
+        flo = fr;
+    }
+    if (!found) return false;
+    for (int it = 0; it < 200 && hi - lo > 4 * std::numeric_limits<double>::epsilon() * hi; ++it) {
+        const double m = 0.5 * (lo + hi), fm = cond(m);
+        if ((fm > 0) == (flo > 0)) { lo = m; flo = fm; } else { hi = m; }
+    }
+    rho_c = 0.5 * (lo + hi);
+    const Dual2 r{rho_c, 1.0, 0.0};
+    e.Tc = -(-e.a * e.att(r)).d / (e.R * e.rep(r)).d;
+    return true;
+}
+
+// chemical potential difference mu(rl) - mu(rg) = int p'(rho)/rho drho
+// = int_{ln rg}^{ln rl} p'(e^s) ds, by Romberg integration (at most 2^15 + 1
+// evaluations; the integrand is analytic in s).
+double dmu(const Eos& e, double rg, double rl, double scale) {
+    const double a = std::log(rg), b = std::log(rl);
+    auto f = [&](double s) { return e.p(std::exp(s)).d; };
+    constexpr int kLevels = 16;
+    double R[kLevels][kLevels];
+    double h = b - a;
+    R[0][0] = 0.5 * h * (f(a) + f(b));
+    for (int k = 1; k < kLevels; ++k) {
+        h *= 0.5;
+        double sum = 0.0;
+        const long n = 1L << (k - 1);
+        for (long j = 0; j < n; ++j) sum += f(a + (2 * j + 1) * h);
+        R[k][0] = 0.5 * R[k - 1][0] + h * sum;
+        double pow4 = 1.0;
+        for (int m = 1; m <= k; ++m) {
+            pow4 *= 4.0;
+            R[k][m] = R[k][m - 1] + (R[k][m - 1] - R[k - 1][m - 1]) / (pow4 - 1.0);
+        }
+        if (k >= 5 && std::fabs(R[k][k] - R[k - 1][k - 1]) <= 1e-15 * (std::fabs(R[k][k]) + scale)) return R[k][k];
+    }
+    return R[kLevels - 1][kLevels - 1];
+}
+
+// Coexistence at temperature e.T: the pressure p* at which the gas and liquid
+// roots of p0(rho) = p* (one on each stable branch) have equal chemical
+// potential, mu(rho_l) - mu(rho_g) = int p'(rho)/rho drho = 0.  The difference
+// decreases monotonically in p*, so p* is bracketed between the spinodal
+// pressures and bisected (geometrically while the bracket spans decades).
+struct Coexist {
+    static double branch_root(const Eos& e, double target, double lo, double hi) {
+        for (int it = 0; it < 300; ++it) {  // p0 increases on [lo, hi]
+            const double m = 0.5 * (lo + hi);
+            if (!(m > lo && m < hi)) break;
+            (e.p(m).v < target ? lo : hi) = m;
+        }
+        return 0.5 * (lo + hi);
+    }
+
+    static bool solve(const Eos& base, double T, double omega, double& rho_g, double& rho_l) {
+        Eos e = base;
+        e.T = T;
+        e.alpha = (e.kind == LBM_EOS_PR) ? pr_alpha(omega, T, e.Tc) : 1.0;
+        const double rmax = e.rho_max();
+        auto dp = [&](double r) { return e.p(r).d; };
+        // spinodals: first sign changes of p' on a geometric grid
+        constexpr int kGrid = 40000;
+        double sg = -1, sl = -1, prev = rmax * 1e-12;
+        bool in_unstable = false;
+        for (int k = 1; k <= kGrid; ++k) {
+            const double r = rmax * 1e-12 * std::pow(1e12 * (1 - 1e-9), double(k) / kGrid);
+            const double d = dp(r);
+            if (!in_unstable && d < 0) {
+                double lo = prev, hi = r;
+                for (int it = 0; it < 200; ++it) { const double m = 0.5 * (lo + hi); (dp(m) > 0 ? lo : hi) = m; }
+                sg = lo;
+                in_unstable = true;
+            } else if (in_unstable && d > 0) {
+                double lo = prev, hi = r;
+                for (int it = 0; it < 200; ++it) { const double m = 0.5 * (lo + hi); (dp(m) < 0 ? lo : hi) = m; }
+                sl = hi;
+                break;
+            }
+            prev = r;
+        }
+        if (sg < 0 || sl < 0) return false;
+        double p_hi = e.p(sg).v, p_lo = e.p(sl).v;
+        if (!(p_lo > 0)) p_lo = p_hi * 1e-300;
+        double g = 0, l = 0;
+        for (int it = 0; it < 3000; ++it) {
+            const double pm = (p_hi > 4 * p_lo) ? std::sqrt(p_lo * p_hi) : 0.5 * (p_lo + p_hi);
+            if (!(pm > p_lo && pm < p_hi)) break;
+            g = branch_root(e, pm, 0.0, sg);
+            l = branch_root(e, pm, sl, rmax);
+            (dmu(e, g, l, e.R * e.T) > 0 ? p_lo : p_hi) = pm;
+        }
+        const double ps = 0.5 * (p_lo + p_hi);
+        rho_g = branch_root(e, ps, 0.0, sg);
+        rho_l = branch_root(e, ps, sl, rmax);
+        return std::isfinite(rho_g) && std::isfinite(rho_l) && rho_g > 0 && rho_g < rho_l && rho_l < rmax;
+    }
+};
+
+// SplitMix64 (Steele, Lea & Flood 2014): the n-th output (0-based) of the
+// generator seeded with `seed`.
+uint64_t splitmix64_nth(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (n + 1);
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t storage_bytes(int storage) {
+    switch (storage) {
+        case LBM_F64: return 8;
+        case LBM_F32:
+        case LBM_F32D:
+        case LBM_F32S: return 4;
+        default: return 2;
+    }
+}
+
+constexpr int kRingCap = 256;  // per-step partial slots before a wall reduction is forced
+
+}  // namespace
+
+struct lbm_ctx {
+    int nx = 0, ny = 0;
+    double tau = 1.0;
+    lbm_params p{};
+    Eos eos{};
+    double rho_c = 0, rho_g = NAN, rho_l = NAN, rho_w = 0, rho0 = 0;
+    int pitch = 0;
+    long long plane = 0;
+    int nstrip = 0, nchunk = 0, ty = 0;
+    // workspace layout (byte offsets)
+    size_t off_f[2]{}, off_rho = 0, off_vx = 0, off_vy = 0, off_tau = 0, off_pw = 0, off_ring = 0, off_hist = 0,
+           off_acc = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, total = 0;
+    char* dev = nullptr;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool bound = false, initialized = false;
+    int cur = 0;
+    int64_t steps = 0;
+    int ring_fill = 0;
+    int64_t ring_first_step = 1;
+    lbm_check_result check{};
+    std::string err;
+
+    template <class T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(dev + off); }
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(ctx, LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+lbm_status reset_diagnostics(lbm_ctx* c) {
+    const long long nxy = (long long)c->nx * c->ny;
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_vx), 0.0, nxy, c->stream));
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_vy), 0.0, nxy, c->stream));
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_tau), 0.0, 2LL * c->nx, c->stream));
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_pw), 0.0, 2LL * c->nx, c->stream));
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_acc), 0.0, 2, c->stream));
+    c->steps = 0;
+    c->ring_fill = 0;
+    c->ring_first_step = 1;
+    c->check = lbm_check_result{};
+    c->check.rupture_step = -1;
+    c->check.unstable_step = -1;
+    c->check.x_rear = NAN;
+    c->check.x_front = NAN;
+    return LBM_OK;
+}
+
+lbm_status run_check(lbm_ctx* c);
+
+lbm_status init_from_device_rho(lbm_ctx* c) {
+    HIP_TRY(c, lbm::launch_init(c->at<double>(c->off_rho), c->dev + c->off_f[0], c->nx, c->ny, c->pitch, c->plane,
+                                c->p.storage, c->rho0, c->stream));
+    c->cur = 0;
+    lbm_status s = reset_diagnostics(c);
+    if (s) return s;
+    c->initialized = true;
+    return run_check(c);
+}
+
+lbm_status flush_wall(lbm_ctx* c) {
+    if (c->ring_fill == 0) return LBM_OK;
+    if (!c->p.y_periodic) {
+        HIP_TRY(c, lbm::launch_wall_reduce(c->at<double>(c->off_ring), 0, kRingCap, c->ring_fill, c->nstrip,
+                                           c->ring_first_step, c->at<lbm_stress_summary>(c->off_hist),
+                                           c->p.history_cap, c->at<double>(c->off_acc), c->stream));
+    }
+    c->ring_first_step += c->ring_fill;
+    c->ring_fill = 0;
+    return LBM_OK;
+}
+
+// Mass, momentum, |v|max and NaNs of the emitted fields, interface positions and rupture.
+lbm_status run_check(lbm_ctx* c) {
+    const long long nxy = (long long)c->nx * c->ny;
+    HIP_TRY(c, lbm::launch_field_reduce(c->at<double>(c->off_rho), c->at<double>(c->off_vx), c->at<double>(c->off_vy),
+                                        nxy, c->at<double>(c->off_red), lbm::kFieldReduceBlocks,
+                                        c->at<double>(c->off_redout), c->stream));
+    HIP_TRY(c, lbm::launch_column_scan(c->at<double>(c->off_rho), c->nx, c->ny, c->at<double>(c->off_colmin),
+                                       c->at<double>(c->off_centre), c->stream));
+    double red[5];
+    std::vector<double> colmin(c->nx), centre(c->nx);
+    HIP_TRY(c, hipMemcpyAsync(red, c->dev + c->off_redout, sizeof red, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(colmin.data(), c->dev + c->off_colmin, c->nx * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(centre.data(), c->dev + c->off_centre, c->nx * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    lbm_check_result& k = c->check;
+    k.step = c->steps;
+    k.mass = red[0];
+    k.momx = red[1];
+    k.momy = red[2];
+    k.vmax = std::sqrt(red[3]);
+    k.nan_count = (int64_t)red[4];
+    // interfaces: crossings of the midpoint density on the centreline
+    const double mid = 0.5 * (c->rho_g + c->rho_l);
+    k.x_rear = NAN;
+    k.x_front = NAN;
+    k.liquid_columns = 0;
+    if (std::isfinite(mid)) {
+        int runs = 0, first = -1, last = -1;
+        bool prev = false;
+        for (int x = 0; x < c->nx; ++x) {
+            const bool liq = centre[x] > mid;
+            if (liq && !prev) { ++runs; first = x; }
+            if (liq) last = x;
+            prev = liq;
+        }
+        if (runs == 1 && first > 0 && last < c->nx - 1) {
+            k.x_rear = (first - 1) + (mid - centre[first - 1]) / (centre[first] - centre[first - 1]);
+            k.x_front = last + (centre[last] - mid) / (centre[last] - centre[last + 1]);
+        }
+        for (int x = 0; x < c->nx; ++x) k.liquid_columns += colmin[x] > mid ? 1 : 0;
+        if (c->steps > 0 && k.liquid_columns == 0 && k.rupture_step < 0) k.rupture_step = c->steps;
+    }
+    const bool bad = k.nan_count > 0 || !(k.vmax <= c->p.v_limit);
+    if (bad && k.unstable_step < 0) {
+        k.unstable_step = c->steps;
+        return fail(c, LBM_EUNSTABLE, "instability at step %lld: nan cells %lld, |v|max %g",
+                    (long long)c->steps, (long long)k.nan_count, k.vmax);
+    }
+    if (bad) return fail(c, LBM_EUNSTABLE, "state is unstable since step %lld", (long long)k.unstable_step);
+    return LBM_OK;
+}
+
+lbm::StepArgs make_args(const lbm_ctx* c) {
+    lbm::StepArgs a{};
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.pitch = c->pitch;
+    a.plane = c->plane;
+    a.nstrip = c->nstrip;
+    a.nchunk = c->nchunk;
+    a.ty = c->ty;
+    a.xper = c->p.x_periodic;
+    a.yper = c->p.y_periodic;
+    a.tau = c->tau;
+    a.s_e = c->p.s_e;
+    a.s_eps = c->p.s_eps;
+    a.s_q = c->p.s_q;
+    a.s_v = 1.0 / c->tau;
+    a.s_j = c->p.s_j > 0 ? c->p.s_j : 1.0 / c->tau;
+    a.k2 = c->p.k * c->p.k;
+    a.kappa = c->p.kappa;
+    a.g = c->p.dp / c->nx;
+    a.nu = (c->tau - 0.5) / 3.0;
+    a.RT = c->eos.R * c->eos.T;
+    a.a_eff = c->eos.a * c->eos.alpha;
+    a.b = c->eos.b;
+    a.rho_w = c->rho_w;
+    a.rho0 = c->rho0;
+    a.tau_w = c->at<double>(c->off_tau);
+    a.p_w = c->at<double>(c->off_pw);
+    a.rho_out = c->at<double>(c->off_rho);
+    a.vx_out = c->at<double>(c->off_vx);
+    a.vy_out = c->at<double>(c->off_vy);
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_params_default(lbm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->eos = LBM_EOS_CS;
+    p->a = 1.0;
+    p->b = 4.0;
+    p->R = 1.0;
+    p->omega = 0.344;
+    p->T_over_Tc = 0.85;
+    p->k = 1.0;
+    p->kappa = 0.001;
+    p->s_e = 1.64;
+    p->s_eps = 1.54;
+    p->s_q = 1.7;
+    p->s_j = 0.0;
+    p->rho_wall = NAN;
+    p->dp = 0.0;
+    p->x_periodic = 0;
+    p->y_periodic = 0;
+    p->storage = LBM_F32;
+    p->rho0_shift = NAN;
+    p->check_every = 1000;
+    p->v_limit = 0.5;
+    p->history_cap = 4096;
+}
+
+lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx** out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (!p) return LBM_EINVAL;
+    auto rate_ok = [](double s) { return s > 0 && s < 2; };
+    if (nx < 4 || ny < 4 || !(tau > 0.5) || !(p->a > 0) || !(p->b > 0) || !(p->R > 0) || !(p->T_over_Tc > 0) ||
+        !std::isfinite(p->T_over_Tc) || !(p->k > 0) || !(p->kappa >= 0) || !rate_ok(p->s_e) || !rate_ok(p->s_eps) ||
+        !rate_ok(p->s_q) || !(p->s_j <= 0 || rate_ok(p->s_j)) || !std::isfinite(p->dp) || p->check_every < 1 ||
+        !(p->v_limit > 0) || p->history_cap < 1 || (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) ||
+        p->storage < LBM_F64 || p->storage > LBM_F32S || (p->x_periodic != 0 && p->x_periodic != 1) ||
+        (p->y_periodic != 0 && p->y_periodic != 1) || !std::isfinite(p->omega) ||
+        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)))
+        return LBM_EINVAL;
+    const int pitch = (nx + 63) / 64 * 64;
+    if ((long long)pitch * ny > 0x7fffffffLL) return LBM_EINVAL;
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    c->nx = nx;
+    c->ny = ny;
+    c->tau = tau;
+    c->p = *p;
+    c->eos.kind = p->eos;
+    c->eos.a = p->a;
+    c->eos.b = p->b;
+    c->eos.R = p->R;
+    if (!critical_point(c->eos, c->rho_c)) { delete c; return LBM_EINVAL; }
+    c->eos.T = p->T_over_Tc * c->eos.Tc;
+    c->eos.alpha = p->eos == LBM_EOS_PR ? pr_alpha(p->omega, c->eos.T, c->eos.Tc) : 1.0;
+    if (p->T_over_Tc < 1.0) {
+        if (!Coexist::solve(c->eos, c->eos.T, p->omega, c->rho_g, c->rho_l)) { delete c; return LBM_EINVAL; }
+    }
+    const double liquid = std::isnan(c->rho_l) ? c->rho_c : c->rho_l;
+    c->rho_w = std::isnan(p->rho_wall) ? liquid : p->rho_wall;
+    c->rho0 = std::isnan(p->rho0_shift) ? (std::isnan(c->rho_g) ? c->rho_c : c->rho_g) : p->rho0_shift;
+    c->pitch = pitch;
+    c->plane = (long long)pitch * ny;
+    c->nstrip = (nx + lbm::kStripOut - 1) / lbm::kStripOut;
+    c->ty = 16;
+    c->nchunk = std::max(1, ny / c->ty);
+    // workspace layout
+    size_t o = 0;
+    const size_t fbytes = align256((size_t)c->plane * 9 * storage_bytes(p->storage));
+    const size_t nxy8 = align256((size_t)nx * ny * sizeof(double));
+    c->off_f[0] = o; o += fbytes;
+    c->off_f[1] = o; o += fbytes;
+    c->off_rho = o; o += nxy8;
+    c->off_vx = o; o += nxy8;
+    c->off_vy = o; o += nxy8;
+    c->off_tau = o; o += align256(2 * (size_t)nx * sizeof(double));
+    c->off_pw = o; o += align256(2 * (size_t)nx * sizeof(double));
+    c->off_ring = o; o += align256((size_t)kRingCap * 2 * c->nstrip * lbm::kPartialVals * sizeof(double));
+    c->off_hist = o; o += align256((size_t)p->history_cap * sizeof(lbm_stress_summary));
+    c->off_acc = o; o += 256;
+    c->off_red = o; o += align256((size_t)lbm::kFieldReduceBlocks * 5 * sizeof(double));
+    c->off_redout = o; o += 256;
+    c->off_colmin = o; o += align256((size_t)nx * sizeof(double));
+    c->off_centre = o; o += align256((size_t)nx * sizeof(double));
+    c->total = o;
+    c->check.rupture_step = -1;
+    c->check.unstable_step = -1;
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_workspace(const lbm_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return LBM_EINVAL;
+    *bytes = c->total;
+    return LBM_OK;
+}
+
+lbm_status lbm_bind(lbm_ctx* c, void* device_ptr, size_t bytes, void* hip_stream) {
+    if (!c) return LBM_EINVAL;
+    if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
+        return fail(c, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
+    if (bytes < c->total) return fail(c, LBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, c->total);
+    HIP_TRY(c, hipGetDevice(&c->device));
+    c->dev = static_cast<char*>(device_ptr);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->bound = true;
+    c->initialized = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_state(const lbm_ctx* c, double* T, double* Tc, double* rho_g, double* rho_l, double* rho_w) {
+    if (!c) return LBM_EINVAL;
+    if (T) *T = c->eos.T;
+    if (Tc) *Tc = c->eos.Tc;
+    if (rho_g) *rho_g = c->rho_g;
+    if (rho_l) *rho_l = c->rho_l;
+    if (rho_w) *rho_w = c->rho_w;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_plug(lbm_ctx* c, double plug_len, double film, double x_center, double noise_amp,
+                         uint64_t seed) {
+    if (!c) return LBM_EINVAL;
+    if (!(plug_len > 0) || plug_len > c->nx || !(film >= 0) || !(2 * film < c->ny) || !(noise_amp >= 0) ||
+        std::isnan(c->rho_l) || (!std::isnan(x_center) && !std::isfinite(x_center)))
+        return fail(c, LBM_EINVAL, "invalid plug: length %g film %g x_center %g noise %g (T/Tc %g)", plug_len, film,
+                    x_center, noise_amp, c->p.T_over_Tc);
+    if (!c->bound) return fail(c, LBM_ESTATE, "lbm_bind must come before initialisation");
+    if (std::isnan(x_center)) x_center = c->nx / 4.0 + plug_len / 2.0;
+    std::vector<double> rho;
+    try {
+        rho.resize((size_t)c->nx * c->ny);
+    } catch (...) {
+        return fail(c, LBM_ENOMEM, "host allocation of the initial density failed");
+    }
+    for (int y = 0; y < c->ny; ++y)
+        for (int x = 0; x < c->nx; ++x) {
+            const bool plug = x >= x_center - plug_len / 2.0 && x < x_center + plug_len / 2.0;
+            const bool filmrow = y < film || y >= c->ny - film;
+            const double base = (plug || filmrow) ? c->rho_l : c->rho_g;
+            const uint64_t z = splitmix64_nth(seed, (uint64_t)y * c->nx + x);
+            const double U = (double)(z >> 11) * 0x1.0p-53;
+            rho[(size_t)y * c->nx + x] = base + noise_amp * (2.0 * U - 1.0);
+        }
+    HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_rho, rho.data(), rho.size() * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return init_from_device_rho(c);
+}
+
+lbm_status lbm_init_density(lbm_ctx* c, const double* rho) {
+    if (!c || !rho) return LBM_EINVAL;
+    for (long long i = 0, n = (long long)c->nx * c->ny; i < n; ++i)
+        if (!(rho[i] > 0) || !std::isfinite(rho[i])) return fail(c, LBM_EINVAL, "density must be positive and finite");
+    if (!c->bound) return fail(c, LBM_ESTATE, "lbm_bind must come before initialisation");
+    HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_rho, rho, (size_t)c->nx * c->ny * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return init_from_device_rho(c);
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c || n < 0) return LBM_EINVAL;
+    if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_step needs lbm_bind and an initialisation");
+    lbm::StepArgs a = make_args(c);
+    const size_t slot = (size_t)2 * c->nstrip * lbm::kPartialVals;
+    int64_t done = 0;
+    while (done < n) {
+        const int64_t next_check = (c->steps / c->p.check_every + 1) * c->p.check_every;
+        const int64_t seg = std::min<int64_t>(n - done, next_check - c->steps);
+        for (int64_t k = 0; k < seg; ++k) {
+            if (c->ring_fill == kRingCap) {
+                lbm_status s = flush_wall(c);
+                if (s) return s;
+            }
+            const bool emit = (k == seg - 1);
+            a.fin = c->dev + c->off_f[c->cur];
+            a.fout = c->dev + c->off_f[1 - c->cur];
+            a.partial = c->at<double>(c->off_ring) + slot * c->ring_fill;
+            HIP_TRY(c, lbm::launch_step(a, c->p.storage, c->p.eos, emit, c->stream));
+            c->cur = 1 - c->cur;
+            c->ring_fill += 1;
+            c->steps += 1;
+        }
+        lbm_status s = flush_wall(c);
+        if (s) return s;
+        done += seg;
+        s = run_check(c);
+        if (s) return s;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_step_count(const lbm_ctx* c, int64_t* steps) {
+    if (!c || !steps) return LBM_EINVAL;
+    *steps = c->steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_fields(lbm_ctx* c, double* rho, double* vx, double* vy) {
+    if (!c) return LBM_EINVAL;
+    if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    const size_t bytes = (size_t)c->nx * c->ny * sizeof(double);
+    if (rho) HIP_TRY(c, hipMemcpyAsync(rho, c->dev + c->off_rho, bytes, hipMemcpyDeviceToHost, c->stream));
+    if (vx) HIP_TRY(c, hipMemcpyAsync(vx, c->dev + c->off_vx, bytes, hipMemcpyDeviceToHost, c->stream));
+    if (vy) HIP_TRY(c, hipMemcpyAsync(vy, c->dev + c->off_vy, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_wall_stress(lbm_ctx* c, double* tau_bot, double* tau_top, double* p_bot, double* p_top,
+                           lbm_stress_summary* s) {
+    if (!c) return LBM_EINVAL;
+    if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    const size_t nxb = (size_t)c->nx * sizeof(double);
+    if (tau_bot) HIP_TRY(c, hipMemcpyAsync(tau_bot, c->dev + c->off_tau, nxb, hipMemcpyDeviceToHost, c->stream));
+    if (tau_top) HIP_TRY(c, hipMemcpyAsync(tau_top, c->dev + c->off_tau + nxb, nxb, hipMemcpyDeviceToHost, c->stream));
+    if (p_bot) HIP_TRY(c, hipMemcpyAsync(p_bot, c->dev + c->off_pw, nxb, hipMemcpyDeviceToHost, c->stream));
+    if (p_top) HIP_TRY(c, hipMemcpyAsync(p_top, c->dev + c->off_pw + nxb, nxb, hipMemcpyDeviceToHost, c->stream));
+    if (s) {
+        std::memset(s, 0, sizeof *s);
+        if (c->steps > 0 && !c->p.y_periodic) {
+            const size_t idx = (size_t)((c->steps - 1) % c->p.history_cap);
+            HIP_TRY(c, hipMemcpyAsync(s, c->dev + c->off_hist + idx * sizeof(lbm_stress_summary),
+                                      sizeof(lbm_stress_summary), hipMemcpyDeviceToHost, c->stream));
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_stress_history(lbm_ctx* c, lbm_stress_summary* buf, int64_t cap, int64_t* n_out) {
+    if (!c || !n_out || cap < 0 || (cap > 0 && !buf)) return LBM_EINVAL;
+    if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    const int64_t have = c->p.y_periodic ? 0 : std::min<int64_t>(c->steps, c->p.history_cap);
+    const int64_t n = std::min(have, cap);
+    std::vector<lbm_stress_summary> ring(c->p.history_cap);
+    if (n > 0) {
+        HIP_TRY(c, hipMemcpyAsync(ring.data(), c->dev + c->off_hist, ring.size() * sizeof(lbm_stress_summary),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t step = c->steps - n + 1 + k;
+            buf[k] = ring[(size_t)((step - 1) % c->p.history_cap)];
+        }
+    }
+    *n_out = n;
+    return LBM_OK;
+}
+
+lbm_status lbm_check_state(const lbm_ctx* c, lbm_check_result* out) {
+    if (!c || !out) return LBM_EINVAL;
+    *out = c->check;
+    return LBM_OK;
+}
+
+static float host_weight(int i) { return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
+
+lbm_status lbm_get_f(lbm_ctx* c, double* f) {
+    if (!c || !f) return LBM_EINVAL;
+    if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    const size_t sb = storage_bytes(c->p.storage);
+    std::vector<unsigned char> raw((size_t)c->plane * 9 * sb);
+    HIP_TRY(c, hipMemcpyAsync(raw.data(), c->dev + c->off_f[c->cur], raw.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const float r0 = (float)c->rho0;
+    for (int i = 0; i < 9; ++i)
+        for (int y = 0; y < c->ny; ++y)
+            for (int x = 0; x < c->nx; ++x) {
+                const size_t src = (size_t)i * c->plane + (size_t)y * c->pitch + x;
+                double v;
+                switch (c->p.storage) {
+                    case LBM_F64: std::memcpy(&v, raw.data() + src * 8, 8); break;
+                    case LBM_F32:
+                    case LBM_F32D: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = t; break; }
+                    case LBM_F32S: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = (double)(t + host_weight(i) * r0); break; }
+                    case LBM_F16S: {
+                        _Float16 h;
+                        std::memcpy(&h, raw.data() + src * 2, 2);
+                        v = (double)((float)h + host_weight(i) * r0);
+                        break;
+                    }
+                    default: {
+                        uint16_t h;
+                        std::memcpy(&h, raw.data() + src * 2, 2);
+                        uint32_t u = (uint32_t)h << 16;
+                        float t;
+                        std::memcpy(&t, &u, 4);
+                        v = (double)(t + host_weight(i) * r0);
+                    }
+                }
+                f[((size_t)i * c->ny + y) * c->nx + x] = v;
+            }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
+    if (!c || !f) return LBM_EINVAL;
+    if (!c->bound) return fail(c, LBM_ESTATE, "lbm_bind must come first");
+    const size_t sb = storage_bytes(c->p.storage);
+    std::vector<unsigned char> raw((size_t)c->plane * 9 * sb, 0);
+    const float r0 = (float)c->rho0;
+    for (int i = 0; i < 9; ++i)
+        for (int y = 0; y < c->ny; ++y)
+            for (int x = 0; x < c->nx; ++x) {
+                const size_t dst = (size_t)i * c->plane + (size_t)y * c->pitch + x;
+                const double v = f[((size_t)i * c->ny + y) * c->nx + x];
+                switch (c->p.storage) {
+                    case LBM_F64: std::memcpy(raw.data() + dst * 8, &v, 8); break;
+                    case LBM_F32:
+                    case LBM_F32D: { const float t = (float)v; std::memcpy(raw.data() + dst * 4, &t, 4); break; }
+                    case LBM_F32S: { const float t = (float)v - host_weight(i) * r0; std::memcpy(raw.data() + dst * 4, &t, 4); break; }
+                    case LBM_F16S: {
+                        const _Float16 h = (_Float16)((float)v - host_weight(i) * r0);
+                        std::memcpy(raw.data() + dst * 2, &h, 2);
+                        break;
+                    }
+                    default: {
+                        const float t = (float)v - host_weight(i) * r0;
+                        uint32_t u;
+                        std::memcpy(&u, &t, 4);
+                        u += 0x7FFFu + ((u >> 16) & 1u);
+                        const uint16_t h = (uint16_t)(u >> 16);
+                        std::memcpy(raw.data() + dst * 2, &h, 2);
+                    }
+                }
+            }
+    HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_f[c->cur], raw.data(), raw.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!c->initialized) {
+        lbm_status s = reset_diagnostics(c);
+        if (s) return s;
+        c->initialized = true;
+    }
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

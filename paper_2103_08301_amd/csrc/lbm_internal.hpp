@@ -1,0 +1,61 @@
+// lbm_internal.hpp -- declarations shared by the library's host code and its
+// HIP kernels.  Not part of the public C ABI (include/lbm.h).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// Output columns per 64-lane wavefront strip: each wave covers 64 consecutive
+// columns, of which the outer two on each side are the radius-2 halo that the
+// force stencil grad(lap rho) needs.
+constexpr int kStripOut = 60;
+constexpr int kWavesPerBlock = 4;
+constexpr int kPartialVals = 9;   // tmax, xtmax, tmin, xtmin, pmax, xpmax, pmin, xpmin, sum tau^2
+
+// Everything one launch of the step kernel needs, passed by value.
+struct StepArgs {
+    const void* fin;          // post-collision distributions of the previous step
+    void* fout;               // new post-collision distributions
+    int nx, ny, pitch;        // pitch: elements per row of a distribution plane
+    long long plane;          // elements per plane (pitch * ny)
+    int nstrip, nchunk, ty;   // x strips, y chunks, nominal rows per chunk
+    int xper, yper;
+    double tau, s_e, s_eps, s_q, s_j, s_v;
+    double k2, kappa, g, nu;
+    double RT, a_eff, b;      // EOS: R T, a * alpha(T), b
+    double rho_w;             // wall ghost density
+    double rho0;              // storage shift (F16S/BF16S)
+    double* tau_w;            // [2][nx] wall shear of this step
+    double* p_w;              // [2][nx] wall pressure of this step
+    double* partial;          // [2][nstrip][kPartialVals] this step's per-strip wall extremes
+    double* rho_out;          // emitted fields [ny][nx] (only read when emitting)
+    double* vx_out;
+    double* vy_out;
+};
+
+hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s);
+hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, long long plane,
+                       int storage, double rho0, hipStream_t s);
+hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
+// Stage 1+2 FP64 reduction over the emitted fields into out[5]:
+// sum rho, sum rho vx, sum rho vy, max |v|^2, NaN count.
+hipError_t launch_field_reduce(const double* rho, const double* vx, const double* vy, long long n,
+                               double* partials, int nblocks, double* out, hipStream_t s);
+// Per column: minimum density over y and the centreline density.
+hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin, double* centre,
+                              hipStream_t s);
+// Reduces `nsteps` consecutive slots of the per-strip partial ring into the
+// history ring and the running time integrals acc[2].
+hipError_t launch_wall_reduce(const double* partial_ring, int ring_first, int ring_cap, int nsteps,
+                              int nstrip, int64_t first_step, lbm_stress_summary* hist,
+                              int hist_cap, double* acc, hipStream_t s);
+
+constexpr int kFieldReduceBlocks = 512;
+
+}  // namespace lbm

@@ -1,0 +1,669 @@
+// lbm_kernels.hip -- gfx950 kernels of the EOS-based multiphase MRT lattice
+// Boltzmann step (arXiv 2103.08301, Sec. 2).
+//
+// The step is one fused kernel.  Each 64-lane wavefront owns a strip of 64
+// consecutive columns (60 output columns plus a 2-column halo on each side)
+// and a chunk of rows, and marches up the chunk one row at a time:
+//
+//   row r     : pull-stream the 9 populations (structure-of-arrays loads that
+//               are coalesced along x), density, EOS field phi(rho)
+//   row r - 1 : Laplacian of rho and gradients of phi (and of rho on the wall
+//               rows), from the three most recent rows kept in registers and
+//               their x-neighbours exchanged across lanes
+//   row r - 2 : gradient of the Laplacian, force of eq. 2.17, velocity shift,
+//               MRT collision, store, wall diagnostics
+//
+// so the density and EOS field never leave registers: the only global traffic
+// per node and step is reading 9 and writing 9 populations (plus the halo rows
+// and columns, which the neighbouring strips also read).  No MFMA: the update
+// is a bandwidth-bound stencil, not a dense contraction.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "lbm_internal.hpp"
+
+namespace lbm {
+namespace {
+
+// D2Q9: e0=(0,0) e1=(1,0) e2=(0,1) e3=(-1,0) e4=(0,-1) e5=(1,1) e6=(-1,1) e7=(-1,-1) e8=(1,-1)
+__host__ __device__ constexpr int ex(int i) {
+    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey(int i) {
+    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i < 5 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5); }
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opposites");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opposites");
+template <class C>
+__host__ __device__ constexpr C wgt(int i) {
+    return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
+}
+
+__device__ inline int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ---------------------------------------------------------------------------
+// Storage codecs.
+
+struct CodecF64 {
+    using S = double;
+    using C = double;
+    template <int I>
+    __device__ static C load(const S* p, C) { return *p; }
+    template <int I>
+    __device__ static void store(S* p, C v, C) { *p = v; }
+};
+
+struct CodecF32 {
+    using S = float;
+    using C = float;
+    template <int I>
+    __device__ static C load(const S* p, C) { return *p; }
+    template <int I>
+    __device__ static void store(S* p, C v, C) { *p = v; }
+};
+
+// FP32 storage, FP64 arithmetic (same bytes per node as FP32).
+struct CodecF32D {
+    using S = float;
+    using C = double;
+    template <int I>
+    __device__ static C load(const S* p, C) { return double(*p); }
+    template <int I>
+    __device__ static void store(S* p, C v, C) { *p = float(v); }
+};
+
+// FP32 storage of f_i - w_i rho0, FP32 arithmetic.
+struct CodecF32S {
+    using S = float;
+    using C = float;
+    template <int I>
+    __device__ static C load(const S* p, C rho0) { return *p + wgt<float>(I) * rho0; }
+    template <int I>
+    __device__ static void store(S* p, C v, C rho0) { *p = v - wgt<float>(I) * rho0; }
+};
+
+// FP16 storage of f_i - w_i rho0, FP32 arithmetic, round-to-nearest-even.
+struct CodecF16S {
+    using S = _Float16;
+    using C = float;
+    template <int I>
+    __device__ static C load(const S* p, C rho0) { return static_cast<float>(*p) + wgt<float>(I) * rho0; }
+    template <int I>
+    __device__ static void store(S* p, C v, C rho0) { *p = static_cast<_Float16>(v - wgt<float>(I) * rho0); }
+};
+
+// BF16 storage of f_i - w_i rho0, FP32 arithmetic, round-to-nearest-even.
+struct CodecBF16S {
+    using S = uint16_t;
+    using C = float;
+    template <int I>
+    __device__ static C load(const S* p, C rho0) {
+        return __uint_as_float(static_cast<uint32_t>(*p) << 16) + wgt<float>(I) * rho0;
+    }
+    template <int I>
+    __device__ static void store(S* p, C v, C rho0) {
+        uint32_t u = __float_as_uint(v - wgt<float>(I) * rho0);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        *p = static_cast<uint16_t>(u >> 16);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Arithmetic helpers.
+
+// Hardware reciprocal refined by one Newton step (error well below 1 ulp).
+__device__ inline float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+__device__ inline double recip(double x) { return 1.0 / x; }
+
+template <class C>
+__device__ inline C shfl_next(C v) { return __shfl_down(v, 1, 64); }  // value of lane + 1 (column x + 1)
+template <class C>
+__device__ inline C shfl_prev(C v) { return __shfl_up(v, 1, 64); }    // value of lane - 1 (column x - 1)
+
+// phi = k^2 p0(rho) - rho/3: the nonideal part of the pressure in mesh units (eq. 2.17).
+template <int EOS, class C>
+__device__ inline C phi_of(C rho, C RT, C a_eff, C b, C k2) {
+    C p0;
+    if (EOS == LBM_EOS_CS) {
+        const C eta = C(0.25) * b * rho;
+        const C num = C(1) + eta * (C(1) + eta * (C(1) - eta));
+        const C d = C(1) - eta;
+        p0 = rho * RT * num * recip(d * d * d) - a_eff * rho * rho;
+    } else {
+        const C d = C(1) - b * rho;
+        const C q = C(1) + b * rho * (C(2) - b * rho);
+        p0 = rho * (RT * q - a_eff * rho * d) * recip(d * q);
+    }
+    return k2 * p0 - rho * C(1.0 / 3.0);
+}
+
+template <int EOS, class C>
+__device__ inline C p0_of(C rho, C RT, C a_eff, C b) {
+    return phi_of<EOS, C>(rho, RT, a_eff, b, C(1)) + rho * C(1.0 / 3.0);
+}
+
+template <class C>
+struct Row3 {  // a field value at a column and its two x-neighbours
+    C c, e, w;
+};
+
+template <class C>
+__device__ inline Row3<C> with_neighbours(C v) {
+    return Row3<C>{v, shfl_next(v), shfl_prev(v)};
+}
+
+// Isotropic D2Q9 operators on three consecutive rows (s = y-1, m = y, n = y+1):
+// grad = 3 sum w_i e_i psi(x + e_i), lap = 6 sum w_i (psi(x + e_i) - psi(x)).
+template <class C>
+__device__ inline C lap3(const Row3<C>& s, const Row3<C>& m, const Row3<C>& n) {
+    return C(2.0 / 3.0) * (m.e + m.w + n.c + s.c) + C(1.0 / 6.0) * (n.e + n.w + s.e + s.w) - C(10.0 / 3.0) * m.c;
+}
+template <class C>
+__device__ inline void grad3(const Row3<C>& s, const Row3<C>& m, const Row3<C>& n, C& gx, C& gy) {
+    gx = C(1.0 / 3.0) * (m.e - m.w) + C(1.0 / 12.0) * ((n.e - n.w) + (s.e - s.w));
+    gy = C(1.0 / 3.0) * (n.c - s.c) + C(1.0 / 12.0) * ((n.e + n.w) - (s.e + s.w));
+}
+
+// Wave-wide reductions (64 lanes) used for the per-strip wall extremes.
+__device__ inline void wave_argmax(double& v, int& x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double ov = __shfl_xor(v, off, 64);
+        int ox = __shfl_xor(x, off, 64);
+        if (ov > v || (ov == v && ox < x)) { v = ov; x = ox; }
+    }
+}
+__device__ inline void wave_argmin(double& v, int& x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double ov = __shfl_xor(v, off, 64);
+        int ox = __shfl_xor(x, off, 64);
+        if (ov < v || (ov == v && ox < x)) { v = ov; x = ox; }
+    }
+}
+__device__ inline double wave_sum(double v) {
+    // fixed butterfly: every lane ends with the same, order-deterministic sum
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of an MI355X; remap so that
+// each XCD (own L2) works on a contiguous range of tiles, keeping the halo rows
+// and columns that neighbouring strips share in one L2.
+__device__ inline int xcd_remap(int b, int G) {
+    const int xcd = b & 7, local = b >> 3, per = G >> 3, rem = G & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+// Pull-streaming of one node (column xe in [0, nx), row yr in [0, ny)).
+// Populations whose source lies beyond a wall are bounced back (halfway
+// bounce-back); sources beyond an end are clamped (extrapolated) or wrapped.
+template <class CD>
+__device__ inline void pull_generic(const typename CD::S* __restrict__ fin, const StepArgs& a, int xe, int yr,
+                                    typename CD::C rho0, typename CD::C (&f)[9]) {
+    using S = typename CD::S;
+#define LBM_PULL(I)                                                                     \
+    {                                                                                   \
+        int sx = xe - ex(I), sy = yr - ey(I);                                           \
+        const S* src;                                                                   \
+        if (!a.yper && (sy < 0 || sy >= a.ny)) {                                        \
+            src = fin + (long long)opp(I) * a.plane + (long long)yr * a.pitch + xe;     \
+            f[I] = CD::template load<opp(I)>(src, rho0);                                \
+        } else {                                                                        \
+            if (a.yper) sy = wrapi(sy, a.ny);                                           \
+            if (sx < 0 || sx >= a.nx) sx = a.xper ? wrapi(sx, a.nx) : clampi(sx, 0, a.nx - 1); \
+            src = fin + (long long)(I) * a.plane + (long long)sy * a.pitch + sx;        \
+            f[I] = CD::template load<I>(src, rho0);                                     \
+        }                                                                               \
+    }
+    LBM_PULL(0) LBM_PULL(1) LBM_PULL(2) LBM_PULL(3) LBM_PULL(4) LBM_PULL(5) LBM_PULL(6) LBM_PULL(7) LBM_PULL(8)
+#undef LBM_PULL
+}
+
+// Interior fast path: every source is in range, no boundary logic.
+template <class CD>
+__device__ inline void pull_interior(const typename CD::S* __restrict__ fin, const StepArgs& a, int xe, int yr,
+                                     typename CD::C rho0, typename CD::C (&f)[9]) {
+    const long long base = (long long)yr * a.pitch + xe;
+#define LBM_PULLI(I) f[I] = CD::template load<I>(fin + (long long)(I) * a.plane + base - (long long)ey(I) * a.pitch - ex(I), rho0);
+    LBM_PULLI(0) LBM_PULLI(1) LBM_PULLI(2) LBM_PULLI(3) LBM_PULLI(4) LBM_PULLI(5) LBM_PULLI(6) LBM_PULLI(7) LBM_PULLI(8)
+#undef LBM_PULLI
+}
+
+// MRT collision (eq. 2.1) in the Lallemand-Luo basis (rho, e, eps, jx, qx, jy, qy, pxx, pxy)
+// with m_eq = M f_eq(rho, u_eq), eq. 2.2, and f* = f - M^-1 S (m - m_eq), M^-1 = M^T diag(1/|row|^2).
+template <class C>
+__device__ inline void collide(C (&f)[9], C rho, C jx, C jy, C Fx, C Fy, C inv_rho, const StepArgs& a,
+                               C tau, C s_e, C s_eps, C s_q, C s_j, C s_v, C& vx, C& vy) {
+    // P = rho u_eq = j + tau F exactly (velocity shift of Sec. 2.2); the reciprocal
+    // of rho only enters the second-order terms, so mass and momentum updates do
+    // not depend on its rounding.
+    const C Px = jx + tau * Fx, Py = jy + tau * Fy;
+    const C uex = Px * inv_rho, uey = Py * inv_rho;
+    vx = (jx + C(0.5) * Fx) * inv_rho;
+    vy = (jy + C(0.5) * Fy) * inv_rho;
+    const C A = f[1] + f[2] + f[3] + f[4];
+    const C D = f[5] + f[6] + f[7] + f[8];
+    const C e = -C(4) * f[0] - A + C(2) * D;
+    const C eps = C(4) * f[0] - C(2) * A + D;
+    const C qx = C(2) * (f[3] - f[1]) + (f[5] - f[6] - f[7] + f[8]);
+    const C qy = C(2) * (f[4] - f[2]) + (f[5] + f[6] - f[7] - f[8]);
+    const C pxx = (f[1] + f[3]) - (f[2] + f[4]);
+    const C pxy = (f[5] + f[7]) - (f[6] + f[8]);
+    const C ru2 = C(3) * (Px * uex + Py * uey);  // 3 rho |u_eq|^2
+    // relaxation terms d_k = S_k (m_k - m_eq_k) / |row_k|^2
+    const C de = s_e * C(1.0 / 36.0) * (e - (ru2 - C(2) * rho));
+    const C deps = s_eps * C(1.0 / 36.0) * (eps - (rho - ru2));
+    const C djx = -s_j * tau * C(1.0 / 6.0) * Fx;
+    const C djy = -s_j * tau * C(1.0 / 6.0) * Fy;
+    const C dqx = s_q * C(1.0 / 12.0) * (qx + Px);
+    const C dqy = s_q * C(1.0 / 12.0) * (qy + Py);
+    const C dxx = s_v * C(0.25) * (pxx - (Px * uex - Py * uey));
+    const C dxy = s_v * C(0.25) * (pxy - Px * uey);
+    // f* = f - sum_k M_ki d_k
+    const C c0 = -de - C(2) * deps;     // shared by the axis directions
+    const C c1 = C(2) * de + deps;      // shared by the diagonals
+    const C X = djx - C(2) * dqx, Y = djy - C(2) * dqy;
+    const C Xd = djx + dqx, Yd = djy + dqy;
+    f[0] -= C(4) * (deps - de);
+    f[1] -= c0 + X + dxx;
+    f[3] -= c0 - X + dxx;
+    f[2] -= c0 + Y - dxx;
+    f[4] -= c0 - Y - dxx;
+    f[5] -= c1 + Xd + Yd + dxy;
+    f[7] -= c1 - Xd - Yd + dxy;
+    f[6] -= c1 - Xd + Yd - dxy;
+    f[8] -= c1 + Xd - Yd - dxy;
+}
+
+template <class CD, int EOS, bool EMIT>
+__global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
+    using S = typename CD::S;
+    using C = typename CD::C;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int nbx = (a.nstrip + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int chunk = bid / nbx;
+    const int strip = (bid - chunk * nbx) * kWavesPerBlock + wave;
+    if (strip >= a.nstrip) return;  // whole wave
+
+    const S* __restrict__ fin = static_cast<const S*>(a.fin);
+    S* __restrict__ fout = static_cast<S*>(a.fout);
+    const int x0 = strip * kStripOut;
+    const int x = x0 - 2 + lane;
+    const bool out_lane = lane >= 2 && lane < 62 && x < a.nx;
+    int xe = x;
+    if (xe < 0 || xe >= a.nx) xe = a.xper ? wrapi(xe, a.nx) : clampi(xe, 0, a.nx - 1);
+    const bool strip_inner = (x0 - 3 >= 0) && (x0 + 62 <= a.nx - 1);
+    const int y0 = chunk * a.ty;
+    const int y1 = (chunk == a.nchunk - 1) ? a.ny : y0 + a.ty;
+    const bool walls = !a.yper;
+
+    const C rho0 = C(a.rho0);
+    const C RT = C(a.RT), a_eff = C(a.a_eff), bb = C(a.b), k2 = C(a.k2), kappa = C(a.kappa), g = C(a.g);
+    const C tau = C(a.tau), s_e = C(a.s_e), s_eps = C(a.s_eps), s_q = C(a.s_q), s_j = C(a.s_j), s_v = C(a.s_v);
+    const C rho_w = C(a.rho_w);
+
+    // register window: rows r-1 (suffix 1) and r-2 (suffix 2), Laplacian rows r-2 and r-3
+    Row3<C> rho1{0, 0, 0}, rho2{0, 0, 0}, phi1{0, 0, 0}, phi2{0, 0, 0}, lap2{0, 0, 0}, lap3r{0, 0, 0};
+    C gphx = 0, gphy = 0, grx = 0, gry = 0;  // gradients of phi and rho at row r-2
+    C f1[9], f2[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { f1[i] = 0; f2[i] = 0; }
+    C wall_rho = 0, wall_vx = 0, wall_p = 0;  // bottom-wall row 0 values kept for row 1; top: vx of ny-2
+
+    for (int r = y0 - 2; r < y1 + 2; ++r) {
+        // ---- row r: pull, density, EOS field --------------------------------
+        C f0[9];
+        C rho;
+        const bool fluid_row = a.yper || (r >= 0 && r < a.ny);
+        if (fluid_row) {
+            const int yr = a.yper ? wrapi(r, a.ny) : r;
+            if (strip_inner && yr >= 1 && yr <= a.ny - 2)
+                pull_interior<CD>(fin, a, xe, yr, rho0, f0);
+            else
+                pull_generic<CD>(fin, a, xe, yr, rho0, f0);
+            rho = ((f0[0] + f0[1]) + (f0[2] + f0[3])) + ((f0[4] + f0[5]) + (f0[6] + f0[7])) + f0[8];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f0[i] = 0;
+            rho = rho_w;
+        }
+        const Row3<C> rho0r = with_neighbours(rho);
+        const Row3<C> phi0 = with_neighbours(phi_of<EOS, C>(rho, RT, a_eff, bb, k2));
+
+        // ---- row r-1: Laplacian, grad phi (and grad rho on wall rows) -------
+        const Row3<C> lap1 = with_neighbours(lap3(rho2, rho1, rho0r));
+        C gphx1, gphy1;
+        grad3(phi2, phi1, phi0, gphx1, gphy1);
+        C grx1 = 0, gry1 = 0;
+        if (walls && (r - 1 == 0 || r - 1 == a.ny - 1)) grad3(rho2, rho1, rho0r, grx1, gry1);
+
+        // ---- row r-2: force, collision, store, wall diagnostics -------------
+        const int y = r - 2;
+        if (y >= y0) {
+            C glx, gly;
+            grad3(lap3r, lap2, lap1, glx, gly);
+            const C rh = rho2.c;
+            const C Fx = -gphx + kappa * rh * glx + g;
+            const C Fy = -gphy + kappa * rh * gly;
+            const C jx = (f2[1] - f2[3]) + (f2[5] - f2[6]) + (f2[8] - f2[7]);
+            const C jy = (f2[2] - f2[4]) + (f2[5] - f2[8]) + (f2[6] - f2[7]);
+            const C inv_rho = recip(rh);
+            C vx, vy;
+            collide<C>(f2, rh, jx, jy, Fx, Fy, inv_rho, a, tau, s_e, s_eps, s_q, s_j, s_v, vx, vy);
+            if (out_lane) {
+                const long long o = (long long)y * a.pitch + x;
+#define LBM_STORE(I) CD::template store<I>(fout + (long long)(I) * a.plane + o, f2[I], rho0);
+                LBM_STORE(0) LBM_STORE(1) LBM_STORE(2) LBM_STORE(3) LBM_STORE(4) LBM_STORE(5) LBM_STORE(6)
+                LBM_STORE(7) LBM_STORE(8)
+#undef LBM_STORE
+                if (EMIT) {
+                    const long long c = (long long)y * a.nx + x;
+                    a.rho_out[c] = double(rh);
+                    a.vx_out[c] = double(vx);
+                    a.vy_out[c] = double(vy);
+                }
+            }
+            if (walls) {
+                // wall pressure: isotropic part of eq. 2.8 on the first fluid row
+                const bool bottom_p = (y == 0), top_p = (y == a.ny - 1);
+                if (bottom_p || top_p) {
+                    wall_p = k2 * p0_of<EOS, C>(rh, RT, a_eff, bb) - kappa * rh * lap2.c
+                           - C(0.5) * kappa * (grx * grx + gry * gry);
+                }
+                if (bottom_p) { wall_rho = rh; wall_vx = vx; }
+                if (y == a.ny - 2 && !(bottom_p)) wall_vx = vx;
+                const bool bottom_t = (y == 1), top_t = (y == a.ny - 1);
+                if (bottom_t || top_t) {
+                    // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
+                    C tw, pw;
+                    if (bottom_t) {
+                        tw = wall_rho * C(a.nu) * (C(9) * wall_vx - vx) * C(1.0 / 3.0);
+                        pw = wall_p;
+                    } else {
+                        tw = rh * C(a.nu) * (C(9) * vx - wall_vx) * C(1.0 / 3.0);
+                        pw = wall_p;
+                    }
+                    const int w = bottom_t ? 0 : 1;
+                    if (bottom_t && top_t) { /* ny == 2 never happens: ny >= 4 */ }
+                    double dt = out_lane ? double(tw) : 0.0, dp = out_lane ? double(pw) : 0.0;
+                    if (out_lane) {
+                        a.tau_w[w * a.nx + x] = dt;
+                        a.p_w[w * a.nx + x] = dp;
+                    }
+                    double tmax = out_lane ? dt : -INFINITY, tmin = out_lane ? dt : INFINITY;
+                    double pmax = out_lane ? dp : -INFINITY, pmin = out_lane ? dp : INFINITY;
+                    int xtmax = out_lane ? x : 0x7fffffff, xtmin = xtmax, xpmax = xtmax, xpmin = xtmax;
+                    wave_argmax(tmax, xtmax);
+                    wave_argmin(tmin, xtmin);
+                    wave_argmax(pmax, xpmax);
+                    wave_argmin(pmin, xpmin);
+                    const double s2 = wave_sum(dt * dt);
+                    if (lane == 0) {
+                        double* o = a.partial + ((long long)w * a.nstrip + strip) * kPartialVals;
+                        o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
+                        o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
+                        o[8] = s2;
+                    }
+                }
+            }
+        }
+
+        // ---- rotate the register window -------------------------------------
+        rho2 = rho1; rho1 = rho0r;
+        phi2 = phi1; phi1 = phi0;
+        lap3r = lap2; lap2 = lap1;
+        gphx = gphx1; gphy = gphy1;
+        grx = grx1; gry = gry1;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) { f2[i] = f1[i]; f1[i] = f0[i]; }
+    }
+}
+
+template <class CD>
+__global__ void init_kernel(const double* __restrict__ rho, void* fv, int nx, int ny, int pitch, long long plane,
+                            double rho0) {
+    using S = typename CD::S;
+    using C = typename CD::C;
+    S* f = static_cast<S*>(fv);
+    const long long n = (long long)nx * ny;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        const int y = int(c / nx), x = int(c - (long long)y * nx);
+        const C r = C(rho[c]);
+        S* p = f + (long long)y * pitch + x;
+        CD::template store<0>(p + 0 * plane, wgt<C>(0) * r, C(rho0));
+        CD::template store<1>(p + 1 * plane, wgt<C>(1) * r, C(rho0));
+        CD::template store<2>(p + 2 * plane, wgt<C>(2) * r, C(rho0));
+        CD::template store<3>(p + 3 * plane, wgt<C>(3) * r, C(rho0));
+        CD::template store<4>(p + 4 * plane, wgt<C>(4) * r, C(rho0));
+        CD::template store<5>(p + 5 * plane, wgt<C>(5) * r, C(rho0));
+        CD::template store<6>(p + 6 * plane, wgt<C>(6) * r, C(rho0));
+        CD::template store<7>(p + 7 * plane, wgt<C>(7) * r, C(rho0));
+        CD::template store<8>(p + 8 * plane, wgt<C>(8) * r, C(rho0));
+    }
+}
+
+__global__ void fill_kernel(double* p, double v, long long n) {
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x)
+        p[c] = v;
+}
+
+// Deterministic two-stage FP64 reduction.  Stage 1: block b reduces the
+// contiguous range [b n/B, (b+1) n/B) with a fixed thread/LDS tree.
+constexpr int kRedThreads = 256;
+
+__device__ inline void block_reduce5(double (&v)[5], double (*sh)[kRedThreads]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sh[k][t] = v[k];
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sh[0][t] += sh[0][t + s];
+            sh[1][t] += sh[1][t + s];
+            sh[2][t] += sh[2][t + s];
+            sh[3][t] = fmax(sh[3][t], sh[3][t + s]);
+            sh[4][t] += sh[4][t + s];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = sh[k][0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void field_reduce_stage1(const double* __restrict__ rho,
+                                                                   const double* __restrict__ vx,
+                                                                   const double* __restrict__ vy, long long n,
+                                                                   double* __restrict__ partials) {
+    __shared__ double sh[5][kRedThreads];
+    const long long lo = n * blockIdx.x / gridDim.x, hi = n * (blockIdx.x + 1) / gridDim.x;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (long long c = lo + threadIdx.x; c < hi; c += kRedThreads) {
+        const double r = rho[c], ux = vx[c], uy = vy[c];
+        v[0] += r;
+        v[1] += r * ux;
+        v[2] += r * uy;
+        const double u2 = ux * ux + uy * uy;
+        if (u2 > v[3]) v[3] = u2;
+        if (r != r || ux != ux || uy != uy) v[4] += 1.0;
+    }
+    block_reduce5(v, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) partials[blockIdx.x * 5 + k] = v[k];
+}
+
+__global__ __launch_bounds__(kRedThreads) void field_reduce_stage2(const double* __restrict__ partials, int nb,
+                                                                   double* __restrict__ out) {
+    __shared__ double sh[5][kRedThreads];
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) {
+        v[0] += partials[b * 5 + 0];
+        v[1] += partials[b * 5 + 1];
+        v[2] += partials[b * 5 + 2];
+        v[3] = fmax(v[3], partials[b * 5 + 3]);
+        v[4] += partials[b * 5 + 4];
+    }
+    block_reduce5(v, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) out[k] = v[k];
+}
+
+__global__ void column_scan_kernel(const double* __restrict__ rho, int nx, int ny, double* __restrict__ colmin,
+                                   double* __restrict__ centre) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    double m = rho[x];
+    for (int y = 1; y < ny; ++y) m = fmin(m, rho[(long long)y * nx + x]);
+    colmin[x] = m;
+    if (ny % 2 == 0)
+        centre[x] = 0.5 * (rho[(long long)(ny / 2 - 1) * nx + x] + rho[(long long)(ny / 2) * nx + x]);
+    else
+        centre[x] = rho[(long long)(ny / 2) * nx + x];
+}
+
+// One thread per step reduces the per-strip partials (strips in x order, so
+// strict comparisons keep the smallest x); thread 0 then accumulates the time
+// integrals in step order.
+constexpr int kWallThreads = 256;
+
+__global__ __launch_bounds__(kWallThreads) void wall_reduce_kernel(const double* __restrict__ ring, int first,
+                                                                   int ring_cap, int nsteps, int nstrip,
+                                                                   int64_t first_step, lbm_stress_summary* hist,
+                                                                   int hist_cap, double* acc) {
+    __shared__ double peak2[kWallThreads], sum2[kWallThreads];
+    const int t = threadIdx.x;
+    if (t < nsteps) {
+        const double* slot = ring + (long long)((first + t) % ring_cap) * 2 * nstrip * kPartialVals;
+        lbm_stress_summary sm;
+        sm.step = first_step + t;
+        double pk = 0.0, s2 = 0.0;
+        for (int w = 0; w < 2; ++w) {
+            const double* p = slot + (long long)w * nstrip * kPartialVals;
+            double tmax = p[0], tmin = p[2], pmax = p[4], pmin = p[6], ws = p[8];
+            double xtmax = p[1], xtmin = p[3], xpmax = p[5], xpmin = p[7];
+            for (int s = 1; s < nstrip; ++s) {
+                const double* q = p + (long long)s * kPartialVals;
+                if (q[0] > tmax) { tmax = q[0]; xtmax = q[1]; }
+                if (q[2] < tmin) { tmin = q[2]; xtmin = q[3]; }
+                if (q[4] > pmax) { pmax = q[4]; xpmax = q[5]; }
+                if (q[6] < pmin) { pmin = q[6]; xpmin = q[7]; }
+                ws += q[8];
+            }
+            sm.tau_max[w] = tmax; sm.tau_min[w] = tmin; sm.p_max[w] = pmax; sm.p_min[w] = pmin;
+            sm.x_tau_max[w] = int32_t(xtmax); sm.x_tau_min[w] = int32_t(xtmin);
+            sm.x_p_max[w] = int32_t(xpmax); sm.x_p_min[w] = int32_t(xpmin);
+            pk = fmax(pk, fmax(tmax * tmax, tmin * tmin));
+            s2 += ws;
+        }
+        sm.sum_tau2 = s2;
+        sm.int_peak_tau2 = 0.0;
+        sm.int_tau2 = 0.0;
+        hist[(sm.step - 1) % hist_cap] = sm;
+        peak2[t] = pk;
+        sum2[t] = s2;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double ip = acc[0], is = acc[1];
+        for (int k = 0; k < nsteps; ++k) {
+            ip += peak2[k];
+            is += sum2[k];
+            lbm_stress_summary* h = &hist[(first_step + k - 1) % hist_cap];
+            h->int_peak_tau2 = ip;
+            h->int_tau2 = is;
+        }
+        acc[0] = ip;
+        acc[1] = is;
+    }
+}
+
+template <class CD, int EOS>
+hipError_t launch_step_t(const StepArgs& a, bool emit, hipStream_t s) {
+    const int nbx = (a.nstrip + kWavesPerBlock - 1) / kWavesPerBlock;
+    const dim3 grid(nbx * a.nchunk), block(64 * kWavesPerBlock);
+    if (emit)
+        hipLaunchKernelGGL((step_kernel<CD, EOS, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((step_kernel<CD, EOS, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <class CD>
+hipError_t launch_step_c(const StepArgs& a, int eos, bool emit, hipStream_t s) {
+    return eos == LBM_EOS_CS ? launch_step_t<CD, LBM_EOS_CS>(a, emit, s) : launch_step_t<CD, LBM_EOS_PR>(a, emit, s);
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s) {
+    switch (storage) {
+        case LBM_F64: return launch_step_c<CodecF64>(a, eos, emit, s);
+        case LBM_F32: return launch_step_c<CodecF32>(a, eos, emit, s);
+        case LBM_F16S: return launch_step_c<CodecF16S>(a, eos, emit, s);
+        case LBM_BF16S: return launch_step_c<CodecBF16S>(a, eos, emit, s);
+        case LBM_F32D: return launch_step_c<CodecF32D>(a, eos, emit, s);
+        case LBM_F32S: return launch_step_c<CodecF32S>(a, eos, emit, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, long long plane, int storage,
+                       double rho0, hipStream_t s) {
+    const long long n = (long long)nx * ny;
+    const int blocks = int((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    switch (storage) {
+        case LBM_F64: hipLaunchKernelGGL(init_kernel<CodecF64>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        case LBM_F32: hipLaunchKernelGGL(init_kernel<CodecF32>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        case LBM_F16S: hipLaunchKernelGGL(init_kernel<CodecF16S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        case LBM_BF16S: hipLaunchKernelGGL(init_kernel<CodecBF16S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        case LBM_F32D: hipLaunchKernelGGL(init_kernel<CodecF32D>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        case LBM_F32S: hipLaunchKernelGGL(init_kernel<CodecF32S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, double v, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = int((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_reduce(const double* rho, const double* vx, const double* vy, long long n, double* partials,
+                               int nblocks, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(field_reduce_stage1, dim3(nblocks), dim3(kRedThreads), 0, s, rho, vx, vy, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(field_reduce_stage2, dim3(1), dim3(kRedThreads), 0, s, partials, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin, double* centre, hipStream_t s) {
+    hipLaunchKernelGGL(column_scan_kernel, dim3((nx + 255) / 256), dim3(256), 0, s, rho, nx, ny, colmin, centre);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_reduce(const double* ring, int first, int ring_cap, int nsteps, int nstrip, int64_t first_step,
+                              lbm_stress_summary* hist, int hist_cap, double* acc, hipStream_t s) {
+    if (nsteps <= 0) return hipSuccess;
+    if (nsteps > kWallThreads) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wall_reduce_kernel, dim3(1), dim3(kWallThreads), 0, s, ring, first, ring_cap, nsteps, nstrip,
+                       first_step, hist, hist_cap, acc);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

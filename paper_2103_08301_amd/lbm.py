@@ -1,0 +1,299 @@
+"""Thin ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+
+The functions below carry the C names (lbm_create, lbm_bind, lbm_step, ...).
+`Lattice` strings them together: torch supplies the device workspace and the
+HIP stream, the library does every step of the method in its own kernels.  The
+binding raises if liblbm.so is missing; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_EOS_CS, LBM_EOS_PR = 0, 1
+LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F32D, LBM_F32S = 0, 1, 2, 3, 4, 5
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S, "f32d": LBM_F32D,
+           "f32s": LBM_F32S}
+
+EXPORTED = [
+    "lbm_params_default", "lbm_create", "lbm_workspace", "lbm_bind", "lbm_state", "lbm_init_plug",
+    "lbm_init_density", "lbm_step", "lbm_step_count", "lbm_fields", "lbm_wall_stress", "lbm_stress_history",
+    "lbm_check_state", "lbm_get_f", "lbm_set_f", "lbm_destroy", "lbm_last_error",
+]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lbm status {status}: {msg}")
+        self.status = status
+
+
+class lbm_params(C.Structure):
+    _fields_ = [
+        ("eos", C.c_int), ("a", C.c_double), ("b", C.c_double), ("R", C.c_double), ("omega", C.c_double),
+        ("T_over_Tc", C.c_double), ("k", C.c_double), ("kappa", C.c_double), ("s_e", C.c_double),
+        ("s_eps", C.c_double), ("s_q", C.c_double), ("s_j", C.c_double), ("rho_wall", C.c_double),
+        ("dp", C.c_double), ("x_periodic", C.c_int), ("y_periodic", C.c_int), ("storage", C.c_int),
+        ("rho0_shift", C.c_double), ("check_every", C.c_int), ("v_limit", C.c_double),
+        ("history_cap", C.c_int),
+    ]
+
+
+class lbm_stress_summary(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("tau_max", C.c_double * 2), ("tau_min", C.c_double * 2),
+        ("p_max", C.c_double * 2), ("p_min", C.c_double * 2), ("x_tau_max", C.c_int32 * 2),
+        ("x_tau_min", C.c_int32 * 2), ("x_p_max", C.c_int32 * 2), ("x_p_min", C.c_int32 * 2),
+        ("sum_tau2", C.c_double), ("int_peak_tau2", C.c_double), ("int_tau2", C.c_double),
+    ]
+
+
+class lbm_check_result(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("mass", C.c_double), ("momx", C.c_double), ("momy", C.c_double),
+        ("vmax", C.c_double), ("nan_count", C.c_int64), ("x_rear", C.c_double), ("x_front", C.c_double),
+        ("liquid_columns", C.c_int32), ("rupture_step", C.c_int64), ("unstable_step", C.c_int64),
+    ]
+
+
+def struct_dict(s) -> dict:
+    out = {}
+    for name, _ in s._fields_:
+        v = getattr(s, name)
+        out[name] = list(v) if hasattr(v, "__len__") else v
+    return out
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+_P = C.c_void_p
+
+
+def library():
+    """Loads liblbm.so; fails loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        PP = C.POINTER(lbm_params)
+        sig = {
+            "lbm_params_default": (None, [PP]),
+            "lbm_create": (C.c_int, [C.c_int, C.c_int, C.c_double, PP, C.POINTER(_P)]),
+            "lbm_workspace": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+            "lbm_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
+            "lbm_state": (C.c_int, [_P, _D, _D, _D, _D, _D]),
+            "lbm_init_plug": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]),
+            "lbm_init_density": (C.c_int, [_P, _D]),
+            "lbm_step": (C.c_int, [_P, C.c_int64]),
+            "lbm_step_count": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+            "lbm_fields": (C.c_int, [_P, _D, _D, _D]),
+            "lbm_wall_stress": (C.c_int, [_P, _D, _D, _D, _D, C.POINTER(lbm_stress_summary)]),
+            "lbm_stress_history": (C.c_int, [_P, C.POINTER(lbm_stress_summary), C.c_int64,
+                                             C.POINTER(C.c_int64)]),
+            "lbm_check_state": (C.c_int, [_P, C.POINTER(lbm_check_result)]),
+            "lbm_get_f": (C.c_int, [_P, _D]),
+            "lbm_set_f": (C.c_int, [_P, _D]),
+            "lbm_destroy": (None, [_P]),
+            "lbm_last_error": (C.c_char_p, [_P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _check(ctx, st: int):
+    if st != LBM_OK:
+        msg = library().lbm_last_error(ctx)
+        raise LbmError(st, msg.decode() if msg else "")
+
+
+# ---- C-named wrappers -------------------------------------------------------
+
+def lbm_params_default(**overrides) -> lbm_params:
+    p = lbm_params()
+    library().lbm_params_default(C.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(f"unknown lbm_params field {k!r}")
+        setattr(p, k, STORAGE[v] if k == "storage" and isinstance(v, str) else v)
+    return p
+
+
+def lbm_create(nx: int, ny: int, tau: float, p: lbm_params):
+    h = C.c_void_p()
+    st = library().lbm_create(nx, ny, tau, C.byref(p), C.byref(h))
+    if st != LBM_OK:
+        raise LbmError(st, f"lbm_create({nx}, {ny}, {tau}) rejected the parameters")
+    return h
+
+
+def lbm_workspace(ctx) -> int:
+    n = C.c_size_t()
+    _check(ctx, library().lbm_workspace(ctx, C.byref(n)))
+    return n.value
+
+
+def lbm_bind(ctx, device_ptr: int, nbytes: int, stream: int):
+    _check(ctx, library().lbm_bind(ctx, C.c_void_p(device_ptr), nbytes, C.c_void_p(stream)))
+
+
+def lbm_state(ctx) -> dict:
+    v = [C.c_double() for _ in range(5)]
+    _check(ctx, library().lbm_state(ctx, *[C.byref(x) for x in v]))
+    return dict(zip(["T", "Tc", "rho_g", "rho_l", "rho_w"], [x.value for x in v]))
+
+
+def lbm_init_plug(ctx, plug_len, film, x_center=math.nan, noise_amp=1e-3, seed=1):
+    _check(ctx, library().lbm_init_plug(ctx, plug_len, film, x_center, noise_amp, seed))
+
+
+def lbm_init_density(ctx, rho: np.ndarray):
+    _check(ctx, library().lbm_init_density(ctx, _ptr(np.ascontiguousarray(rho, dtype=np.float64))))
+
+
+def lbm_step(ctx, n: int) -> int:
+    """Returns the status (LBM_OK or LBM_EUNSTABLE); other failures raise."""
+    st = library().lbm_step(ctx, n)
+    if st not in (LBM_OK, LBM_EUNSTABLE):
+        _check(ctx, st)
+    return st
+
+
+def lbm_step_count(ctx) -> int:
+    n = C.c_int64()
+    _check(ctx, library().lbm_step_count(ctx, C.byref(n)))
+    return n.value
+
+
+def lbm_fields(ctx, rho, vx, vy):
+    _check(ctx, library().lbm_fields(ctx, _ptr(rho), _ptr(vx), _ptr(vy)))
+
+
+def lbm_wall_stress(ctx, tau_bot, tau_top, p_bot, p_top) -> dict:
+    s = lbm_stress_summary()
+    _check(ctx, library().lbm_wall_stress(ctx, _ptr(tau_bot), _ptr(tau_top), _ptr(p_bot), _ptr(p_top),
+                                          C.byref(s)))
+    return struct_dict(s)
+
+
+def lbm_stress_history(ctx, cap: int) -> list:
+    buf = (lbm_stress_summary * max(cap, 1))()
+    n = C.c_int64()
+    _check(ctx, library().lbm_stress_history(ctx, buf, cap, C.byref(n)))
+    return [struct_dict(buf[i]) for i in range(n.value)]
+
+
+def lbm_check_state(ctx) -> dict:
+    r = lbm_check_result()
+    _check(ctx, library().lbm_check_state(ctx, C.byref(r)))
+    return struct_dict(r)
+
+
+def lbm_get_f(ctx, f: np.ndarray):
+    _check(ctx, library().lbm_get_f(ctx, _ptr(f)))
+
+
+def lbm_set_f(ctx, f: np.ndarray):
+    _check(ctx, library().lbm_set_f(ctx, _ptr(np.ascontiguousarray(f, dtype=np.float64))))
+
+
+def lbm_destroy(ctx):
+    library().lbm_destroy(ctx)
+
+
+def lbm_last_error(ctx) -> str:
+    m = library().lbm_last_error(ctx)
+    return m.decode() if m else ""
+
+
+# ---- convenience object -----------------------------------------------------
+
+class Lattice:
+    """One D2Q9 channel on one GPU.  torch provides the device workspace and the stream."""
+
+    def __init__(self, nx: int, ny: int, tau: float, device: str = "cuda:0", stream=None, **params):
+        import torch
+
+        self.nx, self.ny, self.tau = nx, ny, tau
+        self.params = lbm_params_default(**params)
+        self._ctx = lbm_create(nx, ny, tau, self.params)
+        nbytes = lbm_workspace(self._ctx)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            lbm_bind(self._ctx, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            lbm_destroy(ctx)
+            self._ctx = None
+
+    @property
+    def ctx(self):
+        return self._ctx
+
+    def state(self) -> dict:
+        return lbm_state(self._ctx)
+
+    def init_plug(self, plug_len, film, x_center=math.nan, noise_amp=1e-3, seed=1):
+        lbm_init_plug(self._ctx, plug_len, film, x_center, noise_amp, seed)
+
+    def init_density(self, rho: np.ndarray):
+        assert rho.shape == (self.ny, self.nx)
+        lbm_init_density(self._ctx, rho)
+
+    def step(self, n: int) -> int:
+        return lbm_step(self._ctx, n)
+
+    @property
+    def steps(self) -> int:
+        return lbm_step_count(self._ctx)
+
+    def fields(self):
+        r = np.empty((self.ny, self.nx))
+        vx = np.empty_like(r)
+        vy = np.empty_like(r)
+        lbm_fields(self._ctx, r, vx, vy)
+        return r, vx, vy
+
+    def wall(self):
+        a = [np.empty(self.nx) for _ in range(4)]
+        s = lbm_wall_stress(self._ctx, *a)
+        return dict(zip(["tau_bot", "tau_top", "p_bot", "p_top"], a)), s
+
+    def history(self, cap: int = 1 << 16) -> list:
+        return lbm_stress_history(self._ctx, cap)
+
+    def check(self) -> dict:
+        return lbm_check_state(self._ctx)
+
+    def get_f(self) -> np.ndarray:
+        f = np.empty((9, self.ny, self.nx))
+        lbm_get_f(self._ctx, f)
+        return f
+
+    def set_f(self, f: np.ndarray):
+        assert f.shape == (9, self.ny, self.nx)
+        lbm_set_f(self._ctx, f)

@@ -1,0 +1,65 @@
+"""Seeded synthetic workloads shaped like the paper's airway-reopening runs.
+
+The paper (Sec. 2.3, 3.1-3.3) runs a liquid plug spanning a 2-D channel with a
+liquid film on both walls, driven by a pressure drop; it publishes no dataset,
+so every input here is synthetic.  This module only holds the recipes (sizes,
+physical parameters, seeds) and the seeded draws that pick a parameter; it
+contains none of the method's arithmetic, and both the GPU library and the CPU
+oracle take its values as inputs.
+"""
+from __future__ import annotations
+
+import math
+
+_GAMMA = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, n: int) -> int:
+    """n-th output (0-based) of SplitMix64 seeded with `seed` (Steele, Lea & Flood 2014)."""
+    z = (seed + (n + 1) * _GAMMA) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def uniform(seed: int, n: int) -> float:
+    return (splitmix64(seed, n) >> 11) * 2.0**-53
+
+
+# Plug-in-channel workloads.  "noise" is the amplitude of the additive uniform
+# density noise of the initial condition; x_center NaN puts the rear interface at nx/4.
+PLUG_SMALL = dict(
+    name="plug-channel 256x64 FP64 (CS 0.85 Tc, tau 1.0, plug 40 at x=80, film 4, dp 1e-3, 2000 steps)",
+    nx=256, ny=64, tau=1.0, storage="f64", steps=2000,
+    params=dict(T_over_Tc=0.85, dp=1e-3),
+    plug=dict(plug_len=40, film=4, x_center=80.0, noise_amp=1e-3, seed=1),
+)
+
+
+def plug_large(storage: str = "f32") -> dict:
+    """4096x512 channel, CS at 0.80 Tc, tau 0.8, plug 300, film 16, dp drawn from seed 2 in [5e-4, 3e-3]."""
+    dp = 5e-4 + 2.5e-3 * uniform(2, 0)
+    return dict(
+        name=f"plug-channel 4096x512 {storage.upper()} (CS 0.80 Tc, tau 0.8, plug 300, film 16, dp {dp:.6g})",
+        nx=4096, ny=512, tau=0.8, storage=storage, steps=100_000,
+        params=dict(T_over_Tc=0.80, dp=dp),
+        plug=dict(plug_len=300, film=16, x_center=math.nan, noise_amp=1e-3, seed=2),
+    )
+
+
+def plug_large_stable(storage: str = "f32") -> dict:
+    """Same grid, plug and film as plug_large, at the 256x64 case's stable state point (0.85 Tc, tau 1.0)."""
+    w = plug_large(storage)
+    w["name"] = w["name"].replace("CS 0.80 Tc, tau 0.8", "CS 0.85 Tc, tau 1.0")
+    w["tau"] = 1.0
+    w["params"] = dict(w["params"], T_over_Tc=0.85)
+    return w
+
+
+def plug_out_of_cache(storage: str = "f32") -> dict:
+    """16384x2048 control whose distributions (2 x 1.2 GB in FP32) exceed the 256 MB Infinity Cache."""
+    w = plug_large_stable(storage)
+    w.update(nx=16384, ny=2048, name=w["name"].replace("4096x512", "16384x2048"))
+    w["plug"] = dict(w["plug"], plug_len=1200, film=64)
+    return w

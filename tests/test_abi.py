@@ -1,0 +1,116 @@
+"""Host-only checks of the C ABI library (no GPU needed, no kernel launched).
+
+The library loads, exports every entry point declared in include/lbm.h,
+validates parameters on the host, and its own (independent) EOS/Maxwell solver
+agrees with the oracle's.
+"""
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2103_08301_amd import lbm
+
+    if not os.path.exists(lbm.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    lbm.library()
+    return lbm
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "lbm.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:lbm_status|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = L.library()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTED) == names
+
+
+def test_struct_layouts_match_header(L, tmp_path):
+    """sizeof/offsetof of the three structs, as gcc computes them from lbm.h,
+    against the ctypes mirrors of the binding."""
+    import ctypes as C
+    import subprocess
+
+    structs = {"lbm_params": L.lbm_params, "lbm_stress_summary": L.lbm_stress_summary,
+               "lbm_check_result": L.lbm_check_result}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(out[name]) == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
+
+
+def test_defaults(L):
+    p = L.lbm_params_default()
+    assert (p.eos, p.a, p.b, p.R, p.T_over_Tc, p.k, p.kappa) == (0, 1.0, 4.0, 1.0, 0.85, 1.0, 0.001)
+    assert (p.s_e, p.s_eps, p.s_q) == (1.64, 1.54, 1.7)
+    assert math.isnan(p.rho_wall) and p.storage == L.LBM_F32 and p.check_every == 1000
+
+
+@pytest.mark.parametrize("bad", [
+    dict(T_over_Tc=0.0), dict(a=-1.0), dict(b=0.0), dict(k=0.0), dict(kappa=-1.0), dict(s_e=2.0),
+    dict(s_q=0.0), dict(check_every=0), dict(v_limit=0.0), dict(history_cap=0), dict(storage=7),
+    dict(eos=3), dict(x_periodic=2), dict(rho_wall=-1.0), dict(dp=math.inf),
+])
+def test_create_rejects_invalid_parameters(L, bad):
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_create(64, 32, 1.0, L.lbm_params_default(**bad))
+    assert e.value.status == L.LBM_EINVAL
+
+
+@pytest.mark.parametrize("nx,ny,tau", [(3, 32, 1.0), (64, 3, 1.0), (64, 32, 0.5), (64, 32, 0.2)])
+def test_create_rejects_invalid_grid(L, nx, ny, tau):
+    with pytest.raises(L.LbmError):
+        L.lbm_create(nx, ny, tau, L.lbm_params_default())
+
+
+def test_calls_before_bind_are_rejected(L):
+    ctx = L.lbm_create(64, 32, 1.0, L.lbm_params_default())
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_init_plug(ctx, 10, 2)
+    assert e.value.status == L.LBM_ESTATE
+    assert L.library().lbm_step(ctx, 1) == L.LBM_ESTATE
+    assert L.lbm_workspace(ctx) > 2 * 9 * 64 * 32 * 4
+    L.lbm_destroy(ctx)
+
+
+@pytest.mark.parametrize("kw,trs", [
+    ({}, [0.95, 0.85, 0.8, 0.7, 0.5]),
+    (dict(eos=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344), [0.9, 0.7, 0.6, 0.5]),
+    (dict(eos=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.011), [0.8, 0.6]),
+])
+def test_library_coexistence_agrees_with_oracle(L, orc, kw, trs):
+    """Two independent solvers: the oracle bisects the equal-area integral
+    (Gauss-Legendre), the library bisects the chemical-potential difference
+    (Romberg) with hyper-dual derivatives."""
+    for tr in trs:
+        a = L.lbm_state(L.lbm_create(32, 16, 1.0, L.lbm_params_default(T_over_Tc=tr, **kw)))
+        b = orc.Sim(32, 16, orc.params(T_over_Tc=tr, **kw)).state()
+        for k in ("Tc", "T", "rho_g", "rho_l", "rho_w"):
+            assert a[k] == pytest.approx(b[k], rel=1e-11), (tr, k)
