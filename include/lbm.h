@@ -86,6 +86,10 @@ typedef struct {
     int check_every;     /* stability/interface check cadence in steps (>= 1) */
     double v_limit;      /* a check fails when |v| exceeds this or a NaN appears */
     int history_cap;     /* capacity (steps) of the device ring of per-step wall summaries (>= 1) */
+    int tile_rows;       /* output rows per tile (schedule 0: 0, 12 or 28) or per wave chunk
+                            (schedule 1: 0 or 4..256); 0 selects the default (12 / 16) */
+    int schedule;        /* 0: one block per 60 x tile_rows tile, phases coupled through LDS;
+                            1: one wavefront per 60-column strip marching up a row chunk */
 } lbm_params;
 
 /* Per-step wall summary ([0] bottom wall, [1] top wall).  FP64. */
@@ -115,13 +119,14 @@ typedef struct {
 
 /* Defaults: Carnahan-Starling a=1, b=4, R=1 at 0.85 Tc, k=1, kappa=0.001, paper MRT
    rates, rho_wall=rho_l, dp=0, extrapolated ends, walls, FP32 storage, check every
-   1000 steps, v_limit 0.5, history of 4096 steps. */
+   1000 steps, v_limit 0.5, history of 4096 steps, automatic tiling. */
 void lbm_params_default(lbm_params* p);
 
 /* Validates the parameters, solves the EOS critical point and the Maxwell
    coexistence densities on the host (paper Sec. 2.2, "Verification") and
-   returns a new context.  No device work.  tau > 1/2; 4 <= nx, ny;
-   (pitch of nx) * ny < 2^31.  T_over_Tc >= 1 is allowed (single phase) but
+   returns a new context.  No device work.  tau > 1/2; 4 <= nx, ny; one copy
+   of the distributions (9 * ny * nx rounded up to 64 columns, in the storage
+   type) must stay below 4 GiB.  T_over_Tc >= 1 is allowed (single phase) but
    then lbm_init_plug is rejected. */
 lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx** out);
 

@@ -209,6 +209,8 @@ size_t storage_bytes(int storage) {
 }
 
 constexpr int kRingCap = 256;  // per-step partial slots before a wall reduction is forced
+constexpr int kDefaultMarchRows = 16;
+constexpr int kDefaultTileOut = 12;
 
 }  // namespace
 
@@ -220,10 +222,10 @@ struct lbm_ctx {
     double rho_c = 0, rho_g = NAN, rho_l = NAN, rho_w = 0, rho0 = 0;
     int pitch = 0;
     long long plane = 0;
-    int nstrip = 0, nchunk = 0, ty = 0;
+    int nstrip = 0, nchunk = 0, ty = 0, schedule = 0;
     // workspace layout (byte offsets)
     size_t off_f[2]{}, off_rho = 0, off_vx = 0, off_vy = 0, off_tau = 0, off_pw = 0, off_ring = 0, off_hist = 0,
-           off_acc = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, total = 0;
+           off_acc = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, total = 0;
     char* dev = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -292,9 +294,9 @@ lbm_status init_from_device_rho(lbm_ctx* c) {
 lbm_status flush_wall(lbm_ctx* c) {
     if (c->ring_fill == 0) return LBM_OK;
     if (!c->p.y_periodic) {
-        HIP_TRY(c, lbm::launch_wall_reduce(c->at<double>(c->off_ring), 0, kRingCap, c->ring_fill, c->nstrip,
-                                           c->ring_first_step, c->at<lbm_stress_summary>(c->off_hist),
-                                           c->p.history_cap, c->at<double>(c->off_acc), c->stream));
+        HIP_TRY(c, lbm::launch_wall_reduce(c->at<double>(c->off_ring), c->ring_fill, c->nstrip, c->ring_first_step,
+                                           c->at<lbm_stress_summary>(c->off_hist), c->p.history_cap,
+                                           c->at<double>(c->off_wscr), c->at<double>(c->off_acc), c->stream));
     }
     c->ring_first_step += c->ring_fill;
     c->ring_fill = 0;
@@ -364,6 +366,7 @@ lbm::StepArgs make_args(const lbm_ctx* c) {
     a.nstrip = c->nstrip;
     a.nchunk = c->nchunk;
     a.ty = c->ty;
+    a.schedule = c->schedule;
     a.xper = c->p.x_periodic;
     a.yper = c->p.y_periodic;
     a.tau = c->tau;
@@ -417,6 +420,8 @@ void lbm_params_default(lbm_params* p) {
     p->check_every = 1000;
     p->v_limit = 0.5;
     p->history_cap = 4096;
+    p->tile_rows = 0;
+    p->schedule = 0;
 }
 
 lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx** out) {
@@ -430,10 +435,13 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
         !(p->v_limit > 0) || p->history_cap < 1 || (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) ||
         p->storage < LBM_F64 || p->storage > LBM_F32S || (p->x_periodic != 0 && p->x_periodic != 1) ||
         (p->y_periodic != 0 && p->y_periodic != 1) || !std::isfinite(p->omega) ||
-        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)))
+        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || (p->schedule != 0 && p->schedule != 1) ||
+        (p->schedule == 0 && p->tile_rows != 0 && p->tile_rows != 12 && p->tile_rows != 28) ||
+        (p->schedule == 1 && p->tile_rows != 0 && (p->tile_rows < 4 || p->tile_rows > 256)))
         return LBM_EINVAL;
     const int pitch = (nx + 63) / 64 * 64;
-    if ((long long)pitch * ny > 0x7fffffffLL) return LBM_EINVAL;
+    // the step kernel addresses a distribution buffer with 32-bit byte offsets
+    if ((unsigned long long)pitch * ny * 9 * storage_bytes(p->storage) >= (1ULL << 32)) return LBM_EINVAL;
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return LBM_ENOMEM;
     c->nx = nx;
@@ -456,7 +464,8 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->pitch = pitch;
     c->plane = (long long)pitch * ny;
     c->nstrip = (nx + lbm::kStripOut - 1) / lbm::kStripOut;
-    c->ty = 16;
+    c->schedule = p->schedule;
+    c->ty = p->tile_rows > 0 ? p->tile_rows : (p->schedule == lbm::kScheduleTile ? kDefaultTileOut : kDefaultMarchRows);
     c->nchunk = std::max(1, ny / c->ty);
     // workspace layout
     size_t o = 0;
@@ -472,6 +481,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->off_ring = o; o += align256((size_t)kRingCap * 2 * c->nstrip * lbm::kPartialVals * sizeof(double));
     c->off_hist = o; o += align256((size_t)p->history_cap * sizeof(lbm_stress_summary));
     c->off_acc = o; o += 256;
+    c->off_wscr = o; o += align256((size_t)kRingCap * 2 * sizeof(double));
     c->off_red = o; o += align256((size_t)lbm::kFieldReduceBlocks * 5 * sizeof(double));
     c->off_redout = o; o += 256;
     c->off_colmin = o; o += align256((size_t)nx * sizeof(double));

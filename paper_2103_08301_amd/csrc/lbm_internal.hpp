@@ -16,7 +16,9 @@ namespace lbm {
 // force stencil grad(lap rho) needs.
 constexpr int kStripOut = 60;
 constexpr int kWavesPerBlock = 4;
-constexpr int kPartialVals = 9;   // tmax, xtmax, tmin, xtmin, pmax, xpmax, pmin, xpmin, sum tau^2
+constexpr int kPartialVals = 9;
+constexpr int kScheduleTile = 0;   // block-per-tile kernel with LDS-coupled phases
+constexpr int kScheduleMarch = 1;  // wave-per-strip row march with a register window   // tmax, xtmax, tmin, xtmin, pmax, xpmax, pmin, xpmin, sum tau^2
 
 // Everything one launch of the step kernel needs, passed by value.
 struct StepArgs {
@@ -24,7 +26,8 @@ struct StepArgs {
     void* fout;               // new post-collision distributions
     int nx, ny, pitch;        // pitch: elements per row of a distribution plane
     long long plane;          // elements per plane (pitch * ny)
-    int nstrip, nchunk, ty;   // x strips, y chunks, nominal rows per chunk
+    int nstrip, nchunk, ty;   // x strips, y chunks, output rows per chunk/tile
+    int schedule;             // kScheduleTile or kScheduleMarch
     int xper, yper;
     double tau, s_e, s_eps, s_q, s_j, s_v;
     double k2, kappa, g, nu;
@@ -50,11 +53,11 @@ hipError_t launch_field_reduce(const double* rho, const double* vx, const double
 // Per column: minimum density over y and the centreline density.
 hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin, double* centre,
                               hipStream_t s);
-// Reduces `nsteps` consecutive slots of the per-strip partial ring into the
-// history ring and the running time integrals acc[2].
-hipError_t launch_wall_reduce(const double* partial_ring, int ring_first, int ring_cap, int nsteps,
-                              int nstrip, int64_t first_step, lbm_stress_summary* hist,
-                              int hist_cap, double* acc, hipStream_t s);
+// Reduces the first `nsteps` slots of the per-strip partial ring (one wave per
+// step) into the history ring, then accumulates the running time integrals
+// acc[2] in step order.  scratch holds 2 doubles per step.
+hipError_t launch_wall_reduce(const double* partial_ring, int nsteps, int nstrip, int64_t first_step,
+                              lbm_stress_summary* hist, int hist_cap, double* scratch, double* acc, hipStream_t s);
 
 constexpr int kFieldReduceBlocks = 512;
 

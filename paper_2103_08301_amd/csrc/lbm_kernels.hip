@@ -125,10 +125,29 @@ __device__ inline float recip(float x) {
 }
 __device__ inline double recip(double x) { return 1.0 / x; }
 
+// x-neighbours across the 64 lanes of a wave with DPP wave shifts (a VALU
+// operand modifier, no LDS traffic): wave_shl:1 reads lane + 1 (column x + 1),
+// wave_shr:1 reads lane - 1 (column x - 1).  The edge lanes keep their own value;
+// they belong to the halo and their neighbours are never used.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+    const int i = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = int(b & 0xffffffffLL), hi = int(b >> 32);
+    const int nlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const int nhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)nhi << 32) | (unsigned)nlo));
+}
 template <class C>
-__device__ inline C shfl_next(C v) { return __shfl_down(v, 1, 64); }  // value of lane + 1 (column x + 1)
+__device__ inline C shfl_next(C v) { return dpp_move<kDppWaveShl1>(v); }
 template <class C>
-__device__ inline C shfl_prev(C v) { return __shfl_up(v, 1, 64); }    // value of lane - 1 (column x - 1)
+__device__ inline C shfl_prev(C v) { return dpp_move<kDppWaveShr1>(v); }
 
 // phi = k^2 p0(rho) - rho/3: the nonideal part of the pressure in mesh units (eq. 2.17).
 template <int EOS, class C>
@@ -231,12 +250,24 @@ __device__ inline void pull_generic(const typename CD::S* __restrict__ fin, cons
 #undef LBM_PULL
 }
 
-// Interior fast path: every source is in range, no boundary logic.
+// Byte offset within a distribution buffer: 32-bit (the library keeps every
+// buffer below 4 GiB), so loads and stores use a uniform 64-bit base in SGPRs
+// plus one 32-bit lane offset (global_load v, v_off, s[base]).
+template <class S>
+__device__ inline const S* at_bytes(const S* base, uint32_t off) {
+    return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + (uint64_t)off);
+}
+template <class S>
+__device__ inline S* at_bytes(S* base, uint32_t off) {
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (uint64_t)off);
+}
+
+// Interior fast path: every source is in range, no boundary logic.  dir_off[I]
+// is the uniform byte offset of population I's source relative to the node.
 template <class CD>
-__device__ inline void pull_interior(const typename CD::S* __restrict__ fin, const StepArgs& a, int xe, int yr,
+__device__ inline void pull_interior(const typename CD::S* __restrict__ fin, const uint32_t (&dir_off)[9], uint32_t node_off,
                                      typename CD::C rho0, typename CD::C (&f)[9]) {
-    const long long base = (long long)yr * a.pitch + xe;
-#define LBM_PULLI(I) f[I] = CD::template load<I>(fin + (long long)(I) * a.plane + base - (long long)ey(I) * a.pitch - ex(I), rho0);
+#define LBM_PULLI(I) f[I] = CD::template load<I>(at_bytes(fin, node_off + dir_off[I]), rho0);
     LBM_PULLI(0) LBM_PULLI(1) LBM_PULLI(2) LBM_PULLI(3) LBM_PULLI(4) LBM_PULLI(5) LBM_PULLI(6) LBM_PULLI(7) LBM_PULLI(8)
 #undef LBM_PULLI
 }
@@ -287,86 +318,94 @@ __device__ inline void collide(C (&f)[9], C rho, C jx, C jy, C Fx, C Fy, C inv_r
     f[8] -= c1 + Xd - Yd - dxy;
 }
 
-template <class CD, int EOS, bool EMIT>
-__global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
+// Loads (or, for rows beyond a wall, zeroes) the nine pulled populations of row r.
+template <class CD>
+__device__ inline void issue_row(const typename CD::S* __restrict__ fin, const StepArgs& a, int xe, bool strip_inner,
+                                 const uint32_t (&dir_off)[9], int r, typename CD::C rho0, typename CD::C (&f)[9]) {
+    using S = typename CD::S;
+    if (a.yper || (r >= 0 && r < a.ny)) {
+        const int yr = a.yper ? wrapi(r, a.ny) : r;
+        if (strip_inner && yr >= 1 && yr <= a.ny - 2)
+            pull_interior<CD>(fin, dir_off, uint32_t(yr * a.pitch + xe) * uint32_t(sizeof(S)), rho0, f);
+        else
+            pull_generic<CD>(fin, a, xe, yr, rho0, f);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = 0;
+    }
+}
+
+// Per-wave register window of the row march.  Suffix 1 is row r-1, suffix 2
+// row r-2 (the row being collided); lap3r is the Laplacian of row r-3.
+template <class C>
+struct Window {
+    Row3<C> rho1, rho2, phi1, phi2, lap2, lap3r;
+    C gphx, gphy, grx, gry;   // grad phi and grad rho of row r-2
+    C f1[9], f2[9];           // pulled populations of rows r-1 and r-2
+    C fn[9];                  // prefetched populations of row r
+    C wall_rho, wall_vx, wall_p;
+};
+
+template <class CD, int EOS>
+struct Stepper {
     using S = typename CD::S;
     using C = typename CD::C;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int nbx = (a.nstrip + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int chunk = bid / nbx;
-    const int strip = (bid - chunk * nbx) * kWavesPerBlock + wave;
-    if (strip >= a.nstrip) return;  // whole wave
+    const StepArgs& a;
+    const S* __restrict__ fin;
+    S* __restrict__ fout;
+    int lane, strip, x, xe;
+    bool out_lane, strip_inner;
+    C rho0, RT, a_eff, bb, k2, kappa, g, tau, s_e, s_eps, s_q, s_j, s_v, rho_w, nu;
+    uint32_t dir_off[9];  // byte offset of population i's pull source: i*plane - e_i (in elements) times sizeof(S)
+    uint32_t plane_bytes;
 
-    const S* __restrict__ fin = static_cast<const S*>(a.fin);
-    S* __restrict__ fout = static_cast<S*>(a.fout);
-    const int x0 = strip * kStripOut;
-    const int x = x0 - 2 + lane;
-    const bool out_lane = lane >= 2 && lane < 62 && x < a.nx;
-    int xe = x;
-    if (xe < 0 || xe >= a.nx) xe = a.xper ? wrapi(xe, a.nx) : clampi(xe, 0, a.nx - 1);
-    const bool strip_inner = (x0 - 3 >= 0) && (x0 + 62 <= a.nx - 1);
-    const int y0 = chunk * a.ty;
-    const int y1 = (chunk == a.nchunk - 1) ? a.ny : y0 + a.ty;
-    const bool walls = !a.yper;
+    __device__ void prefetch(Window<C>& W, int r) const { issue_row<CD>(fin, a, xe, strip_inner, dir_off, r, rho0, W.fn); }
 
-    const C rho0 = C(a.rho0);
-    const C RT = C(a.RT), a_eff = C(a.a_eff), bb = C(a.b), k2 = C(a.k2), kappa = C(a.kappa), g = C(a.g);
-    const C tau = C(a.tau), s_e = C(a.s_e), s_eps = C(a.s_eps), s_q = C(a.s_q), s_j = C(a.s_j), s_v = C(a.s_v);
-    const C rho_w = C(a.rho_w);
-
-    // register window: rows r-1 (suffix 1) and r-2 (suffix 2), Laplacian rows r-2 and r-3
-    Row3<C> rho1{0, 0, 0}, rho2{0, 0, 0}, phi1{0, 0, 0}, phi2{0, 0, 0}, lap2{0, 0, 0}, lap3r{0, 0, 0};
-    C gphx = 0, gphy = 0, grx = 0, gry = 0;  // gradients of phi and rho at row r-2
-    C f1[9], f2[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) { f1[i] = 0; f2[i] = 0; }
-    C wall_rho = 0, wall_vx = 0, wall_p = 0;  // bottom-wall row 0 values kept for row 1; top: vx of ny-2
-
-    for (int r = y0 - 2; r < y1 + 2; ++r) {
-        // ---- row r: pull, density, EOS field --------------------------------
+    // One row of the march: takes the prefetched populations of row r, issues
+    // the loads of row r+1, forms rho/phi of row r and lap/grad of row r-1, and
+    // (COLLIDE) updates row r-2.  WALL adds the wall-row logic; EMIT writes fields.
+    // FAST: row r is a fluid row and row r+1 is an interior row of an interior
+    // strip, so the prefetch is nine straight loads with no boundary logic.
+    template <bool COLLIDE, bool WALL, bool EMIT, bool FAST>
+    __device__ __forceinline__ void row(Window<C>& W, int r, bool prefetch_next) const {
         C f0[9];
-        C rho;
-        const bool fluid_row = a.yper || (r >= 0 && r < a.ny);
-        if (fluid_row) {
-            const int yr = a.yper ? wrapi(r, a.ny) : r;
-            if (strip_inner && yr >= 1 && yr <= a.ny - 2)
-                pull_interior<CD>(fin, a, xe, yr, rho0, f0);
-            else
-                pull_generic<CD>(fin, a, xe, yr, rho0, f0);
-            rho = ((f0[0] + f0[1]) + (f0[2] + f0[3])) + ((f0[4] + f0[5]) + (f0[6] + f0[7])) + f0[8];
-        } else {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) f0[i] = 0;
-            rho = rho_w;
-        }
+        for (int i = 0; i < 9; ++i) f0[i] = W.fn[i];
+        if (FAST)
+            pull_interior<CD>(fin, dir_off, uint32_t((r + 1) * a.pitch + xe) * uint32_t(sizeof(S)), rho0, W.fn);
+        else if (prefetch_next)
+            prefetch(W, r + 1);
+        // Keep the loads of row r+1 ahead of this row's arithmetic and stores: on
+        // gfx9 the vector-memory counter covers loads and stores in issue order, so
+        // a load sunk below the stores would make its wait drain those stores too.
+        __builtin_amdgcn_sched_barrier(0);
+        const bool fluid_row = FAST || a.yper || (r >= 0 && r < a.ny);
+        const C rho = fluid_row ? ((f0[0] + f0[1]) + (f0[2] + f0[3])) + ((f0[4] + f0[5]) + (f0[6] + f0[7])) + f0[8]
+                                : rho_w;
         const Row3<C> rho0r = with_neighbours(rho);
         const Row3<C> phi0 = with_neighbours(phi_of<EOS, C>(rho, RT, a_eff, bb, k2));
-
-        // ---- row r-1: Laplacian, grad phi (and grad rho on wall rows) -------
-        const Row3<C> lap1 = with_neighbours(lap3(rho2, rho1, rho0r));
+        const Row3<C> lap1 = with_neighbours(lap3(W.rho2, W.rho1, rho0r));
         C gphx1, gphy1;
-        grad3(phi2, phi1, phi0, gphx1, gphy1);
+        grad3(W.phi2, W.phi1, phi0, gphx1, gphy1);
         C grx1 = 0, gry1 = 0;
-        if (walls && (r - 1 == 0 || r - 1 == a.ny - 1)) grad3(rho2, rho1, rho0r, grx1, gry1);
+        if (WALL && !a.yper && (r - 1 == 0 || r - 1 == a.ny - 1)) grad3(W.rho2, W.rho1, rho0r, grx1, gry1);
 
-        // ---- row r-2: force, collision, store, wall diagnostics -------------
-        const int y = r - 2;
-        if (y >= y0) {
+        if (COLLIDE) {
+            const int y = r - 2;
             C glx, gly;
-            grad3(lap3r, lap2, lap1, glx, gly);
-            const C rh = rho2.c;
-            const C Fx = -gphx + kappa * rh * glx + g;
-            const C Fy = -gphy + kappa * rh * gly;
+            grad3(W.lap3r, W.lap2, lap1, glx, gly);
+            const C rh = W.rho2.c;
+            const C Fx = -W.gphx + kappa * rh * glx + g;
+            const C Fy = -W.gphy + kappa * rh * gly;
+            C* f2 = W.f2;
             const C jx = (f2[1] - f2[3]) + (f2[5] - f2[6]) + (f2[8] - f2[7]);
             const C jy = (f2[2] - f2[4]) + (f2[5] - f2[8]) + (f2[6] - f2[7]);
             const C inv_rho = recip(rh);
             C vx, vy;
-            collide<C>(f2, rh, jx, jy, Fx, Fy, inv_rho, a, tau, s_e, s_eps, s_q, s_j, s_v, vx, vy);
+            collide<C>(W.f2, rh, jx, jy, Fx, Fy, inv_rho, a, tau, s_e, s_eps, s_q, s_j, s_v, vx, vy);
             if (out_lane) {
-                const long long o = (long long)y * a.pitch + x;
-#define LBM_STORE(I) CD::template store<I>(fout + (long long)(I) * a.plane + o, f2[I], rho0);
+                const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
+#define LBM_STORE(I) CD::template store<I>(at_bytes(fout, o + uint32_t(I) * plane_bytes), W.f2[I], rho0);
                 LBM_STORE(0) LBM_STORE(1) LBM_STORE(2) LBM_STORE(3) LBM_STORE(4) LBM_STORE(5) LBM_STORE(6)
                 LBM_STORE(7) LBM_STORE(8)
 #undef LBM_STORE
@@ -377,59 +416,308 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
                     a.vy_out[c] = double(vy);
                 }
             }
-            if (walls) {
-                // wall pressure: isotropic part of eq. 2.8 on the first fluid row
-                const bool bottom_p = (y == 0), top_p = (y == a.ny - 1);
-                if (bottom_p || top_p) {
-                    wall_p = k2 * p0_of<EOS, C>(rh, RT, a_eff, bb) - kappa * rh * lap2.c
-                           - C(0.5) * kappa * (grx * grx + gry * gry);
-                }
-                if (bottom_p) { wall_rho = rh; wall_vx = vx; }
-                if (y == a.ny - 2 && !(bottom_p)) wall_vx = vx;
-                const bool bottom_t = (y == 1), top_t = (y == a.ny - 1);
-                if (bottom_t || top_t) {
-                    // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
-                    C tw, pw;
-                    if (bottom_t) {
-                        tw = wall_rho * C(a.nu) * (C(9) * wall_vx - vx) * C(1.0 / 3.0);
-                        pw = wall_p;
-                    } else {
-                        tw = rh * C(a.nu) * (C(9) * vx - wall_vx) * C(1.0 / 3.0);
-                        pw = wall_p;
-                    }
-                    const int w = bottom_t ? 0 : 1;
-                    if (bottom_t && top_t) { /* ny == 2 never happens: ny >= 4 */ }
-                    double dt = out_lane ? double(tw) : 0.0, dp = out_lane ? double(pw) : 0.0;
-                    if (out_lane) {
-                        a.tau_w[w * a.nx + x] = dt;
-                        a.p_w[w * a.nx + x] = dp;
-                    }
-                    double tmax = out_lane ? dt : -INFINITY, tmin = out_lane ? dt : INFINITY;
-                    double pmax = out_lane ? dp : -INFINITY, pmin = out_lane ? dp : INFINITY;
-                    int xtmax = out_lane ? x : 0x7fffffff, xtmin = xtmax, xpmax = xtmax, xpmin = xtmax;
-                    wave_argmax(tmax, xtmax);
-                    wave_argmin(tmin, xtmin);
-                    wave_argmax(pmax, xpmax);
-                    wave_argmin(pmin, xpmin);
-                    const double s2 = wave_sum(dt * dt);
-                    if (lane == 0) {
-                        double* o = a.partial + ((long long)w * a.nstrip + strip) * kPartialVals;
-                        o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
-                        o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
-                        o[8] = s2;
-                    }
-                }
+            if (WALL) wall_row(W, y, rh, vx);
+        }
+        // rotate the window
+        W.rho2 = W.rho1; W.rho1 = rho0r;
+        W.phi2 = W.phi1; W.phi1 = phi0;
+        W.lap3r = W.lap2; W.lap2 = lap1;
+        W.gphx = gphx1; W.gphy = gphy1;
+        W.grx = grx1; W.gry = gry1;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) { W.f2[i] = W.f1[i]; W.f1[i] = f0[i]; }
+    }
+
+    // Wall shear and wall pressure on the first two fluid rows of each wall,
+    // with the per-strip FP64 extremes of this step.
+    __device__ void wall_row(Window<C>& W, int y, C rh, C vx) const {
+        if (a.yper) return;
+        const bool bottom_p = (y == 0), top_p = (y == a.ny - 1);
+        if (bottom_p || top_p) {
+            // isotropic part of eq. 2.8 on the first fluid row
+            W.wall_p = k2 * p0_of<EOS, C>(rh, RT, a_eff, bb) - kappa * rh * W.lap2.c
+                     - C(0.5) * kappa * (W.grx * W.grx + W.gry * W.gry);
+        }
+        if (bottom_p) { W.wall_rho = rh; W.wall_vx = vx; }
+        if (y == a.ny - 2) W.wall_vx = vx;
+        const bool bottom_t = (y == 1), top_t = (y == a.ny - 1);
+        if (!(bottom_t || top_t)) return;
+        // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
+        const C tw = bottom_t ? W.wall_rho * nu * (C(9) * W.wall_vx - vx) * C(1.0 / 3.0)
+                              : rh * nu * (C(9) * vx - W.wall_vx) * C(1.0 / 3.0);
+        const int w = bottom_t ? 0 : 1;
+        const double dt = out_lane ? double(tw) : 0.0, dpw = out_lane ? double(W.wall_p) : 0.0;
+        if (out_lane) {
+            a.tau_w[w * a.nx + x] = dt;
+            a.p_w[w * a.nx + x] = dpw;
+        }
+        double tmax = out_lane ? dt : -INFINITY, tmin = out_lane ? dt : INFINITY;
+        double pmax = out_lane ? dpw : -INFINITY, pmin = out_lane ? dpw : INFINITY;
+        int xtmax = out_lane ? x : 0x7fffffff, xtmin = xtmax, xpmax = xtmax, xpmin = xtmax;
+        wave_argmax(tmax, xtmax);
+        wave_argmin(tmin, xtmin);
+        wave_argmax(pmax, xpmax);
+        wave_argmin(pmin, xpmin);
+        const double s2 = wave_sum(dt * dt);
+        if (lane == 0) {
+            double* o = a.partial + ((long long)w * a.nstrip + strip) * kPartialVals;
+            o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
+            o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
+            o[8] = s2;
+        }
+    }
+};
+
+template <class CD, int EOS, bool EMIT>
+__global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
+    using C = typename CD::C;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int nbx = (a.nstrip + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int chunk = bid / nbx;
+    const int strip = (bid - chunk * nbx) * kWavesPerBlock + wave;
+    if (strip >= a.nstrip) return;  // whole wave
+
+    Stepper<CD, EOS> st{a, static_cast<const typename CD::S*>(a.fin), static_cast<typename CD::S*>(a.fout)};
+    st.lane = lane;
+    st.strip = strip;
+    const int x0 = strip * kStripOut;
+    st.x = x0 - 2 + lane;
+    st.out_lane = lane >= 2 && lane < 62 && st.x < a.nx;
+    st.xe = st.x;
+    if (st.xe < 0 || st.xe >= a.nx) st.xe = a.xper ? wrapi(st.xe, a.nx) : clampi(st.xe, 0, a.nx - 1);
+    st.strip_inner = (x0 - 3 >= 0) && (x0 + 62 <= a.nx - 1);
+    st.plane_bytes = uint32_t(a.plane) * uint32_t(sizeof(typename CD::S));
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        st.dir_off[i] = uint32_t(i) * st.plane_bytes - uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(typename CD::S));
+    st.rho0 = C(a.rho0); st.RT = C(a.RT); st.a_eff = C(a.a_eff); st.bb = C(a.b); st.k2 = C(a.k2);
+    st.kappa = C(a.kappa); st.g = C(a.g); st.tau = C(a.tau); st.s_e = C(a.s_e); st.s_eps = C(a.s_eps);
+    st.s_q = C(a.s_q); st.s_j = C(a.s_j); st.s_v = C(a.s_v); st.rho_w = C(a.rho_w); st.nu = C(a.nu);
+
+    const int y0 = chunk * a.ty;
+    const bool last = chunk == a.nchunk - 1;
+    const int y1 = last ? a.ny : y0 + a.ty;
+    const bool walls = !a.yper;
+    // collided rows: [y0, y1).  The two wall-adjacent rows of the bottom (chunk 0)
+    // and top (last chunk) go through the wall variant; the rest through the plain one.
+    const int ya = (walls && chunk == 0) ? y0 + 2 : y0;
+    const int yb = (walls && last) ? y1 - 2 : y1;
+
+    Window<C> W;
+    W.rho1 = W.rho2 = W.phi1 = W.phi2 = W.lap2 = W.lap3r = Row3<C>{0, 0, 0};
+    W.gphx = W.gphy = W.grx = W.gry = 0;
+    W.wall_rho = W.wall_vx = W.wall_p = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { W.f1[i] = 0; W.f2[i] = 0; }
+
+    const int rend = y1 + 2;  // rows y0-2 .. y1+1 are pulled
+    st.prefetch(W, y0 - 2);
+    // warm-up: rows y0-2 .. y0+1 only build the window (wall variant: grad rho of row 0)
+    for (int r = y0 - 2; r < y0 + 2; ++r) st.template row<false, true, EMIT, false>(W, r, true);
+    int r = y0 + 2;
+    for (; r < ya + 2; ++r) st.template row<true, true, EMIT, false>(W, r, true);  // bottom wall rows
+    if (st.strip_inner) {
+        // interior rows whose prefetched row r+1 lies in 1 .. ny-2 (never true for y-periodic
+        // wrap rows, which keep the generic path), three per trip: the window rotates with
+        // period 3, so the rotation is register renaming in straight-line code
+        const int rfast = a.yper ? r : (yb + 2 < a.ny - 2 ? yb + 2 : a.ny - 2);
+        for (; r + 2 < rfast; r += 3) {
+            st.template row<true, false, EMIT, true>(W, r, true);
+            st.template row<true, false, EMIT, true>(W, r + 1, true);
+            st.template row<true, false, EMIT, true>(W, r + 2, true);
+        }
+        for (; r < rfast; ++r) st.template row<true, false, EMIT, true>(W, r, true);
+    }
+    for (; r < yb + 2; ++r) st.template row<true, false, EMIT, false>(W, r, true);    // remaining interior rows
+    for (; r < rend; ++r) st.template row<true, true, EMIT, false>(W, r, r + 1 < rend);  // top wall rows
+}
+
+// ---------------------------------------------------------------------------
+// Tile schedule.  A block of 4 waves owns a 64-column x (TYO + 4)-row tile: the
+// 60 output columns of a strip and TYO output rows, plus the radius-2 halo.
+// Phase A: every thread pulls its rows (rows wave, wave + 4, ...: all loads of
+//          a thread are independent and in flight together), forms rho and
+//          phi and puts them in LDS; populations of output rows stay in registers.
+// Phase B: Laplacian of rho on rows 1 .. H-2 of the tile, into LDS.
+// Phase C: grad phi, grad lap, force, velocity shift, MRT collision, store.
+// Phase D: (tiles holding a wall row) wall shear/pressure and per-strip extremes.
+// Tiles are TYO rows apart; the last one is moved down to end at row ny - 1, so
+// every tile has TYO output rows and the two rows next to a wall share a tile
+// (rows covered by two tiles are computed identically by both).
+template <class CD, int EOS, bool EMIT, int TYO>
+__global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
+    using S = typename CD::S;
+    using C = typename CD::C;
+    constexpr int H = TYO + 4;   // tile rows including the halo
+    constexpr int RPT = H / 4;   // rows per thread
+    static_assert(H % 4 == 0, "tile height");
+    __shared__ C sRho[H][64], sPhi[H][64], sLap[H][64];
+    __shared__ C sWv[4][64], sWr[2][64], sWp[2][64];  // wall rows: vx (0, 1, ny-2, ny-1), rho and p_w (0, ny-1)
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int ntile = (a.ny + TYO - 1) / TYO;
+    const int strip = bid / ntile;
+    const int tile = bid - strip * ntile;
+    const int y0 = (a.ny >= TYO) ? min(tile * TYO, a.ny - TYO) : 0;
+    const int x0 = strip * kStripOut;
+    const int x = x0 - 2 + lane;
+    const bool out_lane = lane >= 2 && lane < 62 && x < a.nx;
+    int xe = x;
+    if (xe < 0 || xe >= a.nx) xe = a.xper ? wrapi(xe, a.nx) : clampi(xe, 0, a.nx - 1);
+    const bool strip_inner = (x0 - 3 >= 0) && (x0 + 62 <= a.nx - 1);
+    const bool tile_inner = strip_inner && (y0 - 2 >= 1) && (y0 + H - 3 <= a.ny - 2);
+    const bool walls = !a.yper;
+
+    const S* __restrict__ fin = static_cast<const S*>(a.fin);
+    S* __restrict__ fout = static_cast<S*>(a.fout);
+    const uint32_t plane_bytes = uint32_t(a.plane) * uint32_t(sizeof(S));
+    uint32_t dir_off[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dir_off[i] = uint32_t(i) * plane_bytes - uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(S));
+    const C rho0 = C(a.rho0);
+    const C RT = C(a.RT), a_eff = C(a.a_eff), bb = C(a.b), k2 = C(a.k2), kappa = C(a.kappa), g = C(a.g);
+    const C rho_w = C(a.rho_w);
+
+    // ---- phase A: pull, density, EOS field -------------------------------------
+    C f[RPT][9];
+    if (tile_inner) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int r = y0 - 2 + wave + 4 * j;
+            pull_interior<CD>(fin, dir_off, uint32_t(r * a.pitch + xe) * uint32_t(sizeof(S)), rho0, f[j]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int r = y0 - 2 + wave + 4 * j;
+            if (a.yper || (r >= 0 && r < a.ny))
+                pull_generic<CD>(fin, a, xe, a.yper ? wrapi(r, a.ny) : r, rho0, f[j]);
+            else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[j][i] = 0;
             }
         }
-
-        // ---- rotate the register window -------------------------------------
-        rho2 = rho1; rho1 = rho0r;
-        phi2 = phi1; phi1 = phi0;
-        lap3r = lap2; lap2 = lap1;
-        gphx = gphx1; gphy = gphy1;
-        grx = grx1; gry = gry1;
+    }
 #pragma unroll
-        for (int i = 0; i < 9; ++i) { f2[i] = f1[i]; f1[i] = f0[i]; }
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + 4 * j;
+        const int r = y0 - 2 + k;
+        const bool fluid = tile_inner || a.yper || (r >= 0 && r < a.ny);
+        const C rho = fluid ? ((f[j][0] + f[j][1]) + (f[j][2] + f[j][3])) + ((f[j][4] + f[j][5]) + (f[j][6] + f[j][7])) + f[j][8]
+                            : rho_w;
+        sRho[k][lane] = rho;
+        sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+    }
+    __syncthreads();
+
+    const int lm = lane > 0 ? lane - 1 : 0, lp = lane < 63 ? lane + 1 : 63;  // edge lanes are halo: clamped, unused
+    // ---- phase B: Laplacian on rows 1 .. H-2 ------------------------------------
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + 4 * j;
+        if (k >= 1 && k <= H - 2) {
+            const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
+            const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
+            const Row3<C> n{sRho[k + 1][lane], sRho[k + 1][lp], sRho[k + 1][lm]};
+            sLap[k][lane] = lap3(s, m, n);
+        }
+    }
+    __syncthreads();
+
+    // ---- phase C: force, collision, store -----------------------------------------
+    const bool wall_tile = walls && (y0 == 0 || y0 + TYO >= a.ny);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + 4 * j;
+        const int y = y0 - 2 + k;
+        if (k < 2 || k > H - 3 || y >= a.ny) continue;  // halo row (wave-uniform)
+        C gphx, gphy, glx, gly;
+        {
+            const Row3<C> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
+            const Row3<C> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
+            const Row3<C> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
+            grad3(s, m, n, gphx, gphy);
+        }
+        {
+            const Row3<C> s{sLap[k - 1][lane], sLap[k - 1][lp], sLap[k - 1][lm]};
+            const Row3<C> m{sLap[k][lane], sLap[k][lp], sLap[k][lm]};
+            const Row3<C> n{sLap[k + 1][lane], sLap[k + 1][lp], sLap[k + 1][lm]};
+            grad3(s, m, n, glx, gly);
+        }
+        const C rh = sRho[k][lane];
+        const C Fx = -gphx + kappa * rh * glx + g;
+        const C Fy = -gphy + kappa * rh * gly;
+        C* fj = f[j];
+        const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
+        const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
+        C vx, vy;
+        collide<C>(f[j], rh, jx, jy, Fx, Fy, recip(rh), a, C(a.tau), C(a.s_e), C(a.s_eps), C(a.s_q), C(a.s_j),
+                   C(a.s_v), vx, vy);
+        if (out_lane) {
+            const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
+#define LBM_TSTORE(I) CD::template store<I>(at_bytes(fout, o + uint32_t(I) * plane_bytes), f[j][I], rho0);
+            LBM_TSTORE(0) LBM_TSTORE(1) LBM_TSTORE(2) LBM_TSTORE(3) LBM_TSTORE(4) LBM_TSTORE(5) LBM_TSTORE(6)
+            LBM_TSTORE(7) LBM_TSTORE(8)
+#undef LBM_TSTORE
+            if (EMIT) {
+                const long long c = (long long)y * a.nx + x;
+                a.rho_out[c] = double(rh);
+                a.vx_out[c] = double(vx);
+                a.vy_out[c] = double(vy);
+            }
+        }
+        if (wall_tile) {
+            if (y == 0 || y == a.ny - 1) {
+                // wall pressure: isotropic part of eq. 2.8 on the first fluid row
+                const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
+                const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
+                const Row3<C> n{sRho[k + 1][lane], sRho[k + 1][lp], sRho[k + 1][lm]};
+                C grx, gry;
+                grad3(s, m, n, grx, gry);
+                const int w = (y == 0) ? 0 : 1;
+                sWp[w][lane] = k2 * p0_of<EOS, C>(rh, RT, a_eff, bb) - kappa * rh * sLap[k][lane]
+                             - C(0.5) * kappa * (grx * grx + gry * gry);
+                sWr[w][lane] = rh;
+            }
+            if (y == 0) sWv[0][lane] = vx;
+            if (y == 1) sWv[1][lane] = vx;
+            if (y == a.ny - 2) sWv[2][lane] = vx;
+            if (y == a.ny - 1) sWv[3][lane] = vx;
+        }
+    }
+
+    // ---- phase D: wall shear and the per-strip extremes -------------------------------
+    if (!wall_tile) return;  // block-uniform
+    __syncthreads();
+    const bool has_bottom = (y0 == 0), has_top = (y0 + TYO >= a.ny);
+    if ((wave == 0 && has_bottom) || (wave == 1 && has_top)) {
+        const int w = wave;
+        // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
+        const C v_half = sWv[w == 0 ? 0 : 3][lane], v_3half = sWv[w == 0 ? 1 : 2][lane];
+        const C tw = sWr[w][lane] * C(a.nu) * (C(9) * v_half - v_3half) * C(1.0 / 3.0);
+        const double dt = out_lane ? double(tw) : 0.0, dpw = out_lane ? double(sWp[w][lane]) : 0.0;
+        if (out_lane) {
+            a.tau_w[w * a.nx + x] = dt;
+            a.p_w[w * a.nx + x] = dpw;
+        }
+        double tmax = out_lane ? dt : -INFINITY, tmin = out_lane ? dt : INFINITY;
+        double pmax = out_lane ? dpw : -INFINITY, pmin = out_lane ? dpw : INFINITY;
+        int xtmax = out_lane ? x : 0x7fffffff, xtmin = xtmax, xpmax = xtmax, xpmin = xtmax;
+        wave_argmax(tmax, xtmax);
+        wave_argmin(tmin, xtmin);
+        wave_argmax(pmax, xpmax);
+        wave_argmin(pmin, xpmin);
+        const double s2 = wave_sum(dt * dt);
+        if (lane == 0) {
+            double* o = a.partial + ((long long)w * a.nstrip + strip) * kPartialVals;
+            o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
+            o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
+            o[8] = s2;
+        }
     }
 }
 
@@ -534,64 +822,94 @@ __global__ void column_scan_kernel(const double* __restrict__ rho, int nx, int n
         centre[x] = rho[(long long)(ny / 2) * nx + x];
 }
 
-// One thread per step reduces the per-strip partials (strips in x order, so
-// strict comparisons keep the smallest x); thread 0 then accumulates the time
-// integrals in step order.
-constexpr int kWallThreads = 256;
+// One wave per step reduces that step's per-strip partials: lanes take strips
+// lane, lane + 64, ... in x order (strict comparisons keep the smallest x),
+// then a fixed butterfly combines the lanes (ties again to the smaller x).
+__device__ inline void comb_max(double& v, double& x, double ov, double ox) {
+    if (ov > v || (ov == v && ox < x)) { v = ov; x = ox; }
+}
+__device__ inline void comb_min(double& v, double& x, double ov, double ox) {
+    if (ov < v || (ov == v && ox < x)) { v = ov; x = ox; }
+}
 
-__global__ __launch_bounds__(kWallThreads) void wall_reduce_kernel(const double* __restrict__ ring, int first,
-                                                                   int ring_cap, int nsteps, int nstrip,
-                                                                   int64_t first_step, lbm_stress_summary* hist,
-                                                                   int hist_cap, double* acc) {
-    __shared__ double peak2[kWallThreads], sum2[kWallThreads];
-    const int t = threadIdx.x;
-    if (t < nsteps) {
-        const double* slot = ring + (long long)((first + t) % ring_cap) * 2 * nstrip * kPartialVals;
-        lbm_stress_summary sm;
-        sm.step = first_step + t;
-        double pk = 0.0, s2 = 0.0;
-        for (int w = 0; w < 2; ++w) {
-            const double* p = slot + (long long)w * nstrip * kPartialVals;
-            double tmax = p[0], tmin = p[2], pmax = p[4], pmin = p[6], ws = p[8];
-            double xtmax = p[1], xtmin = p[3], xpmax = p[5], xpmin = p[7];
-            for (int s = 1; s < nstrip; ++s) {
-                const double* q = p + (long long)s * kPartialVals;
-                if (q[0] > tmax) { tmax = q[0]; xtmax = q[1]; }
-                if (q[2] < tmin) { tmin = q[2]; xtmin = q[3]; }
-                if (q[4] > pmax) { pmax = q[4]; xpmax = q[5]; }
-                if (q[6] < pmin) { pmin = q[6]; xpmin = q[7]; }
-                ws += q[8];
-            }
-            sm.tau_max[w] = tmax; sm.tau_min[w] = tmin; sm.p_max[w] = pmax; sm.p_min[w] = pmin;
-            sm.x_tau_max[w] = int32_t(xtmax); sm.x_tau_min[w] = int32_t(xtmin);
-            sm.x_p_max[w] = int32_t(xpmax); sm.x_p_min[w] = int32_t(xpmin);
-            pk = fmax(pk, fmax(tmax * tmax, tmin * tmin));
-            s2 += ws;
+__global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __restrict__ ring, int nstrip,
+                                                              int64_t first_step, lbm_stress_summary* hist,
+                                                              int hist_cap, double* __restrict__ scratch) {
+    const int t = blockIdx.x, lane = threadIdx.x;
+    const double* slot = ring + (long long)t * 2 * nstrip * kPartialVals;
+    lbm_stress_summary sm;
+    sm.step = first_step + t;
+    double pk = 0.0, s2 = 0.0;
+    for (int w = 0; w < 2; ++w) {
+        const double* p = slot + (long long)w * nstrip * kPartialVals;
+        double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
+        double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0;
+        for (int st = lane; st < nstrip; st += 64) {
+            const double* q = p + (long long)st * kPartialVals;
+            comb_max(tmax, xtmax, q[0], q[1]);
+            comb_min(tmin, xtmin, q[2], q[3]);
+            comb_max(pmax, xpmax, q[4], q[5]);
+            comb_min(pmin, xpmin, q[6], q[7]);
+            ws += q[8];
         }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            comb_max(tmax, xtmax, __shfl_xor(tmax, off, 64), __shfl_xor(xtmax, off, 64));
+            comb_min(tmin, xtmin, __shfl_xor(tmin, off, 64), __shfl_xor(xtmin, off, 64));
+            comb_max(pmax, xpmax, __shfl_xor(pmax, off, 64), __shfl_xor(xpmax, off, 64));
+            comb_min(pmin, xpmin, __shfl_xor(pmin, off, 64), __shfl_xor(xpmin, off, 64));
+            ws += __shfl_xor(ws, off, 64);
+        }
+        sm.tau_max[w] = tmax; sm.tau_min[w] = tmin; sm.p_max[w] = pmax; sm.p_min[w] = pmin;
+        sm.x_tau_max[w] = int32_t(xtmax); sm.x_tau_min[w] = int32_t(xtmin);
+        sm.x_p_max[w] = int32_t(xpmax); sm.x_p_min[w] = int32_t(xpmin);
+        pk = fmax(pk, fmax(tmax * tmax, tmin * tmin));
+        s2 += ws;
+    }
+    if (lane == 0) {
         sm.sum_tau2 = s2;
         sm.int_peak_tau2 = 0.0;
         sm.int_tau2 = 0.0;
         hist[(sm.step - 1) % hist_cap] = sm;
-        peak2[t] = pk;
-        sum2[t] = s2;
+        scratch[2 * t] = pk;
+        scratch[2 * t + 1] = s2;
     }
-    __syncthreads();
-    if (t == 0) {
-        double ip = acc[0], is = acc[1];
-        for (int k = 0; k < nsteps; ++k) {
-            ip += peak2[k];
-            is += sum2[k];
-            lbm_stress_summary* h = &hist[(first_step + k - 1) % hist_cap];
-            h->int_peak_tau2 = ip;
-            h->int_tau2 = is;
-        }
-        acc[0] = ip;
-        acc[1] = is;
+}
+
+// Running time integrals, in step order (single thread: nsteps additions).
+__global__ void wall_integrate_kernel(const double* __restrict__ scratch, int nsteps, int64_t first_step,
+                                      lbm_stress_summary* hist, int hist_cap, double* acc) {
+    double ip = acc[0], is = acc[1];
+    for (int k = 0; k < nsteps; ++k) {
+        ip += scratch[2 * k];
+        is += scratch[2 * k + 1];
+        lbm_stress_summary* h = &hist[(first_step + k - 1) % hist_cap];
+        h->int_peak_tau2 = ip;
+        h->int_tau2 = is;
     }
+    acc[0] = ip;
+    acc[1] = is;
+}
+
+template <class CD, int EOS, int TYO>
+hipError_t launch_tile(const StepArgs& a, bool emit, hipStream_t s) {
+    const dim3 grid(a.nstrip * ((a.ny + TYO - 1) / TYO)), block(256);
+    if (emit)
+        hipLaunchKernelGGL((tile_kernel<CD, EOS, true, TYO>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((tile_kernel<CD, EOS, false, TYO>), grid, block, 0, s, a);
+    return hipGetLastError();
 }
 
 template <class CD, int EOS>
 hipError_t launch_step_t(const StepArgs& a, bool emit, hipStream_t s) {
+    if (a.schedule == kScheduleTile) {
+        switch (a.ty) {
+            case 12: return launch_tile<CD, EOS, 12>(a, emit, s);
+            case 28: return launch_tile<CD, EOS, 28>(a, emit, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     const int nbx = (a.nstrip + kWavesPerBlock - 1) / kWavesPerBlock;
     const dim3 grid(nbx * a.nchunk), block(64 * kWavesPerBlock);
     if (emit)
@@ -657,12 +975,14 @@ hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin,
     return hipGetLastError();
 }
 
-hipError_t launch_wall_reduce(const double* ring, int first, int ring_cap, int nsteps, int nstrip, int64_t first_step,
-                              lbm_stress_summary* hist, int hist_cap, double* acc, hipStream_t s) {
+hipError_t launch_wall_reduce(const double* ring, int nsteps, int nstrip, int64_t first_step, lbm_stress_summary* hist,
+                              int hist_cap, double* scratch, double* acc, hipStream_t s) {
     if (nsteps <= 0) return hipSuccess;
-    if (nsteps > kWallThreads) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(wall_reduce_kernel, dim3(1), dim3(kWallThreads), 0, s, ring, first, ring_cap, nsteps, nstrip,
-                       first_step, hist, hist_cap, acc);
+    hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps), dim3(64), 0, s, ring, nstrip, first_step, hist, hist_cap,
+                       scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(wall_integrate_kernel, dim3(1), dim3(1), 0, s, scratch, nsteps, first_step, hist, hist_cap, acc);
     return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ class lbm_params(C.Structure):
         ("s_eps", C.c_double), ("s_q", C.c_double), ("s_j", C.c_double), ("rho_wall", C.c_double),
         ("dp", C.c_double), ("x_periodic", C.c_int), ("y_periodic", C.c_int), ("storage", C.c_int),
         ("rho0_shift", C.c_double), ("check_every", C.c_int), ("v_limit", C.c_double),
-        ("history_cap", C.c_int),
+        ("history_cap", C.c_int), ("tile_rows", C.c_int), ("schedule", C.c_int),
     ]
 
 

@@ -25,7 +25,8 @@ if not torch.cuda.is_available():  # pragma: no cover
 import oracle as O  # noqa: E402
 from paper_2103_08301_amd import Lattice, lbm  # noqa: E402
 
-ORACLE_KEYS = {"eos", "a", "b", "R", "omega", "T_over_Tc", "k", "kappa", "s_e", "s_eps", "s_q", "s_j",
+ORACLE_KEYS = {  # parameters the oracle shares with the library
+"eos", "a", "b", "R", "omega", "T_over_Tc", "k", "kappa", "s_e", "s_eps", "s_q", "s_j",
                "rho_wall", "dp", "x_periodic", "y_periodic", "check_every", "v_limit"}
 
 
@@ -61,10 +62,15 @@ CASES = [
 ]
 
 
+SCHEDULES = [dict(schedule=0, tile_rows=28), dict(schedule=0, tile_rows=12), dict(schedule=1, tile_rows=16),
+             dict(schedule=1, tile_rows=5)]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda d: f"s{d['schedule']}t{d['tile_rows']}")
 @pytest.mark.parametrize("nx,ny,tau,kw", CASES)
-def test_fp64_matches_oracle_on_small_grids(nx, ny, tau, kw):
-    log(f"case {nx}x{ny} tau {tau} {kw}")
-    lat, ref = pair(nx, ny, tau, **kw)
+def test_fp64_matches_oracle_on_small_grids(nx, ny, tau, kw, sched):
+    log(f"case {nx}x{ny} tau {tau} {kw} {sched}")
+    lat, ref = pair(nx, ny, tau, **kw, **sched)
     rho0 = plug_density(ref, max(4, nx // 5), 0 if kw.get("y_periodic") else 2, noise=1e-3, seed=nx)
     lat.init_density(rho0)
     ref.init_density(rho0)
