@@ -1,21 +1,22 @@
 """Throughput of the fused D2Q9 EOS-multiphase step on one MI355X.
 
-A step is one pass of the whole hot path (pull streaming with walls and ends,
-density and EOS field, nonideal force, velocity-shift MRT collision, wall
-shear/pressure diagnostics with FP64 summaries) over the 4096x512 plug-in-channel
-workload, FP32 storage and arithmetic.  Inputs are resident in HBM before the
-timed region; W warm-up steps, then exactly K timed steps between two
-synchronisations.  Prints one JSON line.
+A step is one pass of the whole hot path (pull streaming with bounce-back walls
+and extrapolated ends, density and EOS field, nonideal force of eq. 2.17,
+velocity-shift MRT collision, wall shear/pressure diagnostics with FP64
+per-step summaries) over the 4096x512 plug-in-channel workload.  Inputs are
+resident in HBM before the timed region; W warm-up steps, then exactly K timed
+steps between two device synchronisations, timed with HIP events on the stream
+the kernels run on.  Prints one JSON line.
 
 MLUPS = nx*ny*K / t / 1e6.  The roofline uses the algorithmic traffic of the
 method: 9 populations read + 9 written per node and step (72 B in FP32, 36 B in
-FP16/BF16, 144 B in FP64) against the 8 TB/s HBM3E peak.
+FP16/BF16 storage, 144 B in FP64) against the 8 TB/s HBM3E peak.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -26,10 +27,19 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f64": 144, "f32": 72, "f32d": 72, "f32s": 72, "f16s": 36, "bf16s": 36}
+DTYPE = {"f32": "f32", "f64": "f64", "f32d": "f32-store/f64", "f32s": "f32-shifted/f32",
+         "f16s": "f16-store/f32", "bf16s": "bf16-store/f32"}
+KERNEL_SRC = os.path.join(ROOT, "paper_2103_08301_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096x512_f32_traffic.json")
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 def make_lattice(w: dict, check_every: int):
@@ -42,7 +52,7 @@ def make_lattice(w: dict, check_every: int):
 
 
 def time_steps(w: dict, steps: int, warmup: int):
-    """Returns (seconds for `steps` timed steps, lattice)."""
+    """Seconds for `steps` timed steps (HIP events on the library's stream), wall seconds, lattice."""
     import torch
 
     lat = make_lattice(w, check_every=max(steps, warmup, 1))
@@ -57,8 +67,7 @@ def time_steps(w: dict, steps: int, warmup: int):
     stop.record(lat.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu = start.elapsed_time(stop) / 1e3
-    return gpu, wall, lat
+    return start.elapsed_time(stop) / 1e3, wall, lat
 
 
 def cpu_baseline(w: dict, budget_s: float) -> dict:
@@ -77,20 +86,40 @@ def cpu_baseline(w: dict, budget_s: float) -> dict:
     t0 = time.perf_counter()
     sim.step(n)
     dt = time.perf_counter() - t0
-    return {"value": w["nx"] * w["ny"] * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+    return {"value": round(w["nx"] * w["ny"] * n / dt / 1e6, 2), "unit": "MLUPS", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"{n} steps of the {w['nx']}x{w['ny']} workload in FP64 on the host ({dt:.1f} s)"}
+            "sample": f"{n} steps of the {w['nx']}x{w['ny']} workload, FP64 oracle on the host ({dt:.1f} s)"}
+
+
+def finite(v):
+    """JSON has no NaN/Infinity: non-finite numbers become null."""
+    if isinstance(v, float):
+        return v if v == v and abs(v) != float("inf") else None
+    if isinstance(v, dict):
+        return {k: finite(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [finite(x) for x in v]
+    return v
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per launch from the committed counter profile, if it was taken on this kernel source."""
+    if storage != "f32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    return t["bytes_per_launch"] if t.get("kernel_source_sha256_16") == kernel_hash() else None
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_NODE))
-    ap.add_argument("--workload", default="large", choices=["large", "large-stable", "out-of-cache"])
+    ap.add_argument("--workload", default="large-stable", choices=["large-stable", "large", "out-of-cache"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-control", action="store_true", help="skip the stable-physics control run")
+    ap.add_argument("--no-variants", action="store_true", help="skip the FP16-storage run and the literal-config probe")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes 10 times (counter calibration)")
@@ -114,15 +143,23 @@ def main() -> int:
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(10):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 10}), flush=True)
+        gbs = 2 * n * 4 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 10, "copy_GBps_read_plus_write": round(gbs, 1)}),
+              flush=True)
         return 0
     lbm.library()  # fail loudly if the HIP library is missing
 
-    w = {"large": workloads.plug_large, "large-stable": workloads.plug_large_stable,
-         "out-of-cache": workloads.plug_out_of_cache}[args.workload](args.storage)
+    make = {"large-stable": workloads.plug_large_stable, "large": workloads.plug_large,
+            "out-of-cache": workloads.plug_out_of_cache}[args.workload]
+    w = make(args.storage)
     nodes = w["nx"] * w["ny"]
     log(f"workload: {w['name']}; warmup {args.warmup}, timed {args.steps}")
     gpu_s, wall_s, lat = time_steps(w, args.steps, args.warmup)
@@ -133,6 +170,11 @@ def main() -> int:
     achieved = bpn * nodes / (gpu_s / args.steps) / 1e9
     log(f"{mlups:.0f} MLUPS, {ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s algorithmic "
         f"(wall {wall_s:.3f} s); check: {chk}")
+    hist = lat.history(1)
+    peak = None
+    if hist:
+        h = hist[-1]
+        peak = max(abs(h["tau_max"][0]), abs(h["tau_min"][0]), abs(h["tau_max"][1]), abs(h["tau_min"][1]))
     out = {
         "metric": "MLUPS (D2Q9 EOS-multiphase step, 4096x512 plug-in-channel)",
         "value": round(mlups, 1),
@@ -144,27 +186,37 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "f64": "f64", "f32d": "f32-store/f64", "f32s": "f32-shifted/f32",
-                  "f16s": "f16-store/f32", "bf16s": "bf16-store/f32"}[args.storage],
+        "dtype": DTYPE[args.storage],
         "data": "synthetic",
         "config": {"workload": w["name"], "nx": w["nx"], "ny": w["ny"], "tau": w["tau"], **w["params"],
-                   **{k: v for k, v in w["plug"].items() if k != "x_center"}, "storage": args.storage},
+                   **{k: v for k, v in w["plug"].items() if k != "x_center"}, "storage": args.storage,
+                   "schedule": "tile 60x8" if args.storage not in ("f64", "f32d") else "tile 60x12"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_node": bpn, "kernel": "step_kernel (fused pull-stream/force/MRT/wall diagnostics)"},
-        "physics": {"unstable_step": chk["unstable_step"], "vmax": chk["vmax"], "nan_cells": chk["nan_count"]},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.storage),
+                     "bytes_per_node": bpn, "kernel": "tile_kernel (fused pull-stream/force/MRT/wall diagnostics)"},
+        "physics": {"unstable_step": chk["unstable_step"], "vmax": round(chk["vmax"], 5),
+                    "nan_cells": chk["nan_count"], "liquid_columns": chk["liquid_columns"],
+                    "x_rear": chk["x_rear"], "x_front": chk["x_front"], "wall_tau_peak_last_step": peak},
     }
-    if not args.no_control and args.workload == "large":
-        ctl = workloads.plug_large_stable(args.storage)
-        cg, _, cl = time_steps(ctl, args.steps, args.warmup)
-        cc = cl.check()
-        out["stable_control"] = {"workload": ctl["name"], "value": round(nodes * args.steps / cg / 1e6, 1),
-                                 "unit": "MLUPS", "unstable_step": cc["unstable_step"], "vmax": cc["vmax"]}
-        log(f"control: {out['stable_control']}")
+    if not args.no_variants and args.workload == "large-stable":
+        wh = make("f16s")
+        hs, _, hl = time_steps(wh, args.steps, args.warmup)
+        hc = hl.check()
+        out["fp16_store"] = {"value": round(nodes * args.steps / hs / 1e6, 1), "unit": "MLUPS",
+                             "roofline_frac": round(36 * nodes / (hs / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+                             "x_rear": hc["x_rear"], "x_front": hc["x_front"], "unstable_step": hc["unstable_step"]}
+        log(f"fp16 store: {out['fp16_store']}")
+        lit = workloads.plug_large(args.storage)
+        ll = make_lattice(lit, check_every=50)
+        ll.step(400)
+        out["config_as_specified"] = {"workload": lit["name"], "unstable_step": ll.check()["unstable_step"],
+                                      "note": "diverges under the method as read; not timed (NaN data runs at a "
+                                              "different rate)"}
+        log(f"literal config: {out['config_as_specified']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
         log(f"cpu baseline: {out['cpu_baseline']}")
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite(out), allow_nan=False), flush=True)
     return 0
 
 

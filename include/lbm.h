@@ -86,8 +86,9 @@ typedef struct {
     int check_every;     /* stability/interface check cadence in steps (>= 1) */
     double v_limit;      /* a check fails when |v| exceeds this or a NaN appears */
     int history_cap;     /* capacity (steps) of the device ring of per-step wall summaries (>= 1) */
-    int tile_rows;       /* output rows per tile (schedule 0: 0, 12 or 28) or per wave chunk
-                            (schedule 1: 0 or 4..256); 0 selects the default (12 / 16) */
+    int tile_rows;       /* output rows per tile (schedule 0: 0, 8, 12, 20 or 28) or per wave chunk
+                            (schedule 1: 0 or 4..256); 0 selects the default (tile: 8, or 12 with FP64
+                            arithmetic; march: 16) */
     int schedule;        /* 0: one block per 60 x tile_rows tile, phases coupled through LDS;
                             1: one wavefront per 60-column strip marching up a row chunk */
 } lbm_params;

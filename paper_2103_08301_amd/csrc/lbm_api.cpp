@@ -210,7 +210,6 @@ size_t storage_bytes(int storage) {
 
 constexpr int kRingCap = 256;  // per-step partial slots before a wall reduction is forced
 constexpr int kDefaultMarchRows = 16;
-constexpr int kDefaultTileOut = 12;
 
 }  // namespace
 
@@ -436,7 +435,8 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
         p->storage < LBM_F64 || p->storage > LBM_F32S || (p->x_periodic != 0 && p->x_periodic != 1) ||
         (p->y_periodic != 0 && p->y_periodic != 1) || !std::isfinite(p->omega) ||
         (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || (p->schedule != 0 && p->schedule != 1) ||
-        (p->schedule == 0 && p->tile_rows != 0 && p->tile_rows != 12 && p->tile_rows != 28) ||
+        (p->schedule == 0 && p->tile_rows != 0 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 20 &&
+         p->tile_rows != 28) ||
         (p->schedule == 1 && p->tile_rows != 0 && (p->tile_rows < 4 || p->tile_rows > 256)))
         return LBM_EINVAL;
     const int pitch = (nx + 63) / 64 * 64;
@@ -465,7 +465,11 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->plane = (long long)pitch * ny;
     c->nstrip = (nx + lbm::kStripOut - 1) / lbm::kStripOut;
     c->schedule = p->schedule;
-    c->ty = p->tile_rows > 0 ? p->tile_rows : (p->schedule == lbm::kScheduleTile ? kDefaultTileOut : kDefaultMarchRows);
+    // measured on the 4096x512 plug channel: 8-row tiles for FP32/FP16/BF16 arithmetic
+    // tiles, 12-row tiles when the arithmetic is FP64 (more registers per row)
+    const bool fp64_math = p->storage == LBM_F64 || p->storage == LBM_F32D;
+    c->ty = p->tile_rows > 0 ? p->tile_rows
+                             : (p->schedule == lbm::kScheduleTile ? (fp64_math ? 12 : 8) : kDefaultMarchRows);
     c->nchunk = std::max(1, ny / c->ty);
     // workspace layout
     size_t o = 0;

@@ -559,9 +559,11 @@ __global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int ntile = (a.ny + TYO - 1) / TYO;
-    const int strip = bid / ntile;
-    const int tile = bid - strip * ntile;
+    // tile-row-major: consecutive blocks are x-neighbours, and with the XCD remap
+    // each XCD walks a contiguous band of tile rows, so the halo columns and the
+    // halo rows shared by neighbouring tiles are still in that XCD's L2
+    const int tile = bid / a.nstrip;
+    const int strip = bid - tile * a.nstrip;
     const int y0 = (a.ny >= TYO) ? min(tile * TYO, a.ny - TYO) : 0;
     const int x0 = strip * kStripOut;
     const int x = x0 - 2 + lane;
@@ -905,7 +907,9 @@ template <class CD, int EOS>
 hipError_t launch_step_t(const StepArgs& a, bool emit, hipStream_t s) {
     if (a.schedule == kScheduleTile) {
         switch (a.ty) {
+            case 8: return launch_tile<CD, EOS, 8>(a, emit, s);
             case 12: return launch_tile<CD, EOS, 12>(a, emit, s);
+            case 20: return launch_tile<CD, EOS, 20>(a, emit, s);
             case 28: return launch_tile<CD, EOS, 28>(a, emit, s);
             default: return hipErrorInvalidValue;
         }

@@ -49,11 +49,15 @@ def plug_large(storage: str = "f32") -> dict:
 
 
 def plug_large_stable(storage: str = "f32") -> dict:
-    """Same grid, plug and film as plug_large, at the 256x64 case's stable state point (0.85 Tc, tau 1.0)."""
+    """Same grid, tau, plug, film and pressure drop as plug_large, at 0.95 Tc.
+
+    Under the method as implemented, the 0.80 Tc case diverges within ~50 steps
+    and 0.85-0.90 Tc within 12-25k steps (the driven gas of a 512-row channel
+    accelerates past the lattice's low-Mach range); 0.95 Tc with tau 0.8 stays
+    finite beyond 30k steps, so timed runs use it."""
     w = plug_large(storage)
-    w["name"] = w["name"].replace("CS 0.80 Tc, tau 0.8", "CS 0.85 Tc, tau 1.0")
-    w["tau"] = 1.0
-    w["params"] = dict(w["params"], T_over_Tc=0.85)
+    w["name"] = w["name"].replace("CS 0.80 Tc", "CS 0.95 Tc")
+    w["params"] = dict(w["params"], T_over_Tc=0.95)
     return w
 
 
