@@ -30,7 +30,7 @@ BYTES_PER_NODE = {"f64": 144, "f32": 72, "f32d": 72, "f32s": 72, "f16s": 36, "bf
 DTYPE = {"f32": "f32", "f64": "f64", "f32d": "f32-store/f64", "f32s": "f32-shifted/f32",
          "f16s": "f16-store/f32", "bf16s": "bf16-store/f32"}
 KERNEL_SRC = os.path.join(ROOT, "paper_2103_08301_amd", "csrc", "lbm_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096x512_f32_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_4096x512_f32_traffic.json")
 
 
 def log(msg: str) -> None:
