@@ -86,11 +86,18 @@ typedef struct {
     int check_every;     /* stability/interface check cadence in steps (>= 1) */
     double v_limit;      /* a check fails when |v| exceeds this or a NaN appears */
     int history_cap;     /* capacity (steps) of the device ring of per-step wall summaries (>= 1) */
-    int tile_rows;       /* output rows per tile (schedule 0: 0, 8, 12, 20 or 28) or per wave chunk
-                            (schedule 1: 0 or 4..256); 0 selects the default (tile: 8, or 12 with FP64
-                            arithmetic; march: 16) */
+    int tile_rows;       /* output rows per tile or per wave chunk; 0 selects the default.
+                            schedule 0: 8, 12, 20 or 28 (default 8, or 12 with FP64 arithmetic or 8 waves);
+                            schedule 1: 4..256 (default 16);
+                            schedule 2: 4, 8 or 12 with 4 waves, 8 or 16 with 8 waves (default 8) */
     int schedule;        /* 0: one block per 60 x tile_rows tile, phases coupled through LDS;
-                            1: one wavefront per 60-column strip marching up a row chunk */
+                            1: one wavefront per 60-column strip marching up a row chunk;
+                            2: the tiles of schedule 0 taken one after another by resident blocks
+                               (per-XCD ticket counters in the workspace), the next tile's loads
+                               issued before the current tile is computed */
+    int tile_waves;      /* schedules 0 and 2: waves per tile block, 0 (= 4), 4 or 8; schedule 1: 0 */
+    int pipe_blocks;     /* schedule 2: blocks launched; 0 = compute units x blocks one unit holds,
+                            otherwise >= 8 (every one of the 8 tile ranges needs a block) */
 } lbm_params;
 
 /* Per-step wall summary ([0] bottom wall, [1] top wall).  FP64. */

@@ -28,6 +28,9 @@ def build_library(verbose: bool = False) -> str:
         "-Wall", "-Wno-unused-function",
         # packed FP32 VALU forms are kept out of the generated code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # tile tickets are drawn by one lane and must stay in flight: no wave-level
+        # rewrite of the atomic (which would wait for it at once to broadcast it)
+        "-Xarch_device", "-mllvm=-amdgpu-atomic-optimizer-strategy=None",
         "-I", INCLUDE, "-I", CSRC,
         *[os.path.join(CSRC, s) for s in SOURCES],
         "-o", tmp,

@@ -211,6 +211,23 @@ size_t storage_bytes(int storage) {
 constexpr int kRingCap = 256;  // per-step partial slots before a wall reduction is forced
 constexpr int kDefaultMarchRows = 16;
 
+// Tile heights each schedule is compiled for (0 picks the default).
+bool schedule_ok(const lbm_params* p) {
+    const int r = p->tile_rows, w = p->tile_waves;
+    if (w != 0 && w != 4 && w != 8) return false;
+    if (p->pipe_blocks != 0 && (p->schedule != lbm::kSchedulePipe || p->pipe_blocks < 8)) return false;
+    switch (p->schedule) {
+        case lbm::kScheduleTile:
+            if (w == 8) return r == 0 || r == 12 || r == 20 || r == 28;
+            return r == 0 || r == 8 || r == 12 || r == 20 || r == 28;
+        case lbm::kScheduleMarch: return w == 0 && (r == 0 || (r >= 4 && r <= 256));
+        case lbm::kSchedulePipe:
+            if (w == 8) return r == 0 || r == 8 || r == 16;
+            return r == 0 || r == 4 || r == 8 || r == 12;
+        default: return false;
+    }
+}
+
 }  // namespace
 
 struct lbm_ctx {
@@ -221,10 +238,11 @@ struct lbm_ctx {
     double rho_c = 0, rho_g = NAN, rho_l = NAN, rho_w = 0, rho0 = 0;
     int pitch = 0;
     long long plane = 0;
-    int nstrip = 0, nchunk = 0, ty = 0, schedule = 0;
+    int nstrip = 0, nchunk = 0, ty = 0, schedule = 0, tile_waves = 4, pipe_blocks = 0;
     // workspace layout (byte offsets)
     size_t off_f[2]{}, off_rho = 0, off_vx = 0, off_vy = 0, off_tau = 0, off_pw = 0, off_ring = 0, off_hist = 0,
-           off_acc = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, total = 0;
+           off_acc = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, off_tickets = 0,
+           total = 0;
     char* dev = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -366,6 +384,7 @@ lbm::StepArgs make_args(const lbm_ctx* c) {
     a.nchunk = c->nchunk;
     a.ty = c->ty;
     a.schedule = c->schedule;
+    a.tile_waves = c->tile_waves;
     a.xper = c->p.x_periodic;
     a.yper = c->p.y_periodic;
     a.tau = c->tau;
@@ -383,11 +402,16 @@ lbm::StepArgs make_args(const lbm_ctx* c) {
     a.b = c->eos.b;
     a.rho_w = c->rho_w;
     a.rho0 = c->rho0;
+    a.cf = lbm::CoefF32{float(a.tau), float(a.s_e), float(a.s_eps), float(a.s_q), float(a.s_j), float(a.s_v),
+                        float(a.k2), float(a.kappa), float(a.g), float(a.nu), float(a.RT), float(a.a_eff),
+                        float(a.b), float(a.rho_w), float(a.rho0)};
     a.tau_w = c->at<double>(c->off_tau);
     a.p_w = c->at<double>(c->off_pw);
     a.rho_out = c->at<double>(c->off_rho);
     a.vx_out = c->at<double>(c->off_vx);
     a.vy_out = c->at<double>(c->off_vy);
+    a.tickets = c->at<unsigned long long>(c->off_tickets);
+    a.pipe_blocks = c->pipe_blocks;
     return a;
 }
 
@@ -421,6 +445,8 @@ void lbm_params_default(lbm_params* p) {
     p->history_cap = 4096;
     p->tile_rows = 0;
     p->schedule = 0;
+    p->tile_waves = 0;
+    p->pipe_blocks = 0;
 }
 
 lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx** out) {
@@ -434,14 +460,14 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
         !(p->v_limit > 0) || p->history_cap < 1 || (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) ||
         p->storage < LBM_F64 || p->storage > LBM_F32S || (p->x_periodic != 0 && p->x_periodic != 1) ||
         (p->y_periodic != 0 && p->y_periodic != 1) || !std::isfinite(p->omega) ||
-        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || (p->schedule != 0 && p->schedule != 1) ||
-        (p->schedule == 0 && p->tile_rows != 0 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 20 &&
-         p->tile_rows != 28) ||
-        (p->schedule == 1 && p->tile_rows != 0 && (p->tile_rows < 4 || p->tile_rows > 256)))
+        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || !schedule_ok(p))
         return LBM_EINVAL;
     const int pitch = (nx + 63) / 64 * 64;
     // the step kernel addresses a distribution buffer with 32-bit byte offsets
     if ((unsigned long long)pitch * ny * 9 * storage_bytes(p->storage) >= (1ULL << 32)) return LBM_EINVAL;
+    // the pipelined schedule drops halo-lane stores with a 2 GiB out-of-range buffer offset
+    if (p->schedule == lbm::kSchedulePipe && (unsigned long long)pitch * ny * 9 * storage_bytes(p->storage) >= (1ULL << 31))
+        return LBM_EINVAL;
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return LBM_ENOMEM;
     c->nx = nx;
@@ -465,11 +491,18 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->plane = (long long)pitch * ny;
     c->nstrip = (nx + lbm::kStripOut - 1) / lbm::kStripOut;
     c->schedule = p->schedule;
+    c->tile_waves = p->tile_waves > 0 ? p->tile_waves : 4;
     // measured on the 4096x512 plug channel: 8-row tiles for FP32/FP16/BF16 arithmetic
     // tiles, 12-row tiles when the arithmetic is FP64 (more registers per row)
     const bool fp64_math = p->storage == LBM_F64 || p->storage == LBM_F32D;
-    c->ty = p->tile_rows > 0 ? p->tile_rows
-                             : (p->schedule == lbm::kScheduleTile ? (fp64_math ? 12 : 8) : kDefaultMarchRows);
+    if (p->tile_rows > 0)
+        c->ty = p->tile_rows;
+    else if (p->schedule == lbm::kScheduleTile)
+        c->ty = (fp64_math || c->tile_waves == 8) ? 12 : 8;
+    else if (p->schedule == lbm::kSchedulePipe)
+        c->ty = 8;
+    else
+        c->ty = kDefaultMarchRows;
     c->nchunk = std::max(1, ny / c->ty);
     // workspace layout
     size_t o = 0;
@@ -490,6 +523,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->off_redout = o; o += 256;
     c->off_colmin = o; o += align256((size_t)nx * sizeof(double));
     c->off_centre = o; o += align256((size_t)nx * sizeof(double));
+    c->off_tickets = o; o += (size_t)lbm::kTicketGroups * lbm::kTicketStride * sizeof(unsigned long long);
     c->total = o;
     c->check.rupture_step = -1;
     c->check.unstable_step = -1;
@@ -509,6 +543,13 @@ lbm_status lbm_bind(lbm_ctx* c, void* device_ptr, size_t bytes, void* hip_stream
         return fail(c, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
     if (bytes < c->total) return fail(c, LBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, c->total);
     HIP_TRY(c, hipGetDevice(&c->device));
+    if (c->schedule == lbm::kSchedulePipe) {
+        if (c->p.pipe_blocks > 0)
+            c->pipe_blocks = c->p.pipe_blocks;
+        else
+            HIP_TRY(c, lbm::pipe_grid(c->p.storage, c->p.eos, c->ty, c->tile_waves, &c->pipe_blocks));
+        if (c->pipe_blocks < lbm::kTicketGroups) c->pipe_blocks = lbm::kTicketGroups;
+    }
     c->dev = static_cast<char*>(device_ptr);
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->bound = true;
@@ -572,6 +613,12 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_step needs lbm_bind and an initialisation");
     lbm::StepArgs a = make_args(c);
     const size_t slot = (size_t)2 * c->nstrip * lbm::kPartialVals;
+    if (c->schedule == lbm::kSchedulePipe && n > 0) {
+        // the ticket counters start from zero for this run of launches (all-zero bits)
+        HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_tickets), 0.0,
+                                    (long long)lbm::kTicketGroups * lbm::kTicketStride, c->stream));
+    }
+    a.launch = 0;
     int64_t done = 0;
     while (done < n) {
         const int64_t next_check = (c->steps / c->p.check_every + 1) * c->p.check_every;
@@ -586,6 +633,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
             a.fout = c->dev + c->off_f[1 - c->cur];
             a.partial = c->at<double>(c->off_ring) + slot * c->ring_fill;
             HIP_TRY(c, lbm::launch_step(a, c->p.storage, c->p.eos, emit, c->stream));
+            a.launch += 1;
             c->cur = 1 - c->cur;
             c->ring_fill += 1;
             c->steps += 1;
@@ -662,6 +710,7 @@ lbm_status lbm_check_state(const lbm_ctx* c, lbm_check_result* out) {
     return LBM_OK;
 }
 
+// Same shift arithmetic as the device codecs (fused multiply-add with the FP32 weight).
 static float host_weight(int i) { return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
 
 lbm_status lbm_get_f(lbm_ctx* c, double* f) {
@@ -681,11 +730,11 @@ lbm_status lbm_get_f(lbm_ctx* c, double* f) {
                     case LBM_F64: std::memcpy(&v, raw.data() + src * 8, 8); break;
                     case LBM_F32:
                     case LBM_F32D: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = t; break; }
-                    case LBM_F32S: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = (double)(t + host_weight(i) * r0); break; }
+                    case LBM_F32S: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = (double)std::fmaf(host_weight(i), r0, t); break; }
                     case LBM_F16S: {
                         _Float16 h;
                         std::memcpy(&h, raw.data() + src * 2, 2);
-                        v = (double)((float)h + host_weight(i) * r0);
+                        v = (double)std::fmaf(host_weight(i), r0, (float)h);
                         break;
                     }
                     default: {
@@ -694,7 +743,7 @@ lbm_status lbm_get_f(lbm_ctx* c, double* f) {
                         uint32_t u = (uint32_t)h << 16;
                         float t;
                         std::memcpy(&t, &u, 4);
-                        v = (double)(t + host_weight(i) * r0);
+                        v = (double)std::fmaf(host_weight(i), r0, t);
                     }
                 }
                 f[((size_t)i * c->ny + y) * c->nx + x] = v;
@@ -717,14 +766,14 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
                     case LBM_F64: std::memcpy(raw.data() + dst * 8, &v, 8); break;
                     case LBM_F32:
                     case LBM_F32D: { const float t = (float)v; std::memcpy(raw.data() + dst * 4, &t, 4); break; }
-                    case LBM_F32S: { const float t = (float)v - host_weight(i) * r0; std::memcpy(raw.data() + dst * 4, &t, 4); break; }
+                    case LBM_F32S: { const float t = std::fmaf(-host_weight(i), r0, (float)v); std::memcpy(raw.data() + dst * 4, &t, 4); break; }
                     case LBM_F16S: {
-                        const _Float16 h = (_Float16)((float)v - host_weight(i) * r0);
+                        const _Float16 h = (_Float16)std::fmaf(-host_weight(i), r0, (float)v);
                         std::memcpy(raw.data() + dst * 2, &h, 2);
                         break;
                     }
                     default: {
-                        const float t = (float)v - host_weight(i) * r0;
+                        const float t = std::fmaf(-host_weight(i), r0, (float)v);
                         uint32_t u;
                         std::memcpy(&u, &t, 4);
                         u += 0x7FFFu + ((u >> 16) & 1u);

@@ -16,9 +16,18 @@ namespace lbm {
 // force stencil grad(lap rho) needs.
 constexpr int kStripOut = 60;
 constexpr int kWavesPerBlock = 4;
-constexpr int kPartialVals = 9;
+constexpr int kPartialVals = 9;  // tmax, xtmax, tmin, xtmin, pmax, xpmax, pmin, xpmin, sum tau^2
 constexpr int kScheduleTile = 0;   // block-per-tile kernel with LDS-coupled phases
-constexpr int kScheduleMarch = 1;  // wave-per-strip row march with a register window   // tmax, xtmax, tmin, xtmin, pmax, xpmax, pmin, xpmin, sum tau^2
+constexpr int kScheduleMarch = 1;  // wave-per-strip row march with a register window
+constexpr int kSchedulePipe = 2;   // persistent blocks taking tiles by ticket, next tile's loads in flight
+constexpr int kTicketGroups = 8;   // one ticket counter per XCD
+constexpr int kTicketStride = 32;  // counters 256 bytes apart (in 64-bit words)
+
+// The step coefficients rounded to FP32 on the host, so FP32 kernels read them
+// as scalars instead of converting the FP64 values in every wave.
+struct CoefF32 {
+    float tau, s_e, s_eps, s_q, s_j, s_v, k2, kappa, g, nu, RT, a_eff, b, rho_w, rho0;
+};
 
 // Everything one launch of the step kernel needs, passed by value.
 struct StepArgs {
@@ -28,21 +37,29 @@ struct StepArgs {
     long long plane;          // elements per plane (pitch * ny)
     int nstrip, nchunk, ty;   // x strips, y chunks, output rows per chunk/tile
     int schedule;             // kScheduleTile or kScheduleMarch
+    int tile_waves;           // waves per tile block (4 or 8)
     int xper, yper;
     double tau, s_e, s_eps, s_q, s_j, s_v;
     double k2, kappa, g, nu;
     double RT, a_eff, b;      // EOS: R T, a * alpha(T), b
     double rho_w;             // wall ghost density
     double rho0;              // storage shift (F16S/BF16S)
+    CoefF32 cf;               // the coefficients above, rounded to FP32
     double* tau_w;            // [2][nx] wall shear of this step
     double* p_w;              // [2][nx] wall pressure of this step
     double* partial;          // [2][nstrip][kPartialVals] this step's per-strip wall extremes
+    unsigned long long* tickets;  // kTicketGroups counters, kTicketStride apart (pipelined schedule)
+    long long launch;         // launches since the counters were zeroed (pipelined schedule)
+    int pipe_blocks;          // grid of the pipelined schedule
     double* rho_out;          // emitted fields [ny][nx] (only read when emitting)
     double* vx_out;
     double* vy_out;
 };
 
 hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s);
+// Resident blocks of the pipelined kernel for this configuration: CUs times the
+// blocks one CU holds at once.
+hipError_t pipe_grid(int storage, int eos, int ty, int waves, int* blocks);
 hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, long long plane,
                        int storage, double rho0, hipStream_t s);
 hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);

@@ -55,18 +55,26 @@ struct CodecF64 {
     using S = double;
     using C = double;
     template <int I>
-    __device__ static C load(const S* p, C) { return *p; }
+    __device__ static C decode(S s, C) { return s; }
     template <int I>
-    __device__ static void store(S* p, C v, C) { *p = v; }
+    __device__ static C load(const S* p, C r) { return decode<I>(*p, r); }
+    template <int I>
+    __device__ static S encode(C v, C) { return v; }
+    template <int I>
+    __device__ static void store(S* p, C v, C r) { *p = encode<I>(v, r); }
 };
 
 struct CodecF32 {
     using S = float;
     using C = float;
     template <int I>
-    __device__ static C load(const S* p, C) { return *p; }
+    __device__ static C decode(S s, C) { return s; }
     template <int I>
-    __device__ static void store(S* p, C v, C) { *p = v; }
+    __device__ static C load(const S* p, C r) { return decode<I>(*p, r); }
+    template <int I>
+    __device__ static S encode(C v, C) { return v; }
+    template <int I>
+    __device__ static void store(S* p, C v, C r) { *p = encode<I>(v, r); }
 };
 
 // FP32 storage, FP64 arithmetic (same bytes per node as FP32).
@@ -74,19 +82,32 @@ struct CodecF32D {
     using S = float;
     using C = double;
     template <int I>
-    __device__ static C load(const S* p, C) { return double(*p); }
+    __device__ static C decode(S s, C) { return double(s); }
     template <int I>
-    __device__ static void store(S* p, C v, C) { *p = float(v); }
+    __device__ static C load(const S* p, C r) { return decode<I>(*p, r); }
+    template <int I>
+    __device__ static S encode(C v, C) { return float(v); }
+    template <int I>
+    __device__ static void store(S* p, C v, C r) { *p = encode<I>(v, r); }
 };
+
+// The shifted codecs below add and subtract w_i rho0 with explicit FMAs, so
+// both directions use the same exact product: a load/store round trip carries
+// no systematic offset (with one side contracted and the other not, every step
+// would add the product's rounding error to each population, a mass drift).
 
 // FP32 storage of f_i - w_i rho0, FP32 arithmetic.
 struct CodecF32S {
     using S = float;
     using C = float;
     template <int I>
-    __device__ static C load(const S* p, C rho0) { return *p + wgt<float>(I) * rho0; }
+    __device__ static C decode(S s, C rho0) { return __builtin_fmaf(wgt<float>(I), rho0, s); }
     template <int I>
-    __device__ static void store(S* p, C v, C rho0) { *p = v - wgt<float>(I) * rho0; }
+    __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
+    template <int I>
+    __device__ static S encode(C v, C rho0) { return __builtin_fmaf(-wgt<float>(I), rho0, v); }
+    template <int I>
+    __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
 };
 
 // FP16 storage of f_i - w_i rho0, FP32 arithmetic, round-to-nearest-even.
@@ -94,9 +115,13 @@ struct CodecF16S {
     using S = _Float16;
     using C = float;
     template <int I>
-    __device__ static C load(const S* p, C rho0) { return static_cast<float>(*p) + wgt<float>(I) * rho0; }
+    __device__ static C decode(S s, C rho0) { return __builtin_fmaf(wgt<float>(I), rho0, static_cast<float>(s)); }
     template <int I>
-    __device__ static void store(S* p, C v, C rho0) { *p = static_cast<_Float16>(v - wgt<float>(I) * rho0); }
+    __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
+    template <int I>
+    __device__ static S encode(C v, C rho0) { return static_cast<_Float16>(__builtin_fmaf(-wgt<float>(I), rho0, v)); }
+    template <int I>
+    __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
 };
 
 // BF16 storage of f_i - w_i rho0, FP32 arithmetic, round-to-nearest-even.
@@ -104,15 +129,19 @@ struct CodecBF16S {
     using S = uint16_t;
     using C = float;
     template <int I>
-    __device__ static C load(const S* p, C rho0) {
-        return __uint_as_float(static_cast<uint32_t>(*p) << 16) + wgt<float>(I) * rho0;
+    __device__ static C decode(S s, C rho0) {
+        return __builtin_fmaf(wgt<float>(I), rho0, __uint_as_float(static_cast<uint32_t>(s) << 16));
     }
     template <int I>
-    __device__ static void store(S* p, C v, C rho0) {
-        uint32_t u = __float_as_uint(v - wgt<float>(I) * rho0);
+    __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
+    template <int I>
+    __device__ static S encode(C v, C rho0) {
+        uint32_t u = __float_as_uint(__builtin_fmaf(-wgt<float>(I), rho0, v));
         u += 0x7FFFu + ((u >> 16) & 1u);
-        *p = static_cast<uint16_t>(u >> 16);
+        return static_cast<uint16_t>(u >> 16);
     }
+    template <int I>
+    __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
 };
 
 // ---------------------------------------------------------------------------
@@ -124,6 +153,16 @@ __device__ inline float recip(float x) {
     return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
 }
 __device__ inline double recip(double x) { return 1.0 / x; }
+
+// A step coefficient in the arithmetic type: the FP64 value, or its FP32
+// rounding made on the host (the same value a conversion here would give).
+template <class C>
+__device__ inline C coef(double d, float f);
+template <>
+__device__ inline double coef<double>(double d, float) { return d; }
+template <>
+__device__ inline float coef<float>(double, float f) { return f; }
+#define LBM_COEF(C, name) coef<C>(a.name, a.cf.name)
 
 // x-neighbours across the 64 lanes of a wave with DPP wave shifts (a VALU
 // operand modifier, no LDS traffic): wave_shl:1 reads lane + 1 (column x + 1),
@@ -262,6 +301,63 @@ __device__ inline S* at_bytes(S* base, uint32_t off) {
     return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (uint64_t)off);
 }
 
+// Raw buffer stores (a 128-bit resource in SGPRs, a 32-bit byte offset per
+// lane).  The hardware range check drops a store whose offset is at or beyond
+// the resource's size, so lanes that must not write are given kOobOffset
+// instead of being masked off by a branch: the store sequence is then the same
+// on every path, which keeps the compiler's load/store counter waits exact.
+// Valid only while the buffer is smaller than 2 GiB, so that valid offsets stay
+// below kOobOffset and kOobOffset plus any direction offset does not wrap.
+constexpr uint32_t kOobOffset = 0x80000000u;
+constexpr int kRawBufferWord3 = 0x00020000;  // 32-bit data format, no swizzle (gfx9 family)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, kRawBufferWord3);
+}
+// soff is a uniform (SGPR) byte offset added to the lane offset off.
+__device__ inline void buffer_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, 0);
+}
+__device__ inline void buffer_store(float v, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, soff, 0);
+}
+__device__ inline void buffer_store(_Float16 v, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, soff, 0);
+}
+__device__ inline void buffer_store(uint16_t v, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, off, soff, 0);
+}
+template <class S>
+__device__ inline S buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff);
+template <>
+__device__ inline double buffer_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
+template <>
+__device__ inline float buffer_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+template <>
+__device__ inline _Float16 buffer_load<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0));
+}
+template <>
+__device__ inline uint16_t buffer_load<uint16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+}
+
+// Interior pull through a buffer resource: one lane offset per node and the
+// nine uniform source offsets (direction plane minus the source displacement)
+// in SGPRs, so the nine loads need no per-lane address arithmetic.
+template <class CD>
+__device__ inline void pull_interior_buf(__amdgpu_buffer_rsrc_t rin, const uint32_t (&dir_off)[9], uint32_t node_off,
+                                         typename CD::C rho0, typename CD::C (&f)[9]) {
+    using S = typename CD::S;
+#define LBM_PULLB(I) f[I] = CD::template decode<I>(buffer_load<S>(rin, node_off, dir_off[I]), rho0);
+    LBM_PULLB(0) LBM_PULLB(1) LBM_PULLB(2) LBM_PULLB(3) LBM_PULLB(4) LBM_PULLB(5) LBM_PULLB(6) LBM_PULLB(7) LBM_PULLB(8)
+#undef LBM_PULLB
+}
+
 // Interior fast path: every source is in range, no boundary logic.  dir_off[I]
 // is the uniform byte offset of population I's source relative to the node.
 template <class CD>
@@ -275,8 +371,8 @@ __device__ inline void pull_interior(const typename CD::S* __restrict__ fin, con
 // MRT collision (eq. 2.1) in the Lallemand-Luo basis (rho, e, eps, jx, qx, jy, qy, pxx, pxy)
 // with m_eq = M f_eq(rho, u_eq), eq. 2.2, and f* = f - M^-1 S (m - m_eq), M^-1 = M^T diag(1/|row|^2).
 template <class C>
-__device__ inline void collide(C (&f)[9], C rho, C jx, C jy, C Fx, C Fy, C inv_rho, const StepArgs& a,
-                               C tau, C s_e, C s_eps, C s_q, C s_j, C s_v, C& vx, C& vy) {
+__device__ inline void collide(C (&f)[9], C rho, C jx, C jy, C Fx, C Fy, C inv_rho, C tau, C s_e, C s_eps, C s_q,
+                               C s_j, C s_v, C& vx, C& vy) {
     // P = rho u_eq = j + tau F exactly (velocity shift of Sec. 2.2); the reciprocal
     // of rho only enters the second-order terms, so mass and momentum updates do
     // not depend on its rounding.
@@ -402,7 +498,7 @@ struct Stepper {
             const C jy = (f2[2] - f2[4]) + (f2[5] - f2[8]) + (f2[6] - f2[7]);
             const C inv_rho = recip(rh);
             C vx, vy;
-            collide<C>(W.f2, rh, jx, jy, Fx, Fy, inv_rho, a, tau, s_e, s_eps, s_q, s_j, s_v, vx, vy);
+            collide<C>(W.f2, rh, jx, jy, Fx, Fy, inv_rho, tau, s_e, s_eps, s_q, s_j, s_v, vx, vy);
             if (out_lane) {
                 const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
 #define LBM_STORE(I) CD::template store<I>(at_bytes(fout, o + uint32_t(I) * plane_bytes), W.f2[I], rho0);
@@ -492,9 +588,10 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         st.dir_off[i] = uint32_t(i) * st.plane_bytes - uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(typename CD::S));
-    st.rho0 = C(a.rho0); st.RT = C(a.RT); st.a_eff = C(a.a_eff); st.bb = C(a.b); st.k2 = C(a.k2);
-    st.kappa = C(a.kappa); st.g = C(a.g); st.tau = C(a.tau); st.s_e = C(a.s_e); st.s_eps = C(a.s_eps);
-    st.s_q = C(a.s_q); st.s_j = C(a.s_j); st.s_v = C(a.s_v); st.rho_w = C(a.rho_w); st.nu = C(a.nu);
+    st.rho0 = LBM_COEF(C, rho0); st.RT = LBM_COEF(C, RT); st.a_eff = LBM_COEF(C, a_eff);
+    st.bb = LBM_COEF(C, b); st.k2 = LBM_COEF(C, k2); st.kappa = LBM_COEF(C, kappa); st.g = LBM_COEF(C, g);
+    st.tau = LBM_COEF(C, tau); st.s_e = LBM_COEF(C, s_e); st.s_eps = LBM_COEF(C, s_eps); st.s_q = LBM_COEF(C, s_q);
+    st.s_j = LBM_COEF(C, s_j); st.s_v = LBM_COEF(C, s_v); st.rho_w = LBM_COEF(C, rho_w); st.nu = LBM_COEF(C, nu);
 
     const int y0 = chunk * a.ty;
     const bool last = chunk == a.nchunk - 1;
@@ -546,13 +643,13 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
 // Tiles are TYO rows apart; the last one is moved down to end at row ny - 1, so
 // every tile has TYO output rows and the two rows next to a wall share a tile
 // (rows covered by two tiles are computed identically by both).
-template <class CD, int EOS, bool EMIT, int TYO>
-__global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
+template <class CD, int EOS, bool EMIT, int TYO, int NW>
+__global__ __launch_bounds__(64 * NW) void tile_kernel(const StepArgs a) {
     using S = typename CD::S;
     using C = typename CD::C;
-    constexpr int H = TYO + 4;   // tile rows including the halo
-    constexpr int RPT = H / 4;   // rows per thread
-    static_assert(H % 4 == 0, "tile height");
+    constexpr int H = TYO + 4;    // tile rows including the halo
+    constexpr int RPT = H / NW;   // rows per thread
+    static_assert(H % NW == 0, "tile height must be a multiple of the waves per block");
     __shared__ C sRho[H][64], sPhi[H][64], sLap[H][64];
     __shared__ C sWv[4][64], sWr[2][64], sWp[2][64];  // wall rows: vx (0, 1, ny-2, ny-1), rho and p_w (0, ny-1)
 
@@ -580,22 +677,24 @@ __global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
     uint32_t dir_off[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) dir_off[i] = uint32_t(i) * plane_bytes - uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(S));
-    const C rho0 = C(a.rho0);
-    const C RT = C(a.RT), a_eff = C(a.a_eff), bb = C(a.b), k2 = C(a.k2), kappa = C(a.kappa), g = C(a.g);
-    const C rho_w = C(a.rho_w);
+    const C rho0 = LBM_COEF(C, rho0);
+    const C RT = LBM_COEF(C, RT), a_eff = LBM_COEF(C, a_eff), bb = LBM_COEF(C, b);
+    const C k2 = LBM_COEF(C, k2), kappa = LBM_COEF(C, kappa), g = LBM_COEF(C, g);
+    const C rho_w = LBM_COEF(C, rho_w);
 
     // ---- phase A: pull, density, EOS field -------------------------------------
     C f[RPT][9];
     if (tile_inner) {
+        const __amdgpu_buffer_rsrc_t rin = buffer_rsrc(const_cast<S*>(fin), 9u * plane_bytes);
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            const int r = y0 - 2 + wave + 4 * j;
-            pull_interior<CD>(fin, dir_off, uint32_t(r * a.pitch + xe) * uint32_t(sizeof(S)), rho0, f[j]);
+            const int r = y0 - 2 + wave + NW * j;
+            pull_interior_buf<CD>(rin, dir_off, uint32_t(r * a.pitch + xe) * uint32_t(sizeof(S)), rho0, f[j]);
         }
     } else {
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            const int r = y0 - 2 + wave + 4 * j;
+            const int r = y0 - 2 + wave + NW * j;
             if (a.yper || (r >= 0 && r < a.ny))
                 pull_generic<CD>(fin, a, xe, a.yper ? wrapi(r, a.ny) : r, rho0, f[j]);
             else {
@@ -606,7 +705,7 @@ __global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
     }
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        const int k = wave + 4 * j;
+        const int k = wave + NW * j;
         const int r = y0 - 2 + k;
         const bool fluid = tile_inner || a.yper || (r >= 0 && r < a.ny);
         const C rho = fluid ? ((f[j][0] + f[j][1]) + (f[j][2] + f[j][3])) + ((f[j][4] + f[j][5]) + (f[j][6] + f[j][7])) + f[j][8]
@@ -620,7 +719,7 @@ __global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
     // ---- phase B: Laplacian on rows 1 .. H-2 ------------------------------------
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        const int k = wave + 4 * j;
+        const int k = wave + NW * j;
         if (k >= 1 && k <= H - 2) {
             const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
             const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
@@ -632,9 +731,10 @@ __global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
 
     // ---- phase C: force, collision, store -----------------------------------------
     const bool wall_tile = walls && (y0 == 0 || y0 + TYO >= a.ny);
+    const __amdgpu_buffer_rsrc_t rout = buffer_rsrc(fout, 9u * plane_bytes);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        const int k = wave + 4 * j;
+        const int k = wave + NW * j;
         const int y = y0 - 2 + k;
         if (k < 2 || k > H - 3 || y >= a.ny) continue;  // halo row (wave-uniform)
         C gphx, gphy, glx, gly;
@@ -657,11 +757,11 @@ __global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
         const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
         const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
         C vx, vy;
-        collide<C>(f[j], rh, jx, jy, Fx, Fy, recip(rh), a, C(a.tau), C(a.s_e), C(a.s_eps), C(a.s_q), C(a.s_j),
-                   C(a.s_v), vx, vy);
+        collide<C>(f[j], rh, jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
+                   LBM_COEF(C, s_q), LBM_COEF(C, s_j), LBM_COEF(C, s_v), vx, vy);
         if (out_lane) {
             const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
-#define LBM_TSTORE(I) CD::template store<I>(at_bytes(fout, o + uint32_t(I) * plane_bytes), f[j][I], rho0);
+#define LBM_TSTORE(I) buffer_store(CD::template encode<I>(f[j][I], rho0), rout, o, uint32_t(I) * plane_bytes);
             LBM_TSTORE(0) LBM_TSTORE(1) LBM_TSTORE(2) LBM_TSTORE(3) LBM_TSTORE(4) LBM_TSTORE(5) LBM_TSTORE(6)
             LBM_TSTORE(7) LBM_TSTORE(8)
 #undef LBM_TSTORE
@@ -700,7 +800,7 @@ __global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
         const int w = wave;
         // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
         const C v_half = sWv[w == 0 ? 0 : 3][lane], v_3half = sWv[w == 0 ? 1 : 2][lane];
-        const C tw = sWr[w][lane] * C(a.nu) * (C(9) * v_half - v_3half) * C(1.0 / 3.0);
+        const C tw = sWr[w][lane] * LBM_COEF(C, nu) * (C(9) * v_half - v_3half) * C(1.0 / 3.0);
         const double dt = out_lane ? double(tw) : 0.0, dpw = out_lane ? double(sWp[w][lane]) : 0.0;
         if (out_lane) {
             a.tau_w[w * a.nx + x] = dt;
@@ -720,6 +820,298 @@ __global__ __launch_bounds__(256) void tile_kernel(const StepArgs a) {
             o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
             o[8] = s2;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined persistent tile schedule.  Same tiles and phases as tile_kernel,
+// but each block stays resident and takes tile after tile, and the populations
+// of its next tile are in flight while the current one is computed:
+//
+//   A(t)   rho, phi of tile t into LDS buffer (t's loads must have landed)
+//   sync   the ticket of tile t+1 is visible; t+1's loads are issued
+//   B(t)   Laplacian into LDS
+//   sync
+//   C(t)   force, collision and stores while t+1's loads are in flight
+//   D(t)   wall tiles only
+//
+// rho and phi are double-buffered in LDS, so A(t+1) may start while slower
+// waves still read tile t's values in C(t).  Wave w keeps output rows
+// 2 + w + NW j (j < TYO / NW) in registers; waves 0..3 also pull one halo row
+// each (rows 0, 1, H-2, H-1), which only feeds rho and phi.
+//
+// Tickets.  The tiles (row-major over strips) are cut into 8 contiguous ranges;
+// blocks with blockIdx % 8 == g share counter g and walk range g, so with
+// round-robin dispatch every XCD works through its own band of rows and keeps
+// the shared halo rows in its L2.  Every block draws tickets until it draws one
+// past the end of its range, so a launch consumes exactly (tiles of the range +
+// blocks of the group) tickets and launch L of a run starts at L times that
+// count; the host zeroes the counters before each run of launches.  A block
+// draws the ticket of its tile after next while it computes, so the atomic's
+// latency is hidden as well.  The order in which tiles are taken does not
+// change any result: a tile reads only fin and writes only its own outputs.
+template <class CD, int EOS, bool EMIT, int TYO, int NW>
+struct Pipe {
+    using S = typename CD::S;
+    using C = typename CD::C;
+    static constexpr int H = TYO + 4;                       // tile rows including the halo
+    static constexpr int ORW = TYO / NW;                    // output rows per wave
+    static constexpr int LRW = (TYO + 2 + NW - 1) / NW;     // Laplacian rows per wave
+    static_assert(TYO % NW == 0 && NW >= 4, "tile rows must be a multiple of the waves, at least 4 waves");
+
+    struct Smem {
+        C rho[2][H][64], phi[2][H][64], lap[H][64];
+        C wv[4][64], wr[2][64], wp[2][64];  // wall rows: vx (0, 1, ny-2, ny-1), rho and p_w (0, ny-1)
+        int first, next;                    // broadcast tickets
+    };
+
+    struct Geom {
+        int y0, x0, strip;
+        bool inner, wall;
+    };
+
+    __device__ static Geom geom(const StepArgs& a, int t) {
+        Geom g;
+        const int tr = t / a.nstrip;
+        g.strip = t - tr * a.nstrip;
+        g.y0 = (a.ny >= TYO) ? min(tr * TYO, a.ny - TYO) : 0;
+        g.x0 = g.strip * kStripOut;
+        // every pulled source of the tile (rows y0-3 .. y0+TYO+2, columns x0-3 .. x0+62) is in range
+        g.inner = (g.x0 - 3 >= 0) && (g.x0 + 62 <= a.nx - 1) && (g.y0 - 3 >= 0) && (g.y0 + TYO + 2 <= a.ny - 1);
+        g.wall = !a.yper && (g.y0 == 0 || g.y0 + TYO >= a.ny);
+        return g;
+    }
+    __device__ static int halo_k(int w) { return w < 2 ? w : H - 4 + w; }  // waves 0..3: rows 0, 1, H-2, H-1
+
+    __device__ static int edge_x(const StepArgs& a, int x) {
+        if (x < 0 || x >= a.nx) x = a.xper ? wrapi(x, a.nx) : clampi(x, 0, a.nx - 1);
+        return x;
+    }
+
+    __device__ static void row_generic(const S* __restrict__ fin, const StepArgs& a, int xe, int r, C rho0, C (&f)[9]) {
+        if (a.yper || (r >= 0 && r < a.ny)) {
+            pull_generic<CD>(fin, a, xe, a.yper ? wrapi(r, a.ny) : r, rho0, f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = 0;
+        }
+    }
+
+    // Issues the loads of tile g's rows owned by wave w.
+    __device__ static void issue(const S* __restrict__ fin, const StepArgs& a, const uint32_t (&dir_off)[9], const Geom& g,
+                                 int w, int lane, C rho0, C (&fo)[ORW][9], C (&fh)[9]) {
+        const int xe = edge_x(a, g.x0 - 2 + lane);
+        if (g.inner) {
+#pragma unroll
+            for (int j = 0; j < ORW; ++j)
+                pull_interior<CD>(fin, dir_off, uint32_t((g.y0 + w + NW * j) * a.pitch + xe) * uint32_t(sizeof(S)), rho0,
+                                  fo[j]);
+            if (w < 4)
+                pull_interior<CD>(fin, dir_off, uint32_t((g.y0 - 2 + halo_k(w)) * a.pitch + xe) * uint32_t(sizeof(S)),
+                                  rho0, fh);
+        } else {
+#pragma unroll
+            for (int j = 0; j < ORW; ++j) row_generic(fin, a, xe, g.y0 + w + NW * j, rho0, fo[j]);
+            if (w < 4) row_generic(fin, a, xe, g.y0 - 2 + halo_k(w), rho0, fh);
+        }
+    }
+
+    __device__ static C density(const Geom& g, const StepArgs& a, int r, const C (&f)[9], C rho_w) {
+        const bool fluid = g.inner || a.yper || (r >= 0 && r < a.ny);
+        return fluid ? ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8] : rho_w;
+    }
+
+    // One tile: phases A-D on the populations fc (loaded earlier), issuing the
+    // next tile's loads into fn.  Returns the next tile, or -1 when the range is done.
+    template <int BUF>
+    __device__ static int tile(Smem& sm, const StepArgs& a, const S* __restrict__ fin, S* __restrict__ fout,
+                               const uint32_t (&dir_off)[9], int t, int t0, int nt, unsigned long long* ctr,
+                               unsigned long long base, unsigned long long& tk, C (&fc)[ORW][9], C (&fn)[ORW][9],
+                               C (&fh)[9]) {
+        const int lane = threadIdx.x & 63;
+        const int w = threadIdx.x >> 6;
+        const Geom g = geom(a, t);
+        const int x = g.x0 - 2 + lane;
+        const bool out_lane = lane >= 2 && lane < 62 && x < a.nx;
+        const C rho0 = LBM_COEF(C, rho0), rho_w = LBM_COEF(C, rho_w);
+        const C RT = LBM_COEF(C, RT), a_eff = LBM_COEF(C, a_eff), bb = LBM_COEF(C, b);
+        const C k2 = LBM_COEF(C, k2), kappa = LBM_COEF(C, kappa), gx = LBM_COEF(C, g);
+        const int lm = lane > 0 ? lane - 1 : 0, lp = lane < 63 ? lane + 1 : 63;
+        auto& sRho = sm.rho[BUF];
+        auto& sPhi = sm.phi[BUF];
+        const uint32_t plane_bytes = uint32_t(a.plane) * uint32_t(sizeof(S));
+        const __amdgpu_buffer_rsrc_t rout = buffer_rsrc(fout, 9u * plane_bytes);
+
+        // ---- A: density and EOS field of the owned rows -------------------------
+#pragma unroll
+        for (int j = 0; j < ORW; ++j) {
+            const int k = 2 + w + NW * j;
+            const C rho = density(g, a, g.y0 - 2 + k, fc[j], rho_w);
+            sRho[k][lane] = rho;
+            sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+        }
+        if (w < 4) {
+            const int k = halo_k(w);
+            const C rho = density(g, a, g.y0 - 2 + k, fh, rho_w);
+            sRho[k][lane] = rho;
+            sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+        }
+        if (threadIdx.x == 0) sm.next = int(tk - base);
+        __syncthreads();
+
+        // ---- next tile: its ticket is known, issue its loads ------------------------
+        // unsigned: a ticket outside [0, nt) of any kind ends the block
+        const int tn = __builtin_amdgcn_readfirstlane(sm.next);
+        const bool more = unsigned(tn) < unsigned(nt);
+        if (more) {
+            if (threadIdx.x == 0) tk = atomicAdd(ctr, 1ull);  // ticket of the tile after next
+            issue(fin, a, dir_off, geom(a, t0 + tn), w, lane, rho0, fn, fh);
+        }
+
+        // ---- B: Laplacian on rows 1 .. H-2 ---------------------------------------------
+#pragma unroll
+        for (int j = 0; j < LRW; ++j) {
+            const int k = 1 + w + NW * j;
+            if (k <= H - 2) {
+                const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
+                const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
+                const Row3<C> n{sRho[k + 1][lane], sRho[k + 1][lp], sRho[k + 1][lm]};
+                sm.lap[k][lane] = lap3(s, m, n);
+            }
+        }
+        __syncthreads();
+
+        // ---- C: force, collision, store -------------------------------------------------
+#pragma unroll
+        for (int j = 0; j < ORW; ++j) {
+            const int k = 2 + w + NW * j;
+            const int y = g.y0 + w + NW * j;
+            const bool row_ok = g.inner || y < a.ny;  // false only when ny < TYO (wave-uniform)
+            C gphx, gphy, glx, gly;
+            {
+                const Row3<C> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
+                const Row3<C> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
+                const Row3<C> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
+                grad3(s, m, n, gphx, gphy);
+            }
+            {
+                const Row3<C> s{sm.lap[k - 1][lane], sm.lap[k - 1][lp], sm.lap[k - 1][lm]};
+                const Row3<C> m{sm.lap[k][lane], sm.lap[k][lp], sm.lap[k][lm]};
+                const Row3<C> n{sm.lap[k + 1][lane], sm.lap[k + 1][lp], sm.lap[k + 1][lm]};
+                grad3(s, m, n, glx, gly);
+            }
+            const C rh = sRho[k][lane];
+            const C Fx = -gphx + kappa * rh * glx + gx;
+            const C Fy = -gphy + kappa * rh * gly;
+            C* fj = fc[j];
+            const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
+            const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
+            C vx, vy;
+            collide<C>(fc[j], rh, jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
+                       LBM_COEF(C, s_q), LBM_COEF(C, s_j), LBM_COEF(C, s_v), vx, vy);
+            {
+                const uint32_t o = (out_lane && row_ok) ? uint32_t(y * a.pitch + x) * uint32_t(sizeof(S)) : kOobOffset;
+#define LBM_PSTORE(I) buffer_store(CD::template encode<I>(fc[j][I], rho0), rout, o + uint32_t(I) * plane_bytes);
+                LBM_PSTORE(0) LBM_PSTORE(1) LBM_PSTORE(2) LBM_PSTORE(3) LBM_PSTORE(4) LBM_PSTORE(5) LBM_PSTORE(6)
+                LBM_PSTORE(7) LBM_PSTORE(8)
+#undef LBM_PSTORE
+            }
+            if (EMIT && out_lane && row_ok) {
+                const long long c = (long long)y * a.nx + x;
+                a.rho_out[c] = double(rh);
+                a.vx_out[c] = double(vx);
+                a.vy_out[c] = double(vy);
+            }
+            if (g.wall) {
+                if (y == 0 || y == a.ny - 1) {
+                    // wall pressure: isotropic part of eq. 2.8 on the first fluid row
+                    const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
+                    const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
+                    const Row3<C> n{sRho[k + 1][lane], sRho[k + 1][lp], sRho[k + 1][lm]};
+                    C grx, gry;
+                    grad3(s, m, n, grx, gry);
+                    const int wi = (y == 0) ? 0 : 1;
+                    sm.wp[wi][lane] = k2 * p0_of<EOS, C>(rh, RT, a_eff, bb) - kappa * rh * sm.lap[k][lane]
+                                    - C(0.5) * kappa * (grx * grx + gry * gry);
+                    sm.wr[wi][lane] = rh;
+                }
+                if (y == 0) sm.wv[0][lane] = vx;
+                if (y == 1) sm.wv[1][lane] = vx;
+                if (y == a.ny - 2) sm.wv[2][lane] = vx;
+                if (y == a.ny - 1) sm.wv[3][lane] = vx;
+            }
+        }
+
+        // ---- D: wall shear and the per-strip extremes (wall tiles only) -------------------
+        if (g.wall) {  // block-uniform
+            __syncthreads();
+            const bool has_bottom = (g.y0 == 0), has_top = (g.y0 + TYO >= a.ny);
+            if ((w == 0 && has_bottom) || (w == 1 && has_top)) {
+                // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
+                const C v_half = sm.wv[w == 0 ? 0 : 3][lane], v_3half = sm.wv[w == 0 ? 1 : 2][lane];
+                const C tw = sm.wr[w][lane] * LBM_COEF(C, nu) * (C(9) * v_half - v_3half) * C(1.0 / 3.0);
+                const double dt = out_lane ? double(tw) : 0.0, dpw = out_lane ? double(sm.wp[w][lane]) : 0.0;
+                if (out_lane) {
+                    a.tau_w[w * a.nx + x] = dt;
+                    a.p_w[w * a.nx + x] = dpw;
+                }
+                double tmax = out_lane ? dt : -INFINITY, tmin = out_lane ? dt : INFINITY;
+                double pmax = out_lane ? dpw : -INFINITY, pmin = out_lane ? dpw : INFINITY;
+                int xtmax = out_lane ? x : 0x7fffffff, xtmin = xtmax, xpmax = xtmax, xpmin = xtmax;
+                wave_argmax(tmax, xtmax);
+                wave_argmin(tmin, xtmin);
+                wave_argmax(pmax, xpmax);
+                wave_argmin(pmin, xpmin);
+                const double s2 = wave_sum(dt * dt);
+                if (lane == 0) {
+                    double* o = a.partial + ((long long)w * a.nstrip + g.strip) * kPartialVals;
+                    o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
+                    o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
+                    o[8] = s2;
+                }
+            }
+        }
+        return more ? t0 + tn : -1;
+    }
+};
+
+template <class CD, int EOS, bool EMIT, int TYO, int NW>
+__global__ __launch_bounds__(64 * NW) void pipe_kernel(const StepArgs a) {
+    using P = Pipe<CD, EOS, EMIT, TYO, NW>;
+    using S = typename CD::S;
+    using C = typename CD::C;
+    __shared__ typename P::Smem sm;
+
+    const int grp = blockIdx.x & 7;
+    const int nb = (int(gridDim.x) - grp + 7) >> 3;  // blocks in this group
+    const int ntiles = a.nstrip * ((a.ny + TYO - 1) / TYO);
+    const int t0 = int(((long long)ntiles * grp) >> 3), t1 = int(((long long)ntiles * (grp + 1)) >> 3);
+    const int nt = t1 - t0;
+    unsigned long long* ctr = a.tickets + grp * kTicketStride;
+    const unsigned long long base = (unsigned long long)a.launch * (unsigned long long)(nt + nb);
+
+    if (threadIdx.x == 0) sm.first = int(atomicAdd(ctr, 1ull) - base);
+    __syncthreads();
+    const int first = __builtin_amdgcn_readfirstlane(sm.first);
+    if (unsigned(first) >= unsigned(nt)) return;  // block-uniform: this block drew its one past-the-end ticket
+
+    const S* __restrict__ fin = static_cast<const S*>(a.fin);
+    S* __restrict__ fout = static_cast<S*>(a.fout);
+    const uint32_t plane_bytes = uint32_t(a.plane) * uint32_t(sizeof(S));
+    uint32_t dir_off[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dir_off[i] = uint32_t(i) * plane_bytes - uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(S));
+
+    unsigned long long tk = 0;
+    if (threadIdx.x == 0) tk = atomicAdd(ctr, 1ull);  // ticket of the second tile, before the first's loads
+    C fa[P::ORW][9], fb[P::ORW][9], fh[9];
+    int t = t0 + first;
+    P::issue(fin, a, dir_off, P::geom(a, t), threadIdx.x >> 6, threadIdx.x & 63, LBM_COEF(C, rho0), fa, fh);
+    for (;;) {
+        t = P::template tile<0>(sm, a, fin, fout, dir_off, t, t0, nt, ctr, base, tk, fa, fb, fh);
+        if (t < 0) break;
+        t = P::template tile<1>(sm, a, fin, fout, dir_off, t, t0, nt, ctr, base, tk, fb, fa, fh);
+        if (t < 0) break;
     }
 }
 
@@ -893,24 +1285,57 @@ __global__ void wall_integrate_kernel(const double* __restrict__ scratch, int ns
     acc[1] = is;
 }
 
-template <class CD, int EOS, int TYO>
+template <class CD, int EOS, int TYO, int NW>
 hipError_t launch_tile(const StepArgs& a, bool emit, hipStream_t s) {
-    const dim3 grid(a.nstrip * ((a.ny + TYO - 1) / TYO)), block(256);
+    const dim3 grid(a.nstrip * ((a.ny + TYO - 1) / TYO)), block(64 * NW);
     if (emit)
-        hipLaunchKernelGGL((tile_kernel<CD, EOS, true, TYO>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((tile_kernel<CD, EOS, true, TYO, NW>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((tile_kernel<CD, EOS, false, TYO>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((tile_kernel<CD, EOS, false, TYO, NW>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <class CD, int EOS, int TYO, int NW>
+hipError_t launch_pipe(const StepArgs& a, bool emit, hipStream_t s) {
+    const dim3 grid(a.pipe_blocks), block(64 * NW);
+    if (emit)
+        hipLaunchKernelGGL((pipe_kernel<CD, EOS, true, TYO, NW>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((pipe_kernel<CD, EOS, false, TYO, NW>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 template <class CD, int EOS>
 hipError_t launch_step_t(const StepArgs& a, bool emit, hipStream_t s) {
-    if (a.schedule == kScheduleTile) {
+    if (a.schedule == kSchedulePipe) {
+        if (a.tile_waves == 8) {
+            switch (a.ty) {
+                case 8: return launch_pipe<CD, EOS, 8, 8>(a, emit, s);
+                case 16: return launch_pipe<CD, EOS, 16, 8>(a, emit, s);
+                default: return hipErrorInvalidValue;
+            }
+        }
         switch (a.ty) {
-            case 8: return launch_tile<CD, EOS, 8>(a, emit, s);
-            case 12: return launch_tile<CD, EOS, 12>(a, emit, s);
-            case 20: return launch_tile<CD, EOS, 20>(a, emit, s);
-            case 28: return launch_tile<CD, EOS, 28>(a, emit, s);
+            case 4: return launch_pipe<CD, EOS, 4, 4>(a, emit, s);
+            case 8: return launch_pipe<CD, EOS, 8, 4>(a, emit, s);
+            case 12: return launch_pipe<CD, EOS, 12, 4>(a, emit, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (a.schedule == kScheduleTile) {
+        if (a.tile_waves == 8) {
+            switch (a.ty) {
+                case 12: return launch_tile<CD, EOS, 12, 8>(a, emit, s);
+                case 20: return launch_tile<CD, EOS, 20, 8>(a, emit, s);
+                case 28: return launch_tile<CD, EOS, 28, 8>(a, emit, s);
+                default: return hipErrorInvalidValue;
+            }
+        }
+        switch (a.ty) {
+            case 8: return launch_tile<CD, EOS, 8, 4>(a, emit, s);
+            case 12: return launch_tile<CD, EOS, 12, 4>(a, emit, s);
+            case 20: return launch_tile<CD, EOS, 20, 4>(a, emit, s);
+            case 28: return launch_tile<CD, EOS, 28, 4>(a, emit, s);
             default: return hipErrorInvalidValue;
         }
     }
@@ -938,6 +1363,41 @@ hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipSt
         case LBM_BF16S: return launch_step_c<CodecBF16S>(a, eos, emit, s);
         case LBM_F32D: return launch_step_c<CodecF32D>(a, eos, emit, s);
         case LBM_F32S: return launch_step_c<CodecF32S>(a, eos, emit, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <class CD, int EOS>
+hipError_t pipe_grid_t(int ty, int waves, int* blocks) {
+    const void* k = nullptr;
+#define LBM_PK(T, W) reinterpret_cast<const void*>(&pipe_kernel<CD, EOS, false, T, W>)
+    if (waves == 8) k = ty == 8 ? LBM_PK(8, 8) : ty == 16 ? LBM_PK(16, 8) : nullptr;
+    else k = ty == 4 ? LBM_PK(4, 4) : ty == 8 ? LBM_PK(8, 4) : ty == 12 ? LBM_PK(12, 4) : nullptr;
+#undef LBM_PK
+    if (!k) return hipErrorInvalidValue;
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 64 * waves, 0);
+    if (e != hipSuccess) return e;
+    *blocks = (cus > 0 ? cus : 1) * (per > 0 ? per : 1);
+    return hipSuccess;
+}
+template <class CD>
+hipError_t pipe_grid_c(int eos, int ty, int waves, int* blocks) {
+    return eos == LBM_EOS_CS ? pipe_grid_t<CD, LBM_EOS_CS>(ty, waves, blocks) : pipe_grid_t<CD, LBM_EOS_PR>(ty, waves, blocks);
+}
+}  // namespace
+
+hipError_t pipe_grid(int storage, int eos, int ty, int waves, int* blocks) {
+    switch (storage) {
+        case LBM_F64: return pipe_grid_c<CodecF64>(eos, ty, waves, blocks);
+        case LBM_F32: return pipe_grid_c<CodecF32>(eos, ty, waves, blocks);
+        case LBM_F16S: return pipe_grid_c<CodecF16S>(eos, ty, waves, blocks);
+        case LBM_BF16S: return pipe_grid_c<CodecBF16S>(eos, ty, waves, blocks);
+        case LBM_F32D: return pipe_grid_c<CodecF32D>(eos, ty, waves, blocks);
+        case LBM_F32S: return pipe_grid_c<CodecF32S>(eos, ty, waves, blocks);
         default: return hipErrorInvalidValue;
     }
 }

@@ -76,7 +76,10 @@ def test_defaults(L):
 @pytest.mark.parametrize("bad", [
     dict(T_over_Tc=0.0), dict(a=-1.0), dict(b=0.0), dict(k=0.0), dict(kappa=-1.0), dict(s_e=2.0),
     dict(s_q=0.0), dict(check_every=0), dict(v_limit=0.0), dict(history_cap=0), dict(storage=7),
-    dict(eos=3), dict(x_periodic=2), dict(rho_wall=-1.0), dict(dp=math.inf),
+    dict(eos=3), dict(x_periodic=2), dict(rho_wall=-1.0), dict(dp=math.inf), dict(tile_waves=6),
+    dict(tile_waves=8, tile_rows=8), dict(schedule=0, tile_rows=16), dict(schedule=3), dict(schedule=2, tile_rows=20),
+    dict(schedule=2, tile_waves=8, tile_rows=12), dict(schedule=2, pipe_blocks=4), dict(pipe_blocks=64),
+    dict(schedule=1, tile_waves=4),
 ])
 def test_create_rejects_invalid_parameters(L, bad):
     with pytest.raises(L.LbmError) as e:
