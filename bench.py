@@ -111,6 +111,44 @@ def measured_traffic(storage: str):
     return t["bytes_per_launch"] if t.get("kernel_source_sha256_16") == kernel_hash() else None
 
 
+def size_sweep(storage: str) -> int:
+    """Step time against grid size (same physics as the timed workload): fits
+    t = t0 + bytes / B, separating the fixed cost of a launch from streaming."""
+    import torch
+
+    from paper_2103_08301_amd import Lattice, workloads
+
+    w = workloads.plug_large_stable(storage)
+    bpn = BYTES_PER_NODE[storage]
+    rows = []
+    for nx, ny in [(64, 16), (256, 64), (1024, 128), (2048, 256), (2048, 512), (4096, 256), (4096, 512),
+                   (4096, 640), (3072, 1024)]:
+        lat = Lattice(nx, ny, w["tau"], storage=storage, check_every=100000, **w["params"])
+        lat.init_plug(max(8, nx // 14), max(1, ny // 32), float("nan"), 1e-3, 2)
+        n = 2000 if nx * ny < 1e6 else 500
+        lat.step(50)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(n)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / n
+        rows.append((nx * ny * bpn, t))
+        print(json.dumps({"nx": nx, "ny": ny, "bytes_per_step": nx * ny * bpn, "us_per_step": round(t * 1e6, 3),
+                          "MLUPS": round(nx * ny / t / 1e6, 1)}), flush=True)
+        del lat
+    big = [(b, t) for b, t in rows if b >= 3e7]
+    if len(big) >= 2:
+        import numpy as np
+
+        b, t = np.array(big, dtype=float).T
+        slope, t0 = np.polyfit(b, t, 1)
+        print(json.dumps({"fit_over_bytes_ge_30MB": {"fixed_us": round(t0 * 1e6, 2),
+                                                    "stream_GBps": round(1 / slope / 1e9, 1)}}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +161,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes 10 times (counter calibration)")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="only time the step on grids from 64x16 to 3072x1024 (fixed per-launch cost vs bytes)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -156,6 +196,8 @@ def main() -> int:
               flush=True)
         return 0
     lbm.library()  # fail loudly if the HIP library is missing
+    if args.size_sweep:
+        return size_sweep(args.storage)
 
     make = {"large-stable": workloads.plug_large_stable, "large": workloads.plug_large,
             "out-of-cache": workloads.plug_out_of_cache}[args.workload]
