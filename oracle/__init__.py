@@ -64,6 +64,16 @@ class Summary(C.Structure):
         return out
 
 
+class Component(C.Structure):
+    _fields_ = [
+        ("first_cell", C.c_int64), ("cells", C.c_int32), ("wall", C.c_int32),
+        ("mass", C.c_double), ("excess_mass", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 _D = C.POINTER(C.c_double)
 
@@ -107,6 +117,9 @@ def lib():
             "orc_history": (C.c_int64, [C.c_void_p, C.POINTER(Summary), C.c_int64]),
             "orc_totals": (None, [C.c_void_p, _D, _D, _D]),
             "orc_interface": (C.c_int, [C.c_void_p, _D, _D, C.POINTER(C.c_int)]),
+            "orc_components_field": (C.c_int64, [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                                 C.c_int, C.POINTER(Component), C.c_int64]),
+            "orc_components": (C.c_int64, [C.c_void_p, C.c_double, C.c_int, C.POINTER(Component), C.c_int64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -119,6 +132,19 @@ def lib():
 def _ptr(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(_D)
+
+
+def components_field(rho: np.ndarray, threshold: float, rho_g: float = 0.0, connectivity: int = 4,
+                     x_periodic: int = 0, y_periodic: int = 0) -> list:
+    """Liquid components (rho > threshold) of an arbitrary field rho[ny][nx]."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    ny, nx = rho.shape
+    n = lib().orc_components_field(_ptr(rho), nx, ny, x_periodic, y_periodic, threshold, rho_g, connectivity, None, 0)
+    if n < 0:
+        raise ValueError(f"orc_components_field failed: {n}")
+    buf = (Component * max(n, 1))()
+    lib().orc_components_field(_ptr(rho), nx, ny, x_periodic, y_periodic, threshold, rho_g, connectivity, buf, n)
+    return [buf[i].as_dict() for i in range(n)]
 
 
 def params(**kw) -> Params:
@@ -299,3 +325,12 @@ class Sim:
         xr, xf, cols = C.c_double(), C.c_double(), C.c_int()
         lib().orc_interface(self._h, C.byref(xr), C.byref(xf), C.byref(cols))
         return xr.value, xf.value, cols.value
+
+    def components(self, threshold: float = math.nan, connectivity: int = 4) -> list:
+        """Liquid components of the current density (threshold NaN = (rho_g + rho_l) / 2)."""
+        n = lib().orc_components(self._h, threshold, connectivity, None, 0)
+        if n < 0:
+            raise RuntimeError(f"orc_components failed: {n}")
+        buf = (Component * max(n, 1))()
+        lib().orc_components(self._h, threshold, connectivity, buf, n)
+        return [buf[i].as_dict() for i in range(n)]

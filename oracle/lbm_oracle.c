@@ -851,3 +851,97 @@ int orc_interface(const orc_sim* s, double* x_rear, double* x_front, int* liquid
     free(c);
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * Liquid components (aerosol detection, Sec. 3.2-3.3).  A plain breadth-first
+ * flood fill: cells are visited in row-major order, each unvisited liquid cell
+ * seeds a new component (so components come out ordered by first cell), and
+ * the fill walks the 4 or 8 neighbours, wrapping across periodic edges.
+ * ------------------------------------------------------------------------- */
+
+/* Offset d of a coordinate from a reference, moved to the nearest image
+   (-n/2 <= d < n/2) when the direction is periodic. */
+static double nearest_image(int d, int n, int periodic) {
+    if (periodic) {
+        while (d < -n / 2) d += n;
+        while (d >= n - n / 2) d -= n;
+    }
+    return (double)d;
+}
+
+static double wrap_into(double v, int n) {
+    double r = fmod(v, (double)n);
+    return r < 0 ? r + n : r;
+}
+
+int64_t orc_components_field(const double* rho, int nx, int ny, int x_periodic, int y_periodic, double threshold,
+                             double rho_g, int connectivity, orc_component* out, int64_t cap) {
+    if (!rho || nx < 1 || ny < 1 || (connectivity != 4 && connectivity != 8) || cap < 0 || (cap > 0 && !out) ||
+        isnan(threshold))
+        return ORC_EINVAL;
+    const long n = (long)nx * ny;
+    unsigned char* seen = (unsigned char*)calloc((size_t)n, 1);
+    long* queue = (long*)malloc((size_t)n * sizeof(long));
+    if (!seen || !queue) {
+        free(seen);
+        free(queue);
+        return ORC_ENOMEM;
+    }
+    static const int dx8[8] = {1, -1, 0, 0, 1, -1, -1, 1};
+    static const int dy8[8] = {0, 0, 1, -1, 1, 1, -1, -1};
+    int64_t count = 0;
+    for (long seed = 0; seed < n; ++seed) {
+        if (seen[seed] || !(rho[seed] > threshold)) continue;
+        const int x0 = (int)(seed % nx), y0 = (int)(seed / nx);
+        orc_component c;
+        c.first_cell = seed;
+        c.cells = 0;
+        c.wall = 0;
+        c.mass = 0.0;
+        c.excess_mass = 0.0;
+        double sx = 0.0, sy = 0.0;
+        long head = 0, tail = 0;
+        queue[tail++] = seed;
+        seen[seed] = 1;
+        while (head < tail) {
+            const long cell = queue[head++];
+            const int x = (int)(cell % nx), y = (int)(cell / nx);
+            c.cells += 1;
+            c.mass += rho[cell];
+            c.excess_mass += rho[cell] - rho_g;
+            sx += nearest_image(x - x0, nx, x_periodic);
+            sy += nearest_image(y - y0, ny, y_periodic);
+            if (!y_periodic && (y == 0 || y == ny - 1)) c.wall = 1;
+            for (int k = 0; k < connectivity; ++k) {
+                int xn = x + dx8[k], yn = y + dy8[k];
+                if (xn < 0 || xn >= nx) {
+                    if (!x_periodic) continue;
+                    xn = (xn + nx) % nx;
+                }
+                if (yn < 0 || yn >= ny) {
+                    if (!y_periodic) continue;
+                    yn = (yn + ny) % ny;
+                }
+                const long nb = (long)yn * nx + xn;
+                if (!seen[nb] && rho[nb] > threshold) {
+                    seen[nb] = 1;
+                    queue[tail++] = nb;
+                }
+            }
+        }
+        c.cx = x_periodic ? wrap_into(x0 + sx / c.cells, nx) : x0 + sx / c.cells;
+        c.cy = y_periodic ? wrap_into(y0 + sy / c.cells, ny) : y0 + sy / c.cells;
+        if (count < cap) out[count] = c;
+        count += 1;
+    }
+    free(seen);
+    free(queue);
+    return count;
+}
+
+int64_t orc_components(const orc_sim* s, double threshold, int connectivity, orc_component* out, int64_t cap) {
+    if (isnan(threshold)) threshold = 0.5 * (s->rho_g + s->rho_l);
+    if (isnan(threshold)) return ORC_EINVAL;
+    return orc_components_field(s->rho, s->nx, s->ny, s->p.x_periodic, s->p.y_periodic, threshold, s->rho_g,
+                                connectivity, out, cap);
+}

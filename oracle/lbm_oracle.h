@@ -62,6 +62,18 @@ typedef struct {
 
 typedef struct orc_sim orc_sim;
 
+/* One 4- or 8-connected component of the cells with rho > threshold
+   (a liquid region; Sec. 3.2-3.3 call a detached one an aerosol droplet). */
+typedef struct {
+    int64_t first_cell;   /* smallest row-major index y * nx + x among its cells */
+    int32_t cells;        /* number of cells */
+    int32_t wall;         /* 1 if a cell lies on row 0 or row ny-1 and walls are present */
+    double mass;          /* sum of rho over its cells */
+    double excess_mass;   /* sum of (rho - rho_g) over its cells */
+    double cx, cy;        /* centroid; across a periodic direction each cell is taken at its
+                             nearest image to the first cell, and the mean wrapped into [0, n) */
+} orc_component;
+
 void   orc_params_default(orc_params* p);
 
 /* Equation of state (Sec. 2.2; eq. 2.18 for PR). */
@@ -100,6 +112,15 @@ void   orc_wall(const orc_sim* s, double* tau_bot, double* tau_top, double* p_bo
 int64_t orc_history(const orc_sim* s, orc_summary* buf, int64_t cap);
 void   orc_totals(const orc_sim* s, double* mass, double* momx, double* momy);
 int    orc_interface(const orc_sim* s, double* x_rear, double* x_front, int* liquid_columns);
+
+/* Components of an arbitrary field rho[ny][nx].  connectivity is 4 or 8;
+   x_periodic / y_periodic join the opposite edges (y_periodic also means there
+   are no walls).  Writes at most cap components, in increasing first_cell, and
+   returns how many there are (or a negative status). */
+int64_t orc_components_field(const double* rho, int nx, int ny, int x_periodic, int y_periodic, double threshold,
+                             double rho_g, int connectivity, orc_component* out, int64_t cap);
+/* The same on the simulation's density, threshold NaN = (rho_g + rho_l) / 2. */
+int64_t orc_components(const orc_sim* s, double threshold, int connectivity, orc_component* out, int64_t cap);
 
 #ifdef __cplusplus
 }
