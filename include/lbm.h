@@ -110,6 +110,10 @@ typedef struct {
     double sum_tau2;                     /* sum over both walls and all x of tau_w^2 */
     double int_peak_tau2;                /* running sum over steps of max over walls and x of tau_w^2 */
     double int_tau2;                     /* running sum over steps of sum_tau2 */
+    double run_tau_max[2], run_tau_min[2];  /* extremes over x and over steps 1..step since the
+                                               initialisation: run_*_max - run_*_min is the span of
+                                               wall stress over a rupture (Sec. 3.2-3.3) */
+    double run_p_max[2], run_p_min[2];
 } lbm_stress_summary;
 
 /* Result of the latest stability/interface check. */
@@ -189,6 +193,48 @@ lbm_status lbm_stress_history(lbm_ctx* ctx, lbm_stress_summary* buf, int64_t cap
 
 /* Result of the latest stability/interface check. */
 lbm_status lbm_check_state(const lbm_ctx* ctx, lbm_check_result* out);
+
+/* One connected region of liquid cells (rho > threshold) of a density field.
+   Sec. 3.2 and 3.3 of the paper follow the droplets that break away from the
+   plug and the wall films during rupture ("aerosols") and their mass; here an
+   aerosol is a component with no cell on a wall row. */
+typedef struct {
+    int64_t first_cell;  /* smallest row-major index y * nx + x among its cells (identifies it) */
+    int32_t cells;       /* number of cells */
+    int32_t wall;        /* 1 when a cell lies on row 0 or row ny - 1 and the walls are present */
+    double mass;         /* sum of rho over its cells */
+    double excess_mass;  /* sum of (rho - rho_g) over its cells */
+    double cx, cy;       /* centroid; across a periodic direction each cell counts at its nearest
+                            image to the first cell, and the mean is wrapped into [0, n) */
+} lbm_component;
+
+typedef struct {
+    int64_t step;             /* step of the field (0 for lbm_components_field) */
+    int64_t components;       /* liquid components */
+    int64_t aerosols;         /* components with wall == 0 */
+    int64_t aerosol_cells;
+    double threshold;         /* the density threshold used */
+    double liquid_mass;       /* sum of rho over all liquid cells */
+    double aerosol_mass;      /* sum of mass over the aerosols */
+    double aerosol_excess_mass;
+} lbm_aerosol_summary;
+
+/* Liquid components of the density of the last step (as lbm_fields returns
+   it), labelled on the host after one copy of the field.  threshold NaN
+   selects (rho_g + rho_l) / 2; connectivity is 4 (edge neighbours) or 8 (and
+   corners); periodic ends (and periodic y) join opposite edges.  Writes the
+   first min(cap, count) components in increasing first_cell to out (out may
+   be NULL when cap is 0), the count to *n_out and the totals to *summary
+   (either may be NULL).  LBM_EINVAL for a bad connectivity or a threshold
+   that cannot be chosen (NaN above the critical temperature). */
+lbm_status lbm_components(lbm_ctx* ctx, double threshold, int connectivity, lbm_component* out, int64_t cap,
+                          int64_t* n_out, lbm_aerosol_summary* summary);
+
+/* The same on a caller-owned host field rho[ny][nx] (no context, no device);
+   y_periodic = 1 means there are no walls.  rho_g enters excess_mass only. */
+lbm_status lbm_components_field(const double* rho, int nx, int ny, int x_periodic, int y_periodic, double threshold,
+                                double rho_g, int connectivity, lbm_component* out, int64_t cap, int64_t* n_out,
+                                lbm_aerosol_summary* summary);
 
 /* Post-collision distributions as FP64 host arrays [9][ny][nx]
    (decoded from the storage type) / replaced from such an array (encoded with

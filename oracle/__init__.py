@@ -54,6 +54,8 @@ class Summary(C.Structure):
         ("x_tau_max", C.c_int32 * 2), ("x_tau_min", C.c_int32 * 2),
         ("x_p_max", C.c_int32 * 2), ("x_p_min", C.c_int32 * 2),
         ("sum_tau2", C.c_double), ("int_peak_tau2", C.c_double), ("int_tau2", C.c_double),
+        ("run_tau_max", C.c_double * 2), ("run_tau_min", C.c_double * 2),
+        ("run_p_max", C.c_double * 2), ("run_p_min", C.c_double * 2),
     ]
 
     def as_dict(self) -> dict:

@@ -429,6 +429,7 @@ struct orc_sim {
     int64_t hist_n, hist_cap;
     int64_t step, unstable_step;
     double int_peak_tau2, int_tau2;
+    double run[4][2];               /* running extremes: tau max, tau min, p max, p min per wall */
 };
 
 void orc_params_default(orc_params* p) {
@@ -541,6 +542,12 @@ static void set_equilibrium_state(orc_sim* s, const double* rho) {
     s->hist_n = 0;
     s->int_peak_tau2 = 0.0;
     s->int_tau2 = 0.0;
+    for (int w = 0; w < 2; ++w) {
+        s->run[0][w] = -INFINITY;
+        s->run[1][w] = INFINITY;
+        s->run[2][w] = -INFINITY;
+        s->run[3][w] = INFINITY;
+    }
     memset(s->tau_w, 0, 2 * (size_t)s->nx * sizeof(double));
     memset(s->p_w, 0, 2 * (size_t)s->nx * sizeof(double));
 }
@@ -726,6 +733,16 @@ static void stage_wall_diagnostics(orc_sim* s) {
     }
     s->int_peak_tau2 += peak2;
     s->int_tau2 += sum2;
+    for (int w = 0; w < 2; ++w) {
+        s->run[0][w] = fmax(s->run[0][w], sm.tau_max[w]);
+        s->run[1][w] = fmin(s->run[1][w], sm.tau_min[w]);
+        s->run[2][w] = fmax(s->run[2][w], sm.p_max[w]);
+        s->run[3][w] = fmin(s->run[3][w], sm.p_min[w]);
+        sm.run_tau_max[w] = s->run[0][w];
+        sm.run_tau_min[w] = s->run[1][w];
+        sm.run_p_max[w] = s->run[2][w];
+        sm.run_p_min[w] = s->run[3][w];
+    }
     sm.sum_tau2 = sum2;
     sm.int_peak_tau2 = s->int_peak_tau2;
     sm.int_tau2 = s->int_tau2;

@@ -58,6 +58,9 @@ typedef struct {
     double sum_tau2;                    /* sum over both walls and all x of tau_w^2 */
     double int_peak_tau2;               /* running sum over steps of max_{wall,x} tau_w^2 */
     double int_tau2;                    /* running sum over steps of sum_tau2 */
+    double run_tau_max[2], run_tau_min[2];  /* extremes over x and over steps 1..step (the
+                                               max - min spans of Sec. 3.2-3.3) */
+    double run_p_max[2], run_p_min[2];
 } orc_summary;
 
 typedef struct orc_sim orc_sim;

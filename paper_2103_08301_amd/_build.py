@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["lbm_api.cpp", "lbm_kernels.hip"]
+SOURCES = ["lbm_api.cpp", "lbm_post.cpp", "lbm_kernels.hip"]
 
 
 def hipcc() -> str:

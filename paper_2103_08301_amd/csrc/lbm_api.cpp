@@ -284,7 +284,10 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_vy), 0.0, nxy, c->stream));
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_tau), 0.0, 2LL * c->nx, c->stream));
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_pw), 0.0, 2LL * c->nx, c->stream));
-    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_acc), 0.0, 2, c->stream));
+    double* acc = c->at<double>(c->off_acc);
+    HIP_TRY(c, lbm::launch_fill(acc, 0.0, 2, c->stream));
+    for (int q = 0; q < 4; ++q)  // running maxima start at -inf, minima at +inf
+        HIP_TRY(c, lbm::launch_fill(acc + 2 + 2 * q, (q % 2 == 0) ? -INFINITY : INFINITY, 2, c->stream));
     c->steps = 0;
     c->ring_fill = 0;
     c->ring_first_step = 1;
@@ -518,7 +521,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->off_ring = o; o += align256((size_t)kRingCap * 2 * c->nstrip * lbm::kPartialVals * sizeof(double));
     c->off_hist = o; o += align256((size_t)p->history_cap * sizeof(lbm_stress_summary));
     c->off_acc = o; o += 256;
-    c->off_wscr = o; o += align256((size_t)kRingCap * 2 * sizeof(double));
+    c->off_wscr = o; o += align256((size_t)kRingCap * lbm::kWallScratchVals * sizeof(double));
     c->off_red = o; o += align256((size_t)lbm::kFieldReduceBlocks * 5 * sizeof(double));
     c->off_redout = o; o += 256;
     c->off_colmin = o; o += align256((size_t)nx * sizeof(double));
@@ -789,6 +792,24 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
         if (s) return s;
         c->initialized = true;
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_components(lbm_ctx* c, double threshold, int connectivity, lbm_component* out, int64_t cap,
+                          int64_t* n_out, lbm_aerosol_summary* summary) {
+    if (!c) return LBM_EINVAL;
+    if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    if (std::isnan(threshold)) threshold = 0.5 * (c->rho_g + c->rho_l);
+    if (std::isnan(threshold)) return fail(c, LBM_EINVAL, "no coexistence densities above Tc: give a threshold");
+    std::vector<double> rho((size_t)c->nx * c->ny);
+    HIP_TRY(c, hipMemcpyAsync(rho.data(), c->dev + c->off_rho, rho.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double rho_g = std::isnan(c->rho_g) ? 0.0 : c->rho_g;
+    lbm_status s = lbm::label_components(rho.data(), c->nx, c->ny, c->p.x_periodic == 1, c->p.y_periodic == 1,
+                                         threshold, rho_g, connectivity, out, cap, n_out, summary);
+    if (s) return fail(c, s, "lbm_components: connectivity must be 4 or 8 and cap >= 0");
+    if (summary) summary->step = c->steps;
     return LBM_OK;
 }
 

@@ -71,11 +71,19 @@ hipError_t launch_field_reduce(const double* rho, const double* vx, const double
 hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin, double* centre,
                               hipStream_t s);
 // Reduces the first `nsteps` slots of the per-strip partial ring (one wave per
-// step) into the history ring, then accumulates the running time integrals
-// acc[2] in step order.  scratch holds 2 doubles per step.
+// step) into the history ring, then accumulates the running time integrals and
+// running extremes acc[kWallAccVals] in step order.  scratch holds
+// kWallScratchVals doubles per step.
 hipError_t launch_wall_reduce(const double* partial_ring, int nsteps, int nstrip, int64_t first_step,
                               lbm_stress_summary* hist, int hist_cap, double* scratch, double* acc, hipStream_t s);
 
 constexpr int kFieldReduceBlocks = 512;
+constexpr int kWallScratchVals = 10;  // per step: peak tau^2, sum tau^2, tau max/min, p max/min per wall
+constexpr int kWallAccVals = 10;      // int peak tau^2, int sum tau^2, running tau max/min, p max/min per wall
+
+// Liquid components of a host density field (lbm_post.cpp).
+lbm_status label_components(const double* rho, int nx, int ny, bool xper, bool yper, double threshold, double rho_g,
+                            int connectivity, lbm_component* out, int64_t cap, int64_t* n_out,
+                            lbm_aerosol_summary* summary);
 
 }  // namespace lbm

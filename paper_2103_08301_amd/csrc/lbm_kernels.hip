@@ -1265,24 +1265,49 @@ __global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __re
         sm.int_peak_tau2 = 0.0;
         sm.int_tau2 = 0.0;
         hist[(sm.step - 1) % hist_cap] = sm;
-        scratch[2 * t] = pk;
-        scratch[2 * t + 1] = s2;
+        double* o = scratch + (long long)t * kWallScratchVals;
+        o[0] = pk;
+        o[1] = s2;
+        for (int w = 0; w < 2; ++w) {
+            o[2 + w] = sm.tau_max[w];
+            o[4 + w] = sm.tau_min[w];
+            o[6 + w] = sm.p_max[w];
+            o[8 + w] = sm.p_min[w];
+        }
     }
 }
 
-// Running time integrals, in step order (single thread: nsteps additions).
+// Running time integrals and running extremes, in step order (single thread).
+// acc: [0] int peak tau^2, [1] int sum tau^2, [2 + 2q + w] running extreme q
+// (tau max, tau min, p max, p min) of wall w.
 __global__ void wall_integrate_kernel(const double* __restrict__ scratch, int nsteps, int64_t first_step,
                                       lbm_stress_summary* hist, int hist_cap, double* acc) {
     double ip = acc[0], is = acc[1];
+    double run[8];
+    for (int q = 0; q < 8; ++q) run[q] = acc[2 + q];
     for (int k = 0; k < nsteps; ++k) {
-        ip += scratch[2 * k];
-        is += scratch[2 * k + 1];
+        const double* o = scratch + (long long)k * kWallScratchVals;
+        ip += o[0];
+        is += o[1];
+        for (int w = 0; w < 2; ++w) {
+            run[w] = fmax(run[w], o[2 + w]);
+            run[2 + w] = fmin(run[2 + w], o[4 + w]);
+            run[4 + w] = fmax(run[4 + w], o[6 + w]);
+            run[6 + w] = fmin(run[6 + w], o[8 + w]);
+        }
         lbm_stress_summary* h = &hist[(first_step + k - 1) % hist_cap];
         h->int_peak_tau2 = ip;
         h->int_tau2 = is;
+        for (int w = 0; w < 2; ++w) {
+            h->run_tau_max[w] = run[w];
+            h->run_tau_min[w] = run[2 + w];
+            h->run_p_max[w] = run[4 + w];
+            h->run_p_min[w] = run[6 + w];
+        }
     }
     acc[0] = ip;
     acc[1] = is;
+    for (int q = 0; q < 8; ++q) acc[2 + q] = run[q];
 }
 
 template <class CD, int EOS, int TYO, int NW>

@@ -26,7 +26,8 @@ STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S,
 EXPORTED = [
     "lbm_params_default", "lbm_create", "lbm_workspace", "lbm_bind", "lbm_state", "lbm_init_plug",
     "lbm_init_density", "lbm_step", "lbm_step_count", "lbm_fields", "lbm_wall_stress", "lbm_stress_history",
-    "lbm_check_state", "lbm_get_f", "lbm_set_f", "lbm_destroy", "lbm_last_error",
+    "lbm_check_state", "lbm_components", "lbm_components_field", "lbm_get_f", "lbm_set_f", "lbm_destroy",
+    "lbm_last_error",
 ]
 
 
@@ -54,6 +55,8 @@ class lbm_stress_summary(C.Structure):
         ("p_max", C.c_double * 2), ("p_min", C.c_double * 2), ("x_tau_max", C.c_int32 * 2),
         ("x_tau_min", C.c_int32 * 2), ("x_p_max", C.c_int32 * 2), ("x_p_min", C.c_int32 * 2),
         ("sum_tau2", C.c_double), ("int_peak_tau2", C.c_double), ("int_tau2", C.c_double),
+        ("run_tau_max", C.c_double * 2), ("run_tau_min", C.c_double * 2),
+        ("run_p_max", C.c_double * 2), ("run_p_min", C.c_double * 2),
     ]
 
 
@@ -62,6 +65,21 @@ class lbm_check_result(C.Structure):
         ("step", C.c_int64), ("mass", C.c_double), ("momx", C.c_double), ("momy", C.c_double),
         ("vmax", C.c_double), ("nan_count", C.c_int64), ("x_rear", C.c_double), ("x_front", C.c_double),
         ("liquid_columns", C.c_int32), ("rupture_step", C.c_int64), ("unstable_step", C.c_int64),
+    ]
+
+
+class lbm_component(C.Structure):
+    _fields_ = [
+        ("first_cell", C.c_int64), ("cells", C.c_int32), ("wall", C.c_int32),
+        ("mass", C.c_double), ("excess_mass", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+    ]
+
+
+class lbm_aerosol_summary(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("components", C.c_int64), ("aerosols", C.c_int64), ("aerosol_cells", C.c_int64),
+        ("threshold", C.c_double), ("liquid_mass", C.c_double), ("aerosol_mass", C.c_double),
+        ("aerosol_excess_mass", C.c_double),
     ]
 
 
@@ -102,6 +120,11 @@ def library():
             "lbm_stress_history": (C.c_int, [_P, C.POINTER(lbm_stress_summary), C.c_int64,
                                              C.POINTER(C.c_int64)]),
             "lbm_check_state": (C.c_int, [_P, C.POINTER(lbm_check_result)]),
+            "lbm_components": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(lbm_component), C.c_int64,
+                                         C.POINTER(C.c_int64), C.POINTER(lbm_aerosol_summary)]),
+            "lbm_components_field": (C.c_int, [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                               C.c_int, C.POINTER(lbm_component), C.c_int64, C.POINTER(C.c_int64),
+                                               C.POINTER(lbm_aerosol_summary)]),
             "lbm_get_f": (C.c_int, [_P, _D]),
             "lbm_set_f": (C.c_int, [_P, _D]),
             "lbm_destroy": (None, [_P]),
@@ -210,6 +233,31 @@ def lbm_check_state(ctx) -> dict:
     return struct_dict(r)
 
 
+def lbm_components(ctx, threshold: float = math.nan, connectivity: int = 4):
+    """(components as dicts, summary dict) of the last step's density."""
+    n, summ = C.c_int64(), lbm_aerosol_summary()
+    _check(ctx, library().lbm_components(ctx, threshold, connectivity, None, 0, C.byref(n), None))
+    buf = (lbm_component * max(n.value, 1))()
+    _check(ctx, library().lbm_components(ctx, threshold, connectivity, buf, n.value, C.byref(n), C.byref(summ)))
+    return [struct_dict(buf[i]) for i in range(n.value)], struct_dict(summ)
+
+
+def lbm_components_field(rho: np.ndarray, threshold: float, rho_g: float = 0.0, connectivity: int = 4,
+                         x_periodic: int = 0, y_periodic: int = 0):
+    """(components, summary) of a host field rho[ny][nx]; host code only, no device."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    ny, nx = rho.shape
+    n, summ = C.c_int64(), lbm_aerosol_summary()
+    st = library().lbm_components_field(_ptr(rho), nx, ny, x_periodic, y_periodic, threshold, rho_g, connectivity,
+                                        None, 0, C.byref(n), None)
+    if st != LBM_OK:
+        raise LbmError(st, "lbm_components_field: invalid arguments")
+    buf = (lbm_component * max(n.value, 1))()
+    library().lbm_components_field(_ptr(rho), nx, ny, x_periodic, y_periodic, threshold, rho_g, connectivity, buf,
+                                   n.value, C.byref(n), C.byref(summ))
+    return [struct_dict(buf[i]) for i in range(n.value)], struct_dict(summ)
+
+
 def lbm_get_f(ctx, f: np.ndarray):
     _check(ctx, library().lbm_get_f(ctx, _ptr(f)))
 
@@ -289,6 +337,10 @@ class Lattice:
 
     def check(self) -> dict:
         return lbm_check_state(self._ctx)
+
+    def components(self, threshold: float = math.nan, connectivity: int = 4):
+        """Liquid components of the last step's density and the aerosol totals."""
+        return lbm_components(self._ctx, threshold, connectivity)
 
     def get_f(self) -> np.ndarray:
         f = np.empty((9, self.ny, self.nx))

@@ -47,7 +47,8 @@ def test_struct_layouts_match_header(L, tmp_path):
     import subprocess
 
     structs = {"lbm_params": L.lbm_params, "lbm_stress_summary": L.lbm_stress_summary,
-               "lbm_check_result": L.lbm_check_result}
+               "lbm_check_result": L.lbm_check_result, "lbm_component": L.lbm_component,
+               "lbm_aerosol_summary": L.lbm_aerosol_summary}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')

@@ -105,7 +105,8 @@ def test_fp64_matches_oracle_on_small_grids(nx, ny, tau, kw, sched):
         hg, hr = lat.history(), ref.history()
         assert [h["step"] for h in hg] == [h["step"] for h in hr] == list(range(1, 101))
         for a, b in zip(hg, hr):
-            for key in ("tau_max", "tau_min", "p_max", "p_min"):
+            for key in ("tau_max", "tau_min", "p_max", "p_min", "run_tau_max", "run_tau_min", "run_p_max",
+                        "run_p_min"):
                 assert np.allclose(a[key], b[key], rtol=1e-9, atol=1e-18), key
             assert a["sum_tau2"] == pytest.approx(b["sum_tau2"], rel=1e-9, abs=1e-30)
             assert a["int_tau2"] == pytest.approx(b["int_tau2"], rel=1e-9, abs=1e-30)

@@ -228,3 +228,20 @@ def test_wall_summary_bookkeeping(orc):
     assert last["int_tau2"] == pytest.approx(sum(x["sum_tau2"] for x in h), rel=1e-13)
     peaks = [max(x["tau_max"][0] ** 2, x["tau_min"][0] ** 2, x["tau_max"][1] ** 2, x["tau_min"][1] ** 2) for x in h]
     assert last["int_peak_tau2"] == pytest.approx(sum(peaks), rel=1e-13)
+    # running extremes: over x (the wall arrays of every step) and over all steps so far
+    taus, ps = [], []
+    s2 = orc.Sim(nx, ny, p)
+    s2.init_plug(20, 3, math.nan, 1e-3, 2)
+    for _ in range(30):
+        s2.step(1)
+        w2 = s2.wall()
+        taus.append((w2["tau_bot"].copy(), w2["tau_top"].copy()))
+        ps.append((w2["p_bot"].copy(), w2["p_top"].copy()))
+    h2 = s2.history()
+    for n in (1, 7, 30):
+        e = h2[n - 1]
+        for k in range(2):
+            assert e["run_tau_max"][k] == max(t[k].max() for t in taus[:n])
+            assert e["run_tau_min"][k] == min(t[k].min() for t in taus[:n])
+            assert e["run_p_max"][k] == max(q[k].max() for q in ps[:n])
+            assert e["run_p_min"][k] == min(q[k].min() for q in ps[:n])
