@@ -149,6 +149,67 @@ def size_sweep(storage: str) -> int:
     return 0
 
 
+def sweep_cases() -> list:
+    """48 uneven cases shaped like the sweeps of Sec. 3.3 (Figs 10-12): channels of
+    radius 32, 48 and 64 cells (nx = 8 R), pressure drops, plug and film
+    thicknesses varied around a droplet-forming state point (CS 0.90 Tc, tau 1)."""
+    cases = []
+    for R in (32, 48, 64):
+        for dp in (2e-4, 4e-4):
+            for b in (0.6, 1.0):
+                for h in (0.1, 0.15, 0.2, 0.25):
+                    cases.append(dict(nx=8 * R, ny=2 * R, tau=1.0, T_over_Tc=0.90, dp=dp * 4 * R / 256,
+                                      x_periodic=1, plug=b * R, film=h * R))
+    return cases
+
+
+def batch_sweep(storage: str, steps: int, warmup: int) -> int:
+    """Aggregate throughput of the 48 sweep cases as one batch (one launch per
+    step for all cases) and one after another (one launch per case and step)."""
+    import numpy as np
+    import torch
+
+    from paper_2103_08301_amd import Batch, Lattice
+
+    cases = sweep_cases()
+    nodes = sum(c["nx"] * c["ny"] for c in cases)
+    spec = [{k: v for k, v in c.items() if k not in ("plug", "film")} for c in cases]
+    batch = Batch(spec, storage=storage, check_every=max(steps, warmup, 1), v_limit=0.5)
+    for k, c in enumerate(cases):
+        batch[k].init_plug(c["plug"], c["film"], float("nan"), 1e-3, k + 1)
+    batch.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(batch.stream)
+    batch.step(steps)
+    e1.record(batch.stream)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / 1e3
+    lats = []
+    for k, (c, s) in enumerate(zip(cases, spec)):
+        s = dict(s)
+        lat = Lattice(s.pop("nx"), s.pop("ny"), s.pop("tau"), storage=storage, check_every=max(steps, warmup, 1),
+                      v_limit=0.5, **s)
+        lat.init_plug(c["plug"], c["film"], float("nan"), 1e-3, k + 1)
+        lat.step(warmup)
+        lats.append(lat)
+    torch.cuda.synchronize()
+    e0.record(lats[0].stream)
+    for lat in lats:
+        lat.step(steps)
+    e1.record(lats[0].stream)
+    torch.cuda.synchronize()
+    t_seq = e0.elapsed_time(e1) / 1e3
+    same = all(np.array_equal(batch[k].fields()[0], lats[k].fields()[0]) for k in range(len(cases)))
+    out = {"metric": "aggregate MLUPS, 48 uneven sweep cases", "unit": "MLUPS", "storage": storage,
+           "cases": len(cases), "nodes": nodes, "steps": steps,
+           "batch": {"MLUPS": round(nodes * steps / t_batch / 1e6, 1), "us_per_step": round(t_batch / steps * 1e6, 2)},
+           "sequential": {"MLUPS": round(nodes * steps / t_seq / 1e6, 1), "us_per_step": round(t_seq / steps * 1e6, 2)},
+           "speedup": round(t_seq / t_batch, 2), "batch_equals_sequential": bool(same)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +224,8 @@ def main() -> int:
                     help="only run a plain device-to-device copy of MIB mebibytes 10 times (counter calibration)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only time the step on grids from 64x16 to 3072x1024 (fixed per-launch cost vs bytes)")
+    ap.add_argument("--batch", action="store_true",
+                    help="only time 48 uneven sweep cases as one batch against the same cases stepped one by one")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -198,6 +261,8 @@ def main() -> int:
     lbm.library()  # fail loudly if the HIP library is missing
     if args.size_sweep:
         return size_sweep(args.storage)
+    if args.batch:
+        return batch_sweep(args.storage, steps=min(args.steps, 2000), warmup=min(args.warmup, 100))
 
     make = {"large-stable": workloads.plug_large_stable, "large": workloads.plug_large,
             "out-of-cache": workloads.plug_out_of_cache}[args.workload]

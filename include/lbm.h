@@ -242,8 +242,42 @@ lbm_status lbm_components_field(const double* rho, int nx, int ny, int x_periodi
 lbm_status lbm_get_f(lbm_ctx* ctx, double* f);
 lbm_status lbm_set_f(lbm_ctx* ctx, const double* f);
 
+/* Frees a context (a no-op for a context owned by a batch). */
 void lbm_destroy(lbm_ctx* ctx);
 const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* ---- Batches -------------------------------------------------------------
+   The studies of Sec. 3.3 (Figs 10-12) sweep the pressure drop, the plug and
+   the film thickness over many cases.  A batch advances many independent
+   lattices, of any sizes and parameters, with one kernel launch per step for
+   all of them (the tile schedule over the concatenated tiles), so small cases
+   share the fixed cost of a launch.  Every case is an ordinary context (init,
+   fields, wall stress, history, checks, components, get_f/set_f all work on
+   it) except that only lbm_batch_step advances it. */
+typedef struct lbm_batch lbm_batch;
+
+/* n cases of sizes nx[k] x ny[k], relaxation times tau[k] and parameters
+   params[k] (all host arrays of n entries).  storage, eos, tile_rows,
+   tile_waves and check_every must be equal across the cases and schedule must
+   be 0; otherwise LBM_EINVAL, as for any case lbm_create would reject. */
+lbm_status lbm_batch_create(int n, const int* nx, const int* ny, const double* tau, const lbm_params* params,
+                            lbm_batch** out);
+/* Device bytes the batch needs (all cases' workspaces and the per-case launch table). */
+lbm_status lbm_batch_workspace(const lbm_batch* b, size_t* bytes);
+/* Binds caller-owned device memory (256-byte aligned, at least lbm_batch_workspace
+   bytes; the caller keeps ownership) and a stream to the batch and all its
+   cases, and uploads the launch table (synchronises the stream). */
+lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hip_stream);
+/* Borrowed handle of case k (0 <= k < n), valid until lbm_batch_destroy. */
+lbm_status lbm_batch_case(lbm_batch* b, int k, lbm_ctx** ctx);
+/* Advances every case by n >= 0 steps, one launch per step, with each case's
+   checks at the common check cadence.  All cases must be initialised and have
+   equal step counts (initialise them together).  On a failed check returns
+   that status, stops, and sets *failed_case (may be NULL) to the case index
+   (-1 otherwise). */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case);
+void lbm_batch_destroy(lbm_batch* b);
+const char* lbm_batch_last_error(const lbm_batch* b);
 
 #ifdef __cplusplus
 }

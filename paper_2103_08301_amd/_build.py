@@ -26,6 +26,9 @@ def build_library(verbose: bool = False) -> str:
     cmd = [
         hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
         "-Wall", "-Wno-unused-function",
+        # fused multiply-adds only within one source expression: every kernel that
+        # inlines the same step code rounds identically (single, batched, pipelined)
+        "-ffp-contract=on",
         # packed FP32 VALU forms are kept out of the generated code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         # tile tickets are drawn by one lane and must stay in flight: no wave-level

@@ -247,6 +247,7 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     bool bound = false, initialized = false;
+    bool in_batch = false;  // owned by an lbm_batch: stepped only through lbm_batch_step
     int cur = 0;
     int64_t steps = 0;
     int ring_fill = 0;
@@ -613,6 +614,7 @@ lbm_status lbm_init_density(lbm_ctx* c, const double* rho) {
 
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     if (!c || n < 0) return LBM_EINVAL;
+    if (c->in_batch) return fail(c, LBM_ESTATE, "this context belongs to a batch: step it with lbm_batch_step");
     if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_step needs lbm_bind and an initialisation");
     lbm::StepArgs a = make_args(c);
     const size_t slot = (size_t)2 * c->nstrip * lbm::kPartialVals;
@@ -813,8 +815,185 @@ lbm_status lbm_components(lbm_ctx* c, double threshold, int connectivity, lbm_co
     return LBM_OK;
 }
 
-void lbm_destroy(lbm_ctx* c) { delete c; }
+void lbm_destroy(lbm_ctx* c) {
+    if (c && c->in_batch) return;  // owned by its batch (lbm_batch_destroy frees it)
+    delete c;
+}
 
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many independent lattices advanced by one kernel launch per step.
+
+struct lbm_batch {
+    std::vector<lbm_ctx*> cases;
+    std::vector<int> tile_start;  // ncases + 1
+    size_t off_desc = 0, off_tiles = 0, total = 0;
+    std::vector<size_t> off_case;
+    char* dev = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    std::string err;
+    ~lbm_batch() {
+        for (lbm_ctx* c : cases) delete c;
+    }
+};
+
+namespace {
+
+lbm_status bfail(lbm_batch* b, lbm_status s, const std::string& msg) {
+    if (b) b->err = msg;
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_create(int n, const int* nx, const int* ny, const double* tau, const lbm_params* params,
+                            lbm_batch** out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (n < 1 || !nx || !ny || !tau || !params) return LBM_EINVAL;
+    auto* b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_ENOMEM;
+    const lbm_params& p0 = params[0];
+    for (int k = 0; k < n; ++k) {
+        const lbm_params& p = params[k];
+        // one kernel instance serves every case: storage, EOS kind and tile shape agree, and the
+        // cases are checked together
+        if (p.storage != p0.storage || p.eos != p0.eos || p.schedule != lbm::kScheduleTile ||
+            p.tile_rows != p0.tile_rows || p.tile_waves != p0.tile_waves || p.check_every != p0.check_every) {
+            delete b;
+            return LBM_EINVAL;
+        }
+        lbm_ctx* c = nullptr;
+        lbm_status s = lbm_create(nx[k], ny[k], tau[k], &p, &c);
+        if (s) {
+            delete b;
+            return s;
+        }
+        c->in_batch = true;
+        b->cases.push_back(c);
+    }
+    size_t o = 0;
+    b->off_desc = o; o += align256((size_t)n * sizeof(lbm::StepArgs));
+    b->off_tiles = o; o += align256((size_t)(n + 1) * sizeof(int));
+    int tiles = 0;
+    for (int k = 0; k < n; ++k) {
+        lbm_ctx* c = b->cases[k];
+        b->off_case.push_back(o);
+        o += align256(c->total);
+        b->tile_start.push_back(tiles);
+        const long long t = (long long)tiles + (long long)c->nstrip * ((c->ny + c->ty - 1) / c->ty);
+        if (t > (1LL << 30)) {
+            delete b;
+            return LBM_EINVAL;
+        }
+        tiles = (int)t;
+    }
+    b->tile_start.push_back(tiles);
+    b->total = o;
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_workspace(const lbm_batch* b, size_t* bytes) {
+    if (!b || !bytes) return LBM_EINVAL;
+    *bytes = b->total;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hip_stream) {
+    if (!b) return LBM_EINVAL;
+    if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
+        return bfail(b, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
+    if (bytes < b->total) return bfail(b, LBM_ENOMEM, "workspace too small for the batch");
+    b->dev = static_cast<char*>(device_ptr);
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    std::vector<lbm::StepArgs> desc;
+    for (size_t k = 0; k < b->cases.size(); ++k) {
+        lbm_ctx* c = b->cases[k];
+        c->in_batch = false;  // lbm_bind is shared with single contexts
+        lbm_status s = lbm_bind(c, b->dev + b->off_case[k], c->total, hip_stream);
+        c->in_batch = true;
+        if (s) return bfail(b, s, "case " + std::to_string(k) + ": " + c->err);
+        lbm::StepArgs a = make_args(c);
+        a.fin = c->dev + c->off_f[0];
+        a.fout = c->dev + c->off_f[1];
+        a.partial = c->at<double>(c->off_ring);
+        desc.push_back(a);
+    }
+    hipError_t e = hipMemcpyAsync(b->dev + b->off_desc, desc.data(), desc.size() * sizeof(lbm::StepArgs),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dev + b->off_tiles, b->tile_start.data(), b->tile_start.size() * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch descriptors: ") + hipGetErrorString(e));
+    b->bound = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_case(lbm_batch* b, int k, lbm_ctx** ctx) {
+    if (!b || !ctx || k < 0 || k >= (int)b->cases.size()) return LBM_EINVAL;
+    *ctx = b->cases[(size_t)k];
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
+    if (failed_case) *failed_case = -1;
+    if (!b || n < 0) return LBM_EINVAL;
+    if (!b->bound) return bfail(b, LBM_ESTATE, "lbm_batch_bind must come first");
+    lbm_ctx* c0 = b->cases[0];
+    for (lbm_ctx* c : b->cases) {
+        if (!c->initialized) return bfail(b, LBM_ESTATE, "every case must be initialised before stepping");
+        if (c->steps != c0->steps || c->cur != c0->cur || c->ring_fill != c0->ring_fill)
+            return bfail(b, LBM_ESTATE, "the cases must be initialised together (equal step counts)");
+    }
+    const int ncases = (int)b->cases.size();
+    const auto* desc = reinterpret_cast<const lbm::StepArgs*>(b->dev + b->off_desc);
+    const auto* tiles = reinterpret_cast<const int*>(b->dev + b->off_tiles);
+    int64_t done = 0;
+    while (done < n) {
+        const int64_t next_check = (c0->steps / c0->p.check_every + 1) * c0->p.check_every;
+        const int64_t seg = std::min<int64_t>(n - done, next_check - c0->steps);
+        for (int64_t k = 0; k < seg; ++k) {
+            if (c0->ring_fill == kRingCap)
+                for (lbm_ctx* c : b->cases) {
+                    lbm_status s = flush_wall(c);
+                    if (s) return bfail(b, s, c->err);
+                }
+            const bool emit = (k == seg - 1);
+            hipError_t e = lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), c0->cur, c0->ring_fill,
+                                                  c0->p.storage, c0->p.eos, c0->ty, c0->tile_waves, emit, b->stream);
+            if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
+            for (lbm_ctx* c : b->cases) {
+                c->cur = 1 - c->cur;
+                c->ring_fill += 1;
+                c->steps += 1;
+            }
+        }
+        for (lbm_ctx* c : b->cases) {
+            lbm_status s = flush_wall(c);
+            if (s) return bfail(b, s, c->err);
+        }
+        done += seg;
+        for (int k = 0; k < ncases; ++k) {
+            lbm_status s = run_check(b->cases[(size_t)k]);
+            if (s) {
+                if (failed_case) *failed_case = k;
+                return bfail(b, s, "case " + std::to_string(k) + ": " + b->cases[(size_t)k]->err);
+            }
+        }
+    }
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) { delete b; }
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : "null batch"; }
 
 }  // extern "C"

@@ -57,6 +57,11 @@ struct StepArgs {
 };
 
 hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s);
+// One step of many lattices in one launch (tile schedule): cases[c] holds case
+// c's arguments with both distribution buffers (f[0] as fin, f[1] as fout) and
+// the base of its wall ring; tile_start[c] is its first tile (device arrays).
+hipError_t launch_step_batch(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                             int slot, int storage, int eos, int ty, int waves, bool emit, hipStream_t s);
 // Resident blocks of the pipelined kernel for this configuration: CUs times the
 // blocks one CU holds at once.
 hipError_t pipe_grid(int storage, int eos, int ty, int waves, int* blocks);

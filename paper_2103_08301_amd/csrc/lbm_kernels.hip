@@ -643,8 +643,11 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
 // Tiles are TYO rows apart; the last one is moved down to end at row ny - 1, so
 // every tile has TYO output rows and the two rows next to a wall share a tile
 // (rows covered by two tiles are computed identically by both).
+// One tile of one lattice: `bid` is the tile index in tile-row-major order,
+// fin/fout/partial the buffers of this step (the kernels below pick them).
 template <class CD, int EOS, bool EMIT, int TYO, int NW>
-__global__ __launch_bounds__(64 * NW) void tile_kernel(const StepArgs a) {
+__device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, void* fout_v, double* partial,
+                                          int bid) {
     using S = typename CD::S;
     using C = typename CD::C;
     constexpr int H = TYO + 4;    // tile rows including the halo
@@ -655,7 +658,6 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(const StepArgs a) {
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
     // tile-row-major: consecutive blocks are x-neighbours, and with the XCD remap
     // each XCD walks a contiguous band of tile rows, so the halo columns and the
     // halo rows shared by neighbouring tiles are still in that XCD's L2
@@ -671,8 +673,8 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(const StepArgs a) {
     const bool tile_inner = strip_inner && (y0 - 2 >= 1) && (y0 + H - 3 <= a.ny - 2);
     const bool walls = !a.yper;
 
-    const S* __restrict__ fin = static_cast<const S*>(a.fin);
-    S* __restrict__ fout = static_cast<S*>(a.fout);
+    const S* __restrict__ fin = static_cast<const S*>(fin_v);
+    S* __restrict__ fout = static_cast<S*>(fout_v);
     const uint32_t plane_bytes = uint32_t(a.plane) * uint32_t(sizeof(S));
     uint32_t dir_off[9];
 #pragma unroll
@@ -815,12 +817,39 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(const StepArgs a) {
         wave_argmin(pmin, xpmin);
         const double s2 = wave_sum(dt * dt);
         if (lane == 0) {
-            double* o = a.partial + ((long long)w * a.nstrip + strip) * kPartialVals;
+            double* o = partial + ((long long)w * a.nstrip + strip) * kPartialVals;
             o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
             o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
             o[8] = s2;
         }
     }
+}
+
+template <class CD, int EOS, bool EMIT, int TYO, int NW>
+__global__ __launch_bounds__(64 * NW) void tile_kernel(const StepArgs a) {
+    tile_body<CD, EOS, EMIT, TYO, NW>(a, a.fin, a.fout, a.partial, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Many lattices in one launch: the tiles of case c are blocks
+// tile_start[c] .. tile_start[c+1]-1 (after the XCD remap).  The per-case
+// arguments hold both distribution buffers (f[0] in fin, f[1] in fout) and the
+// base of the wall ring; parity picks which buffer is read this step and slot
+// the ring slot, the same for every case since the cases step together.
+template <class CD, int EOS, bool EMIT, int TYO, int NW>
+__global__ __launch_bounds__(64 * NW) void tile_batch_kernel(const StepArgs* __restrict__ cases,
+                                                             const int* __restrict__ tile_start, int ncases,
+                                                             int parity, int slot) {
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = ncases - 1;  // last case whose first tile is <= bid (uniform search)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= bid) lo = mid; else hi = mid - 1;
+    }
+    const StepArgs& a = cases[lo];
+    const void* fin = parity ? a.fout : a.fin;
+    void* fout = parity ? const_cast<void*>(a.fin) : a.fout;
+    tile_body<CD, EOS, EMIT, TYO, NW>(a, fin, fout, a.partial + (long long)slot * 2 * a.nstrip * kPartialVals,
+                                      bid - tile_start[lo]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1321,6 +1350,47 @@ hipError_t launch_tile(const StepArgs& a, bool emit, hipStream_t s) {
 }
 
 template <class CD, int EOS, int TYO, int NW>
+hipError_t launch_batch_t(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                          int slot, bool emit, hipStream_t s) {
+    const dim3 grid(total_tiles), block(64 * NW);
+    if (emit)
+        hipLaunchKernelGGL((tile_batch_kernel<CD, EOS, true, TYO, NW>), grid, block, 0, s, cases, tile_start, ncases,
+                           parity, slot);
+    else
+        hipLaunchKernelGGL((tile_batch_kernel<CD, EOS, false, TYO, NW>), grid, block, 0, s, cases, tile_start, ncases,
+                           parity, slot);
+    return hipGetLastError();
+}
+
+template <class CD, int EOS>
+hipError_t launch_batch_e(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                          int slot, int ty, int waves, bool emit, hipStream_t s) {
+    if (waves == 8) {
+        switch (ty) {
+            case 12: return launch_batch_t<CD, EOS, 12, 8>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s);
+            case 20: return launch_batch_t<CD, EOS, 20, 8>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s);
+            case 28: return launch_batch_t<CD, EOS, 28, 8>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (ty) {
+        case 8: return launch_batch_t<CD, EOS, 8, 4>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s);
+        case 12: return launch_batch_t<CD, EOS, 12, 4>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s);
+        case 20: return launch_batch_t<CD, EOS, 20, 4>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s);
+        case 28: return launch_batch_t<CD, EOS, 28, 4>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class CD>
+hipError_t launch_batch_c(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                          int slot, int eos, int ty, int waves, bool emit, hipStream_t s) {
+    return eos == LBM_EOS_CS
+               ? launch_batch_e<CD, LBM_EOS_CS>(cases, tile_start, ncases, total_tiles, parity, slot, ty, waves, emit, s)
+               : launch_batch_e<CD, LBM_EOS_PR>(cases, tile_start, ncases, total_tiles, parity, slot, ty, waves, emit, s);
+}
+
+template <class CD, int EOS, int TYO, int NW>
 hipError_t launch_pipe(const StepArgs& a, bool emit, hipStream_t s) {
     const dim3 grid(a.pipe_blocks), block(64 * NW);
     if (emit)
@@ -1414,6 +1484,20 @@ hipError_t pipe_grid_c(int eos, int ty, int waves, int* blocks) {
     return eos == LBM_EOS_CS ? pipe_grid_t<CD, LBM_EOS_CS>(ty, waves, blocks) : pipe_grid_t<CD, LBM_EOS_PR>(ty, waves, blocks);
 }
 }  // namespace
+
+hipError_t launch_step_batch(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                             int slot, int storage, int eos, int ty, int waves, bool emit, hipStream_t s) {
+    if (ncases < 1 || total_tiles < 1) return hipErrorInvalidValue;
+    switch (storage) {
+        case LBM_F64: return launch_batch_c<CodecF64>(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
+        case LBM_F32: return launch_batch_c<CodecF32>(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
+        case LBM_F16S: return launch_batch_c<CodecF16S>(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
+        case LBM_BF16S: return launch_batch_c<CodecBF16S>(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
+        case LBM_F32D: return launch_batch_c<CodecF32D>(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
+        case LBM_F32S: return launch_batch_c<CodecF32S>(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t pipe_grid(int storage, int eos, int ty, int waves, int* blocks) {
     switch (storage) {

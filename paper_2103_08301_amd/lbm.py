@@ -27,7 +27,8 @@ EXPORTED = [
     "lbm_params_default", "lbm_create", "lbm_workspace", "lbm_bind", "lbm_state", "lbm_init_plug",
     "lbm_init_density", "lbm_step", "lbm_step_count", "lbm_fields", "lbm_wall_stress", "lbm_stress_history",
     "lbm_check_state", "lbm_components", "lbm_components_field", "lbm_get_f", "lbm_set_f", "lbm_destroy",
-    "lbm_last_error",
+    "lbm_last_error", "lbm_batch_create", "lbm_batch_workspace", "lbm_batch_bind", "lbm_batch_case",
+    "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error",
 ]
 
 
@@ -129,6 +130,14 @@ def library():
             "lbm_set_f": (C.c_int, [_P, _D]),
             "lbm_destroy": (None, [_P]),
             "lbm_last_error": (C.c_char_p, [_P]),
+            "lbm_batch_create": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _D, PP,
+                                           C.POINTER(_P)]),
+            "lbm_batch_workspace": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+            "lbm_batch_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
+            "lbm_batch_case": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
+            "lbm_batch_step": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int)]),
+            "lbm_batch_destroy": (None, [_P]),
+            "lbm_batch_last_error": (C.c_char_p, [_P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -277,6 +286,12 @@ def lbm_last_error(ctx) -> str:
 
 # ---- convenience object -----------------------------------------------------
 
+def _batch_check(b, st: int):
+    if st != LBM_OK:
+        msg = library().lbm_batch_last_error(b)
+        raise LbmError(st, msg.decode() if msg else "")
+
+
 class Lattice:
     """One D2Q9 channel on one GPU.  torch provides the device workspace and the stream."""
 
@@ -286,6 +301,7 @@ class Lattice:
         self.nx, self.ny, self.tau = nx, ny, tau
         self.params = lbm_params_default(**params)
         self._ctx = lbm_create(nx, ny, tau, self.params)
+        self._owner = None
         nbytes = lbm_workspace(self._ctx)
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -293,11 +309,23 @@ class Lattice:
         with torch.cuda.device(self.device):
             lbm_bind(self._ctx, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
 
+    @classmethod
+    def _case_of(cls, batch, k: int, nx: int, ny: int, tau: float, params):
+        """View of case k of a batch (stepped by the batch; keeps the batch alive)."""
+        self = cls.__new__(cls)
+        self.nx, self.ny, self.tau, self.params = nx, ny, tau, params
+        ctx = _P()
+        _batch_check(batch._b, library().lbm_batch_case(batch._b, k, C.byref(ctx)))
+        self._ctx = ctx
+        self._owner = batch
+        self.device, self.stream, self.workspace = batch.device, batch.stream, None
+        return self
+
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
-        if ctx is not None and ctx.value:
+        if ctx is not None and ctx.value and getattr(self, "_owner", None) is None:
             lbm_destroy(ctx)
-            self._ctx = None
+        self._ctx = None
 
     @property
     def ctx(self):
@@ -350,3 +378,60 @@ class Lattice:
     def set_f(self, f: np.ndarray):
         assert f.shape == (9, self.ny, self.nx)
         lbm_set_f(self._ctx, f)
+
+
+class Batch:
+    """Many independent channels advanced by one kernel launch per step.
+
+    cases: a list of dicts with nx, ny, tau and any lbm_params fields; keywords
+    given to the constructor apply to every case (storage, eos, tile_rows,
+    tile_waves and check_every must agree).  batch[k] is case k as a Lattice
+    (initialise and read it there); batch.step(n) advances all cases."""
+
+    def __init__(self, cases: list, device: str = "cuda:0", stream=None, **common):
+        import torch
+
+        n = len(cases)
+        specs = [dict(common, **c) for c in cases]
+        nx = (C.c_int * n)(*[int(c.pop("nx")) for c in specs])
+        ny = (C.c_int * n)(*[int(c.pop("ny")) for c in specs])
+        tau = (C.c_double * n)(*[float(c.pop("tau")) for c in specs])
+        params = (lbm_params * n)(*[lbm_params_default(**c) for c in specs])
+        b = _P()
+        st = library().lbm_batch_create(n, nx, ny, tau, params, C.byref(b))
+        if st != LBM_OK:
+            raise LbmError(st, "lbm_batch_create: the cases disagree on storage/eos/tile shape/check cadence, "
+                               "or a case is invalid")
+        self._b = b
+        size = C.c_size_t()
+        _batch_check(b, library().lbm_batch_workspace(b, C.byref(size)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            _batch_check(b, library().lbm_batch_bind(b, self.workspace.data_ptr(), size.value,
+                                                     self.stream.cuda_stream))
+        self.cases = [Lattice._case_of(self, k, nx[k], ny[k], tau[k], params[k]) for k in range(n)]
+
+    def __len__(self):
+        return len(self.cases)
+
+    def __getitem__(self, k: int) -> Lattice:
+        return self.cases[k]
+
+    def step(self, n: int) -> int:
+        failed = C.c_int(-1)
+        st = library().lbm_batch_step(self._b, n, C.byref(failed))
+        if st != LBM_OK:
+            msg = library().lbm_batch_last_error(self._b)
+            err = LbmError(st, msg.decode() if msg else "")
+            err.case = failed.value
+            raise err
+        return LBM_OK
+
+    def __del__(self):
+        b = getattr(self, "_b", None)
+        if b is not None and b.value:
+            self.cases = []
+            library().lbm_batch_destroy(b)
+            self._b = None

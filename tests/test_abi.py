@@ -118,3 +118,28 @@ def test_library_coexistence_agrees_with_oracle(L, orc, kw, trs):
         b = orc.Sim(32, 16, orc.params(T_over_Tc=tr, **kw)).state()
         for k in ("Tc", "T", "rho_g", "rho_l", "rho_w"):
             assert a[k] == pytest.approx(b[k], rel=1e-11), (tr, k)
+
+
+def test_batch_create_validates_cases(L):
+    import ctypes as C
+
+    def create(plist, sizes=((64, 32), (96, 40))):
+        n = len(plist)
+        nx = (C.c_int * n)(*[s[0] for s in sizes[:n]])
+        ny = (C.c_int * n)(*[s[1] for s in sizes[:n]])
+        tau = (C.c_double * n)(*([1.0] * n))
+        params = (L.lbm_params * n)(*plist)
+        b = L._P()
+        st = L.library().lbm_batch_create(n, nx, ny, tau, params, C.byref(b))
+        return st, b
+
+    p = L.lbm_params_default
+    st, b = create([p(), p(dp=2e-3, T_over_Tc=0.9)])
+    assert st == L.LBM_OK
+    size = C.c_size_t()
+    assert L.library().lbm_batch_workspace(b, C.byref(size)) == L.LBM_OK and size.value > 0
+    L.library().lbm_batch_destroy(b)
+    for bad in ([p(), p(storage=L.LBM_F64)], [p(), p(eos=L.LBM_EOS_PR, a=2 / 49, b=2 / 21)], [p(), p(tile_rows=12)],
+                [p(), p(check_every=10)], [p(), p(schedule=1)], [p(), p(T_over_Tc=-1.0)]):
+        st, _ = create(bad)
+        assert st == L.LBM_EINVAL

@@ -1,0 +1,126 @@
+"""Batches: many lattices advanced by one launch per step.
+
+The batched kernel runs the same tile code as the single-lattice kernel on the
+concatenated tiles of all cases, so every case of a batch must reproduce, bit
+for bit, the same case run on its own (distributions, wall history, checks),
+whatever the mix of sizes, parameters and boundaries; one case is also
+checked against the FP64 oracle directly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+from paper_2103_08301_amd import Batch, Lattice, lbm  # noqa: E402
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    dict(nx=256, ny=64, tau=1.0, T_over_Tc=0.85, dp=1e-3),
+    dict(nx=61, ny=9, tau=0.9, T_over_Tc=0.9, dp=2e-3),                      # ragged strip and tile
+    dict(nx=130, ny=37, tau=0.8, T_over_Tc=0.95, dp=5e-4, x_periodic=1),
+    dict(nx=200, ny=33, tau=1.0, T_over_Tc=0.9, dp=1e-3, x_periodic=1, y_periodic=1),
+    dict(nx=400, ny=100, tau=1.2, T_over_Tc=0.85, dp=1e-3, rho_wall=0.2, kappa=0.01, k=0.7),
+    dict(nx=16, ny=8, tau=1.0, T_over_Tc=0.9, dp=1e-3),
+]
+
+
+def same_dict(a, b):
+    """Exact equality, with NaN equal to NaN (interface positions when there is no plug)."""
+    assert a.keys() == b.keys()
+    for k in a:
+        x, y = a[k], b[k]
+        if isinstance(x, float) and math.isnan(x):
+            assert isinstance(y, float) and math.isnan(y), k
+        else:
+            assert x == y, k
+
+
+def plug(case):
+    return max(4, case["nx"] // 5), (0 if case.get("y_periodic") else max(1, case["ny"] // 16))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_matches_single_runs_bitwise(storage):
+    b = Batch(CASES, storage=storage, v_limit=1.0, check_every=50)
+    for k, c in enumerate(CASES):
+        pl, fl = plug(c)
+        b[k].init_plug(pl, fl, math.nan, 1e-3, k + 1)
+    b.step(1)
+    b.step(149)
+    for k, c in enumerate(CASES):
+        spec = dict(c)
+        nx, ny, tau = spec.pop("nx"), spec.pop("ny"), spec.pop("tau")
+        lat = Lattice(nx, ny, tau, storage=storage, v_limit=1.0, check_every=50, **spec)
+        pl, fl = plug(c)
+        lat.init_plug(pl, fl, math.nan, 1e-3, k + 1)
+        lat.step(1)
+        lat.step(149)
+        assert b[k].steps == lat.steps == 150
+        fb, fl_ = b[k].get_f(), lat.get_f()
+        d = np.abs(fb - fl_)
+        log(f"case {k}: max |f batch - f single| {d.max():.3e} at {np.unravel_index(np.argmax(d), d.shape)}, "
+            f"{int((d > 0).sum())} differing values")
+        assert np.array_equal(fb, fl_), k
+        rb, rl = b[k].fields()[0], lat.fields()[0]
+        assert np.array_equal(rb, rl), k
+        same_dict(b[k].check(), lat.check())
+        if not c.get("y_periodic"):
+            assert b[k].history() == lat.history(), k
+        log(f"case {k} {nx}x{ny}: identical to its single run")
+        del lat
+
+
+def test_batch_case_against_oracle():
+    cases = [dict(nx=96, ny=20, tau=1.0, T_over_Tc=0.85, dp=1e-3), dict(nx=150, ny=40, tau=0.9, T_over_Tc=0.9, dp=1e-3)]
+    b = Batch(cases, storage="f64", v_limit=1.0)
+    ref = O.Sim(150, 40, O.params(tau=0.9, T_over_Tc=0.9, dp=1e-3, v_limit=1.0))
+    ref.init_plug(30, 3, math.nan, 1e-3, 4)
+    b[0].init_plug(20, 2, math.nan, 1e-3, 3)
+    b[1].init_density(ref.fields()[0])
+    b.step(200)
+    ref.step(200)
+    fg, fr = b[1].get_f(), ref.get_f()
+    e = float(np.abs(fg - fr).max() / np.abs(fr).max())
+    log(f"batch case vs oracle after 200 steps: rel Linf f {e:.2e}")
+    assert e < 1e-12
+
+
+def test_batch_rules_and_errors():
+    b = Batch([dict(nx=64, ny=16, tau=1.0), dict(nx=80, ny=24, tau=1.0)], storage="f64", v_limit=1.0)
+    with pytest.raises(lbm.LbmError) as e:
+        b.step(1)  # not initialised
+    assert e.value.status == lbm.LBM_ESTATE
+    b[0].init_plug(10, 2, math.nan, 0.0, 1)
+    b[1].init_plug(10, 2, math.nan, 0.0, 1)
+    with pytest.raises(lbm.LbmError) as e:
+        b[0].step(1)  # a case is stepped only by its batch
+    assert e.value.status == lbm.LBM_ESTATE
+    b.step(5)
+    b[1].init_plug(10, 2, math.nan, 0.0, 1)  # re-initialised alone: step counts differ
+    with pytest.raises(lbm.LbmError) as e:
+        b.step(1)
+    assert e.value.status == lbm.LBM_ESTATE
+
+
+def test_batch_reports_the_unstable_case():
+    cases = [dict(nx=64, ny=16, tau=1.0, dp=1e-3), dict(nx=64, ny=16, tau=1.0, dp=1e-3, v_limit=1e-9)]
+    b = Batch(cases, storage="f64", check_every=10)
+    for k in range(2):
+        b[k].init_plug(10, 2, math.nan, 1e-3, 1)
+    with pytest.raises(lbm.LbmError) as e:
+        b.step(30)
+    assert e.value.status == lbm.LBM_EUNSTABLE and e.value.case == 1
+    assert b[0].check()["unstable_step"] == -1 and b[1].check()["unstable_step"] == 10
