@@ -64,7 +64,14 @@ typedef enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 } lbm_eos_kind;
    F64: FP64 / FP64.  F32: FP32 / FP32.  F16S, BF16S: f_i - w_i rho0_shift in
    FP16 / BF16, FP32 arithmetic.  F32D: FP32 storage, FP64 arithmetic.
    F32S: f_i - w_i rho0_shift in FP32, FP32 arithmetic. */
-typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_F32D = 4, LBM_F32S = 5 } lbm_storage;
+/* Storage of the distributions.  F64T keeps each population as an FP64 value
+   and its FP64 tangent along a direction of the parameters (lbm_set_tangent):
+   the step then runs in tangent-linear arithmetic and the wall summaries carry
+   the derivative of the squared wall shear (forward-mode sensitivities).  F64T
+   runs on the tile schedule with 12-row, 8-wave tiles, CS or PR. */
+typedef enum {
+    LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_F32D = 4, LBM_F32S = 5, LBM_F64T = 6
+} lbm_storage;
 
 typedef struct {
     int eos;             /* lbm_eos_kind. CS: Carnahan-Starling p0 = rho R T (1+h+h^2-h^3)/(1-h)^3 - a rho^2,
@@ -114,6 +121,8 @@ typedef struct {
                                                initialisation: run_*_max - run_*_min is the span of
                                                wall stress over a rupture (Sec. 3.2-3.3) */
     double run_p_max[2], run_p_min[2];
+    double d_sum_tau2;                   /* F64T storage: derivative of sum_tau2 along the tangent direction */
+    double d_int_tau2;                   /* F64T storage: derivative of int_tau2 along the tangent direction */
 } lbm_stress_summary;
 
 /* Result of the latest stability/interface check. */
@@ -135,7 +144,7 @@ typedef struct {
 void lbm_params_default(lbm_params* p);
 
 /* Validates the parameters, solves the EOS critical point and the Maxwell
-   coexistence densities on the host (paper Sec. 2.2, "Verification") and
+   coexistence densities on the host (paper Sec. 2.2, verification paragraph) and
    returns a new context.  No device work.  tau > 1/2; 4 <= nx, ny; one copy
    of the distributions (9 * ny * nx rounded up to 64 columns, in the storage
    type) must stay below 4 GiB.  T_over_Tc >= 1 is allowed (single phase) but
@@ -235,6 +244,18 @@ lbm_status lbm_components(lbm_ctx* ctx, double threshold, int connectivity, lbm_
 lbm_status lbm_components_field(const double* rho, int nx, int ny, int x_periodic, int y_periodic, double threshold,
                                 double rho_g, int connectivity, lbm_component* out, int64_t cap, int64_t* n_out,
                                 lbm_aerosol_summary* summary);
+
+/* F64T storage: the direction of the parameter tangent, dtheta = (d dp, d a,
+   d b, d T) with T the absolute temperature (T_over_Tc times the critical
+   temperature of the unperturbed a, b, R).  The initial state and the wall
+   ghost density are held fixed, so the tangents start at zero at every
+   initialisation and d int_tau2 is the derivative of the time integral of
+   squared wall shear.  For PR, d a and d b must be 0 (its alpha depends on the
+   critical temperature).  Takes effect from the next lbm_step; LBM_EINVAL for
+   another storage type or non-finite entries. */
+lbm_status lbm_set_tangent(lbm_ctx* ctx, const double* dtheta);
+/* F64T storage: the tangents of the post-collision distributions [9][ny][nx]. */
+lbm_status lbm_get_f_tangent(lbm_ctx* ctx, double* df);
 
 /* Post-collision distributions as FP64 host arrays [9][ny][nx]
    (decoded from the storage type) / replaced from such an array (encoded with

@@ -70,6 +70,13 @@ double pr_alpha(double omega, double T, double Tc) {
     return s * s;
 }
 
+// d alpha / dT at fixed Tc.
+double pr_alpha_dT(double omega, double T, double Tc) {
+    const double kw = 0.37464 + 1.54226 * omega - 0.26992 * omega * omega;
+    const double s = 1.0 + kw * (1.0 - std::sqrt(T / Tc));
+    return -kw * s / std::sqrt(T * Tc);
+}
+
 // Critical point: p' = p'' = 0.  With p = T A(rho) + B(rho) (alpha(Tc) = 1),
 // T = -B'/A' and the density solves A' B'' - A'' B' = 0.
 bool critical_point(Eos& e, double& rho_c) {
@@ -200,6 +207,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 size_t storage_bytes(int storage) {
     switch (storage) {
+        case LBM_F64T: return 16;
         case LBM_F64: return 8;
         case LBM_F32:
         case LBM_F32D:
@@ -216,6 +224,8 @@ bool schedule_ok(const lbm_params* p) {
     const int r = p->tile_rows, w = p->tile_waves;
     if (w != 0 && w != 4 && w != 8) return false;
     if (p->pipe_blocks != 0 && (p->schedule != lbm::kSchedulePipe || p->pipe_blocks < 8)) return false;
+    if (p->storage == LBM_F64T)  // tangent-linear runs: the tile schedule with 12-row, 8-wave tiles
+        return p->schedule == lbm::kScheduleTile && (r == 0 || r == 12) && (w == 0 || w == 8);
     switch (p->schedule) {
         case lbm::kScheduleTile:
             if (w == 8) return r == 0 || r == 12 || r == 20 || r == 28;
@@ -248,6 +258,7 @@ struct lbm_ctx {
     int device = 0;
     bool bound = false, initialized = false;
     bool in_batch = false;  // owned by an lbm_batch: stepped only through lbm_batch_step
+    double dtheta[4] = {0, 0, 0, 0};  // F64T: tangent direction (dp, a, b, T)
     int cur = 0;
     int64_t steps = 0;
     int ring_fill = 0;
@@ -289,6 +300,7 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     HIP_TRY(c, lbm::launch_fill(acc, 0.0, 2, c->stream));
     for (int q = 0; q < 4; ++q)  // running maxima start at -inf, minima at +inf
         HIP_TRY(c, lbm::launch_fill(acc + 2 + 2 * q, (q % 2 == 0) ? -INFINITY : INFINITY, 2, c->stream));
+    HIP_TRY(c, lbm::launch_fill(acc + 10, 0.0, 1, c->stream));  // tangent of the sum-of-squares integral
     c->steps = 0;
     c->ring_fill = 0;
     c->ring_first_step = 1;
@@ -414,6 +426,15 @@ lbm::StepArgs make_args(const lbm_ctx* c) {
     a.rho_out = c->at<double>(c->off_rho);
     a.vx_out = c->at<double>(c->off_vx);
     a.vy_out = c->at<double>(c->off_vy);
+    a.ct = lbm::CoefTangent{};
+    if (c->p.storage == LBM_F64T) {
+        const double dT = c->dtheta[3];
+        a.ct.g = c->dtheta[0] / c->nx;
+        a.ct.RT = c->eos.R * dT;
+        a.ct.a_eff = c->eos.alpha * c->dtheta[1] +
+                     (c->p.eos == LBM_EOS_PR ? c->eos.a * pr_alpha_dT(c->p.omega, c->eos.T, c->eos.Tc) * dT : 0.0);
+        a.ct.b = c->dtheta[2];
+    }
     a.tickets = c->at<unsigned long long>(c->off_tickets);
     a.pipe_blocks = c->pipe_blocks;
     return a;
@@ -462,7 +483,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
         !std::isfinite(p->T_over_Tc) || !(p->k > 0) || !(p->kappa >= 0) || !rate_ok(p->s_e) || !rate_ok(p->s_eps) ||
         !rate_ok(p->s_q) || !(p->s_j <= 0 || rate_ok(p->s_j)) || !std::isfinite(p->dp) || p->check_every < 1 ||
         !(p->v_limit > 0) || p->history_cap < 1 || (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) ||
-        p->storage < LBM_F64 || p->storage > LBM_F32S || (p->x_periodic != 0 && p->x_periodic != 1) ||
+        p->storage < LBM_F64 || p->storage > LBM_F64T || (p->x_periodic != 0 && p->x_periodic != 1) ||
         (p->y_periodic != 0 && p->y_periodic != 1) || !std::isfinite(p->omega) ||
         (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || !schedule_ok(p))
         return LBM_EINVAL;
@@ -495,10 +516,10 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->plane = (long long)pitch * ny;
     c->nstrip = (nx + lbm::kStripOut - 1) / lbm::kStripOut;
     c->schedule = p->schedule;
-    c->tile_waves = p->tile_waves > 0 ? p->tile_waves : 4;
+    c->tile_waves = p->tile_waves > 0 ? p->tile_waves : (p->storage == LBM_F64T ? 8 : 4);
     // measured on the 4096x512 plug channel: 8-row tiles for FP32/FP16/BF16 arithmetic
     // tiles, 12-row tiles when the arithmetic is FP64 (more registers per row)
-    const bool fp64_math = p->storage == LBM_F64 || p->storage == LBM_F32D;
+    const bool fp64_math = p->storage == LBM_F64 || p->storage == LBM_F32D || p->storage == LBM_F64T;
     if (p->tile_rows > 0)
         c->ty = p->tile_rows;
     else if (p->schedule == lbm::kScheduleTile)
@@ -733,6 +754,7 @@ lbm_status lbm_get_f(lbm_ctx* c, double* f) {
                 double v;
                 switch (c->p.storage) {
                     case LBM_F64: std::memcpy(&v, raw.data() + src * 8, 8); break;
+                    case LBM_F64T: std::memcpy(&v, raw.data() + src * 16, 8); break;
                     case LBM_F32:
                     case LBM_F32D: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = t; break; }
                     case LBM_F32S: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = (double)std::fmaf(host_weight(i), r0, t); break; }
@@ -769,6 +791,7 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
                 const double v = f[((size_t)i * c->ny + y) * c->nx + x];
                 switch (c->p.storage) {
                     case LBM_F64: std::memcpy(raw.data() + dst * 8, &v, 8); break;
+                    case LBM_F64T: std::memcpy(raw.data() + dst * 16, &v, 8); break;  // tangent zero
                     case LBM_F32:
                     case LBM_F32D: { const float t = (float)v; std::memcpy(raw.data() + dst * 4, &t, 4); break; }
                     case LBM_F32S: { const float t = std::fmaf(-host_weight(i), r0, (float)v); std::memcpy(raw.data() + dst * 4, &t, 4); break; }
@@ -794,6 +817,33 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
         if (s) return s;
         c->initialized = true;
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_tangent(lbm_ctx* c, const double* dtheta) {
+    if (!c || !dtheta) return LBM_EINVAL;
+    if (c->p.storage != LBM_F64T) return fail(c, LBM_EINVAL, "lbm_set_tangent needs F64T storage");
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(dtheta[k])) return fail(c, LBM_EINVAL, "tangent direction must be finite");
+    if (c->p.eos == LBM_EOS_PR && (dtheta[1] != 0.0 || dtheta[2] != 0.0))
+        return fail(c, LBM_EINVAL, "PR tangents support d dp and d T only");
+    for (int k = 0; k < 4; ++k) c->dtheta[k] = dtheta[k];
+    return LBM_OK;
+}
+
+lbm_status lbm_get_f_tangent(lbm_ctx* c, double* df) {
+    if (!c || !df) return LBM_EINVAL;
+    if (c->p.storage != LBM_F64T) return fail(c, LBM_EINVAL, "lbm_get_f_tangent needs F64T storage");
+    if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    std::vector<unsigned char> raw((size_t)c->plane * 9 * 16);
+    HIP_TRY(c, hipMemcpyAsync(raw.data(), c->dev + c->off_f[c->cur], raw.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 9; ++i)
+        for (int y = 0; y < c->ny; ++y)
+            for (int x = 0; x < c->nx; ++x) {
+                const size_t src = (size_t)i * c->plane + (size_t)y * c->pitch + x;
+                std::memcpy(&df[((size_t)i * c->ny + y) * c->nx + x], raw.data() + src * 16 + 8, 8);
+            }
     return LBM_OK;
 }
 
@@ -864,7 +914,7 @@ lbm_status lbm_batch_create(int n, const int* nx, const int* ny, const double* t
         const lbm_params& p = params[k];
         // one kernel instance serves every case: storage, EOS kind and tile shape agree, and the
         // cases are checked together
-        if (p.storage != p0.storage || p.eos != p0.eos || p.schedule != lbm::kScheduleTile ||
+        if (p.storage != p0.storage || p.storage == LBM_F64T || p.eos != p0.eos || p.schedule != lbm::kScheduleTile ||
             p.tile_rows != p0.tile_rows || p.tile_waves != p0.tile_waves || p.check_every != p0.check_every) {
             delete b;
             return LBM_EINVAL;

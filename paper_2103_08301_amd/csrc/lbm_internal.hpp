@@ -16,7 +16,7 @@ namespace lbm {
 // force stencil grad(lap rho) needs.
 constexpr int kStripOut = 60;
 constexpr int kWavesPerBlock = 4;
-constexpr int kPartialVals = 9;  // tmax, xtmax, tmin, xtmin, pmax, xpmax, pmin, xpmin, sum tau^2
+constexpr int kPartialVals = 10;  // tmax, xtmax, tmin, xtmin, pmax, xpmax, pmin, xpmin, sum tau^2, its tangent
 constexpr int kScheduleTile = 0;   // block-per-tile kernel with LDS-coupled phases
 constexpr int kScheduleMarch = 1;  // wave-per-strip row march with a register window
 constexpr int kSchedulePipe = 2;   // persistent blocks taking tiles by ticket, next tile's loads in flight
@@ -27,6 +27,12 @@ constexpr int kTicketStride = 32;  // counters 256 bytes apart (in 64-bit words)
 // as scalars instead of converting the FP64 values in every wave.
 struct CoefF32 {
     float tau, s_e, s_eps, s_q, s_j, s_v, k2, kappa, g, nu, RT, a_eff, b, rho_w, rho0;
+};
+
+// Tangents of the step coefficients along the parameter direction of the
+// tangent-linear storage (zero otherwise).  Only g, RT, a_eff and b move.
+struct CoefTangent {
+    double tau, s_e, s_eps, s_q, s_j, s_v, k2, kappa, g, nu, RT, a_eff, b, rho_w, rho0;
 };
 
 // Everything one launch of the step kernel needs, passed by value.
@@ -45,6 +51,7 @@ struct StepArgs {
     double rho_w;             // wall ghost density
     double rho0;              // storage shift (F16S/BF16S)
     CoefF32 cf;               // the coefficients above, rounded to FP32
+    CoefTangent ct;           // their tangents (tangent-linear storage)
     double* tau_w;            // [2][nx] wall shear of this step
     double* p_w;              // [2][nx] wall pressure of this step
     double* partial;          // [2][nstrip][kPartialVals] this step's per-strip wall extremes
@@ -83,8 +90,8 @@ hipError_t launch_wall_reduce(const double* partial_ring, int nsteps, int nstrip
                               lbm_stress_summary* hist, int hist_cap, double* scratch, double* acc, hipStream_t s);
 
 constexpr int kFieldReduceBlocks = 512;
-constexpr int kWallScratchVals = 10;  // per step: peak tau^2, sum tau^2, tau max/min, p max/min per wall
-constexpr int kWallAccVals = 10;      // int peak tau^2, int sum tau^2, running tau max/min, p max/min per wall
+constexpr int kWallScratchVals = 11;  // per step: peak tau^2, sum tau^2, tau max/min, p max/min per wall, d sum tau^2
+constexpr int kWallAccVals = 11;      // int peak tau^2, int sum tau^2, running tau/p max/min per wall, d int tau^2
 
 // Liquid components of a host density field (lbm_post.cpp).
 lbm_status label_components(const double* rho, int nx, int ny, bool xper, bool yper, double threshold, double rho_g,

@@ -156,13 +156,62 @@ __device__ inline double recip(double x) { return 1.0 / x; }
 
 // A step coefficient in the arithmetic type: the FP64 value, or its FP32
 // rounding made on the host (the same value a conversion here would give).
+// ---------------------------------------------------------------------------
+// Tangent-linear arithmetic: a value and its derivative along one direction of
+// the parameters (dp, a, b, T).  Running the step in this type propagates the
+// exact derivative of every quantity (forward-mode differentiation).
+struct Dual {
+    double v, d;
+    Dual() = default;  // trivial, so LDS arrays of Dual need no constructor
+    __device__ constexpr Dual(double x) : v(x), d(0) {}  // constants have no tangent
+    __device__ constexpr Dual(double x, double dx) : v(x), d(dx) {}
+    __device__ explicit operator double() const { return v; }
+};
+__device__ inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ inline Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+__device__ inline Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+__device__ inline Dual recip(Dual a) {
+    const double r = 1.0 / a.v;
+    return Dual(r, -a.d * r * r);
+}
+__device__ inline double value_of(double x) { return x; }
+__device__ inline double value_of(float x) { return x; }
+__device__ inline double value_of(Dual x) { return x.v; }
+__device__ inline double tangent_of(double) { return 0.0; }
+__device__ inline double tangent_of(float) { return 0.0; }
+__device__ inline double tangent_of(Dual x) { return x.d; }
+
 template <class C>
-__device__ inline C coef(double d, float f);
+__device__ inline C coef(double d, float f, double t);
 template <>
-__device__ inline double coef<double>(double d, float) { return d; }
+__device__ inline double coef<double>(double d, float, double) { return d; }
 template <>
-__device__ inline float coef<float>(double, float f) { return f; }
-#define LBM_COEF(C, name) coef<C>(a.name, a.cf.name)
+__device__ inline float coef<float>(double, float f, double) { return f; }
+template <>
+__device__ inline Dual coef<Dual>(double d, float, double t) { return Dual(d, t); }
+#define LBM_COEF(C, name) coef<C>(a.name, a.cf.name, a.ct.name)
+
+template <>
+__host__ __device__ inline Dual wgt<Dual>(int i) {
+    return Dual(wgt<double>(i));
+}
+
+// FP64 value and FP64 tangent of each population (16 bytes), tangent-linear arithmetic.
+struct CodecF64T {
+    using S = Dual;
+    using C = Dual;
+    template <int I>
+    __device__ static C decode(S s, C) { return s; }
+    template <int I>
+    __device__ static C load(const S* p, C r) { return decode<I>(*p, r); }
+    template <int I>
+    __device__ static S encode(C v, C) { return v; }
+    template <int I>
+    __device__ static void store(S* p, C v, C r) { *p = encode<I>(v, r); }
+};
 
 // x-neighbours across the 64 lanes of a wave with DPP wave shifts (a VALU
 // operand modifier, no LDS traffic): wave_shl:1 reads lane + 1 (column x + 1),
@@ -327,8 +376,16 @@ __device__ inline void buffer_store(_Float16 v, __amdgpu_buffer_rsrc_t r, uint32
 __device__ inline void buffer_store(uint16_t v, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0) {
     __builtin_amdgcn_raw_buffer_store_b16(v, r, off, soff, 0);
 }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ inline void buffer_store(Dual v, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, soff, 0);
+}
 template <class S>
 __device__ inline S buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff);
+template <>
+__device__ inline Dual buffer_load<Dual>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(Dual, __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0));
+}
 template <>
 __device__ inline double buffer_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
@@ -555,11 +612,12 @@ struct Stepper {
         wave_argmax(pmax, xpmax);
         wave_argmin(pmin, xpmin);
         const double s2 = wave_sum(dt * dt);
+        const double ds2 = wave_sum(out_lane ? 2.0 * dt * tangent_of(tw) : 0.0);  // d(sum tau^2) along the tangent
         if (lane == 0) {
             double* o = a.partial + ((long long)w * a.nstrip + strip) * kPartialVals;
             o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
             o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
-            o[8] = s2;
+            o[8] = s2; o[9] = ds2;
         }
     }
 };
@@ -816,11 +874,12 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
         wave_argmax(pmax, xpmax);
         wave_argmin(pmin, xpmin);
         const double s2 = wave_sum(dt * dt);
+        const double ds2 = wave_sum(out_lane ? 2.0 * dt * tangent_of(tw) : 0.0);  // d(sum tau^2) along the tangent
         if (lane == 0) {
             double* o = partial + ((long long)w * a.nstrip + strip) * kPartialVals;
             o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
             o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
-            o[8] = s2;
+            o[8] = s2; o[9] = ds2;
         }
     }
 }
@@ -1092,11 +1151,12 @@ struct Pipe {
                 wave_argmax(pmax, xpmax);
                 wave_argmin(pmin, xpmin);
                 const double s2 = wave_sum(dt * dt);
+                const double ds2 = wave_sum(out_lane ? 2.0 * dt * tangent_of(tw) : 0.0);  // d(sum tau^2) along the tangent
                 if (lane == 0) {
                     double* o = a.partial + ((long long)w * a.nstrip + g.strip) * kPartialVals;
                     o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
                     o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
-                    o[8] = s2;
+                    o[8] = s2; o[9] = ds2;
                 }
             }
         }
@@ -1262,11 +1322,11 @@ __global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __re
     const double* slot = ring + (long long)t * 2 * nstrip * kPartialVals;
     lbm_stress_summary sm;
     sm.step = first_step + t;
-    double pk = 0.0, s2 = 0.0;
+    double pk = 0.0, s2 = 0.0, ds2 = 0.0;
     for (int w = 0; w < 2; ++w) {
         const double* p = slot + (long long)w * nstrip * kPartialVals;
         double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
-        double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0;
+        double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0, wds = 0.0;
         for (int st = lane; st < nstrip; st += 64) {
             const double* q = p + (long long)st * kPartialVals;
             comb_max(tmax, xtmax, q[0], q[1]);
@@ -1274,6 +1334,7 @@ __global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __re
             comb_max(pmax, xpmax, q[4], q[5]);
             comb_min(pmin, xpmin, q[6], q[7]);
             ws += q[8];
+            wds += q[9];
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -1282,7 +1343,9 @@ __global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __re
             comb_max(pmax, xpmax, __shfl_xor(pmax, off, 64), __shfl_xor(xpmax, off, 64));
             comb_min(pmin, xpmin, __shfl_xor(pmin, off, 64), __shfl_xor(xpmin, off, 64));
             ws += __shfl_xor(ws, off, 64);
+            wds += __shfl_xor(wds, off, 64);
         }
+        ds2 += wds;
         sm.tau_max[w] = tmax; sm.tau_min[w] = tmin; sm.p_max[w] = pmax; sm.p_min[w] = pmin;
         sm.x_tau_max[w] = int32_t(xtmax); sm.x_tau_min[w] = int32_t(xtmin);
         sm.x_p_max[w] = int32_t(xpmax); sm.x_p_min[w] = int32_t(xpmin);
@@ -1291,8 +1354,10 @@ __global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __re
     }
     if (lane == 0) {
         sm.sum_tau2 = s2;
+        sm.d_sum_tau2 = ds2;
         sm.int_peak_tau2 = 0.0;
         sm.int_tau2 = 0.0;
+        sm.d_int_tau2 = 0.0;
         hist[(sm.step - 1) % hist_cap] = sm;
         double* o = scratch + (long long)t * kWallScratchVals;
         o[0] = pk;
@@ -1303,21 +1368,23 @@ __global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __re
             o[6 + w] = sm.p_max[w];
             o[8 + w] = sm.p_min[w];
         }
+        o[10] = ds2;
     }
 }
 
 // Running time integrals and running extremes, in step order (single thread).
 // acc: [0] int peak tau^2, [1] int sum tau^2, [2 + 2q + w] running extreme q
-// (tau max, tau min, p max, p min) of wall w.
+// (tau max, tau min, p max, p min) of wall w, [10] tangent of int sum tau^2.
 __global__ void wall_integrate_kernel(const double* __restrict__ scratch, int nsteps, int64_t first_step,
                                       lbm_stress_summary* hist, int hist_cap, double* acc) {
-    double ip = acc[0], is = acc[1];
+    double ip = acc[0], is = acc[1], dis = acc[10];
     double run[8];
     for (int q = 0; q < 8; ++q) run[q] = acc[2 + q];
     for (int k = 0; k < nsteps; ++k) {
         const double* o = scratch + (long long)k * kWallScratchVals;
         ip += o[0];
         is += o[1];
+        dis += o[10];
         for (int w = 0; w < 2; ++w) {
             run[w] = fmax(run[w], o[2 + w]);
             run[2 + w] = fmin(run[2 + w], o[4 + w]);
@@ -1327,6 +1394,7 @@ __global__ void wall_integrate_kernel(const double* __restrict__ scratch, int ns
         lbm_stress_summary* h = &hist[(first_step + k - 1) % hist_cap];
         h->int_peak_tau2 = ip;
         h->int_tau2 = is;
+        h->d_int_tau2 = dis;
         for (int w = 0; w < 2; ++w) {
             h->run_tau_max[w] = run[w];
             h->run_tau_min[w] = run[2 + w];
@@ -1336,6 +1404,7 @@ __global__ void wall_integrate_kernel(const double* __restrict__ scratch, int ns
     }
     acc[0] = ip;
     acc[1] = is;
+    acc[10] = dis;
     for (int q = 0; q < 8; ++q) acc[2 + q] = run[q];
 }
 
@@ -1451,6 +1520,11 @@ hipError_t launch_step_c(const StepArgs& a, int eos, bool emit, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s) {
+    if (storage == LBM_F64T) {  // tangent-linear runs use the tile schedule with 12-row, 8-wave tiles only
+        if (a.schedule != kScheduleTile || a.ty != 12 || a.tile_waves != 8) return hipErrorInvalidValue;
+        return eos == LBM_EOS_CS ? launch_tile<CodecF64T, LBM_EOS_CS, 12, 8>(a, emit, s)
+                                 : launch_tile<CodecF64T, LBM_EOS_PR, 12, 8>(a, emit, s);
+    }
     switch (storage) {
         case LBM_F64: return launch_step_c<CodecF64>(a, eos, emit, s);
         case LBM_F32: return launch_step_c<CodecF32>(a, eos, emit, s);
@@ -1522,6 +1596,7 @@ hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, lo
         case LBM_BF16S: hipLaunchKernelGGL(init_kernel<CodecBF16S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
         case LBM_F32D: hipLaunchKernelGGL(init_kernel<CodecF32D>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
         case LBM_F32S: hipLaunchKernelGGL(init_kernel<CodecF32S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        case LBM_F64T: hipLaunchKernelGGL(init_kernel<CodecF64T>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

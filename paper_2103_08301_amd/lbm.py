@@ -19,16 +19,16 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_EOS_CS, LBM_EOS_PR = 0, 1
-LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F32D, LBM_F32S = 0, 1, 2, 3, 4, 5
+LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F32D, LBM_F32S, LBM_F64T = 0, 1, 2, 3, 4, 5, 6
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S, "f32d": LBM_F32D,
-           "f32s": LBM_F32S}
+           "f32s": LBM_F32S, "f64t": LBM_F64T}
 
 EXPORTED = [
     "lbm_params_default", "lbm_create", "lbm_workspace", "lbm_bind", "lbm_state", "lbm_init_plug",
     "lbm_init_density", "lbm_step", "lbm_step_count", "lbm_fields", "lbm_wall_stress", "lbm_stress_history",
     "lbm_check_state", "lbm_components", "lbm_components_field", "lbm_get_f", "lbm_set_f", "lbm_destroy",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_workspace", "lbm_batch_bind", "lbm_batch_case",
-    "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error",
+    "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_set_tangent", "lbm_get_f_tangent",
 ]
 
 
@@ -58,6 +58,7 @@ class lbm_stress_summary(C.Structure):
         ("sum_tau2", C.c_double), ("int_peak_tau2", C.c_double), ("int_tau2", C.c_double),
         ("run_tau_max", C.c_double * 2), ("run_tau_min", C.c_double * 2),
         ("run_p_max", C.c_double * 2), ("run_p_min", C.c_double * 2),
+        ("d_sum_tau2", C.c_double), ("d_int_tau2", C.c_double),
     ]
 
 
@@ -126,6 +127,8 @@ def library():
             "lbm_components_field": (C.c_int, [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                                C.c_int, C.POINTER(lbm_component), C.c_int64, C.POINTER(C.c_int64),
                                                C.POINTER(lbm_aerosol_summary)]),
+            "lbm_set_tangent": (C.c_int, [_P, _D]),
+            "lbm_get_f_tangent": (C.c_int, [_P, _D]),
             "lbm_get_f": (C.c_int, [_P, _D]),
             "lbm_set_f": (C.c_int, [_P, _D]),
             "lbm_destroy": (None, [_P]),
@@ -267,6 +270,16 @@ def lbm_components_field(rho: np.ndarray, threshold: float, rho_g: float = 0.0, 
     return [struct_dict(buf[i]) for i in range(n.value)], struct_dict(summ)
 
 
+def lbm_set_tangent(ctx, dtheta):
+    d = np.ascontiguousarray(dtheta, dtype=np.float64)
+    assert d.shape == (4,)
+    _check(ctx, library().lbm_set_tangent(ctx, _ptr(d)))
+
+
+def lbm_get_f_tangent(ctx, df: np.ndarray):
+    _check(ctx, library().lbm_get_f_tangent(ctx, _ptr(df)))
+
+
 def lbm_get_f(ctx, f: np.ndarray):
     _check(ctx, library().lbm_get_f(ctx, _ptr(f)))
 
@@ -374,6 +387,16 @@ class Lattice:
         f = np.empty((9, self.ny, self.nx))
         lbm_get_f(self._ctx, f)
         return f
+
+    def set_tangent(self, dp: float = 0.0, a: float = 0.0, b: float = 0.0, T: float = 0.0):
+        """F64T storage: tangent direction in (dp, a, b, absolute T); the state's tangent restarts at zero
+        with each initialisation."""
+        lbm_set_tangent(self._ctx, [dp, a, b, T])
+
+    def get_f_tangent(self) -> np.ndarray:
+        df = np.empty((9, self.ny, self.nx))
+        lbm_get_f_tangent(self._ctx, df)
+        return df
 
     def set_f(self, f: np.ndarray):
         assert f.shape == (9, self.ny, self.nx)

@@ -80,7 +80,8 @@ def test_defaults(L):
     dict(eos=3), dict(x_periodic=2), dict(rho_wall=-1.0), dict(dp=math.inf), dict(tile_waves=6),
     dict(tile_waves=8, tile_rows=8), dict(schedule=0, tile_rows=16), dict(schedule=3), dict(schedule=2, tile_rows=20),
     dict(schedule=2, tile_waves=8, tile_rows=12), dict(schedule=2, pipe_blocks=4), dict(pipe_blocks=64),
-    dict(schedule=1, tile_waves=4),
+    dict(schedule=1, tile_waves=4), dict(storage=6, schedule=1), dict(storage=6, tile_rows=8),
+    dict(storage=6, tile_waves=4),
 ])
 def test_create_rejects_invalid_parameters(L, bad):
     with pytest.raises(L.LbmError) as e:
