@@ -149,6 +149,45 @@ def size_sweep(storage: str) -> int:
     return 0
 
 
+def tangent_cost(steps: int, warmup: int) -> int:
+    """Per-step time of the tangent-linear step (FP64 value + FP64 tangent per
+    population, one parameter direction) against the FP64 step, 4096x512."""
+    from paper_2103_08301_amd import workloads
+
+    out = {"metric": "tangent-linear step cost, 4096x512", "steps": steps}
+    for storage in ("f64", "f64t"):
+        w = workloads.plug_large_stable("f64")
+        w["storage"] = storage
+        lat = make_lattice(w, check_every=max(steps, warmup, 1))
+        if storage == "f64t":
+            lat.set_tangent(dp=1.0)
+        t, _, lat = _time_lattice(lat, steps, warmup)
+        nodes = w["nx"] * w["ny"]
+        out[storage] = {"us_per_step": round(t / steps * 1e6, 2), "MLUPS": round(nodes * steps / t / 1e6, 1),
+                        "GBps_algorithmic": round((144 if storage == "f64" else 288) * nodes / (t / steps) / 1e9, 1)}
+        if storage == "f64t":
+            out["d_int_tau2"] = lat.history(1)[-1]["d_int_tau2"]
+        del lat
+    out["ratio_tangent_over_f64"] = round(out["f64t"]["us_per_step"] / out["f64"]["us_per_step"], 3)
+    out["gradient_4_params_over_f64"] = round(4 * out["ratio_tangent_over_f64"], 2)
+    print(json.dumps(finite(out)), flush=True)
+    return 0
+
+
+def _time_lattice(lat, steps: int, warmup: int):
+    import torch
+
+    if warmup:
+        lat.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, None, lat
+
+
 def sweep_cases() -> list:
     """48 uneven cases shaped like the sweeps of Sec. 3.3 (Figs 10-12): channels of
     radius 32, 48 and 64 cells (nx = 8 R), pressure drops, plug and film
@@ -224,6 +263,8 @@ def main() -> int:
                     help="only run a plain device-to-device copy of MIB mebibytes 10 times (counter calibration)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only time the step on grids from 64x16 to 3072x1024 (fixed per-launch cost vs bytes)")
+    ap.add_argument("--tangent", action="store_true",
+                    help="only time the tangent-linear (F64T) step against the FP64 step on the timed workload")
     ap.add_argument("--batch", action="store_true",
                     help="only time 48 uneven sweep cases as one batch against the same cases stepped one by one")
     args = ap.parse_args()
@@ -261,6 +302,8 @@ def main() -> int:
     lbm.library()  # fail loudly if the HIP library is missing
     if args.size_sweep:
         return size_sweep(args.storage)
+    if args.tangent:
+        return tangent_cost(steps=min(args.steps, 2000), warmup=min(args.warmup, 100))
     if args.batch:
         return batch_sweep(args.storage, steps=min(args.steps, 2000), warmup=min(args.warmup, 100))
 
