@@ -203,6 +203,12 @@ lbm_status lbm_stress_history(lbm_ctx* ctx, lbm_stress_summary* buf, int64_t cap
 /* Result of the latest stability/interface check. */
 lbm_status lbm_check_state(const lbm_ctx* ctx, lbm_check_result* out);
 
+/* Restarts the running extremes of the wall summaries (run_tau_*, run_p_*)
+   from the next step on, so that their spans cover a chosen window (for
+   example the rupture, without the start-up transient).  Time integrals and
+   step counts are unchanged.  Enqueued on the bound stream. */
+lbm_status lbm_reset_stress_extremes(lbm_ctx* ctx);
+
 /* One connected region of liquid cells (rho > threshold) of a density field.
    Sec. 3.2 and 3.3 of the paper follow the droplets that break away from the
    plug and the wall films during rupture ("aerosols") and their mass; here an

@@ -820,6 +820,15 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
     return LBM_OK;
 }
 
+lbm_status lbm_reset_stress_extremes(lbm_ctx* c) {
+    if (!c) return LBM_EINVAL;
+    if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    double* acc = c->at<double>(c->off_acc);
+    for (int q = 0; q < 4; ++q)  // every lbm_step call flushes the wall ring, so no earlier step is pending
+        HIP_TRY(c, lbm::launch_fill(acc + 2 + 2 * q, (q % 2 == 0) ? -INFINITY : INFINITY, 2, c->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_set_tangent(lbm_ctx* c, const double* dtheta) {
     if (!c || !dtheta) return LBM_EINVAL;
     if (c->p.storage != LBM_F64T) return fail(c, LBM_EINVAL, "lbm_set_tangent needs F64T storage");

@@ -64,6 +64,22 @@ struct StepArgs {
 };
 
 hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s);
+// Per storage type (one translation unit each, lbm_step_<type>.hip): the step,
+// batch-step and pipelined-grid launchers that launch_step, launch_step_batch
+// and pipe_grid dispatch to.
+#define LBM_DECLARE_STORAGE_LAUNCHERS(NAME)                                                                   \
+    hipError_t launch_step_##NAME(const StepArgs& a, int eos, bool emit, hipStream_t s);                     \
+    hipError_t launch_batch_##NAME(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, \
+                                   int parity, int slot, int eos, int ty, int waves, bool emit, hipStream_t s); \
+    hipError_t pipe_grid_##NAME(int eos, int ty, int waves, int* blocks);
+LBM_DECLARE_STORAGE_LAUNCHERS(f64)
+LBM_DECLARE_STORAGE_LAUNCHERS(f32)
+LBM_DECLARE_STORAGE_LAUNCHERS(f16s)
+LBM_DECLARE_STORAGE_LAUNCHERS(bf16s)
+LBM_DECLARE_STORAGE_LAUNCHERS(f32d)
+LBM_DECLARE_STORAGE_LAUNCHERS(f32s)
+#undef LBM_DECLARE_STORAGE_LAUNCHERS
+hipError_t launch_step_f64t(const StepArgs& a, int eos, bool emit, hipStream_t s);
 // One step of many lattices in one launch (tile schedule): cases[c] holds case
 // c's arguments with both distribution buffers (f[0] as fin, f[1] as fout) and
 // the base of its wall ring; tile_start[c] is its first tile (device arrays).

@@ -29,6 +29,7 @@ EXPORTED = [
     "lbm_check_state", "lbm_components", "lbm_components_field", "lbm_get_f", "lbm_set_f", "lbm_destroy",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_workspace", "lbm_batch_bind", "lbm_batch_case",
     "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_set_tangent", "lbm_get_f_tangent",
+    "lbm_reset_stress_extremes",
 ]
 
 
@@ -127,6 +128,7 @@ def library():
             "lbm_components_field": (C.c_int, [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                                C.c_int, C.POINTER(lbm_component), C.c_int64, C.POINTER(C.c_int64),
                                                C.POINTER(lbm_aerosol_summary)]),
+            "lbm_reset_stress_extremes": (C.c_int, [_P]),
             "lbm_set_tangent": (C.c_int, [_P, _D]),
             "lbm_get_f_tangent": (C.c_int, [_P, _D]),
             "lbm_get_f": (C.c_int, [_P, _D]),
@@ -378,6 +380,10 @@ class Lattice:
 
     def check(self) -> dict:
         return lbm_check_state(self._ctx)
+
+    def reset_stress_extremes(self):
+        """Restart the running wall-stress extremes from the next step on."""
+        _check(self._ctx, library().lbm_reset_stress_extremes(self._ctx))
 
     def components(self, threshold: float = math.nan, connectivity: int = 4):
         """Liquid components of the last step's density and the aerosol totals."""

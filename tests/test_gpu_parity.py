@@ -288,3 +288,25 @@ def test_instability_is_reported_at_a_check():
     assert st == lbm.LBM_EUNSTABLE
     ref.step(2000)
     assert lat.check()["unstable_step"] == ref.unstable_step
+
+
+def test_reset_stress_extremes_restarts_the_running_spans():
+    """After a reset the running extremes cover only the later steps: they equal the extremes of the per-step
+    wall summaries (themselves compared with the oracle above) over that window; the time integrals go on."""
+    lat, ref = pair(96, 24, 1.0, dp=1e-3)
+    rho0 = plug_density(ref, 20, 3, noise=1e-3, seed=5)
+    lat.init_density(rho0)
+    assert lat.step(40) == 0
+    int_before = lat.history(1)[-1]["int_tau2"]
+    lat.reset_stress_extremes()
+    assert lat.step(60) == 0
+    hist = lat.history()
+    window = [h for h in hist if h["step"] > 40]
+    assert len(window) == 60
+    last = hist[-1]
+    for w in (0, 1):
+        assert last["run_tau_max"][w] == max(h["tau_max"][w] for h in window)
+        assert last["run_tau_min"][w] == min(h["tau_min"][w] for h in window)
+        assert last["run_p_max"][w] == max(h["p_max"][w] for h in window)
+        assert last["run_p_min"][w] == min(h["p_min"][w] for h in window)
+    assert last["int_tau2"] > int_before  # the integral is not restarted
