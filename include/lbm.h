@@ -203,6 +203,45 @@ lbm_status lbm_stress_history(lbm_ctx* ctx, lbm_stress_summary* buf, int64_t cap
 /* Result of the latest stability/interface check. */
 lbm_status lbm_check_state(const lbm_ctx* ctx, lbm_check_result* out);
 
+/* Reverse-mode sensitivities (adjoint) of the wall-shear objective
+   J = sum over steps, walls and columns of tau_w^2 (the time integral of
+   squared wall shear, int_tau2 of lbm_stress_summary; Figs. 3, 5 and 8 and
+   Sec. 3.2-3.3 study the wall stresses against the pressure drop and the
+   fluid), with respect to theta = (dp, a, b, T), T the absolute temperature.
+   The initial state and the wall ghost density are held fixed, as for
+   lbm_set_tangent.  One backward sweep gives all four derivatives: each
+   adjoint step is the exact transpose of the step of eq. 2.1 with the force
+   of eq. 2.17 (halfway bounce-back, extrapolated or periodic ends and wetting
+   ghost rows included), run backwards from the last step.
+
+   Memory: nsteps steps are recorded with one checkpoint of the state every
+   `segment` steps (0 picks ceil(sqrt(nsteps))); the backward sweep recomputes
+   each segment's states from its checkpoint.  The adjoint workspace holds
+   ceil(nsteps/segment) + segment states, two adjoint fields of the arithmetic
+   type, segment x 2 x nx FP64 wall shears and small scratch; it is
+   caller-owned device memory like the main workspace, 256-byte aligned, and
+   bound once.  Storage F64, F32 or F32D with the tile schedule; otherwise
+   LBM_EINVAL. */
+lbm_status lbm_adjoint_workspace(const lbm_ctx* ctx, int64_t nsteps, int64_t segment, size_t* bytes);
+lbm_status lbm_adjoint_bind(lbm_ctx* ctx, void* device_ptr, size_t bytes, int64_t nsteps, int64_t segment);
+
+/* Runs the next nsteps steps from the lattice's current state (through
+   lbm_step, so checks and summaries proceed as usual) and records the
+   checkpoints.  *J (may be NULL) receives J over these steps.  Errors of
+   lbm_step (LBM_EUNSTABLE) are returned as they are; the record is then
+   incomplete and lbm_adjoint_backward refuses it (LBM_ESTATE). */
+lbm_status lbm_adjoint_forward(lbm_ctx* ctx, double* J);
+
+/* Backward sweep over the recorded steps: grad[4] = seed * dJ/d(dp, a, b, T).
+   For PR, dJ/da and dJ/db are NaN (alpha(T) depends on the critical
+   temperature and with it on a and b).  Host grad; blocks until done.  The
+   record stays valid, so the sweep can be repeated with another seed. */
+lbm_status lbm_adjoint_backward(lbm_ctx* ctx, double seed, double* grad);
+
+/* After lbm_adjoint_backward: seed * dJ/df*_i(x) of the recorded run's initial
+   post-collision state, host FP64 [9][ny][nx]. */
+lbm_status lbm_adjoint_state_gradient(lbm_ctx* ctx, double* dJ_df);
+
 /* Restarts the running extremes of the wall summaries (run_tau_*, run_p_*)
    from the next step on, so that their spans cover a chosen window (for
    example the rupture, without the start-up transient).  Time integrals and

@@ -5,6 +5,6 @@ include/lbm.h); `lbm` is its ctypes binding.  Importing the package does not
 load the library; the first call that needs it raises if it is not built.
 """
 from . import lbm  # noqa: F401
-from .lbm import Batch, Lattice  # noqa: F401
+from .lbm import Batch, Lattice, WallShearObjective  # noqa: F401
 
-__all__ = ["lbm", "Batch", "Lattice"]
+__all__ = ["lbm", "Batch", "Lattice", "WallShearObjective"]

@@ -1,2 +1,515 @@
-// lbm_adjoint.hip -- placeholder
+// lbm_adjoint.hip -- reverse-mode (adjoint) step of the EOS-based multiphase
+// MRT lattice Boltzmann method (arXiv 2103.08301, Sec. 2).
+//
+// Objective: J = sum over steps, walls and columns of tau_w^2 (the time
+// integral of the squared wall shear of Figs. 3, 5 and 8).  One launch takes
+// the adjoint of one step n backwards: given lam_in = dJ/df(x) of step n + 1's
+// pulled populations (before its own streaming adjoint), it produces lam_out,
+// the same quantity for step n, and the step's contribution to dJ/dtheta.
+//
+// Forward step n, per fluid node (eqs. 2.1, 2.2, 2.12, 2.17; Sec. 2.2-2.3):
+//   f_i(x)  = f*_{i}(x - e_i)            (bounce-back / clamped / wrapped)
+//   rho, j  = sum f_i, sum e_i f_i
+//   phi     = k^2 p0(rho) - rho/3,  L = lap rho,  F = -grad phi + kappa rho grad L + (g, 0)
+//   P       = j + tau F,  u = P / rho,  v = (j + F/2) / rho
+//   f*      = f - M^-1 S (M f - m_eq(rho, P))
+//   tau_w   = rho nu (9 v_x(s=1/2) - v_x(s=3/2)) / 3 on the two rows next to a wall
+// The adjoint runs these in reverse with the transposed operators: the
+// collision's Jacobian in f is the constant symmetric I - M^T D M (D = S /
+// |row|^2), the gradient stencil transposes to minus a divergence and the
+// Laplacian to itself, ghost copies of the end columns add their adjoints back
+// into the copied column, and the pull transposes to a gather of lam_in from
+// the downstream neighbours x + e_i (bounce-back from the node itself).
+//
+// A tile of 64 columns (56 outputs and a 4-column halo on each side) by TYO + 8
+// rows recomputes the forward quantities it needs from step n's input state:
+// the force adjoint at a node needs lam and the forward force within 2 nodes,
+// which need rho within 4.  Phases, with barriers between them:
+//   A  pull the state, rho/phi to LDS (radius 4), gather lam (radius 2)
+//   B  Laplacian of rho (radius 3)
+//   C  force, velocity shift, wall seeds, the collision's vector-Jacobian
+//      product: the local part of dJ/df and the force adjoint F~ (radius 2)
+//   D  phi~ = div F~ and L~ = -div(kappa rho F~) (radius 1)
+//   E  rho~ = lap L~ + phi'(rho) phi~ (+ ghost columns), store dJ/df, and the
+//      parameter sums sum F~_x, sum phi~ dphi/d(RT, a_eff, b)
+// No MFMA: like the forward step this is a bandwidth-bound stencil.
 #include "lbm_device.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int kAdjHalo = 4;
+
+// A value and its partial derivatives along four independent inputs
+// (forward mode), for the local derivatives of the equation of state.
+template <class C>
+struct G4 {
+    C v, d[4];
+    G4() = default;
+    __device__ constexpr G4(double x) : v(C(x)), d{C(0), C(0), C(0), C(0)} {}
+    __device__ static G4 var(C x, int k) {
+        G4 r(0.0);
+        r.v = x;
+        r.d[k] = C(1);
+        return r;
+    }
+};
+template <class C>
+__device__ inline G4<C> operator+(const G4<C>& a, const G4<C>& b) {
+    G4<C> r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] + b.d[k];
+    return r;
+}
+template <class C>
+__device__ inline G4<C> operator-(const G4<C>& a, const G4<C>& b) {
+    G4<C> r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+template <class C>
+__device__ inline G4<C> operator*(const G4<C>& a, const G4<C>& b) {
+    G4<C> r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+template <class C>
+__device__ inline G4<C> recip(const G4<C>& a) {
+    const C q = recip(a.v);
+    G4<C> r;
+    r.v = q;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.d[k] = -a.d[k] * q * q;
+    return r;
+}
+
+// dphi/drho and dphi/d(RT, a_eff, b) at one density.
+template <int EOS, class C>
+__device__ inline void phi_partials(C rho, C RT, C a_eff, C b, C k2, C& d_rho, C& d_RT, C& d_a, C& d_b) {
+    using G = G4<C>;
+    const G out = phi_of<EOS, G>(G::var(rho, 0), G::var(RT, 1), G::var(a_eff, 2), G::var(b, 3), G(double(k2)));
+    d_rho = out.d[0];
+    d_RT = out.d[1];
+    d_a = out.d[2];
+    d_b = out.d[3];
+}
+
+// Transpose of the pull at fluid node (xe, yr): lam_i(x) = dJ/df*_i(x) gathers
+// the adjoint of every pulled population that was read from f*_i(x).
+//  * x + e_i beyond a wall: node x bounced it back into its own population
+//    opposite to i, so lam_i(x) = lb_opp(i)(x).
+//  * otherwise node x + e_i pulled it (wrapped with periodic ends, absent past
+//    an extrapolated end), and at an extrapolated end the end node of row
+//    y + e_iy also read it through the clamped source column.
+template <class C>
+__device__ inline void gather_lambda(const C* __restrict__ lb, const StepArgs& a, int xe, int yr, C (&lam)[9]) {
+#define LBM_GATHER(I)                                                                           \
+    {                                                                                           \
+        int ty = yr + ey(I);                                                                    \
+        if (!a.yper && (ty < 0 || ty >= a.ny)) {                                                \
+            lam[I] = lb[(long long)opp(I) * a.plane + (long long)yr * a.pitch + xe];            \
+        } else {                                                                                \
+            if (a.yper) ty = wrapi(ty, a.ny);                                                   \
+            const C* row = lb + (long long)(I) * a.plane + (long long)ty * a.pitch;             \
+            const int tx = xe + ex(I);                                                          \
+            C v = C(0);                                                                         \
+            if (a.xper) {                                                                       \
+                v = row[wrapi(tx, a.nx)];                                                       \
+            } else {                                                                            \
+                if (tx >= 0 && tx < a.nx) v = row[tx];                                          \
+                if (ex(I) == 1 && xe == 0) v += row[0];                                         \
+                if (ex(I) == -1 && xe == a.nx - 1) v += row[a.nx - 1];                          \
+            }                                                                                   \
+            lam[I] = v;                                                                         \
+        }                                                                                       \
+    }
+    LBM_GATHER(0) LBM_GATHER(1) LBM_GATHER(2) LBM_GATHER(3) LBM_GATHER(4) LBM_GATHER(5) LBM_GATHER(6)
+    LBM_GATHER(7) LBM_GATHER(8)
+#undef LBM_GATHER
+}
+
+// div of a vector field on three rows with the gradient stencil of grad3:
+// sum_i 3 w_i e_i . V(x + e_i).
+template <class C>
+__device__ inline C div3(const Row3<C>& sx, const Row3<C>& mx, const Row3<C>& nx_, const Row3<C>& sy,
+                         const Row3<C>& ny_) {
+    return C(1.0 / 3.0) * (mx.e - mx.w) + C(1.0 / 12.0) * ((nx_.e - nx_.w) + (sx.e - sx.w)) +
+           C(1.0 / 3.0) * (ny_.c - sy.c) + C(1.0 / 12.0) * ((ny_.e + ny_.w) - (sy.e + sy.w));
+}
+
+template <class CD, int EOS, int TYO, int NW>
+__global__ __launch_bounds__(64 * NW) void adjoint_kernel(const AdjArgs A) {
+    using S = typename CD::S;
+    using C = typename CD::C;
+    constexpr int H = TYO + 2 * kAdjHalo;
+    constexpr int RPT = H / NW;
+    static_assert(H % NW == 0, "tile height must be a multiple of the waves per block");
+    __shared__ C sRho[H][64], sPhi[H][64], sLap[H][64], sFx[H][64], sFy[H][64];
+    __shared__ double sRed[NW][4];
+
+    const StepArgs& a = A.s;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = bid / A.nstrip;
+    const int strip = bid - tile * A.nstrip;
+    const int y0 = (a.ny >= TYO) ? min(tile * TYO, a.ny - TYO) : 0;
+    const int x = strip * kAdjStripOut - kAdjHalo + lane;
+    const bool xin = x >= 0 && x < a.nx;
+    const bool xfl = a.xper || xin;
+    int xe = x;
+    if (!xin) xe = a.xper ? wrapi(x, a.nx) : clampi(x, 0, a.nx - 1);
+    const bool out_lane = lane >= kAdjHalo && lane < 64 - kAdjHalo && xin;
+    const int lm = lane > 0 ? lane - 1 : 0, lp = lane < 63 ? lane + 1 : 63;  // edge lanes are halo: clamped, unused
+
+    const S* __restrict__ fin = static_cast<const S*>(a.fin);
+    const C* __restrict__ lb = static_cast<const C*>(A.lam_in);
+    C* __restrict__ lout = static_cast<C*>(A.lam_out);
+    const C rho0 = LBM_COEF(C, rho0);
+    const C RT = LBM_COEF(C, RT), a_eff = LBM_COEF(C, a_eff), bb = LBM_COEF(C, b);
+    const C k2 = LBM_COEF(C, k2), kappa = LBM_COEF(C, kappa), g = LBM_COEF(C, g);
+    const C rho_w = LBM_COEF(C, rho_w), tau = LBM_COEF(C, tau), nu = LBM_COEF(C, nu);
+    const C s_e = LBM_COEF(C, s_e), s_eps = LBM_COEF(C, s_eps), s_q = LBM_COEF(C, s_q);
+    const C s_j = LBM_COEF(C, s_j), s_v = LBM_COEF(C, s_v);
+
+    // ---- phase A: pull, density, EOS field; gather lam -------------------------
+    C jx[RPT], jy[RPT], lam[RPT][9];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + NW * j;
+        const int r = y0 - kAdjHalo + k;
+        const bool yfl = a.yper || (r >= 0 && r < a.ny);
+        const int yr = a.yper ? wrapi(r, a.ny) : r;
+        C rho = rho_w;
+        jx[j] = C(0);
+        jy[j] = C(0);
+        if (yfl) {
+            C f[9];
+            pull_generic<CD>(fin, a, xe, yr, rho0, f);
+            rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+            jx[j] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+            jy[j] = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
+        }
+        sRho[k][lane] = rho;
+        sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+        sFx[k][lane] = C(0);
+        sFy[k][lane] = C(0);
+        if (k >= 2 && k <= H - 3 && yfl && xfl) {
+            gather_lambda<C>(lb, a, xe, yr, lam[j]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) lam[j][i] = C(0);
+        }
+    }
+    __syncthreads();
+
+    // ---- phase B: Laplacian of rho on rows 1 .. H-2 ------------------------------
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + NW * j;
+        if (k >= 1 && k <= H - 2) {
+            const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
+            const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
+            const Row3<C> n{sRho[k + 1][lane], sRho[k + 1][lp], sRho[k + 1][lm]};
+            sLap[k][lane] = lap3(s, m, n);
+        }
+    }
+    __syncthreads();
+
+    // Force at tile row k of this lane (rows 2 .. H-3), with the forward step's expressions.
+    auto force = [&](int k, C& Fx, C& Fy, C& glx, C& gly) {
+        C gphx, gphy;
+        {
+            const Row3<C> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
+            const Row3<C> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
+            const Row3<C> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
+            grad3(s, m, n, gphx, gphy);
+        }
+        {
+            const Row3<C> s{sLap[k - 1][lane], sLap[k - 1][lp], sLap[k - 1][lm]};
+            const Row3<C> m{sLap[k][lane], sLap[k][lp], sLap[k][lm]};
+            const Row3<C> n{sLap[k + 1][lane], sLap[k + 1][lp], sLap[k + 1][lm]};
+            grad3(s, m, n, glx, gly);
+        }
+        const C rh = sRho[k][lane];
+        Fx = -gphx + kappa * rh * glx + g;
+        Fy = -gphy + kappa * rh * gly;
+    };
+
+    // ---- phase C: the collision's vector-Jacobian product --------------------------
+    const bool walls = !a.yper;
+    double acc_g = 0.0;
+    C fb[RPT][9];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + NW * j;
+        const int y = y0 - kAdjHalo + k;
+        const bool yfl = a.yper || (y >= 0 && y < a.ny);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fb[j][i] = C(0);
+        if (k < 2 || k > H - 3 || !yfl || !xfl) continue;
+        C Fx, Fy, glx, gly;
+        force(k, Fx, Fy, glx, gly);
+        const C rh = sRho[k][lane];
+        const C inv = recip(rh);
+        const C Px = jx[j] + tau * Fx, Py = jy[j] + tau * Fy;
+        const C ux = Px * inv, uy = Py * inv;
+        // seeds of J = sum tau_w^2 on the two rows next to each wall: dJ/dtau_w = 2 tau_w, with
+        // tau_w = rho_w nu (9 v_x(1/2) - v_x(3/2)) / 3 of this step (written by its forward recompute)
+        C vbx = C(0), rbw = C(0);
+        if (walls && (y <= 1 || y >= a.ny - 2)) {
+            const bool bottom = y <= 1;
+            const int kw = bottom ? (y == 0 ? k : k - 1) : (y == a.ny - 1 ? k : k + 1);  // row next to the wall
+            const C rw = sRho[kw][lane];
+            const C tw = C(A.tau_w[(bottom ? 0 : a.nx) + xe]);
+            const C tb = C(2) * tw;
+            if (y == 0 || y == a.ny - 1) {
+                rbw = tb * tw * recip(rw);  // d tau_w / d rho_w = tau_w / rho_w
+                vbx = tb * rw * nu * C(3);
+            } else {
+                vbx = -(tb * rw * nu * C(1.0 / 3.0));
+            }
+        }
+        const C vx = (jx[j] + C(0.5) * Fx) * inv;
+        C* l = lam[j];
+        // moments of lam, scaled by the relaxation rates over the squared row norms
+        const C A4 = (l[1] + l[2]) + (l[3] + l[4]);
+        const C D4 = (l[5] + l[6]) + (l[7] + l[8]);
+        const C ne = s_e * C(1.0 / 36.0) * (C(-4) * l[0] - A4 + C(2) * D4);
+        const C neps = s_eps * C(1.0 / 36.0) * (C(4) * l[0] - C(2) * A4 + D4);
+        const C njx = s_j * C(1.0 / 6.0) * ((l[1] - l[3]) + (l[5] - l[6]) + (l[8] - l[7]));
+        const C nqx = s_q * C(1.0 / 12.0) * (C(2) * (l[3] - l[1]) + ((l[5] - l[6]) - (l[7] - l[8])));
+        const C njy = s_j * C(1.0 / 6.0) * ((l[2] - l[4]) + (l[5] - l[8]) + (l[6] - l[7]));
+        const C nqy = s_q * C(1.0 / 12.0) * (C(2) * (l[4] - l[2]) + ((l[5] + l[6]) - (l[7] + l[8])));
+        const C nxx = s_v * C(0.25) * ((l[1] + l[3]) - (l[2] + l[4]));
+        const C nxy = s_v * C(0.25) * ((l[5] + l[7]) - (l[6] + l[8]));
+        // m_eq = (rho, 3|P|^2/rho - 2 rho, rho - 3|P|^2/rho, Px, -Px, Py, -Py, (Px^2 - Py^2)/rho, Px Py/rho)
+        const C u2 = ux * ux + uy * uy;
+        C rb = ne * (C(-2) - C(3) * u2) + neps * (C(1) + C(3) * u2) - nxx * (ux * ux - uy * uy) - nxy * (ux * uy);
+        const C dee = C(6) * (ne - neps);
+        const C Pbx = dee * ux + (njx - nqx) + C(2) * nxx * ux + nxy * uy;
+        const C Pby = dee * uy + (njy - nqy) - C(2) * nxx * uy + nxy * ux;
+        // P = j + tau F; v = (j + F/2)/rho
+        const C jbx = Pbx + vbx * inv, jby = Pby;
+        const C Fbx = tau * Pbx + C(0.5) * vbx * inv, Fby = tau * Pby;
+        rb += rbw - vbx * vx * inv;
+        rb += kappa * (glx * Fbx + gly * Fby);  // F contains kappa rho grad L
+        sFx[k][lane] = Fbx;
+        sFy[k][lane] = Fby;
+        if (k >= kAdjHalo && k < kAdjHalo + TYO && out_lane && y < a.ny) {
+            acc_g += double(Fbx);
+            // f~ = lam - M^T (D M lam) + rho~ + e . j~ (rho~ gets the stencil terms in phase E)
+            const C c0 = -ne - C(2) * neps, c1 = C(2) * ne + neps;
+            const C X = njx - C(2) * nqx, Y = njy - C(2) * nqy, Xd = njx + nqx, Yd = njy + nqy;
+            fb[j][0] = l[0] - C(4) * (neps - ne) + rb;
+            fb[j][1] = l[1] - (c0 + X + nxx) + rb + jbx;
+            fb[j][3] = l[3] - (c0 - X + nxx) + rb - jbx;
+            fb[j][2] = l[2] - (c0 + Y - nxx) + rb + jby;
+            fb[j][4] = l[4] - (c0 - Y - nxx) + rb - jby;
+            fb[j][5] = l[5] - (c1 + Xd + Yd + nxy) + rb + jbx + jby;
+            fb[j][7] = l[7] - (c1 - Xd - Yd + nxy) + rb - jbx - jby;
+            fb[j][6] = l[6] - (c1 - Xd + Yd - nxy) + rb - jbx + jby;
+            fb[j][8] = l[8] - (c1 + Xd - Yd - nxy) + rb + jbx - jby;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase D: phi~ = div F~, L~ = -div(kappa rho F~) on rows 1 .. H-2 -----------
+    // Both overwrite their forward fields (phi, L), which nothing reads any more.
+    C phib[RPT], lapb[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + NW * j;
+        phib[j] = C(0);
+        lapb[j] = C(0);
+        if (k < 1 || k > H - 2) continue;
+        const Row3<C> sx{sFx[k - 1][lane], sFx[k - 1][lp], sFx[k - 1][lm]};
+        const Row3<C> mx{sFx[k][lane], sFx[k][lp], sFx[k][lm]};
+        const Row3<C> nx_{sFx[k + 1][lane], sFx[k + 1][lp], sFx[k + 1][lm]};
+        const Row3<C> sy{sFy[k - 1][lane], sFy[k - 1][lp], sFy[k - 1][lm]};
+        const Row3<C> ny_{sFy[k + 1][lane], sFy[k + 1][lp], sFy[k + 1][lm]};
+        phib[j] = div3(sx, mx, nx_, sy, ny_);
+#define LBM_G(F, kk, ll) (kappa * sRho[kk][ll] * F[kk][ll])
+        const Row3<C> gsx{LBM_G(sFx, k - 1, lane), LBM_G(sFx, k - 1, lp), LBM_G(sFx, k - 1, lm)};
+        const Row3<C> gmx{LBM_G(sFx, k, lane), LBM_G(sFx, k, lp), LBM_G(sFx, k, lm)};
+        const Row3<C> gnx{LBM_G(sFx, k + 1, lane), LBM_G(sFx, k + 1, lp), LBM_G(sFx, k + 1, lm)};
+        const Row3<C> gsy{LBM_G(sFy, k - 1, lane), LBM_G(sFy, k - 1, lp), LBM_G(sFy, k - 1, lm)};
+        const Row3<C> gny{LBM_G(sFy, k + 1, lane), LBM_G(sFy, k + 1, lp), LBM_G(sFy, k + 1, lm)};
+#undef LBM_G
+        lapb[j] = -div3(gsx, gmx, gnx, gsy, gny);
+    }
+    // every read of phi and L (phases A-C) is behind the barrier above
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + NW * j;
+        if (k < 1 || k > H - 2) continue;
+        sPhi[k][lane] = phib[j];
+        sLap[k][lane] = lapb[j];
+    }
+    __syncthreads();
+
+    // ---- phase E: rho~, dJ/df of the outputs, parameter sums ------------------------
+    double acc_rt = 0.0, acc_a = 0.0, acc_b = 0.0;
+    auto rho_bar_at = [&](int k, int l2, C& dRT, C& dA, C& dB) {
+        // lap(L~) + phi'(rho) phi~ at tile position (k, l2); returns the EOS partials too
+        const Row3<C> s{sLap[k - 1][l2], sLap[k - 1][l2 + 1], sLap[k - 1][l2 - 1]};
+        const Row3<C> m{sLap[k][l2], sLap[k][l2 + 1], sLap[k][l2 - 1]};
+        const Row3<C> n{sLap[k + 1][l2], sLap[k + 1][l2 + 1], sLap[k + 1][l2 - 1]};
+        C dr;
+        phi_partials<EOS, C>(sRho[k][l2], RT, a_eff, bb, k2, dr, dRT, dA, dB);
+        return lap3(s, m, n) + dr * sPhi[k][l2];
+    };
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + NW * j;
+        const int y = y0 - kAdjHalo + k;
+        if (k < kAdjHalo || k >= kAdjHalo + TYO || !out_lane || y >= a.ny) continue;  // y < ny: fluid row
+        C dRT, dA, dB;
+        C rb = rho_bar_at(k, lane, dRT, dA, dB);
+        const C ph = sPhi[k][lane];
+        acc_rt += double(ph * dRT);
+        acc_a += double(ph * dA);
+        acc_b += double(ph * dB);
+        if (!a.xper && (x == 0 || x == a.nx - 1)) {
+            // ghost columns copy this end column: their adjoints add back here
+            const int sgn = x == 0 ? -1 : 1;
+            C t0, t1, t2;
+            rb += rho_bar_at(k, lane + sgn, t0, t1, t2);
+            rb += rho_bar_at(k, lane + 2 * sgn, t0, t1, t2);
+        }
+        const bool edge = (!a.yper && (y == 0 || y == a.ny - 1)) || (!a.xper && (x == 0 || x == a.nx - 1));
+        if (edge) {
+            // ghost positions next to the domain whose nearest node is this one: their phi
+            // depends on the parameters (wall rows at the fixed rho_w, end columns at copies)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int zx = x + dx, zy = y + dy;
+                    const bool zyf = a.yper || (zy >= 0 && zy < a.ny);
+                    const bool zxf = a.xper || (zx >= 0 && zx < a.nx);
+                    if (zyf && zxf) continue;
+                    const int px = a.xper ? wrapi(zx, a.nx) : clampi(zx, 0, a.nx - 1);
+                    const int py = a.yper ? wrapi(zy, a.ny) : clampi(zy, 0, a.ny - 1);
+                    if (px != x || py != y) continue;
+                    C dr, tRT, tA, tB;
+                    phi_partials<EOS, C>(sRho[k + dy][lane + dx], RT, a_eff, bb, k2, dr, tRT, tA, tB);
+                    const C pz = sPhi[k + dy][lane + dx];
+                    acc_rt += double(pz * tRT);
+                    acc_a += double(pz * tA);
+                    acc_b += double(pz * tB);
+                }
+        }
+        const long long o = (long long)y * a.pitch + x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lout[(long long)i * a.plane + o] = fb[j][i] + rb;
+    }
+
+    // ---- block sums of the parameter adjoints (fixed order) ----------------------
+    const double r0 = wave_sum(acc_g), r1 = wave_sum(acc_rt), r2 = wave_sum(acc_a), r3 = wave_sum(acc_b);
+    if (lane == 0) {
+        sRed[wave][0] = r0;
+        sRed[wave][1] = r1;
+        sRed[wave][2] = r2;
+        sRed[wave][3] = r3;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += sRed[w][threadIdx.x];
+        A.partial[(long long)blockIdx.x * 4 + threadIdx.x] = t;
+    }
+}
+
+// Sums n consecutive groups of 4 partials in a fixed order and adds them to acc[0..3].
+constexpr int kAdjRedThreads = 256;
+__global__ __launch_bounds__(kAdjRedThreads) void adjoint_reduce_kernel(const double* __restrict__ partial, long long n,
+                                                                        double* __restrict__ acc) {
+    __shared__ double sh[4][kAdjRedThreads];
+    const int t = threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = t; i < n; i += kAdjRedThreads)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += partial[i * 4 + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh[q][t] = v[q];
+    __syncthreads();
+    for (int s = kAdjRedThreads / 2; s > 0; s >>= 1) {
+        if (t < s)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sh[q][t] += sh[q][t + s];
+        __syncthreads();
+    }
+    if (t < 4) acc[t] += sh[t][0];
+}
+
+// dJ/df* of the initial state: the pull transpose of the last adjoint step's
+// output, as FP64 [9][ny][nx].
+template <class C>
+__global__ void adjoint_gather_kernel(const C* __restrict__ lb, const StepArgs a, double* __restrict__ out) {
+    const long long n = (long long)a.nx * a.ny;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        const int y = int(c / a.nx), x = int(c - (long long)y * a.nx);
+        C lam[9];
+        gather_lambda<C>(lb, a, x, y, lam);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[(long long)i * n + c] = double(lam[i]);
+    }
+}
+
+template <class CD, int EOS, int TYO, int NW>
+hipError_t launch_adj_t(const AdjArgs& A, hipStream_t s) {
+    const dim3 grid(A.nstrip * ((A.s.ny + TYO - 1) / TYO)), block(64 * NW);
+    hipLaunchKernelGGL((adjoint_kernel<CD, EOS, TYO, NW>), grid, block, 0, s, A);
+    return hipGetLastError();
+}
+
+template <class CD>
+hipError_t launch_adj_c(const AdjArgs& A, int eos, hipStream_t s) {
+    return eos == LBM_EOS_CS ? launch_adj_t<CD, LBM_EOS_CS, kAdjTileRows, 8>(A, s)
+                             : launch_adj_t<CD, LBM_EOS_PR, kAdjTileRows, 8>(A, s);
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjArgs& A, int storage, int eos, hipStream_t s) {
+    switch (storage) {
+        case LBM_F64: return launch_adj_c<CodecF64>(A, eos, s);
+        case LBM_F32: return launch_adj_c<CodecF32>(A, eos, s);
+        case LBM_F32D: return launch_adj_c<CodecF32D>(A, eos, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adjoint_reduce(const double* partial, long long ngroups, double* acc, hipStream_t s) {
+    if (ngroups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(1), dim3(kAdjRedThreads), 0, s, partial, ngroups, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gather(const void* lam, const StepArgs& a, int storage, double* out, hipStream_t s) {
+    const long long n = (long long)a.nx * a.ny;
+    const int blocks = int((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+    switch (storage) {
+        case LBM_F64:
+        case LBM_F32D:
+            hipLaunchKernelGGL(adjoint_gather_kernel<double>, dim3(blocks), dim3(256), 0, s,
+                               static_cast<const double*>(lam), a, out);
+            break;
+        case LBM_F32:
+            hipLaunchKernelGGL(adjoint_gather_kernel<float>, dim3(blocks), dim3(256), 0, s,
+                               static_cast<const float*>(lam), a, out);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int adjoint_blocks(int nx, int ny) {
+    return ((nx + kAdjStripOut - 1) / kAdjStripOut) * ((ny + kAdjTileRows - 1) / kAdjTileRows);
+}
+
+}  // namespace lbm

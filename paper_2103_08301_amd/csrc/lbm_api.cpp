@@ -259,6 +259,17 @@ struct lbm_ctx {
     bool bound = false, initialized = false;
     bool in_batch = false;  // owned by an lbm_batch: stepped only through lbm_batch_step
     double dtheta[4] = {0, 0, 0, 0};  // F64T: tangent direction (dp, a, b, T)
+    // reverse-mode sensitivities (lbm_adjoint_*): a second caller-owned workspace
+    struct Adjoint {
+        char* dev = nullptr;
+        bool bound = false, recorded = false, swept = false;
+        int64_t n = 0, seg = 0, nckpt = 0;  // recorded steps, segment length, checkpoints
+        size_t state = 0, lam = 0;          // bytes of one state / one adjoint field (aligned)
+        size_t off_ckpt = 0, off_seg = 0, off_lam[2]{}, off_tw = 0, off_part = 0, off_acc = 0, off_scr = 0,
+               off_pw = 0, off_g0 = 0, total = 0;
+        int blocks = 0, cur = 0;
+        double J = 0, seed = 1;
+    } adj;
     int cur = 0;
     int64_t steps = 0;
     int ring_fill = 0;
@@ -853,6 +864,167 @@ lbm_status lbm_get_f_tangent(lbm_ctx* c, double* df) {
                 const size_t src = (size_t)i * c->plane + (size_t)y * c->pitch + x;
                 std::memcpy(&df[((size_t)i * c->ny + y) * c->nx + x], raw.data() + src * 16 + 8, 8);
             }
+    return LBM_OK;
+}
+
+// ---- reverse-mode sensitivities ------------------------------------------------
+
+namespace {
+constexpr int kAdjRing = 64;  // adjoint launches whose parameter partials are reduced together
+
+size_t adjoint_arith_bytes(int storage) { return storage == LBM_F32 ? 4 : 8; }
+
+lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm_ctx::Adjoint& A) {
+    if (c->p.storage != LBM_F64 && c->p.storage != LBM_F32 && c->p.storage != LBM_F32D) return LBM_EINVAL;
+    if (c->schedule != lbm::kScheduleTile || nsteps < 1 || segment < 0 || segment > nsteps) return LBM_EINVAL;
+    A.n = nsteps;
+    A.seg = segment > 0 ? segment : (int64_t)std::ceil(std::sqrt((double)nsteps));
+    A.nckpt = (nsteps + A.seg - 1) / A.seg;
+    A.state = align256((size_t)c->plane * 9 * storage_bytes(c->p.storage));
+    A.lam = align256((size_t)c->plane * 9 * adjoint_arith_bytes(c->p.storage));
+    A.blocks = lbm::adjoint_blocks(c->nx, c->ny);
+    size_t o = 0;
+    A.off_ckpt = o; o += (size_t)A.nckpt * A.state;
+    A.off_seg = o; o += (size_t)A.seg * A.state;
+    A.off_lam[0] = o; o += A.lam;
+    A.off_lam[1] = o; o += A.lam;
+    A.off_tw = o; o += align256((size_t)A.seg * 2 * c->nx * sizeof(double));
+    A.off_part = o; o += align256((size_t)kAdjRing * A.blocks * 4 * sizeof(double));
+    A.off_acc = o; o += 256;
+    A.off_scr = o; o += align256((size_t)2 * c->nstrip * lbm::kPartialVals * sizeof(double));
+    A.off_pw = o; o += align256((size_t)2 * c->nx * sizeof(double));
+    A.off_g0 = o; o += align256((size_t)9 * c->nx * c->ny * sizeof(double));
+    A.total = o;
+    return LBM_OK;
+}
+}  // namespace
+
+lbm_status lbm_adjoint_workspace(const lbm_ctx* c, int64_t nsteps, int64_t segment, size_t* bytes) {
+    if (!c || !bytes) return LBM_EINVAL;
+    lbm_ctx::Adjoint A;
+    lbm_status s = adjoint_layout(c, nsteps, segment, A);
+    if (s) return s;
+    *bytes = A.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_bind(lbm_ctx* c, void* device_ptr, size_t bytes, int64_t nsteps, int64_t segment) {
+    if (!c) return LBM_EINVAL;
+    if (c->in_batch) return fail(c, LBM_ESTATE, "a batch case has no adjoint");
+    lbm_ctx::Adjoint A;
+    if (adjoint_layout(c, nsteps, segment, A))
+        return fail(c, LBM_EINVAL, "adjoint: storage must be f64, f32 or f32d with the tile schedule, "
+                                   "1 <= nsteps and 0 <= segment <= nsteps");
+    if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
+        return fail(c, LBM_EINVAL, "adjoint workspace pointer must be non-null and 256-byte aligned");
+    if (bytes < A.total) return fail(c, LBM_ENOMEM, "adjoint workspace of %zu bytes < %zu needed", bytes, A.total);
+    A.dev = static_cast<char*>(device_ptr);
+    A.bound = true;
+    c->adj = A;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_forward(lbm_ctx* c, double* J) {
+    if (!c) return LBM_EINVAL;
+    if (!c->adj.bound) return fail(c, LBM_ESTATE, "lbm_adjoint_bind must come first");
+    if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_adjoint_forward needs an initialised lattice");
+    lbm_ctx::Adjoint& A = c->adj;
+    A.recorded = A.swept = false;
+    lbm_status s = flush_wall(c);
+    if (s) return s;
+    double acc0[2], acc1[2];
+    HIP_TRY(c, hipMemcpyAsync(acc0, c->dev + c->off_acc, sizeof acc0, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const size_t fbytes = (size_t)c->plane * 9 * storage_bytes(c->p.storage);
+    for (int64_t k = 0; k < A.nckpt; ++k) {
+        HIP_TRY(c, hipMemcpyAsync(A.dev + A.off_ckpt + (size_t)k * A.state, c->dev + c->off_f[c->cur], fbytes,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        s = lbm_step(c, std::min(A.seg, A.n - k * A.seg));
+        if (s) return s;
+    }
+    HIP_TRY(c, hipMemcpyAsync(acc1, c->dev + c->off_acc, sizeof acc1, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    A.J = acc1[1] - acc0[1];  // time integral of sum tau_w^2 over the recorded steps
+    A.recorded = true;
+    if (J) *J = A.J;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
+    if (!c || !grad || !std::isfinite(seed)) return LBM_EINVAL;
+    lbm_ctx::Adjoint& A = c->adj;
+    if (!A.bound || !A.recorded) return fail(c, LBM_ESTATE, "lbm_adjoint_backward needs lbm_adjoint_forward first");
+    const int storage = c->p.storage, eos = c->p.eos;
+    lbm::StepArgs base = make_args(c);
+    auto state = [&](int64_t ck, int64_t start, int64_t k) -> char* {  // state after step k of segment ck
+        return k == start ? A.dev + A.off_ckpt + (size_t)ck * A.state : A.dev + A.off_seg + (size_t)(k - start - 1) * A.state;
+    };
+    double* tw = reinterpret_cast<double*>(A.dev + A.off_tw);
+    double* part = reinterpret_cast<double*>(A.dev + A.off_part);
+    double* acc = reinterpret_cast<double*>(A.dev + A.off_acc);
+    HIP_TRY(c, lbm::launch_fill(reinterpret_cast<double*>(A.dev + A.off_lam[0]), 0.0, (long long)(A.lam / 8), c->stream));
+    HIP_TRY(c, lbm::launch_fill(acc, 0.0, 4, c->stream));
+    A.cur = 0;
+    lbm::StepArgs fa = base;  // forward recompute: wall shear to the per-step slots, other diagnostics to scratch
+    fa.partial = reinterpret_cast<double*>(A.dev + A.off_scr);
+    fa.p_w = reinterpret_cast<double*>(A.dev + A.off_pw);
+    lbm::AdjArgs aa{};
+    aa.s = base;
+    aa.nstrip = (c->nx + lbm::kAdjStripOut - 1) / lbm::kAdjStripOut;
+    int ring = 0;
+    for (int64_t ck = A.nckpt - 1; ck >= 0; --ck) {
+        const int64_t start = ck * A.seg, end = std::min(start + A.seg, A.n);
+        for (int64_t k = start + 1; k <= end; ++k) {
+            fa.fin = state(ck, start, k - 1);
+            fa.fout = state(ck, start, k);
+            fa.tau_w = tw + (size_t)(k - start - 1) * 2 * c->nx;
+            HIP_TRY(c, lbm::launch_step(fa, storage, eos, false, c->stream));
+        }
+        for (int64_t k = end; k > start; --k) {
+            aa.s.fin = state(ck, start, k - 1);
+            aa.lam_in = A.dev + A.off_lam[A.cur];
+            aa.lam_out = A.dev + A.off_lam[1 - A.cur];
+            aa.tau_w = tw + (size_t)(k - start - 1) * 2 * c->nx;
+            aa.partial = part + (size_t)ring * A.blocks * 4;
+            HIP_TRY(c, lbm::launch_adjoint(aa, storage, eos, c->stream));
+            A.cur = 1 - A.cur;
+            if (++ring == kAdjRing) {
+                HIP_TRY(c, lbm::launch_adjoint_reduce(part, (long long)ring * A.blocks, acc, c->stream));
+                ring = 0;
+            }
+        }
+    }
+    if (ring > 0) HIP_TRY(c, lbm::launch_adjoint_reduce(part, (long long)ring * A.blocks, acc, c->stream));
+    double sums[4];
+    HIP_TRY(c, hipMemcpyAsync(sums, acc, sizeof sums, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // theta = (dp, a, b, T): g = dp/nx, RT = R T, a_eff = a alpha(T) (alpha = 1 for CS), b
+    grad[0] = seed * sums[0] / c->nx;
+    if (eos == LBM_EOS_CS) {
+        grad[1] = seed * sums[2];
+        grad[2] = seed * sums[3];
+        grad[3] = seed * sums[1] * c->eos.R;
+    } else {  // PR: alpha depends on T/Tc and Tc on (a, b); like the tangents, only dp and T
+        grad[1] = NAN;
+        grad[2] = NAN;
+        grad[3] = seed * (sums[1] * c->eos.R + sums[2] * c->eos.a * pr_alpha_dT(c->p.omega, c->eos.T, c->eos.Tc));
+    }
+    A.seed = seed;
+    A.swept = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_state_gradient(lbm_ctx* c, double* dJ_df) {
+    if (!c || !dJ_df) return LBM_EINVAL;
+    lbm_ctx::Adjoint& A = c->adj;
+    if (!A.bound || !A.swept) return fail(c, LBM_ESTATE, "lbm_adjoint_state_gradient needs lbm_adjoint_backward first");
+    lbm::StepArgs a = make_args(c);
+    double* g0 = reinterpret_cast<double*>(A.dev + A.off_g0);
+    HIP_TRY(c, lbm::launch_adjoint_gather(A.dev + A.off_lam[A.cur], a, c->p.storage, g0, c->stream));
+    const size_t n = (size_t)9 * c->nx * c->ny;
+    HIP_TRY(c, hipMemcpyAsync(dJ_df, g0, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < n; ++i) dJ_df[i] *= A.seed;
     return LBM_OK;
 }
 

@@ -29,7 +29,8 @@ EXPORTED = [
     "lbm_check_state", "lbm_components", "lbm_components_field", "lbm_get_f", "lbm_set_f", "lbm_destroy",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_workspace", "lbm_batch_bind", "lbm_batch_case",
     "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_set_tangent", "lbm_get_f_tangent",
-    "lbm_reset_stress_extremes",
+    "lbm_reset_stress_extremes", "lbm_adjoint_workspace", "lbm_adjoint_bind", "lbm_adjoint_forward",
+    "lbm_adjoint_backward", "lbm_adjoint_state_gradient",
 ]
 
 
@@ -129,6 +130,11 @@ def library():
                                                C.c_int, C.POINTER(lbm_component), C.c_int64, C.POINTER(C.c_int64),
                                                C.POINTER(lbm_aerosol_summary)]),
             "lbm_reset_stress_extremes": (C.c_int, [_P]),
+            "lbm_adjoint_workspace": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+            "lbm_adjoint_bind": (C.c_int, [_P, _P, C.c_size_t, C.c_int64, C.c_int64]),
+            "lbm_adjoint_forward": (C.c_int, [_P, _D]),
+            "lbm_adjoint_backward": (C.c_int, [_P, C.c_double, _D]),
+            "lbm_adjoint_state_gradient": (C.c_int, [_P, _D]),
             "lbm_set_tangent": (C.c_int, [_P, _D]),
             "lbm_get_f_tangent": (C.c_int, [_P, _D]),
             "lbm_get_f": (C.c_int, [_P, _D]),
@@ -282,6 +288,37 @@ def lbm_get_f_tangent(ctx, df: np.ndarray):
     _check(ctx, library().lbm_get_f_tangent(ctx, _ptr(df)))
 
 
+def lbm_adjoint_workspace(ctx, nsteps: int, segment: int = 0) -> int:
+    n = C.c_size_t()
+    st = library().lbm_adjoint_workspace(ctx, nsteps, segment, C.byref(n))
+    if st != LBM_OK:
+        raise LbmError(st, f"lbm_adjoint_workspace({nsteps}, {segment}) rejected the request")
+    return n.value
+
+
+def lbm_adjoint_bind(ctx, device_ptr: int, nbytes: int, nsteps: int, segment: int = 0):
+    _check(ctx, library().lbm_adjoint_bind(ctx, C.c_void_p(device_ptr), nbytes, nsteps, segment))
+
+
+def lbm_adjoint_forward(ctx) -> tuple:
+    """Returns (status, J): status LBM_OK or LBM_EUNSTABLE; other failures raise."""
+    J = C.c_double(math.nan)
+    st = library().lbm_adjoint_forward(ctx, C.byref(J))
+    if st not in (LBM_OK, LBM_EUNSTABLE):
+        _check(ctx, st)
+    return st, J.value
+
+
+def lbm_adjoint_backward(ctx, seed: float = 1.0) -> np.ndarray:
+    g = np.empty(4)
+    _check(ctx, library().lbm_adjoint_backward(ctx, seed, _ptr(g)))
+    return g
+
+
+def lbm_adjoint_state_gradient(ctx, out: np.ndarray):
+    _check(ctx, library().lbm_adjoint_state_gradient(ctx, _ptr(out)))
+
+
 def lbm_get_f(ctx, f: np.ndarray):
     _check(ctx, library().lbm_get_f(ctx, _ptr(f)))
 
@@ -408,6 +445,28 @@ class Lattice:
         assert f.shape == (9, self.ny, self.nx)
         lbm_set_f(self._ctx, f)
 
+    def adjoint_bind(self, nsteps: int, segment: int = 0):
+        """Device workspace for recording nsteps steps with a checkpoint every `segment` steps."""
+        import torch
+
+        nbytes = lbm_adjoint_workspace(self._ctx, nsteps, segment)
+        self.adjoint_workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            lbm_adjoint_bind(self._ctx, self.adjoint_workspace.data_ptr(), nbytes, nsteps, segment)
+
+    def adjoint_forward(self) -> tuple:
+        """Runs and records the bound number of steps; returns (status, J = int of sum tau_w^2)."""
+        return lbm_adjoint_forward(self._ctx)
+
+    def adjoint_backward(self, seed: float = 1.0) -> np.ndarray:
+        """seed * dJ/d(dp, a, b, T) by one reverse sweep over the recorded steps."""
+        return lbm_adjoint_backward(self._ctx, seed)
+
+    def adjoint_state_gradient(self) -> np.ndarray:
+        g = np.empty((9, self.ny, self.nx))
+        lbm_adjoint_state_gradient(self._ctx, g)
+        return g
+
 
 class Batch:
     """Many independent channels advanced by one kernel launch per step.
@@ -464,3 +523,65 @@ class Batch:
             self.cases = []
             library().lbm_batch_destroy(b)
             self._b = None
+
+
+# ---- autograd ------------------------------------------------------------------
+
+def _wall_shear_lattice(theta, spec: dict):
+    """A lattice at theta = (dp, a, b, T) with T absolute, initialised with spec['rho_init']."""
+    dp, a, b, T = (float(v) for v in theta)
+    kw = dict(spec.get("params", {}))
+    kw.update(a=a, b=b, dp=dp)
+    probe = Lattice(spec["nx"], spec["ny"], spec["tau"], device=spec.get("device", "cuda:0"),
+                    T_over_Tc=spec.get("T_over_Tc_probe", 0.9), **kw)
+    tc = probe.state()["Tc"]  # the library's critical temperature of (a, b, R)
+    del probe
+    lat = Lattice(spec["nx"], spec["ny"], spec["tau"], device=spec.get("device", "cuda:0"), T_over_Tc=T / tc, **kw)
+    lat.init_density(spec["rho_init"])
+    return lat
+
+
+class WallShearObjective:
+    """J(theta) = time integral over `nsteps` steps of the squared wall shear summed over both walls, as a
+    differentiable function of theta = (dp, a, b, T) (a float64 tensor of 4; T absolute).  Forward runs the
+    lattice on the GPU and records checkpoints; backward is one reverse (adjoint) sweep of the hand-written
+    adjoint kernels.
+
+    spec: nx, ny, tau, nsteps, rho_init (ny x nx initial density, held fixed), params (other lbm_params
+    fields; give rho_wall to hold the wall density fixed), optional segment and device.
+
+        J = WallShearObjective.apply(theta, spec); J.backward()  ->  theta.grad
+    """
+
+    _fn = None
+
+    @staticmethod
+    def _function():
+        if WallShearObjective._fn is not None:
+            return WallShearObjective._fn
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, theta, spec):
+                lat = _wall_shear_lattice(theta.detach().cpu().tolist(), spec)
+                lat.adjoint_bind(spec["nsteps"], spec.get("segment", 0))
+                st, J = lat.adjoint_forward()
+                if st != LBM_OK:
+                    raise LbmError(st, "the forward run went unstable")
+                ctx.lattice = lat
+                ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
+                return torch.tensor(J, dtype=theta.dtype, device=theta.device)
+
+            @staticmethod
+            def backward(ctx, grad_out):
+                g = ctx.lattice.adjoint_backward(float(grad_out))
+                ctx.lattice = None
+                return torch.tensor(g, dtype=ctx.theta_dtype, device=ctx.theta_device), None
+
+        WallShearObjective._fn = _Fn
+        return _Fn
+
+    @classmethod
+    def apply(cls, theta, spec: dict):
+        return cls._function().apply(theta, spec)

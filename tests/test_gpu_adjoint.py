@@ -1,0 +1,161 @@
+"""Reverse-mode sensitivities (the hand-written adjoint of the step) of the wall-shear objective.
+
+J = int_tau2 over S steps, theta = (dp, a, b, T) with T absolute; the initial
+density and the wall ghost density are held fixed (the problem of
+sensitivity_problem.py).  One backward sweep gives all four derivatives; they
+must match
+
+  * the forward-mode (tangent-linear) derivatives of the same FP64 run to
+    rounding (the adjoint is the exact transpose of the step, so the two are
+    the same number computed in another order): relative 1e-9;
+  * Richardson-extrapolated central differences of the FP64 oracle, which
+    shares no code with the HIP path: relative 1e-6 (the difference quotients'
+    own truncation is ~1e-9);
+  * with FP32 storage and arithmetic on a 128 x 32 channel: the oracle's
+    differences within 1e-3 relative.
+
+The gradient with respect to the initial populations (lbm_adjoint_state_gradient)
+is compared with oracle differences at nodes on the walls, at the extrapolated
+ends, in the corners and inside, which exercises the transposed bounce-back,
+clamped-end and ghost-column rules.  The checkpoint segment length changes
+only the schedule of recomputation, so gradients must be bitwise equal for
+every segment length.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+from paper_2103_08301_amd import Lattice, lbm  # noqa: E402
+from paper_2103_08301_amd.lbm import WallShearObjective  # noqa: E402
+from sensitivity_problem import CS, PR, Problem, log, richardson  # noqa: E402
+
+NAMES = ["dp", "a", "b", "T"]
+
+
+def adjoint(P, storage="f64", segment=0, theta=None):
+    lat = P.lattice(P.theta0 if theta is None else theta, storage)
+    lat.adjoint_bind(P.steps, segment)
+    st, J = lat.adjoint_forward()
+    assert st == 0
+    return J, lat.adjoint_backward(), lat
+
+
+@pytest.mark.parametrize("cfg", [CS, PR], ids=lambda c: c["name"])
+def test_adjoint_equals_tangent_and_oracle_differences(cfg):
+    P = Problem(cfg)
+    J, grad, _ = adjoint(P)
+    j64 = P.J_gpu(P.theta0)
+    assert J == pytest.approx(j64, rel=1e-12)  # the recorded forward run is the FP64 run
+    for k in range(4):
+        if k not in cfg["dirs"]:
+            assert math.isnan(grad[k])  # PR: a and b are not parameters of their own
+            continue
+        _, dj = P.jvp(k)
+        fd = richardson(P.J_oracle, P.theta0, k, 1e-3)
+        log(f"{cfg['name']} dJ/d{NAMES[k]}: adjoint {grad[k]:.12e}  tangent {dj:.12e}  oracle FD {fd:.12e}  "
+            f"rel {abs(grad[k] - dj) / abs(dj):.1e} / {abs(grad[k] - fd) / abs(fd):.1e}")
+        assert grad[k] == pytest.approx(dj, rel=1e-9)
+        assert grad[k] == pytest.approx(fd, rel=1e-6)
+
+
+def test_segment_length_does_not_change_the_gradient():
+    P = Problem(CS)
+    ref = adjoint(P, segment=0)[1]
+    for seg in (1, 7, 64, P.steps):
+        g = adjoint(P, segment=seg)[1]
+        log(f"segment {seg}: {g}")
+        assert np.array_equal(g, ref), seg
+
+
+def test_fp32_adjoint_within_1e3_of_oracle_differences():
+    P = Problem(CS, nx=128, ny=32, steps=200)
+    J, grad, _ = adjoint(P, storage="f32")
+    j_or = P.J_oracle(P.theta0)
+    assert J == pytest.approx(j_or, rel=1e-3)
+    for k in CS["dirs"]:
+        fd = richardson(P.J_oracle, P.theta0, k, 1e-3)
+        log(f"FP32 dJ/d{NAMES[k]}: adjoint {grad[k]:.6e}  oracle FD {fd:.6e}  rel {abs(grad[k] - fd) / abs(fd):.1e}")
+        assert grad[k] == pytest.approx(fd, rel=1e-3)
+
+
+@pytest.mark.parametrize("xper", [0, 1])
+def test_initial_state_gradient_matches_oracle_differences(xper):
+    cfg = dict(CS)
+    P = Problem(cfg)
+    nx, ny = P.nx, P.ny
+    lat = Lattice(nx, ny, cfg["tau"], storage="f64", a=cfg["a"], b=cfg["b"], dp=cfg["dp"], k=cfg["k"],
+                  kappa=cfg["kappa"], T_over_Tc=cfg["Tr"], rho_wall=P.rho_w, x_periodic=xper, v_limit=1.0,
+                  check_every=10 ** 6)
+    lat.init_density(P.rho_init)
+    lat.adjoint_bind(P.steps, 13)
+    assert lat.adjoint_forward()[0] == 0
+    lat.adjoint_backward()
+    g = lat.adjoint_state_gradient()
+    assert np.isfinite(g).all()
+
+    p = O.params(tau=cfg["tau"], a=cfg["a"], b=cfg["b"], dp=cfg["dp"], k=cfg["k"], kappa=cfg["kappa"],
+                 T_over_Tc=cfg["Tr"], rho_wall=P.rho_w, x_periodic=xper, v_limit=1.0, check_every=10 ** 6)
+    ref = O.Sim(nx, ny, p)
+    ref.init_density(P.rho_init)
+    f0 = ref.get_f()
+
+    def J(i, y, x, h):
+        s = O.Sim(nx, ny, p)
+        s.init_density(P.rho_init)
+        f = f0.copy()
+        f[i, y, x] += h
+        s.set_f(f)
+        assert s.step(P.steps) == 0
+        return s.history()[-1]["int_tau2"]
+
+    points = [(1, 0, 0), (3, 0, nx - 1), (5, 0, 1), (7, ny - 1, nx - 1), (6, ny - 1, 0), (2, ny - 1, 40),
+              (4, 0, 50), (8, 1, 0), (1, 15, 0), (3, 15, nx - 1), (0, 16, 48), (5, 2, nx - 2), (6, 1, 2)]
+    for (i, y, x) in points:
+        h = 1e-4 * f0[i, y, x]
+        d1 = (J(i, y, x, h) - J(i, y, x, -h)) / (2 * h)
+        d2 = (J(i, y, x, h / 2) - J(i, y, x, -h / 2)) / h
+        fd = (4 * d2 - d1) / 3
+        log(f"xper {xper} dJ/df[{i},{y},{x}]: adjoint {g[i, y, x]:.10e}  oracle FD {fd:.10e}")
+        assert g[i, y, x] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(g).max())
+
+
+def test_autograd_function():
+    P = Problem(CS)
+    spec = dict(nx=P.nx, ny=P.ny, tau=CS["tau"], nsteps=P.steps, rho_init=P.rho_init,
+                params=dict(P.common(), rho_wall=P.rho_w, v_limit=1.0, check_every=10 ** 6, storage="f64"))
+    theta = torch.tensor(P.theta0, dtype=torch.float64, requires_grad=True)
+    J = WallShearObjective.apply(theta, spec)
+    (3.0 * J).backward()
+    J_ref, grad_ref, _ = adjoint(P)
+    assert float(J) == pytest.approx(J_ref, rel=1e-12)
+    assert np.allclose(theta.grad.numpy(), 3.0 * grad_ref, rtol=1e-12, atol=0)
+
+
+def test_adjoint_api_rules():
+    lat = Lattice(64, 16, 1.0, storage="f16s")
+    with pytest.raises(lbm.LbmError):
+        lat.adjoint_bind(10)  # storage without an adjoint
+    lat = Lattice(64, 16, 1.0, storage="f64")
+    with pytest.raises(lbm.LbmError):
+        lat.adjoint_bind(10, 11)  # segment longer than the run
+    lat.adjoint_bind(10)
+    with pytest.raises(lbm.LbmError) as e:
+        lat.adjoint_backward()  # nothing recorded
+    assert e.value.status == lbm.LBM_ESTATE
+    with pytest.raises(lbm.LbmError) as e:
+        lat.adjoint_forward()  # not initialised
+    assert e.value.status == lbm.LBM_ESTATE
+    lat.init_plug(16, 2)
+    st, J = lat.adjoint_forward()
+    assert st == 0 and J > 0 and lat.steps == 10
+    g1 = lat.adjoint_backward(1.0)
+    g2 = lat.adjoint_backward(-2.0)  # the record stays valid
+    assert np.array_equal(g2, -2.0 * g1)
