@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -174,6 +175,53 @@ def tangent_cost(steps: int, warmup: int) -> int:
     return 0
 
 
+def adjoint_cost(storage: str, steps: int, segment: int, large: bool) -> int:
+    """Time of one gradient of J = int sum tau_w^2 (recorded forward run with checkpoints + one reverse sweep)
+    against a plain forward run of the same steps, on the 1024x256 adjoint workload (or 4096x512)."""
+    import torch
+
+    from paper_2103_08301_amd import workloads
+
+    w = workloads.plug_large_stable(storage) if large else workloads.plug_adjoint(storage)
+    nodes = w["nx"] * w["ny"]
+    fwd = make_lattice(w, check_every=steps)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(fwd.stream)
+    st = fwd.step(steps)
+    e[1].record(fwd.stream)
+    torch.cuda.synchronize()
+    t_fwd = e[0].elapsed_time(e[1]) / 1e3
+    J_fwd = fwd.history(1)[-1]["int_tau2"]
+    del fwd
+    lat = make_lattice(w, check_every=steps)
+    lat.adjoint_bind(steps, segment)
+    torch.cuda.synchronize()
+    e[0].record(lat.stream)
+    st2, J = lat.adjoint_forward()
+    e[1].record(lat.stream)
+    grad = lat.adjoint_backward()
+    e[2].record(lat.stream)
+    torch.cuda.synchronize()
+    t_rec, t_bwd = e[0].elapsed_time(e[1]) / 1e3, e[1].elapsed_time(e[2]) / 1e3
+    seg = segment or math.ceil(math.sqrt(steps))
+    recompute_steps = steps  # every step is recomputed once from its segment's checkpoint
+    t_adj_kernel = max(t_bwd - recompute_steps * t_fwd / steps, 0.0) / steps
+    bpn = 9 * (BYTES_PER_NODE[storage] // 18) + 18 * (4 if storage == "f32" else 8)  # state read, adjoint read+write
+    out = {"metric": "adjoint/fwd time (gradient of int sum tau_w^2 w.r.t. dp, a, b, T)", "workload": w["name"],
+           "storage": storage, "steps": steps, "segment": seg, "checkpoints": math.ceil(steps / seg),
+           "forward_s": round(t_fwd, 4), "record_s": round(t_rec, 4), "backward_s": round(t_bwd, 4),
+           "adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3),
+           "forward_us_per_step": round(t_fwd / steps * 1e6, 2),
+           "adjoint_kernel_us_per_step_est": round(t_adj_kernel * 1e6, 2),
+           "adjoint_kernel_GBps_est": round(bpn * nodes / t_adj_kernel / 1e9, 1) if t_adj_kernel > 0 else None,
+           "adjoint_bytes_per_node": bpn,
+           "status": [st, st2], "J": J, "J_plain_forward": J_fwd,
+           "dJ_ddp": grad[0], "dJ_da": grad[1], "dJ_db": grad[2], "dJ_dT": grad[3]}
+    print(json.dumps(finite(out)), flush=True)
+    return 0
+
+
 def _time_lattice(lat, steps: int, warmup: int):
     import torch
 
@@ -265,6 +313,11 @@ def main() -> int:
                     help="only time the step on grids from 64x16 to 3072x1024 (fixed per-launch cost vs bytes)")
     ap.add_argument("--tangent", action="store_true",
                     help="only time the tangent-linear (F64T) step against the FP64 step on the timed workload")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only time one reverse-mode gradient against a forward run (1024x256, 20k steps)")
+    ap.add_argument("--adjoint-large", action="store_true",
+                    help="with --adjoint: the 4096x512 workload instead (--steps steps)")
+    ap.add_argument("--segment", type=int, default=0, help="with --adjoint: checkpoint spacing (0: sqrt(steps))")
     ap.add_argument("--batch", action="store_true",
                     help="only time 48 uneven sweep cases as one batch against the same cases stepped one by one")
     args = ap.parse_args()
@@ -304,6 +357,8 @@ def main() -> int:
         return size_sweep(args.storage)
     if args.tangent:
         return tangent_cost(steps=min(args.steps, 2000), warmup=min(args.warmup, 100))
+    if args.adjoint:
+        return adjoint_cost(args.storage, steps=args.steps, segment=args.segment, large=args.adjoint_large)
     if args.batch:
         return batch_sweep(args.storage, steps=min(args.steps, 2000), warmup=min(args.warmup, 100))
 

@@ -40,63 +40,35 @@ namespace {
 
 constexpr int kAdjHalo = 4;
 
-// A value and its partial derivatives along four independent inputs
-// (forward mode), for the local derivatives of the equation of state.
-template <class C>
-struct G4 {
-    C v, d[4];
-    G4() = default;
-    __device__ constexpr G4(double x) : v(C(x)), d{C(0), C(0), C(0), C(0)} {}
-    __device__ static G4 var(C x, int k) {
-        G4 r(0.0);
-        r.v = x;
-        r.d[k] = C(1);
-        return r;
-    }
-};
-template <class C>
-__device__ inline G4<C> operator+(const G4<C>& a, const G4<C>& b) {
-    G4<C> r;
-    r.v = a.v + b.v;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] + b.d[k];
-    return r;
-}
-template <class C>
-__device__ inline G4<C> operator-(const G4<C>& a, const G4<C>& b) {
-    G4<C> r;
-    r.v = a.v - b.v;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] - b.d[k];
-    return r;
-}
-template <class C>
-__device__ inline G4<C> operator*(const G4<C>& a, const G4<C>& b) {
-    G4<C> r;
-    r.v = a.v * b.v;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
-    return r;
-}
-template <class C>
-__device__ inline G4<C> recip(const G4<C>& a) {
-    const C q = recip(a.v);
-    G4<C> r;
-    r.v = q;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) r.d[k] = -a.d[k] * q * q;
-    return r;
-}
-
-// dphi/drho and dphi/d(RT, a_eff, b) at one density.
+// dphi/drho and dphi/d(RT, a_eff, b) of phi = k^2 p0(rho) - rho/3 at one density
+// (the same p0 as phi_of: eq. A9 with the van der Waals attraction, eq. A8).
 template <int EOS, class C>
 __device__ inline void phi_partials(C rho, C RT, C a_eff, C b, C k2, C& d_rho, C& d_RT, C& d_a, C& d_b) {
-    using G = G4<C>;
-    const G out = phi_of<EOS, G>(G::var(rho, 0), G::var(RT, 1), G::var(a_eff, 2), G::var(b, 3), G(double(k2)));
-    d_rho = out.d[0];
-    d_RT = out.d[1];
-    d_a = out.d[2];
-    d_b = out.d[3];
+    if (EOS == LBM_EOS_CS) {
+        // p0 = rho RT Z(eta) - a rho^2, Z = (1 + eta + eta^2 - eta^3)/(1 - eta)^3, eta = b rho/4
+        const C eta = C(0.25) * b * rho;
+        const C num = C(1) + eta * (C(1) + eta * (C(1) - eta));
+        const C dnum = C(1) + eta * (C(2) - C(3) * eta);
+        const C d = C(1) - eta;
+        const C id = recip(d);
+        const C id3 = id * id * id;
+        const C Z = num * id3;
+        const C dZ = (dnum * d + C(3) * num) * id3 * id;  // dZ/deta
+        d_RT = k2 * rho * Z;
+        d_a = -(k2 * rho * rho);
+        d_b = k2 * RT * rho * rho * dZ * C(0.25);
+        d_rho = k2 * (RT * (Z + eta * dZ) - C(2) * a_eff * rho) - C(1.0 / 3.0);
+    } else {
+        // p0 = rho RT/d - a rho^2/q, d = 1 - b rho, q = 1 + 2 b rho - b^2 rho^2
+        const C br = b * rho;
+        const C d = C(1) - br;
+        const C q = C(1) + br * (C(2) - br);
+        const C id = recip(d), iq = recip(q);
+        d_RT = k2 * rho * id;
+        d_a = -(k2 * rho * rho * iq);
+        d_b = k2 * rho * rho * (RT * id * id + C(2) * a_eff * rho * d * iq * iq);
+        d_rho = k2 * (RT * id * id - C(2) * a_eff * rho * (q - br * d) * iq * iq) - C(1.0 / 3.0);
+    }
 }
 
 // Transpose of the pull at fluid node (xe, yr): lam_i(x) = dJ/df*_i(x) gathers
@@ -108,29 +80,35 @@ __device__ inline void phi_partials(C rho, C RT, C a_eff, C b, C k2, C& d_rho, C
 //    y + e_iy also read it through the clamped source column.
 template <class C>
 __device__ inline void gather_lambda(const C* __restrict__ lb, const StepArgs& a, int xe, int yr, C (&lam)[9]) {
+    // Branch-free: every population issues two in-range loads (the main source and
+    // the clamped-end extra) and selects, so all 18 loads are in flight together.
 #define LBM_GATHER(I)                                                                           \
     {                                                                                           \
         int ty = yr + ey(I);                                                                    \
-        if (!a.yper && (ty < 0 || ty >= a.ny)) {                                                \
-            lam[I] = lb[(long long)opp(I) * a.plane + (long long)yr * a.pitch + xe];            \
-        } else {                                                                                \
-            if (a.yper) ty = wrapi(ty, a.ny);                                                   \
-            const C* row = lb + (long long)(I) * a.plane + (long long)ty * a.pitch;             \
-            const int tx = xe + ex(I);                                                          \
-            C v = C(0);                                                                         \
-            if (a.xper) {                                                                       \
-                v = row[wrapi(tx, a.nx)];                                                       \
-            } else {                                                                            \
-                if (tx >= 0 && tx < a.nx) v = row[tx];                                          \
-                if (ex(I) == 1 && xe == 0) v += row[0];                                         \
-                if (ex(I) == -1 && xe == a.nx - 1) v += row[a.nx - 1];                          \
-            }                                                                                   \
-            lam[I] = v;                                                                         \
-        }                                                                                       \
+        const bool bounce = !a.yper && (ty < 0 || ty >= a.ny);                                  \
+        ty = a.yper ? wrapi(ty, a.ny) : clampi(ty, 0, a.ny - 1);                                \
+        int tx = xe + ex(I);                                                                    \
+        const bool inx = a.xper || (tx >= 0 && tx < a.nx);                                      \
+        tx = a.xper ? wrapi(tx, a.nx) : clampi(tx, 0, a.nx - 1);                                \
+        const bool extra = !a.xper && ((ex(I) == 1 && xe == 0) || (ex(I) == -1 && xe == a.nx - 1)); \
+        const long long mo = bounce ? (long long)opp(I) * a.plane + (long long)yr * a.pitch + xe \
+                                    : (long long)(I) * a.plane + (long long)ty * a.pitch + tx;  \
+        const C vm = lb[mo];                                                                    \
+        const C ve = lb[(long long)(I) * a.plane + (long long)ty * a.pitch + xe];               \
+        lam[I] = bounce ? vm : ((inx ? vm : C(0)) + (extra ? ve : C(0)));                       \
     }
     LBM_GATHER(0) LBM_GATHER(1) LBM_GATHER(2) LBM_GATHER(3) LBM_GATHER(4) LBM_GATHER(5) LBM_GATHER(6)
     LBM_GATHER(7) LBM_GATHER(8)
 #undef LBM_GATHER
+}
+
+// Interior gather: every x + e_i is a fluid node in range, so lam_i(x) =
+// lb_i(x + e_i); gat_off[i] is the uniform byte offset of that source.
+template <class C>
+__device__ inline void gather_lambda_buf(__amdgpu_buffer_rsrc_t r, const uint32_t (&gat_off)[9], uint32_t node_off,
+                                         C (&lam)[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lam[i] = buffer_load<C>(r, node_off, gat_off[i]);
 }
 
 // div of a vector field on three rows with the gradient stencil of grad3:
@@ -178,33 +156,73 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(const AdjArgs A) {
     const C s_j = LBM_COEF(C, s_j), s_v = LBM_COEF(C, s_v);
 
     // ---- phase A: pull, density, EOS field; gather lam -------------------------
+    // Interior tiles (every pulled source and every gathered target in range, no
+    // wall or end rule) load through buffer resources with uniform offsets.
+    const int x0 = strip * kAdjStripOut;
+    const bool tile_inner = (x0 - kAdjHalo - 1 >= 0) && (x0 + 64 - kAdjHalo <= a.nx - 1) &&
+                            (y0 - kAdjHalo - 1 >= 0) && (y0 + TYO + kAdjHalo <= a.ny - 1);
     C jx[RPT], jy[RPT], lam[RPT][9];
+    C rho_r[RPT];
+    if (tile_inner) {
+        const uint32_t plane_s = uint32_t(a.plane) * uint32_t(sizeof(S)), plane_c = uint32_t(a.plane) * uint32_t(sizeof(C));
+        uint32_t dir_off[9], gat_off[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            dir_off[i] = uint32_t(i) * plane_s - uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(S));
+            gat_off[i] = uint32_t(i) * plane_c + uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(C));
+        }
+        const __amdgpu_buffer_rsrc_t rin = buffer_rsrc(const_cast<S*>(fin), 9u * plane_s);
+        const __amdgpu_buffer_rsrc_t rlb = buffer_rsrc(const_cast<C*>(lb), 9u * plane_c);
+        C f[RPT][9];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int k = wave + NW * j;
+            const int r = y0 - kAdjHalo + k;
+            pull_interior_buf<CD>(rin, dir_off, uint32_t(r * a.pitch + xe) * uint32_t(sizeof(S)), rho0, f[j]);
+            if (k >= 2 && k <= H - 3)
+                gather_lambda_buf<C>(rlb, gat_off, uint32_t(r * a.pitch + xe) * uint32_t(sizeof(C)), lam[j]);
+            else
+#pragma unroll
+                for (int i = 0; i < 9; ++i) lam[j][i] = C(0);
+        }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            rho_r[j] = ((f[j][0] + f[j][1]) + (f[j][2] + f[j][3])) + ((f[j][4] + f[j][5]) + (f[j][6] + f[j][7])) + f[j][8];
+            jx[j] = (f[j][1] - f[j][3]) + (f[j][5] - f[j][6]) + (f[j][8] - f[j][7]);
+            jy[j] = (f[j][2] - f[j][4]) + (f[j][5] - f[j][8]) + (f[j][6] - f[j][7]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int k = wave + NW * j;
+            const int r = y0 - kAdjHalo + k;
+            const bool yfl = a.yper || (r >= 0 && r < a.ny);
+            const int yr = a.yper ? wrapi(r, a.ny) : r;
+            rho_r[j] = rho_w;
+            jx[j] = C(0);
+            jy[j] = C(0);
+            if (yfl) {
+                C f[9];
+                pull_generic<CD>(fin, a, xe, yr, rho0, f);
+                rho_r[j] = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+                jx[j] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+                jy[j] = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
+            }
+            if (k >= 2 && k <= H - 3 && yfl && xfl) {
+                gather_lambda<C>(lb, a, xe, yr, lam[j]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) lam[j][i] = C(0);
+            }
+        }
+    }
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int k = wave + NW * j;
-        const int r = y0 - kAdjHalo + k;
-        const bool yfl = a.yper || (r >= 0 && r < a.ny);
-        const int yr = a.yper ? wrapi(r, a.ny) : r;
-        C rho = rho_w;
-        jx[j] = C(0);
-        jy[j] = C(0);
-        if (yfl) {
-            C f[9];
-            pull_generic<CD>(fin, a, xe, yr, rho0, f);
-            rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-            jx[j] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-            jy[j] = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
-        }
-        sRho[k][lane] = rho;
-        sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+        sRho[k][lane] = rho_r[j];
+        sPhi[k][lane] = phi_of<EOS, C>(rho_r[j], RT, a_eff, bb, k2);
         sFx[k][lane] = C(0);
         sFy[k][lane] = C(0);
-        if (k >= 2 && k <= H - 3 && yfl && xfl) {
-            gather_lambda<C>(lb, a, xe, yr, lam[j]);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) lam[j][i] = C(0);
-        }
     }
     __syncthreads();
 
@@ -467,10 +485,18 @@ hipError_t launch_adj_t(const AdjArgs& A, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <class CD, int EOS>
+hipError_t launch_adj_e(const AdjArgs& A, hipStream_t s) {
+    switch (A.ty) {
+        case 8: return launch_adj_t<CD, EOS, 8, 8>(A, s);
+        case 16: return launch_adj_t<CD, EOS, 16, 8>(A, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <class CD>
 hipError_t launch_adj_c(const AdjArgs& A, int eos, hipStream_t s) {
-    return eos == LBM_EOS_CS ? launch_adj_t<CD, LBM_EOS_CS, kAdjTileRows, 8>(A, s)
-                             : launch_adj_t<CD, LBM_EOS_PR, kAdjTileRows, 8>(A, s);
+    return eos == LBM_EOS_CS ? launch_adj_e<CD, LBM_EOS_CS>(A, s) : launch_adj_e<CD, LBM_EOS_PR>(A, s);
 }
 
 }  // namespace
@@ -508,8 +534,8 @@ hipError_t launch_adjoint_gather(const void* lam, const StepArgs& a, int storage
     return hipGetLastError();
 }
 
-int adjoint_blocks(int nx, int ny) {
-    return ((nx + kAdjStripOut - 1) / kAdjStripOut) * ((ny + kAdjTileRows - 1) / kAdjTileRows);
+int adjoint_blocks(int nx, int ny, int ty) {
+    return ((nx + kAdjStripOut - 1) / kAdjStripOut) * ((ny + ty - 1) / ty);
 }
 
 }  // namespace lbm

@@ -106,9 +106,8 @@ hipError_t launch_wall_reduce(const double* partial_ring, int nsteps, int nstrip
                               lbm_stress_summary* hist, int hist_cap, double* scratch, double* acc, hipStream_t s);
 
 // Reverse-mode (adjoint) step (lbm_adjoint.hip).  Tiles of 64 columns give 56
-// outputs (a 4-column halo on each side) and kAdjTileRows output rows.
+// outputs (a 4-column halo on each side) and ty output rows.
 constexpr int kAdjStripOut = 56;
-constexpr int kAdjTileRows = 8;
 struct AdjArgs {
     StepArgs s;            // the step's coefficients; s.fin is the state the step started from
     const void* lam_in;    // dJ/df of the next step's pulled populations [9][ny][pitch] (arithmetic type)
@@ -116,13 +115,14 @@ struct AdjArgs {
     const double* tau_w;   // [2][nx] this step's wall shear (from its forward recompute)
     double* partial;       // [blocks][4]: sum F~_x, sum phi~ dphi/dRT, dphi/da_eff, dphi/db
     int nstrip;            // 56-column strips
+    int ty;                // output rows per tile: 8 or 16
 };
 hipError_t launch_adjoint(const AdjArgs& A, int storage, int eos, hipStream_t s);
 // acc[0..3] += the sums of ngroups groups of 4 partials (fixed order).
 hipError_t launch_adjoint_reduce(const double* partial, long long ngroups, double* acc, hipStream_t s);
 // dJ/df* of a state from the adjoint of the step that read it, as FP64 [9][ny][nx].
 hipError_t launch_adjoint_gather(const void* lam, const StepArgs& a, int storage, double* out, hipStream_t s);
-int adjoint_blocks(int nx, int ny);
+int adjoint_blocks(int nx, int ny, int ty);
 
 constexpr int kFieldReduceBlocks = 512;
 constexpr int kWallScratchVals = 11;  // per step: peak tau^2, sum tau^2, tau max/min, p max/min per wall, d sum tau^2

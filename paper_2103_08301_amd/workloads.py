@@ -67,3 +67,17 @@ def plug_out_of_cache(storage: str = "f32") -> dict:
     w.update(nx=16384, ny=2048, name=w["name"].replace("4096x512", "16384x2048"))
     w["plug"] = dict(w["plug"], plug_len=1200, film=64)
     return w
+
+
+def plug_adjoint(storage: str = "f32") -> dict:
+    """1024x256 plug case for the wall-shear gradient: plug 120, film 8, 20k steps.
+
+    At 0.85 Tc this channel diverges within 5-16k steps for every pressure
+    drop from 1e-3 down to 1e-4 (tau 1), so the gradient runs use 0.95 Tc,
+    tau 1 and dp 5e-4, which stay finite through the rupture (~11k steps)."""
+    return dict(
+        name=f"plug-channel 1024x256 {storage.upper()} (CS 0.95 Tc, tau 1.0, plug 120, film 8, dp 5e-4)",
+        nx=1024, ny=256, tau=1.0, storage=storage, steps=20_000,
+        params=dict(T_over_Tc=0.95, dp=5e-4),
+        plug=dict(plug_len=120, film=8, x_center=math.nan, noise_amp=1e-3, seed=5),
+    )
