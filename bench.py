@@ -43,10 +43,14 @@ def kernel_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
+GRAPH_STEPS = 0  # steps per captured HIP graph (--graph-steps)
+
+
 def make_lattice(w: dict, check_every: int):
     from paper_2103_08301_amd import Lattice
 
-    lat = Lattice(w["nx"], w["ny"], w["tau"], storage=w["storage"], check_every=check_every, **w["params"])
+    lat = Lattice(w["nx"], w["ny"], w["tau"], storage=w["storage"], check_every=check_every,
+                  graph_steps=GRAPH_STEPS, **w["params"])
     pl = w["plug"]
     lat.init_plug(pl["plug_len"], pl["film"], pl["x_center"], pl["noise_amp"], pl["seed"])
     return lat
@@ -261,7 +265,7 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
     cases = sweep_cases()
     nodes = sum(c["nx"] * c["ny"] for c in cases)
     spec = [{k: v for k, v in c.items() if k not in ("plug", "film")} for c in cases]
-    batch = Batch(spec, storage=storage, check_every=max(steps, warmup, 1), v_limit=0.5)
+    batch = Batch(spec, storage=storage, check_every=max(steps, warmup, 1), v_limit=0.5, graph_steps=GRAPH_STEPS)
     for k, c in enumerate(cases):
         batch[k].init_plug(c["plug"], c["film"], float("nan"), 1e-3, k + 1)
     batch.step(warmup)
@@ -276,7 +280,7 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
     for k, (c, s) in enumerate(zip(cases, spec)):
         s = dict(s)
         lat = Lattice(s.pop("nx"), s.pop("ny"), s.pop("tau"), storage=storage, check_every=max(steps, warmup, 1),
-                      v_limit=0.5, **s)
+                      v_limit=0.5, graph_steps=GRAPH_STEPS, **s)
         lat.init_plug(c["plug"], c["film"], float("nan"), 1e-3, k + 1)
         lat.step(warmup)
         lats.append(lat)
@@ -318,9 +322,13 @@ def main() -> int:
     ap.add_argument("--adjoint-large", action="store_true",
                     help="with --adjoint: the 4096x512 workload instead (--steps steps)")
     ap.add_argument("--segment", type=int, default=0, help="with --adjoint: checkpoint spacing (0: sqrt(steps))")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="steps per captured HIP graph of the step loop (0: library default, -1: direct launches)")
     ap.add_argument("--batch", action="store_true",
                     help="only time 48 uneven sweep cases as one batch against the same cases stepped one by one")
     args = ap.parse_args()
+    global GRAPH_STEPS
+    GRAPH_STEPS = args.graph_steps
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)

@@ -105,6 +105,9 @@ typedef struct {
     int tile_waves;      /* schedules 0 and 2: waves per tile block, 0 (= 4), 4 or 8; schedule 1: 0 */
     int pipe_blocks;     /* schedule 2: blocks launched; 0 = compute units x blocks one unit holds,
                             otherwise >= 8 (every one of the 8 tile ranges needs a block) */
+    int graph_steps;     /* schedules 0 and 1 (and batches): steps per captured HIP graph of step launches,
+                            replayed instead of launching kernel by kernel; 0 selects 64, -1 launches every
+                            step directly; otherwise 2, 4, 8, 16, 32 or 64 */
 } lbm_params;
 
 /* Per-step wall summary ([0] bottom wall, [1] top wall).  FP64. */

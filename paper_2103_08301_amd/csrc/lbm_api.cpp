@@ -238,6 +238,44 @@ bool schedule_ok(const lbm_params* p) {
     }
 }
 
+bool graph_steps_ok(int g) { return g == -1 || g == 0 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+
+// Captured HIP graphs of consecutive step launches, one per (parity of the
+// input buffer, first wall-ring slot), made when first needed: replaying a
+// graph issues its launches without a host call per kernel.  The graphs hold
+// only step kernels (no memset nodes).
+struct StepGraphs {
+    hipStream_t cap = nullptr;  // private capture stream (default priority)
+    hipGraphExec_t exec[2][kRingCap] = {};
+    void drop() {
+        for (auto& row : exec)
+            for (auto& e : row)
+                if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+    }
+    ~StepGraphs() {
+        drop();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+// Captures `steps` launches made by launch(k) (k = 0 .. steps-1) into one executable graph.
+template <class F>
+hipError_t capture_graph(StepGraphs& g, int steps, F&& launch, hipGraphExec_t* out) {
+    hipError_t e = hipSuccess;
+    if (!g.cap) e = hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < steps && le == hipSuccess; ++k) le = launch(k, g.cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g.cap, &graph);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    return e;
+}
+
 }  // namespace
 
 struct lbm_ctx {
@@ -276,6 +314,11 @@ struct lbm_ctx {
     int64_t ring_first_step = 1;
     lbm_check_result check{};
     std::string err;
+    StepGraphs graphs;  // captured step loops (invalidated when the launch arguments change)
+    int graph_steps() const {
+        if (p.graph_steps < 0 || schedule == lbm::kSchedulePipe) return 0;
+        return p.graph_steps == 0 ? 64 : p.graph_steps;
+    }
 
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(dev + off); }
@@ -483,6 +526,7 @@ void lbm_params_default(lbm_params* p) {
     p->schedule = 0;
     p->tile_waves = 0;
     p->pipe_blocks = 0;
+    p->graph_steps = 0;
 }
 
 lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx** out) {
@@ -496,7 +540,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
         !(p->v_limit > 0) || p->history_cap < 1 || (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) ||
         p->storage < LBM_F64 || p->storage > LBM_F64T || (p->x_periodic != 0 && p->x_periodic != 1) ||
         (p->y_periodic != 0 && p->y_periodic != 1) || !std::isfinite(p->omega) ||
-        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || !schedule_ok(p))
+        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || !schedule_ok(p) || !graph_steps_ok(p->graph_steps))
         return LBM_EINVAL;
     const int pitch = (nx + 63) / 64 * 64;
     // the step kernel addresses a distribution buffer with 32-bit byte offsets
@@ -590,6 +634,7 @@ lbm_status lbm_bind(lbm_ctx* c, void* device_ptr, size_t bytes, void* hip_stream
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->bound = true;
     c->initialized = false;
+    c->graphs.drop();
     return LBM_OK;
 }
 
@@ -656,11 +701,38 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
                                     (long long)lbm::kTicketGroups * lbm::kTicketStride, c->stream));
     }
     a.launch = 0;
+    const int G = c->graph_steps();
     int64_t done = 0;
     while (done < n) {
         const int64_t next_check = (c->steps / c->p.check_every + 1) * c->p.check_every;
         const int64_t seg = std::min<int64_t>(n - done, next_check - c->steps);
-        for (int64_t k = 0; k < seg; ++k) {
+        int64_t k = 0;
+        // whole graphs while at least one eager step (the emitting one) remains
+        while (G > 0 && seg - k - 1 >= G) {
+            if (c->ring_fill + G > kRingCap) {
+                lbm_status s = flush_wall(c);
+                if (s) return s;
+            }
+            hipGraphExec_t& ge = c->graphs.exec[c->cur][c->ring_fill];
+            if (!ge) {
+                const int par = c->cur, fill0 = c->ring_fill;
+                auto launch = [&](int j, hipStream_t s) {
+                    lbm::StepArgs b = a;
+                    const int in = (par + j) & 1;
+                    b.fin = c->dev + c->off_f[in];
+                    b.fout = c->dev + c->off_f[1 - in];
+                    b.partial = c->at<double>(c->off_ring) + slot * (fill0 + j);
+                    return lbm::launch_step(b, c->p.storage, c->p.eos, false, s);
+                };
+                HIP_TRY(c, capture_graph(c->graphs, G, launch, &ge));
+            }
+            HIP_TRY(c, hipGraphLaunch(ge, c->stream));
+            if (G & 1) c->cur = 1 - c->cur;
+            c->ring_fill += G;
+            c->steps += G;
+            k += G;
+        }
+        for (; k < seg; ++k) {
             if (c->ring_fill == kRingCap) {
                 lbm_status s = flush_wall(c);
                 if (s) return s;
@@ -848,6 +920,7 @@ lbm_status lbm_set_tangent(lbm_ctx* c, const double* dtheta) {
     if (c->p.eos == LBM_EOS_PR && (dtheta[1] != 0.0 || dtheta[2] != 0.0))
         return fail(c, LBM_EINVAL, "PR tangents support d dp and d T only");
     for (int k = 0; k < 4; ++k) c->dtheta[k] = dtheta[k];
+    c->graphs.drop();  // the step coefficients' tangents are kernel arguments
     return LBM_OK;
 }
 
@@ -1068,6 +1141,7 @@ const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null
 // Batches: many independent lattices advanced by one kernel launch per step.
 
 struct lbm_batch {
+    StepGraphs graphs;
     std::vector<lbm_ctx*> cases;
     std::vector<int> tile_start;  // ncases + 1
     size_t off_desc = 0, off_tiles = 0, total = 0;
@@ -1105,7 +1179,8 @@ lbm_status lbm_batch_create(int n, const int* nx, const int* ny, const double* t
         // one kernel instance serves every case: storage, EOS kind and tile shape agree, and the
         // cases are checked together
         if (p.storage != p0.storage || p.storage == LBM_F64T || p.eos != p0.eos || p.schedule != lbm::kScheduleTile ||
-            p.tile_rows != p0.tile_rows || p.tile_waves != p0.tile_waves || p.check_every != p0.check_every) {
+            p.tile_rows != p0.tile_rows || p.tile_waves != p0.tile_waves || p.check_every != p0.check_every ||
+            p.graph_steps != p0.graph_steps) {
             delete b;
             return LBM_EINVAL;
         }
@@ -1153,6 +1228,7 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
     if (bytes < b->total) return bfail(b, LBM_ENOMEM, "workspace too small for the batch");
     b->dev = static_cast<char*>(device_ptr);
     b->stream = static_cast<hipStream_t>(hip_stream);
+    b->graphs.drop();
     std::vector<lbm::StepArgs> desc;
     for (size_t k = 0; k < b->cases.size(); ++k) {
         lbm_ctx* c = b->cases[k];
@@ -1196,25 +1272,56 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
     const int ncases = (int)b->cases.size();
     const auto* desc = reinterpret_cast<const lbm::StepArgs*>(b->dev + b->off_desc);
     const auto* tiles = reinterpret_cast<const int*>(b->dev + b->off_tiles);
+    const int G = c0->graph_steps();
+    auto advance = [&](int nsteps) {
+        for (lbm_ctx* c : b->cases) {
+            c->cur = (c->cur + nsteps) & 1;
+            c->ring_fill += nsteps;
+            c->steps += nsteps;
+        }
+    };
+    auto flush_all = [&]() -> lbm_status {
+        for (lbm_ctx* c : b->cases) {
+            lbm_status s = flush_wall(c);
+            if (s) return bfail(b, s, c->err);
+        }
+        return LBM_OK;
+    };
     int64_t done = 0;
     while (done < n) {
         const int64_t next_check = (c0->steps / c0->p.check_every + 1) * c0->p.check_every;
         const int64_t seg = std::min<int64_t>(n - done, next_check - c0->steps);
-        for (int64_t k = 0; k < seg; ++k) {
-            if (c0->ring_fill == kRingCap)
-                for (lbm_ctx* c : b->cases) {
-                    lbm_status s = flush_wall(c);
-                    if (s) return bfail(b, s, c->err);
-                }
+        int64_t k = 0;
+        while (G > 0 && seg - k - 1 >= G) {  // whole graphs while the emitting step remains
+            if (c0->ring_fill + G > kRingCap) {
+                lbm_status s = flush_all();
+                if (s) return s;
+            }
+            hipGraphExec_t& ge = b->graphs.exec[c0->cur][c0->ring_fill];
+            if (!ge) {
+                const int par = c0->cur, fill0 = c0->ring_fill;
+                auto launch = [&](int j, hipStream_t s) {
+                    return lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), (par + j) & 1, fill0 + j,
+                                                  c0->p.storage, c0->p.eos, c0->ty, c0->tile_waves, false, s);
+                };
+                hipError_t e = capture_graph(b->graphs, G, launch, &ge);
+                if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+            }
+            hipError_t e = hipGraphLaunch(ge, b->stream);
+            if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch graph launch: ") + hipGetErrorString(e));
+            advance(G);
+            k += G;
+        }
+        for (; k < seg; ++k) {
+            if (c0->ring_fill == kRingCap) {
+                lbm_status s = flush_all();
+                if (s) return s;
+            }
             const bool emit = (k == seg - 1);
             hipError_t e = lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), c0->cur, c0->ring_fill,
                                                   c0->p.storage, c0->p.eos, c0->ty, c0->tile_waves, emit, b->stream);
             if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
-            for (lbm_ctx* c : b->cases) {
-                c->cur = 1 - c->cur;
-                c->ring_fill += 1;
-                c->steps += 1;
-            }
+            advance(1);
         }
         for (lbm_ctx* c : b->cases) {
             lbm_status s = flush_wall(c);

@@ -48,7 +48,7 @@ class lbm_params(C.Structure):
         ("dp", C.c_double), ("x_periodic", C.c_int), ("y_periodic", C.c_int), ("storage", C.c_int),
         ("rho0_shift", C.c_double), ("check_every", C.c_int), ("v_limit", C.c_double),
         ("history_cap", C.c_int), ("tile_rows", C.c_int), ("schedule", C.c_int),
-        ("tile_waves", C.c_int), ("pipe_blocks", C.c_int),
+        ("tile_waves", C.c_int), ("pipe_blocks", C.c_int), ("graph_steps", C.c_int),
     ]
 
 

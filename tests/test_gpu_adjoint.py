@@ -159,3 +159,26 @@ def test_adjoint_api_rules():
     g1 = lat.adjoint_backward(1.0)
     g2 = lat.adjoint_backward(-2.0)  # the record stays valid
     assert np.array_equal(g2, -2.0 * g1)
+
+
+def test_large_grid_16_row_tiles_equal_tangent():
+    """Grids of 1M nodes and more take the 16-row adjoint tiles: same check against the tangents."""
+    nx, ny, steps = 2048, 512, 24
+    kw = dict(T_over_Tc=0.9, dp=1e-3, v_limit=1.0, check_every=10 ** 6, rho_wall=0.3)
+    lat = Lattice(nx, ny, 1.0, storage="f64", **kw)
+    lat.init_plug(200, 12, math.nan, 1e-3, 3)
+    lat.adjoint_bind(steps, 5)
+    st, J = lat.adjoint_forward()
+    assert st == 0
+    grad = lat.adjoint_backward()
+    for k, name in ((0, "dp"), (3, "T")):
+        tl = Lattice(nx, ny, 1.0, storage="f64t", **kw)
+        e = [0.0] * 4
+        e[k] = 1.0
+        tl.set_tangent(*e)
+        tl.init_plug(200, 12, math.nan, 1e-3, 3)
+        assert tl.step(steps) == 0
+        h = tl.history(1)[-1]
+        log(f"2048x512 dJ/d{name}: adjoint {grad[k]:.12e} tangent {h['d_int_tau2']:.12e}")
+        assert h["int_tau2"] == pytest.approx(J, rel=1e-12)
+        assert grad[k] == pytest.approx(h["d_int_tau2"], rel=1e-9)
