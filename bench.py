@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f64": 144, "f32": 72, "f32d": 72, "f32s": 72, "f16s": 36, "bf16s": 36}
 DTYPE = {"f32": "f32", "f64": "f64", "f32d": "f32-store/f64", "f32s": "f32-shifted/f32",
          "f16s": "f16-store/f32", "bf16s": "bf16-store/f32"}
-KERNEL_SRC = os.path.join(ROOT, "paper_2103_08301_amd", "csrc", "lbm_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2103_08301_amd", "csrc", "lbm_device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_4096x512_f32_traffic.json")
 
 
@@ -44,6 +44,7 @@ def kernel_hash() -> str:
 
 
 GRAPH_STEPS = 0  # steps per captured HIP graph (--graph-steps)
+AUTOTUNE = True  # time every tile shape after the warm-up and keep the fastest (--no-autotune)
 
 
 def make_lattice(w: dict, check_every: int):
@@ -63,6 +64,9 @@ def time_steps(w: dict, steps: int, warmup: int):
     lat = make_lattice(w, check_every=max(steps, warmup, 1))
     if warmup:
         lat.step(warmup)
+    lat.tuned = lat.autotune(50) if AUTOTUNE else None
+    if lat.tuned:
+        log(f"autotune: {lat.tuned}")
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -269,6 +273,7 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
     for k, c in enumerate(cases):
         batch[k].init_plug(c["plug"], c["film"], float("nan"), 1e-3, k + 1)
     batch.step(warmup)
+    tuned = batch.autotune(20) if AUTOTUNE else None
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(batch.stream)
@@ -296,7 +301,8 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
            "cases": len(cases), "nodes": nodes, "steps": steps,
            "batch": {"MLUPS": round(nodes * steps / t_batch / 1e6, 1), "us_per_step": round(t_batch / steps * 1e6, 2)},
            "sequential": {"MLUPS": round(nodes * steps / t_seq / 1e6, 1), "us_per_step": round(t_seq / steps * 1e6, 2)},
-           "speedup": round(t_seq / t_batch, 2), "batch_equals_sequential": bool(same)}
+           "speedup": round(t_seq / t_batch, 2), "batch_equals_sequential": bool(same), "batch_tiles": tuned,
+           "graph_steps": GRAPH_STEPS}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -322,13 +328,15 @@ def main() -> int:
     ap.add_argument("--adjoint-large", action="store_true",
                     help="with --adjoint: the 4096x512 workload instead (--steps steps)")
     ap.add_argument("--segment", type=int, default=0, help="with --adjoint: checkpoint spacing (0: sqrt(steps))")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape instead of timing all")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="steps per captured HIP graph of the step loop (0: library default, -1: direct launches)")
     ap.add_argument("--batch", action="store_true",
                     help="only time 48 uneven sweep cases as one batch against the same cases stepped one by one")
     args = ap.parse_args()
-    global GRAPH_STEPS
+    global GRAPH_STEPS, AUTOTUNE
     GRAPH_STEPS = args.graph_steps
+    AUTOTUNE = not args.no_autotune
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -403,7 +411,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w["name"], "nx": w["nx"], "ny": w["ny"], "tau": w["tau"], **w["params"],
                    **{k: v for k, v in w["plug"].items() if k != "x_center"}, "storage": args.storage,
-                   "schedule": "tile 60x8" if args.storage not in ("f64", "f32d") else "tile 60x12"},
+                   "schedule": (f"tile 60x{lat.tuned['tile_rows']}, {lat.tuned['tile_waves']} waves (autotuned)"
+                                if lat.tuned else ("tile 60x8" if args.storage not in ("f64", "f32d") else "tile 60x12")),
+                   "graph_steps": GRAPH_STEPS},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.storage),
                      "bytes_per_node": bpn, "kernel": "tile_kernel (fused pull-stream/force/MRT/wall diagnostics)"},

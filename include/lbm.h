@@ -206,6 +206,16 @@ lbm_status lbm_stress_history(lbm_ctx* ctx, lbm_stress_summary* buf, int64_t cap
 /* Result of the latest stability/interface check. */
 lbm_status lbm_check_state(const lbm_ctx* ctx, lbm_check_result* out);
 
+/* Tile autotuner of the tile schedule: times trial_steps launches of every
+   tile shape (output rows x waves per block: 8x4, 12x4, 20x4, 28x4, 12x8,
+   20x8, 28x8) on the current state and keeps the fastest for later steps.
+   Trials read the current state and write only scratch (the other
+   distribution buffer and the flushed wall ring), so the state, fields and
+   wall diagnostics are unchanged, and results do not depend on the shape.
+   Outputs (any may be NULL): the chosen shape and its mean time per step in
+   microseconds.  Blocks until done.  LBM_EINVAL for other schedules or F64T. */
+lbm_status lbm_autotune(lbm_ctx* ctx, int trial_steps, int* tile_rows, int* tile_waves, double* us_per_step);
+
 /* Reverse-mode sensitivities (adjoint) of the wall-shear objective
    J = sum over steps, walls and columns of tau_w^2 (the time integral of
    squared wall shear, int_tau2 of lbm_stress_summary; Figs. 3, 5 and 8 and
@@ -345,6 +355,11 @@ lbm_status lbm_batch_case(lbm_batch* b, int k, lbm_ctx** ctx);
    that status, stops, and sets *failed_case (may be NULL) to the case index
    (-1 otherwise). */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case);
+/* The tile autotuner for a batch: one trial launch covers every case's tiles
+   for a shape (the cases share one kernel), and the fastest shape is kept for
+   all cases.  As lbm_autotune otherwise; every case must be initialised. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int* tile_waves, double* us_per_step);
+
 void lbm_batch_destroy(lbm_batch* b);
 const char* lbm_batch_last_error(const lbm_batch* b);
 

@@ -940,6 +940,85 @@ lbm_status lbm_get_f_tangent(lbm_ctx* c, double* df) {
     return LBM_OK;
 }
 
+// ---- tile autotuner ----------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+struct TileShape {
+    int rows, waves;
+};
+// Tile shapes of the tile schedule (schedule_ok), in the order they are tried.
+constexpr TileShape kTileShapes[] = {{8, 4}, {12, 4}, {20, 4}, {28, 4}, {12, 8}, {20, 8}, {28, 8}};
+
+// Step arguments for timing trials: the wall shear, wall pressure and per-strip
+// partials go to the wall ring (free after a flush), so a trial leaves every
+// diagnostic the caller can read untouched.
+lbm::StepArgs trial_args(const lbm_ctx* c) {
+    lbm::StepArgs a = make_args(c);
+    double* ring = c->at<double>(c->off_ring);
+    const size_t slot = (size_t)2 * c->nstrip * lbm::kPartialVals;
+    a.partial = ring;
+    a.tau_w = ring + slot;             // 255 slots of >= nx/3 doubles hold 4 nx doubles
+    a.p_w = ring + slot + 2 * (size_t)c->nx;
+    a.fin = c->dev + c->off_f[c->cur];  // every trial reads the current state and writes the other buffer
+    a.fout = c->dev + c->off_f[1 - c->cur];
+    return a;
+}
+
+// Mean time per launch of `trials` launches after one warm-up launch.
+template <class F>
+hipError_t time_launches(hipStream_t s, int trials, F&& launch, double* us) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int k = 0; k < trials && e == hipSuccess; ++k) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    *us = 1e3 * ms / trials;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_autotune(lbm_ctx* c, int trial_steps, int* tile_rows, int* tile_waves, double* us_per_step) {
+    if (!c || trial_steps < 1) return LBM_EINVAL;
+    if (c->in_batch) return fail(c, LBM_ESTATE, "a batch case is tuned with lbm_batch_autotune");
+    if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_autotune needs an initialised lattice");
+    if (c->schedule != lbm::kScheduleTile || c->p.storage == LBM_F64T)
+        return fail(c, LBM_EINVAL, "lbm_autotune tunes the tile schedule (not F64T storage)");
+    lbm_status s = flush_wall(c);
+    if (s) return s;
+    double best = INFINITY;
+    TileShape pick = {c->ty, c->tile_waves};
+    for (const TileShape& t : kTileShapes) {
+        lbm::StepArgs a = trial_args(c);
+        a.ty = t.rows;
+        a.tile_waves = t.waves;
+        double us = 0;
+        HIP_TRY(c, time_launches(c->stream, trial_steps,
+                                 [&] { return lbm::launch_step(a, c->p.storage, c->p.eos, false, c->stream); }, &us));
+        if (us < best) { best = us; pick = t; }
+    }
+    c->ty = c->p.tile_rows = pick.rows;
+    c->tile_waves = c->p.tile_waves = pick.waves;
+    c->nchunk = std::max(1, c->ny / c->ty);
+    c->graphs.drop();  // the tile shape is part of the captured launches
+    if (tile_rows) *tile_rows = pick.rows;
+    if (tile_waves) *tile_waves = pick.waves;
+    if (us_per_step) *us_per_step = best;
+    return LBM_OK;
+}
+
 // ---- reverse-mode sensitivities ------------------------------------------------
 
 namespace {
@@ -1144,7 +1223,8 @@ struct lbm_batch {
     StepGraphs graphs;
     std::vector<lbm_ctx*> cases;
     std::vector<int> tile_start;  // ncases + 1
-    size_t off_desc = 0, off_tiles = 0, total = 0;
+    size_t off_desc = 0, off_tiles = 0, off_flush = 0, total = 0;
+    int nflush = 0;  // cases with walls (their wall rings are reduced together)
     std::vector<size_t> off_case;
     char* dev = nullptr;
     hipStream_t stream = nullptr;
@@ -1196,6 +1276,7 @@ lbm_status lbm_batch_create(int n, const int* nx, const int* ny, const double* t
     size_t o = 0;
     b->off_desc = o; o += align256((size_t)n * sizeof(lbm::StepArgs));
     b->off_tiles = o; o += align256((size_t)(n + 1) * sizeof(int));
+    b->off_flush = o; o += align256((size_t)n * sizeof(lbm::WallFlush));
     int tiles = 0;
     for (int k = 0; k < n; ++k) {
         lbm_ctx* c = b->cases[k];
@@ -1242,8 +1323,17 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
         a.partial = c->at<double>(c->off_ring);
         desc.push_back(a);
     }
+    std::vector<lbm::WallFlush> flush;
+    for (lbm_ctx* c : b->cases)
+        if (!c->p.y_periodic)
+            flush.push_back(lbm::WallFlush{c->at<double>(c->off_ring), c->nstrip, c->at<lbm_stress_summary>(c->off_hist),
+                                           c->p.history_cap, c->at<double>(c->off_wscr), c->at<double>(c->off_acc)});
+    b->nflush = (int)flush.size();
     hipError_t e = hipMemcpyAsync(b->dev + b->off_desc, desc.data(), desc.size() * sizeof(lbm::StepArgs),
                                   hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !flush.empty())
+        e = hipMemcpyAsync(b->dev + b->off_flush, flush.data(), flush.size() * sizeof(lbm::WallFlush),
+                           hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->dev + b->off_tiles, b->tile_start.data(), b->tile_start.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream);
@@ -1280,10 +1370,14 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
             c->steps += nsteps;
         }
     };
-    auto flush_all = [&]() -> lbm_status {
+    auto flush_all = [&]() -> lbm_status {  // every case's wall ring in one pair of launches
+        if (c0->ring_fill == 0) return LBM_OK;
+        hipError_t e = lbm::launch_wall_reduce_batch(reinterpret_cast<const lbm::WallFlush*>(b->dev + b->off_flush),
+                                                     b->nflush, c0->ring_fill, c0->ring_first_step, b->stream);
+        if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch wall reduce: ") + hipGetErrorString(e));
         for (lbm_ctx* c : b->cases) {
-            lbm_status s = flush_wall(c);
-            if (s) return bfail(b, s, c->err);
+            c->ring_first_step += c->ring_fill;
+            c->ring_fill = 0;
         }
         return LBM_OK;
     };
@@ -1323,10 +1417,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
             if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
             advance(1);
         }
-        for (lbm_ctx* c : b->cases) {
-            lbm_status s = flush_wall(c);
-            if (s) return bfail(b, s, c->err);
-        }
+        lbm_status fs = flush_all();
+        if (fs) return fs;
         done += seg;
         for (int k = 0; k < ncases; ++k) {
             lbm_status s = run_check(b->cases[(size_t)k]);
@@ -1336,6 +1428,76 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
             }
         }
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int* tile_waves, double* us_per_step) {
+    if (!b || trial_steps < 1) return LBM_EINVAL;
+    if (!b->bound) return bfail(b, LBM_ESTATE, "lbm_batch_bind must come first");
+    lbm_ctx* c0 = b->cases[0];
+    for (lbm_ctx* c : b->cases) {
+        if (!c->initialized) return bfail(b, LBM_ESTATE, "every case must be initialised before tuning");
+        lbm_status s = flush_wall(c);
+        if (s) return bfail(b, s, c->err);
+    }
+    const int ncases = (int)b->cases.size();
+    // trial launch table: each case's diagnostics redirected into its (flushed) wall ring
+    std::vector<lbm::StepArgs> trial, real;
+    for (lbm_ctx* c : b->cases) {
+        lbm::StepArgs a = trial_args(c);
+        a.fin = c->dev + c->off_f[0];
+        a.fout = c->dev + c->off_f[1];
+        trial.push_back(a);
+        lbm::StepArgs r = make_args(c);
+        r.fin = a.fin;
+        r.fout = a.fout;
+        r.partial = c->at<double>(c->off_ring);
+        real.push_back(r);
+    }
+    auto* desc = reinterpret_cast<lbm::StepArgs*>(b->dev + b->off_desc);
+    const auto* tiles = reinterpret_cast<const int*>(b->dev + b->off_tiles);
+    const size_t bytes = trial.size() * sizeof(lbm::StepArgs);
+    hipError_t e = hipMemcpyAsync(desc, trial.data(), bytes, hipMemcpyHostToDevice, b->stream);
+    double best = INFINITY;
+    TileShape pick = {c0->ty, c0->tile_waves};
+    std::vector<std::vector<int>> starts;  // host sources of the copies stay alive until the final synchronisation
+    for (const TileShape& t : kTileShapes) {
+        if (e != hipSuccess) break;
+        double us = 0;
+        // the tile count of a shape differs: one launch of every case's tiles for this shape
+        starts.emplace_back(1, 0);
+        std::vector<int>& start = starts.back();
+        for (lbm_ctx* c : b->cases) start.push_back(start.back() + c->nstrip * ((c->ny + t.rows - 1) / t.rows));
+        // the per-case first-tile table lives after the descriptors; keep the real one and restore it below
+        e = hipMemcpyAsync(const_cast<int*>(tiles), start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice,
+                           b->stream);
+        if (e != hipSuccess) break;
+        e = time_launches(b->stream, trial_steps, [&] {
+            return lbm::launch_step_batch(desc, tiles, ncases, start.back(), c0->cur, 0, c0->p.storage, c0->p.eos,
+                                          t.rows, t.waves, false, b->stream);
+        }, &us);
+        if (e == hipSuccess && us < best) { best = us; pick = t; }
+    }
+    // the chosen shape's tile table and the real launch table
+    starts.emplace_back(1, 0);
+    std::vector<int>& start = starts.back();
+    for (lbm_ctx* c : b->cases) start.push_back(start.back() + c->nstrip * ((c->ny + pick.rows - 1) / pick.rows));
+    if (e == hipSuccess) e = hipMemcpyAsync(desc, real.data(), bytes, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(const_cast<int*>(tiles), start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch autotune: ") + hipGetErrorString(e));
+    b->tile_start = start;
+    for (lbm_ctx* c : b->cases) {
+        c->ty = c->p.tile_rows = pick.rows;
+        c->tile_waves = c->p.tile_waves = pick.waves;
+        c->nchunk = std::max(1, c->ny / c->ty);
+    }
+    b->graphs.drop();
+    if (tile_rows) *tile_rows = pick.rows;
+    if (tile_waves) *tile_waves = pick.waves;
+    if (us_per_step) *us_per_step = best;
     return LBM_OK;
 }
 

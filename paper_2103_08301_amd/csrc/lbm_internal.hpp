@@ -104,6 +104,18 @@ hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin,
 // kWallScratchVals doubles per step.
 hipError_t launch_wall_reduce(const double* partial_ring, int nsteps, int nstrip, int64_t first_step,
                               lbm_stress_summary* hist, int hist_cap, double* scratch, double* acc, hipStream_t s);
+// The wall ring, history, scratch and accumulators of one lattice.
+struct WallFlush {
+    const double* ring;
+    int nstrip;
+    lbm_stress_summary* hist;
+    int hist_cap;
+    double* scratch;
+    double* acc;
+};
+// launch_wall_reduce for the ncases lattices of tbl (device array) at once;
+// they have stepped together, so nsteps and first_step are shared.
+hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, int64_t first_step, hipStream_t s);
 
 // Reverse-mode (adjoint) step (lbm_adjoint.hip).  Tiles of 64 columns give 56
 // outputs (a 4-column halo on each side) and ty output rows.

@@ -117,11 +117,10 @@ __device__ inline void comb_min(double& v, double& x, double ov, double ox) {
     if (ov < v || (ov == v && ox < x)) { v = ov; x = ox; }
 }
 
-__global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __restrict__ ring, int nstrip,
-                                                              int64_t first_step, lbm_stress_summary* hist,
-                                                              int hist_cap, double* __restrict__ scratch) {
-    const int t = blockIdx.x, lane = threadIdx.x;
-    const double* slot = ring + (long long)t * 2 * nstrip * kPartialVals;
+__device__ void wall_step_reduce_body(const WallFlush& f, int t, int64_t first_step) {
+    const int lane = threadIdx.x;
+    const int nstrip = f.nstrip;
+    const double* slot = f.ring + (long long)t * 2 * nstrip * kPartialVals;
     lbm_stress_summary sm;
     sm.step = first_step + t;
     double pk = 0.0, s2 = 0.0, ds2 = 0.0;
@@ -160,8 +159,8 @@ __global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __re
         sm.int_peak_tau2 = 0.0;
         sm.int_tau2 = 0.0;
         sm.d_int_tau2 = 0.0;
-        hist[(sm.step - 1) % hist_cap] = sm;
-        double* o = scratch + (long long)t * kWallScratchVals;
+        f.hist[(sm.step - 1) % f.hist_cap] = sm;
+        double* o = f.scratch + (long long)t * kWallScratchVals;
         o[0] = pk;
         o[1] = s2;
         for (int w = 0; w < 2; ++w) {
@@ -177,8 +176,11 @@ __global__ __launch_bounds__(64) void wall_step_reduce_kernel(const double* __re
 // Running time integrals and running extremes, in step order (single thread).
 // acc: [0] int peak tau^2, [1] int sum tau^2, [2 + 2q + w] running extreme q
 // (tau max, tau min, p max, p min) of wall w, [10] tangent of int sum tau^2.
-__global__ void wall_integrate_kernel(const double* __restrict__ scratch, int nsteps, int64_t first_step,
-                                      lbm_stress_summary* hist, int hist_cap, double* acc) {
+__device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t first_step) {
+    const double* __restrict__ scratch = f.scratch;
+    lbm_stress_summary* hist = f.hist;
+    const int hist_cap = f.hist_cap;
+    double* acc = f.acc;
     double ip = acc[0], is = acc[1], dis = acc[10];
     double run[8];
     for (int q = 0; q < 8; ++q) run[q] = acc[2 + q];
@@ -208,6 +210,25 @@ __global__ void wall_integrate_kernel(const double* __restrict__ scratch, int ns
     acc[1] = is;
     acc[10] = dis;
     for (int q = 0; q < 8; ++q) acc[2 + q] = run[q];
+}
+
+// One lattice: one wave per step, then the step-ordered integration.
+__global__ __launch_bounds__(64) void wall_step_reduce_kernel(const WallFlush f, int64_t first_step) {
+    wall_step_reduce_body(f, blockIdx.x, first_step);
+}
+__global__ void wall_integrate_kernel(const WallFlush f, int nsteps, int64_t first_step) {
+    wall_integrate_body(f, nsteps, first_step);
+}
+
+// Many lattices stepped together (same steps): blockIdx.y is the case.
+__global__ __launch_bounds__(64) void wall_step_reduce_batch_kernel(const WallFlush* __restrict__ tbl,
+                                                                    int64_t first_step) {
+    wall_step_reduce_body(tbl[blockIdx.y], blockIdx.x, first_step);
+}
+__global__ __launch_bounds__(64) void wall_integrate_batch_kernel(const WallFlush* __restrict__ tbl, int ncases,
+                                                                  int nsteps, int64_t first_step) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncases) wall_integrate_body(tbl[c], nsteps, first_step);
 }
 
 }  // namespace
@@ -292,11 +313,21 @@ hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin,
 hipError_t launch_wall_reduce(const double* ring, int nsteps, int nstrip, int64_t first_step, lbm_stress_summary* hist,
                               int hist_cap, double* scratch, double* acc, hipStream_t s) {
     if (nsteps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps), dim3(64), 0, s, ring, nstrip, first_step, hist, hist_cap,
-                       scratch);
+    const WallFlush f{ring, nstrip, hist, hist_cap, scratch, acc};
+    hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps), dim3(64), 0, s, f, first_step);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(wall_integrate_kernel, dim3(1), dim3(1), 0, s, scratch, nsteps, first_step, hist, hist_cap, acc);
+    hipLaunchKernelGGL(wall_integrate_kernel, dim3(1), dim3(1), 0, s, f, nsteps, first_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, int64_t first_step, hipStream_t s) {
+    if (nsteps <= 0 || ncases <= 0) return hipSuccess;
+    hipLaunchKernelGGL(wall_step_reduce_batch_kernel, dim3(nsteps, ncases), dim3(64), 0, s, tbl, first_step);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(wall_integrate_batch_kernel, dim3((ncases + 63) / 64), dim3(64), 0, s, tbl, ncases, nsteps,
+                       first_step);
     return hipGetLastError();
 }
 

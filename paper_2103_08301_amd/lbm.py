@@ -30,7 +30,7 @@ EXPORTED = [
     "lbm_last_error", "lbm_batch_create", "lbm_batch_workspace", "lbm_batch_bind", "lbm_batch_case",
     "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_set_tangent", "lbm_get_f_tangent",
     "lbm_reset_stress_extremes", "lbm_adjoint_workspace", "lbm_adjoint_bind", "lbm_adjoint_forward",
-    "lbm_adjoint_backward", "lbm_adjoint_state_gradient",
+    "lbm_adjoint_backward", "lbm_adjoint_state_gradient", "lbm_autotune", "lbm_batch_autotune",
 ]
 
 
@@ -130,6 +130,8 @@ def library():
                                                C.c_int, C.POINTER(lbm_component), C.c_int64, C.POINTER(C.c_int64),
                                                C.POINTER(lbm_aerosol_summary)]),
             "lbm_reset_stress_extremes": (C.c_int, [_P]),
+            "lbm_autotune": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _D]),
+            "lbm_batch_autotune": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _D]),
             "lbm_adjoint_workspace": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
             "lbm_adjoint_bind": (C.c_int, [_P, _P, C.c_size_t, C.c_int64, C.c_int64]),
             "lbm_adjoint_forward": (C.c_int, [_P, _D]),
@@ -286,6 +288,12 @@ def lbm_set_tangent(ctx, dtheta):
 
 def lbm_get_f_tangent(ctx, df: np.ndarray):
     _check(ctx, library().lbm_get_f_tangent(ctx, _ptr(df)))
+
+
+def lbm_autotune(ctx, trial_steps: int = 50) -> dict:
+    r, w, us = C.c_int(), C.c_int(), C.c_double()
+    _check(ctx, library().lbm_autotune(ctx, trial_steps, C.byref(r), C.byref(w), C.byref(us)))
+    return dict(tile_rows=r.value, tile_waves=w.value, us_per_step=us.value)
 
 
 def lbm_adjoint_workspace(ctx, nsteps: int, segment: int = 0) -> int:
@@ -445,6 +453,10 @@ class Lattice:
         assert f.shape == (9, self.ny, self.nx)
         lbm_set_f(self._ctx, f)
 
+    def autotune(self, trial_steps: int = 50) -> dict:
+        """Times every tile shape of the tile schedule on the current state and keeps the fastest."""
+        return lbm_autotune(self._ctx, trial_steps)
+
     def adjoint_bind(self, nsteps: int, segment: int = 0):
         """Device workspace for recording nsteps steps with a checkpoint every `segment` steps."""
         import torch
@@ -516,6 +528,13 @@ class Batch:
             err.case = failed.value
             raise err
         return LBM_OK
+
+    def autotune(self, trial_steps: int = 20) -> dict:
+        """Times every tile shape on all cases at once and keeps the fastest for the batch."""
+        r, w, us = C.c_int(), C.c_int(), C.c_double()
+        _batch_check(self._b, library().lbm_batch_autotune(self._b, trial_steps, C.byref(r), C.byref(w),
+                                                           C.byref(us)))
+        return dict(tile_rows=r.value, tile_waves=w.value, us_per_step=us.value)
 
     def __del__(self):
         b = getattr(self, "_b", None)

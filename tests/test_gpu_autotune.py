@@ -1,0 +1,79 @@
+"""The tile autotuner: it picks one of the tile schedule's shapes, leaves the
+state and every diagnostic untouched, and later steps with the chosen shape are
+bit-identical to steps with the default shape (every tile computes its nodes
+with the same expressions, whatever its height)."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2103_08301_amd import Batch, Lattice, lbm  # noqa: E402
+
+SHAPES = {(8, 4), (12, 4), (20, 4), (28, 4), (12, 8), (20, 8), (28, 8)}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_autotune_keeps_state_and_results(storage):
+    kw = dict(storage=storage, T_over_Tc=0.95, dp=1e-3, check_every=50, v_limit=1.0)
+    ref = Lattice(700, 90, 1.0, **kw)
+    lat = Lattice(700, 90, 1.0, **kw)
+    for l in (ref, lat):
+        l.init_plug(80, 5, math.nan, 1e-3, 9)
+        assert l.step(33) == 0
+    f0, w0, h0 = lat.get_f(), lat.wall(), lat.history()
+    r0 = lat.fields()
+    pick = lat.autotune(20)
+    print("chosen", pick, flush=True)
+    assert (pick["tile_rows"], pick["tile_waves"]) in SHAPES and pick["us_per_step"] > 0
+    assert np.array_equal(lat.get_f(), f0)
+    w1 = lat.wall()
+    for k in w0[0]:
+        assert np.array_equal(w1[0][k], w0[0][k])
+    assert repr(lat.history()) == repr(h0)
+    for a, b in zip(lat.fields(), r0):
+        assert np.array_equal(a, b)
+    for l in (ref, lat):
+        assert l.step(141) == 0
+    assert np.array_equal(lat.get_f(), ref.get_f())
+    assert repr(lat.history()) == repr(ref.history())
+
+
+def test_batch_autotune_keeps_results():
+    cases = [dict(nx=200 + 40 * k, ny=40 + 8 * k, tau=1.0, dp=1e-3, T_over_Tc=0.95) for k in range(4)]
+
+    def make():
+        b = Batch(cases, storage="f32", check_every=60, v_limit=1.0)
+        for k in range(4):
+            b[k].init_plug(30, 3, math.nan, 1e-3, 20 + k)
+        assert b.step(17) == 0
+        return b
+
+    ref, bat = make(), make()
+    f0 = [bat[k].get_f() for k in range(4)]
+    pick = bat.autotune(10)
+    print("batch chosen", pick, flush=True)
+    assert (pick["tile_rows"], pick["tile_waves"]) in SHAPES
+    for k in range(4):
+        assert np.array_equal(bat[k].get_f(), f0[k])
+    for b in (ref, bat):
+        assert b.step(150) == 0
+    for k in range(4):
+        assert np.array_equal(bat[k].get_f(), ref[k].get_f())
+        assert repr(bat[k].history()) == repr(ref[k].history())
+
+
+def test_autotune_rules():
+    lat = Lattice(64, 16, 1.0, schedule=1)
+    lat.init_plug(10, 2)
+    with pytest.raises(lbm.LbmError):
+        lat.autotune()  # the row-march schedule has no tile shapes
+    lat = Lattice(64, 16, 1.0)
+    with pytest.raises(lbm.LbmError) as e:
+        lat.autotune()  # not initialised
+    assert e.value.status == lbm.LBM_ESTATE

@@ -52,23 +52,27 @@ def plug(case):
     return max(4, case["nx"] // 5), (0 if case.get("y_periodic") else max(1, case["ny"] // 16))
 
 
+@pytest.mark.parametrize("check_every", [50, 300])  # 300: captured graphs and several wall-ring flushes
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_batch_matches_single_runs_bitwise(storage):
-    b = Batch(CASES, storage=storage, v_limit=1.0, check_every=50)
-    for k, c in enumerate(CASES):
+def test_batch_matches_single_runs_bitwise(storage, check_every):
+    # the long run leaves out the rho_wall = 0.2 case, which goes unstable after 200 steps (oracle too)
+    cases = CASES if check_every == 50 else [c for i, c in enumerate(CASES) if i != 4]
+    calls = (1, 149) if check_every == 50 else (1, 149, 330)
+    b = Batch(cases, storage=storage, v_limit=1.0, check_every=check_every)
+    for k, c in enumerate(cases):
         pl, fl = plug(c)
         b[k].init_plug(pl, fl, math.nan, 1e-3, k + 1)
-    b.step(1)
-    b.step(149)
-    for k, c in enumerate(CASES):
+    for n in calls:
+        b.step(n)
+    for k, c in enumerate(cases):
         spec = dict(c)
         nx, ny, tau = spec.pop("nx"), spec.pop("ny"), spec.pop("tau")
-        lat = Lattice(nx, ny, tau, storage=storage, v_limit=1.0, check_every=50, **spec)
+        lat = Lattice(nx, ny, tau, storage=storage, v_limit=1.0, check_every=check_every, graph_steps=-1, **spec)
         pl, fl = plug(c)
         lat.init_plug(pl, fl, math.nan, 1e-3, k + 1)
-        lat.step(1)
-        lat.step(149)
-        assert b[k].steps == lat.steps == 150
+        for n in calls:
+            lat.step(n)
+        assert b[k].steps == lat.steps == sum(calls)
         fb, fl_ = b[k].get_f(), lat.get_f()
         d = np.abs(fb - fl_)
         log(f"case {k}: max |f batch - f single| {d.max():.3e} at {np.unravel_index(np.argmax(d), d.shape)}, "
