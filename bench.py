@@ -44,7 +44,7 @@ def kernel_hash() -> str:
 
 
 GRAPH_STEPS = 0  # steps per captured HIP graph (--graph-steps)
-AUTOTUNE = True  # time every tile shape after the warm-up and keep the fastest (--no-autotune)
+AUTOTUNE = False  # time every tile shape after the warm-up and keep the fastest (--autotune; always for --batch)
 
 
 def make_lattice(w: dict, check_every: int):
@@ -273,7 +273,7 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
     for k, c in enumerate(cases):
         batch[k].init_plug(c["plug"], c["film"], float("nan"), 1e-3, k + 1)
     batch.step(warmup)
-    tuned = batch.autotune(20) if AUTOTUNE else None
+    tuned = batch.autotune(20)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(batch.stream)
@@ -328,7 +328,9 @@ def main() -> int:
     ap.add_argument("--adjoint-large", action="store_true",
                     help="with --adjoint: the 4096x512 workload instead (--steps steps)")
     ap.add_argument("--segment", type=int, default=0, help="with --adjoint: checkpoint spacing (0: sqrt(steps))")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape instead of timing all")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every tile shape after the warm-up and keep the fastest (the 4096x512 FP32 default "
+                         "shape, 60x8 with 4 waves, is within 2%% of the best; --batch always tunes)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="steps per captured HIP graph of the step loop (0: library default, -1: direct launches)")
     ap.add_argument("--batch", action="store_true",
@@ -336,7 +338,7 @@ def main() -> int:
     args = ap.parse_args()
     global GRAPH_STEPS, AUTOTUNE
     GRAPH_STEPS = args.graph_steps
-    AUTOTUNE = not args.no_autotune
+    AUTOTUNE = args.autotune
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)

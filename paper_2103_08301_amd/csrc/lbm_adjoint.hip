@@ -442,16 +442,12 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(const AdjArgs A) {
     }
 }
 
-// Sums n consecutive groups of 4 partials in a fixed order and adds them to acc[0..3].
+// Sums n consecutive groups of 4 partials in a fixed order and adds them to
+// acc[0..3]: stage 1 reduces kAdjRedBlocks contiguous ranges (one block each)
+// into red[block][4], stage 2 sums those in block order.
 constexpr int kAdjRedThreads = 256;
-__global__ __launch_bounds__(kAdjRedThreads) void adjoint_reduce_kernel(const double* __restrict__ partial, long long n,
-                                                                        double* __restrict__ acc) {
-    __shared__ double sh[4][kAdjRedThreads];
+__device__ inline void block_sum4(double (&v)[4], double (*sh)[kAdjRedThreads]) {
     const int t = threadIdx.x;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long i = t; i < n; i += kAdjRedThreads)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += partial[i * 4 + q];
 #pragma unroll
     for (int q = 0; q < 4; ++q) sh[q][t] = v[q];
     __syncthreads();
@@ -461,7 +457,31 @@ __global__ __launch_bounds__(kAdjRedThreads) void adjoint_reduce_kernel(const do
             for (int q = 0; q < 4; ++q) sh[q][t] += sh[q][t + s];
         __syncthreads();
     }
-    if (t < 4) acc[t] += sh[t][0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = sh[q][0];
+}
+
+__global__ __launch_bounds__(kAdjRedThreads) void adjoint_reduce_stage1(const double* __restrict__ partial, long long n,
+                                                                        double* __restrict__ red) {
+    __shared__ double sh[4][kAdjRedThreads];
+    const long long lo = n * blockIdx.x / gridDim.x, hi = n * (blockIdx.x + 1) / gridDim.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = lo + threadIdx.x; i < hi; i += kAdjRedThreads)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += partial[i * 4 + q];
+    block_sum4(v, sh);
+    if (threadIdx.x < 4) red[blockIdx.x * 4 + threadIdx.x] = v[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kAdjRedThreads) void adjoint_reduce_stage2(const double* __restrict__ red, int nb,
+                                                                        double* __restrict__ acc) {
+    __shared__ double sh[4][kAdjRedThreads];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nb; i += kAdjRedThreads)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += red[i * 4 + q];
+    block_sum4(v, sh);
+    if (threadIdx.x < 4) acc[threadIdx.x] += v[threadIdx.x];
 }
 
 // dJ/df* of the initial state: the pull transpose of the last adjoint step's
@@ -510,9 +530,12 @@ hipError_t launch_adjoint(const AdjArgs& A, int storage, int eos, hipStream_t s)
     }
 }
 
-hipError_t launch_adjoint_reduce(const double* partial, long long ngroups, double* acc, hipStream_t s) {
+hipError_t launch_adjoint_reduce(const double* partial, long long ngroups, double* red, double* acc, hipStream_t s) {
     if (ngroups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(1), dim3(kAdjRedThreads), 0, s, partial, ngroups, acc);
+    hipLaunchKernelGGL(adjoint_reduce_stage1, dim3(kAdjRedBlocks), dim3(kAdjRedThreads), 0, s, partial, ngroups, red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(adjoint_reduce_stage2, dim3(1), dim3(kAdjRedThreads), 0, s, red, kAdjRedBlocks, acc);
     return hipGetLastError();
 }
 

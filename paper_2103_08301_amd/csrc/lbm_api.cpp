@@ -303,8 +303,8 @@ struct lbm_ctx {
         bool bound = false, recorded = false, swept = false;
         int64_t n = 0, seg = 0, nckpt = 0;  // recorded steps, segment length, checkpoints
         size_t state = 0, lam = 0;          // bytes of one state / one adjoint field (aligned)
-        size_t off_ckpt = 0, off_seg = 0, off_lam[2]{}, off_tw = 0, off_part = 0, off_acc = 0, off_scr = 0,
-               off_pw = 0, off_g0 = 0, total = 0;
+        size_t off_ckpt = 0, off_seg = 0, off_lam[2]{}, off_tw = 0, off_part = 0, off_red = 0, off_acc = 0,
+               off_scr = 0, off_pw = 0, off_g0 = 0, total = 0;
         int blocks = 0, cur = 0, ty = 8;
         double J = 0, seed = 1;
     } adj;
@@ -1050,6 +1050,7 @@ lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm
     A.off_lam[1] = o; o += A.lam;
     A.off_tw = o; o += align256((size_t)A.seg * 2 * c->nx * sizeof(double));
     A.off_part = o; o += align256((size_t)kAdjRing * A.blocks * 4 * sizeof(double));
+    A.off_red = o; o += align256((size_t)lbm::kAdjRedBlocks * 4 * sizeof(double));
     A.off_acc = o; o += 256;
     A.off_scr = o; o += align256((size_t)2 * c->nstrip * lbm::kPartialVals * sizeof(double));
     A.off_pw = o; o += align256((size_t)2 * c->nx * sizeof(double));
@@ -1122,6 +1123,7 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     double* tw = reinterpret_cast<double*>(A.dev + A.off_tw);
     double* part = reinterpret_cast<double*>(A.dev + A.off_part);
     double* acc = reinterpret_cast<double*>(A.dev + A.off_acc);
+    double* red = reinterpret_cast<double*>(A.dev + A.off_red);
     HIP_TRY(c, lbm::launch_fill(reinterpret_cast<double*>(A.dev + A.off_lam[0]), 0.0, (long long)(A.lam / 8), c->stream));
     HIP_TRY(c, lbm::launch_fill(acc, 0.0, 4, c->stream));
     A.cur = 0;
@@ -1150,12 +1152,12 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
             HIP_TRY(c, lbm::launch_adjoint(aa, storage, eos, c->stream));
             A.cur = 1 - A.cur;
             if (++ring == kAdjRing) {
-                HIP_TRY(c, lbm::launch_adjoint_reduce(part, (long long)ring * A.blocks, acc, c->stream));
+                HIP_TRY(c, lbm::launch_adjoint_reduce(part, (long long)ring * A.blocks, red, acc, c->stream));
                 ring = 0;
             }
         }
     }
-    if (ring > 0) HIP_TRY(c, lbm::launch_adjoint_reduce(part, (long long)ring * A.blocks, acc, c->stream));
+    if (ring > 0) HIP_TRY(c, lbm::launch_adjoint_reduce(part, (long long)ring * A.blocks, red, acc, c->stream));
     double sums[4];
     HIP_TRY(c, hipMemcpyAsync(sums, acc, sizeof sums, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
