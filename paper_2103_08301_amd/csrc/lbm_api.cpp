@@ -216,7 +216,7 @@ size_t storage_bytes(int storage) {
     }
 }
 
-constexpr int kRingCap = 256;  // per-step partial slots before a wall reduction is forced
+constexpr int kRingCap = 256;  // per-step wall-ring slots before a wall reduction is forced
 constexpr int kDefaultMarchRows = 16;
 
 // Tile heights each schedule is compiled for (0 picks the default).
@@ -288,7 +288,7 @@ struct lbm_ctx {
     long long plane = 0;
     int nstrip = 0, nchunk = 0, ty = 0, schedule = 0, tile_waves = 4, pipe_blocks = 0;
     // workspace layout (byte offsets)
-    size_t off_f[2]{}, off_rho = 0, off_vx = 0, off_vy = 0, off_tau = 0, off_pw = 0, off_ring = 0, off_hist = 0,
+    size_t off_f[2]{}, off_rho = 0, off_vx = 0, off_vy = 0, off_ring = 0, off_hist = 0,
            off_acc = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, off_tickets = 0,
            total = 0;
     char* dev = nullptr;
@@ -304,13 +304,14 @@ struct lbm_ctx {
         int64_t n = 0, seg = 0, nckpt = 0;  // recorded steps, segment length, checkpoints
         size_t state = 0, lam = 0;          // bytes of one state / one adjoint field (aligned)
         size_t off_ckpt = 0, off_seg = 0, off_lam[2]{}, off_tw = 0, off_part = 0, off_red = 0, off_acc = 0,
-               off_scr = 0, off_pw = 0, off_g0 = 0, total = 0;
+               off_pw = 0, off_g0 = 0, total = 0;
         int blocks = 0, cur = 0, ty = 8;
         double J = 0, seed = 1;
     } adj;
     int cur = 0;
     int64_t steps = 0;
     int ring_fill = 0;
+    int last_slot = -1;  // wall-ring slot of the latest step (its wall arrays)
     int64_t ring_first_step = 1;
     lbm_check_result check{};
     std::string err;
@@ -348,8 +349,6 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     const long long nxy = (long long)c->nx * c->ny;
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_vx), 0.0, nxy, c->stream));
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_vy), 0.0, nxy, c->stream));
-    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_tau), 0.0, 2LL * c->nx, c->stream));
-    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_pw), 0.0, 2LL * c->nx, c->stream));
     double* acc = c->at<double>(c->off_acc);
     HIP_TRY(c, lbm::launch_fill(acc, 0.0, 2, c->stream));
     for (int q = 0; q < 4; ++q)  // running maxima start at -inf, minima at +inf
@@ -357,6 +356,7 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     HIP_TRY(c, lbm::launch_fill(acc + 10, 0.0, 1, c->stream));  // tangent of the sum-of-squares integral
     c->steps = 0;
     c->ring_fill = 0;
+    c->last_slot = -1;
     c->ring_first_step = 1;
     c->check = lbm_check_result{};
     c->check.rupture_step = -1;
@@ -381,7 +381,7 @@ lbm_status init_from_device_rho(lbm_ctx* c) {
 lbm_status flush_wall(lbm_ctx* c) {
     if (c->ring_fill == 0) return LBM_OK;
     if (!c->p.y_periodic) {
-        HIP_TRY(c, lbm::launch_wall_reduce(c->at<double>(c->off_ring), c->ring_fill, c->nstrip, c->ring_first_step,
+        HIP_TRY(c, lbm::launch_wall_reduce(c->at<double>(c->off_ring), c->ring_fill, c->nx, c->ring_first_step,
                                            c->at<lbm_stress_summary>(c->off_hist), c->p.history_cap,
                                            c->at<double>(c->off_wscr), c->at<double>(c->off_acc), c->stream));
     }
@@ -444,6 +444,14 @@ lbm_status run_check(lbm_ctx* c) {
     return LBM_OK;
 }
 
+// Points the wall arrays of a step's arguments at a slot of the wall ring.
+void set_wall_slot(lbm::StepArgs& a, const lbm_ctx* c, int slot) {
+    double* w = c->at<double>(c->off_ring) + (size_t)slot * lbm::kWallSlotVals * c->nx;
+    a.tau_w = w;
+    a.p_w = w + 2 * (size_t)c->nx;
+    a.dtau_w = w + 4 * (size_t)c->nx;
+}
+
 lbm::StepArgs make_args(const lbm_ctx* c) {
     lbm::StepArgs a{};
     a.nx = c->nx;
@@ -475,8 +483,7 @@ lbm::StepArgs make_args(const lbm_ctx* c) {
     a.cf = lbm::CoefF32{float(a.tau), float(a.s_e), float(a.s_eps), float(a.s_q), float(a.s_j), float(a.s_v),
                         float(a.k2), float(a.kappa), float(a.g), float(a.nu), float(a.RT), float(a.a_eff),
                         float(a.b), float(a.rho_w), float(a.rho0)};
-    a.tau_w = c->at<double>(c->off_tau);
-    a.p_w = c->at<double>(c->off_pw);
+    a.ring = c->at<double>(c->off_ring);
     a.rho_out = c->at<double>(c->off_rho);
     a.vx_out = c->at<double>(c->off_vx);
     a.vy_out = c->at<double>(c->off_vy);
@@ -593,9 +600,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->off_rho = o; o += nxy8;
     c->off_vx = o; o += nxy8;
     c->off_vy = o; o += nxy8;
-    c->off_tau = o; o += align256(2 * (size_t)nx * sizeof(double));
-    c->off_pw = o; o += align256(2 * (size_t)nx * sizeof(double));
-    c->off_ring = o; o += align256((size_t)kRingCap * 2 * c->nstrip * lbm::kPartialVals * sizeof(double));
+    c->off_ring = o; o += align256((size_t)kRingCap * lbm::kWallSlotVals * nx * sizeof(double));
     c->off_hist = o; o += align256((size_t)p->history_cap * sizeof(lbm_stress_summary));
     c->off_acc = o; o += 256;
     c->off_wscr = o; o += align256((size_t)kRingCap * lbm::kWallScratchVals * sizeof(double));
@@ -694,7 +699,6 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     if (c->in_batch) return fail(c, LBM_ESTATE, "this context belongs to a batch: step it with lbm_batch_step");
     if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_step needs lbm_bind and an initialisation");
     lbm::StepArgs a = make_args(c);
-    const size_t slot = (size_t)2 * c->nstrip * lbm::kPartialVals;
     if (c->schedule == lbm::kSchedulePipe && n > 0) {
         // the ticket counters start from zero for this run of launches (all-zero bits)
         HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_tickets), 0.0,
@@ -721,13 +725,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
                     const int in = (par + j) & 1;
                     b.fin = c->dev + c->off_f[in];
                     b.fout = c->dev + c->off_f[1 - in];
-                    b.partial = c->at<double>(c->off_ring) + slot * (fill0 + j);
+                    set_wall_slot(b, c, fill0 + j);
                     return lbm::launch_step(b, c->p.storage, c->p.eos, false, s);
                 };
                 HIP_TRY(c, capture_graph(c->graphs, G, launch, &ge));
             }
             HIP_TRY(c, hipGraphLaunch(ge, c->stream));
             if (G & 1) c->cur = 1 - c->cur;
+            c->last_slot = c->ring_fill + G - 1;
             c->ring_fill += G;
             c->steps += G;
             k += G;
@@ -740,10 +745,11 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
             const bool emit = (k == seg - 1);
             a.fin = c->dev + c->off_f[c->cur];
             a.fout = c->dev + c->off_f[1 - c->cur];
-            a.partial = c->at<double>(c->off_ring) + slot * c->ring_fill;
+            set_wall_slot(a, c, c->ring_fill);
             HIP_TRY(c, lbm::launch_step(a, c->p.storage, c->p.eos, emit, c->stream));
             a.launch += 1;
             c->cur = 1 - c->cur;
+            c->last_slot = c->ring_fill;
             c->ring_fill += 1;
             c->steps += 1;
         }
@@ -778,10 +784,16 @@ lbm_status lbm_wall_stress(lbm_ctx* c, double* tau_bot, double* tau_top, double*
     if (!c) return LBM_EINVAL;
     if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
     const size_t nxb = (size_t)c->nx * sizeof(double);
-    if (tau_bot) HIP_TRY(c, hipMemcpyAsync(tau_bot, c->dev + c->off_tau, nxb, hipMemcpyDeviceToHost, c->stream));
-    if (tau_top) HIP_TRY(c, hipMemcpyAsync(tau_top, c->dev + c->off_tau + nxb, nxb, hipMemcpyDeviceToHost, c->stream));
-    if (p_bot) HIP_TRY(c, hipMemcpyAsync(p_bot, c->dev + c->off_pw, nxb, hipMemcpyDeviceToHost, c->stream));
-    if (p_top) HIP_TRY(c, hipMemcpyAsync(p_top, c->dev + c->off_pw + nxb, nxb, hipMemcpyDeviceToHost, c->stream));
+    double* outs[4] = {tau_bot, tau_top, p_bot, p_top};
+    for (int q = 0; q < 4; ++q) {
+        if (!outs[q]) continue;
+        if (c->last_slot < 0 || c->p.y_periodic) {  // no step yet, or no walls: zeros
+            std::memset(outs[q], 0, nxb);
+            continue;
+        }
+        const char* src = c->dev + c->off_ring + ((size_t)c->last_slot * lbm::kWallSlotVals + q) * nxb;
+        HIP_TRY(c, hipMemcpyAsync(outs[q], src, nxb, hipMemcpyDeviceToHost, c->stream));
+    }
     if (s) {
         std::memset(s, 0, sizeof *s);
         if (c->steps > 0 && !c->p.y_periodic) {
@@ -952,16 +964,12 @@ struct TileShape {
 // Tile shapes of the tile schedule (schedule_ok), in the order they are tried.
 constexpr TileShape kTileShapes[] = {{8, 4}, {12, 4}, {20, 4}, {28, 4}, {12, 8}, {20, 8}, {28, 8}};
 
-// Step arguments for timing trials: the wall shear, wall pressure and per-strip
-// partials go to the wall ring (free after a flush), so a trial leaves every
-// diagnostic the caller can read untouched.
+// Step arguments for timing trials: the wall arrays go to a slot of the (flushed)
+// wall ring other than the latest step's, so a trial leaves every diagnostic
+// the caller can read untouched.
 lbm::StepArgs trial_args(const lbm_ctx* c) {
     lbm::StepArgs a = make_args(c);
-    double* ring = c->at<double>(c->off_ring);
-    const size_t slot = (size_t)2 * c->nstrip * lbm::kPartialVals;
-    a.partial = ring;
-    a.tau_w = ring + slot;             // 255 slots of >= nx/3 doubles hold 4 nx doubles
-    a.p_w = ring + slot + 2 * (size_t)c->nx;
+    set_wall_slot(a, c, (c->last_slot + 1) % kRingCap);
     a.fin = c->dev + c->off_f[c->cur];  // every trial reads the current state and writes the other buffer
     a.fout = c->dev + c->off_f[1 - c->cur];
     return a;
@@ -1052,8 +1060,7 @@ lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm
     A.off_part = o; o += align256((size_t)kAdjRing * A.blocks * 4 * sizeof(double));
     A.off_red = o; o += align256((size_t)lbm::kAdjRedBlocks * 4 * sizeof(double));
     A.off_acc = o; o += 256;
-    A.off_scr = o; o += align256((size_t)2 * c->nstrip * lbm::kPartialVals * sizeof(double));
-    A.off_pw = o; o += align256((size_t)2 * c->nx * sizeof(double));
+    A.off_pw = o; o += align256((size_t)4 * c->nx * sizeof(double));
     A.off_g0 = o; o += align256((size_t)9 * c->nx * c->ny * sizeof(double));
     A.total = o;
     return LBM_OK;
@@ -1128,8 +1135,8 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     HIP_TRY(c, lbm::launch_fill(acc, 0.0, 4, c->stream));
     A.cur = 0;
     lbm::StepArgs fa = base;  // forward recompute: wall shear to the per-step slots, other diagnostics to scratch
-    fa.partial = reinterpret_cast<double*>(A.dev + A.off_scr);
     fa.p_w = reinterpret_cast<double*>(A.dev + A.off_pw);
+    fa.dtau_w = fa.p_w + 2 * (size_t)c->nx;
     lbm::AdjArgs aa{};
     aa.s = base;
     aa.nstrip = (c->nx + lbm::kAdjStripOut - 1) / lbm::kAdjStripOut;
@@ -1322,13 +1329,12 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
         lbm::StepArgs a = make_args(c);
         a.fin = c->dev + c->off_f[0];
         a.fout = c->dev + c->off_f[1];
-        a.partial = c->at<double>(c->off_ring);
         desc.push_back(a);
     }
     std::vector<lbm::WallFlush> flush;
     for (lbm_ctx* c : b->cases)
         if (!c->p.y_periodic)
-            flush.push_back(lbm::WallFlush{c->at<double>(c->off_ring), c->nstrip, c->at<lbm_stress_summary>(c->off_hist),
+            flush.push_back(lbm::WallFlush{c->at<double>(c->off_ring), c->nx, c->at<lbm_stress_summary>(c->off_hist),
                                            c->p.history_cap, c->at<double>(c->off_wscr), c->at<double>(c->off_acc)});
     b->nflush = (int)flush.size();
     hipError_t e = hipMemcpyAsync(b->dev + b->off_desc, desc.data(), desc.size() * sizeof(lbm::StepArgs),
@@ -1368,6 +1374,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
     auto advance = [&](int nsteps) {
         for (lbm_ctx* c : b->cases) {
             c->cur = (c->cur + nsteps) & 1;
+            c->last_slot = c->ring_fill + nsteps - 1;
             c->ring_fill += nsteps;
             c->steps += nsteps;
         }
@@ -1453,7 +1460,6 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int
         lbm::StepArgs r = make_args(c);
         r.fin = a.fin;
         r.fout = a.fout;
-        r.partial = c->at<double>(c->off_ring);
         real.push_back(r);
     }
     auto* desc = reinterpret_cast<lbm::StepArgs*>(b->dev + b->off_desc);
@@ -1474,9 +1480,9 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int
         e = hipMemcpyAsync(const_cast<int*>(tiles), start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice,
                            b->stream);
         if (e != hipSuccess) break;
-        e = time_launches(b->stream, trial_steps, [&] {
-            return lbm::launch_step_batch(desc, tiles, ncases, start.back(), c0->cur, 0, c0->p.storage, c0->p.eos,
-                                          t.rows, t.waves, false, b->stream);
+        e = time_launches(b->stream, trial_steps, [&] {  // wall arrays to a slot other than the latest step's
+            return lbm::launch_step_batch(desc, tiles, ncases, start.back(), c0->cur, (c0->last_slot + 1) % kRingCap,
+                                          c0->p.storage, c0->p.eos, t.rows, t.waves, false, b->stream);
         }, &us);
         if (e == hipSuccess && us < best) { best = us; pick = t; }
     }

@@ -589,8 +589,8 @@ struct Stepper {
         for (int i = 0; i < 9; ++i) { W.f2[i] = W.f1[i]; W.f1[i] = f0[i]; }
     }
 
-    // Wall shear and wall pressure on the first two fluid rows of each wall,
-    // with the per-strip FP64 extremes of this step.
+    // Wall shear and wall pressure on the first two fluid rows of each wall
+    // (FP64, into this step's slot of the wall ring).
     __device__ void wall_row(Window<C>& W, int y, C rh, C vx) const {
         if (a.yper) return;
         const bool bottom_p = (y == 0), top_p = (y == a.ny - 1);
@@ -607,25 +607,10 @@ struct Stepper {
         const C tw = bottom_t ? W.wall_rho * nu * (C(9) * W.wall_vx - vx) * C(1.0 / 3.0)
                               : rh * nu * (C(9) * vx - W.wall_vx) * C(1.0 / 3.0);
         const int w = bottom_t ? 0 : 1;
-        const double dt = out_lane ? double(tw) : 0.0, dpw = out_lane ? double(W.wall_p) : 0.0;
         if (out_lane) {
-            a.tau_w[w * a.nx + x] = dt;
-            a.p_w[w * a.nx + x] = dpw;
-        }
-        double tmax = out_lane ? dt : -INFINITY, tmin = out_lane ? dt : INFINITY;
-        double pmax = out_lane ? dpw : -INFINITY, pmin = out_lane ? dpw : INFINITY;
-        int xtmax = out_lane ? x : 0x7fffffff, xtmin = xtmax, xpmax = xtmax, xpmin = xtmax;
-        wave_argmax(tmax, xtmax);
-        wave_argmin(tmin, xtmin);
-        wave_argmax(pmax, xpmax);
-        wave_argmin(pmin, xpmin);
-        const double s2 = wave_sum(dt * dt);
-        const double ds2 = wave_sum(out_lane ? 2.0 * dt * tangent_of(tw) : 0.0);  // d(sum tau^2) along the tangent
-        if (lane == 0) {
-            double* o = a.partial + ((long long)w * a.nstrip + strip) * kPartialVals;
-            o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
-            o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
-            o[8] = s2; o[9] = ds2;
+            a.tau_w[w * a.nx + x] = double(tw);
+            a.p_w[w * a.nx + x] = double(W.wall_p);
+            a.dtau_w[w * a.nx + x] = tangent_of(tw);
         }
     }
 };
@@ -710,10 +695,11 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
 // every tile has TYO output rows and the two rows next to a wall share a tile
 // (rows covered by two tiles are computed identically by both).
 // One tile of one lattice: `bid` is the tile index in tile-row-major order,
-// fin/fout/partial the buffers of this step (the kernels below pick them).
+// fin/fout the distribution buffers of this step and tau_w/p_w/dtau_w its wall
+// arrays (the kernels below pick them).
 template <class CD, int EOS, bool EMIT, int TYO, int NW>
-__device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, void* fout_v, double* partial,
-                                          int bid) {
+__device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, void* fout_v, double* tau_w,
+                                          double* p_w, double* dtau_w, int bid) {
     using S = typename CD::S;
     using C = typename CD::C;
     constexpr int H = TYO + 4;    // tile rows including the halo
@@ -860,7 +846,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
         }
     }
 
-    // ---- phase D: wall shear and the per-strip extremes -------------------------------
+    // ---- phase D: wall shear and wall pressure into this step's wall arrays ----------
     if (!wall_tile) return;  // block-uniform
     __syncthreads();
     const bool has_bottom = (y0 == 0), has_top = (y0 + TYO >= a.ny);
@@ -869,32 +855,17 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
         // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
         const C v_half = sWv[w == 0 ? 0 : 3][lane], v_3half = sWv[w == 0 ? 1 : 2][lane];
         const C tw = sWr[w][lane] * LBM_COEF(C, nu) * (C(9) * v_half - v_3half) * C(1.0 / 3.0);
-        const double dt = out_lane ? double(tw) : 0.0, dpw = out_lane ? double(sWp[w][lane]) : 0.0;
         if (out_lane) {
-            a.tau_w[w * a.nx + x] = dt;
-            a.p_w[w * a.nx + x] = dpw;
-        }
-        double tmax = out_lane ? dt : -INFINITY, tmin = out_lane ? dt : INFINITY;
-        double pmax = out_lane ? dpw : -INFINITY, pmin = out_lane ? dpw : INFINITY;
-        int xtmax = out_lane ? x : 0x7fffffff, xtmin = xtmax, xpmax = xtmax, xpmin = xtmax;
-        wave_argmax(tmax, xtmax);
-        wave_argmin(tmin, xtmin);
-        wave_argmax(pmax, xpmax);
-        wave_argmin(pmin, xpmin);
-        const double s2 = wave_sum(dt * dt);
-        const double ds2 = wave_sum(out_lane ? 2.0 * dt * tangent_of(tw) : 0.0);  // d(sum tau^2) along the tangent
-        if (lane == 0) {
-            double* o = partial + ((long long)w * a.nstrip + strip) * kPartialVals;
-            o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
-            o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
-            o[8] = s2; o[9] = ds2;
+            tau_w[w * a.nx + x] = double(tw);
+            p_w[w * a.nx + x] = double(sWp[w][lane]);
+            dtau_w[w * a.nx + x] = tangent_of(tw);
         }
     }
 }
 
 template <class CD, int EOS, bool EMIT, int TYO, int NW>
 __global__ __launch_bounds__(64 * NW) void tile_kernel(const StepArgs a) {
-    tile_body<CD, EOS, EMIT, TYO, NW>(a, a.fin, a.fout, a.partial, xcd_remap(blockIdx.x, gridDim.x));
+    tile_body<CD, EOS, EMIT, TYO, NW>(a, a.fin, a.fout, a.tau_w, a.p_w, a.dtau_w, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Many lattices in one launch: the tiles of case c are blocks
@@ -915,8 +886,8 @@ __global__ __launch_bounds__(64 * NW) void tile_batch_kernel(const StepArgs* __r
     const StepArgs& a = cases[lo];
     const void* fin = parity ? a.fout : a.fin;
     void* fout = parity ? const_cast<void*>(a.fin) : a.fout;
-    tile_body<CD, EOS, EMIT, TYO, NW>(a, fin, fout, a.partial + (long long)slot * 2 * a.nstrip * kPartialVals,
-                                      bid - tile_start[lo]);
+    double* w = a.ring + (long long)slot * kWallSlotVals * a.nx;
+    tile_body<CD, EOS, EMIT, TYO, NW>(a, fin, fout, w, w + 2 * a.nx, w + 4 * a.nx, bid - tile_start[lo]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1138,7 +1109,7 @@ struct Pipe {
             }
         }
 
-        // ---- D: wall shear and the per-strip extremes (wall tiles only) -------------------
+        // ---- D: wall shear and wall pressure (wall tiles only) ----------------------------
         if (g.wall) {  // block-uniform
             __syncthreads();
             const bool has_bottom = (g.y0 == 0), has_top = (g.y0 + TYO >= a.ny);
@@ -1146,25 +1117,10 @@ struct Pipe {
                 // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
                 const C v_half = sm.wv[w == 0 ? 0 : 3][lane], v_3half = sm.wv[w == 0 ? 1 : 2][lane];
                 const C tw = sm.wr[w][lane] * LBM_COEF(C, nu) * (C(9) * v_half - v_3half) * C(1.0 / 3.0);
-                const double dt = out_lane ? double(tw) : 0.0, dpw = out_lane ? double(sm.wp[w][lane]) : 0.0;
                 if (out_lane) {
-                    a.tau_w[w * a.nx + x] = dt;
-                    a.p_w[w * a.nx + x] = dpw;
-                }
-                double tmax = out_lane ? dt : -INFINITY, tmin = out_lane ? dt : INFINITY;
-                double pmax = out_lane ? dpw : -INFINITY, pmin = out_lane ? dpw : INFINITY;
-                int xtmax = out_lane ? x : 0x7fffffff, xtmin = xtmax, xpmax = xtmax, xpmin = xtmax;
-                wave_argmax(tmax, xtmax);
-                wave_argmin(tmin, xtmin);
-                wave_argmax(pmax, xpmax);
-                wave_argmin(pmin, xpmin);
-                const double s2 = wave_sum(dt * dt);
-                const double ds2 = wave_sum(out_lane ? 2.0 * dt * tangent_of(tw) : 0.0);  // d(sum tau^2) along the tangent
-                if (lane == 0) {
-                    double* o = a.partial + ((long long)w * a.nstrip + g.strip) * kPartialVals;
-                    o[0] = tmax; o[1] = double(xtmax); o[2] = tmin; o[3] = double(xtmin);
-                    o[4] = pmax; o[5] = double(xpmax); o[6] = pmin; o[7] = double(xpmin);
-                    o[8] = s2; o[9] = ds2;
+                    a.tau_w[w * a.nx + x] = double(tw);
+                    a.p_w[w * a.nx + x] = double(sm.wp[w][lane]);
+                    a.dtau_w[w * a.nx + x] = tangent_of(tw);
                 }
             }
         }

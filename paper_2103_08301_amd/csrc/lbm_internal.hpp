@@ -16,7 +16,10 @@ namespace lbm {
 // force stencil grad(lap rho) needs.
 constexpr int kStripOut = 60;
 constexpr int kWavesPerBlock = 4;
-constexpr int kPartialVals = 10;  // tmax, xtmax, tmin, xtmin, pmax, xpmax, pmin, xpmin, sum tau^2, its tangent
+// One step's slot of the wall ring: per wall column, FP64 wall shear [2][nx],
+// wall pressure [2][nx] and the wall shear's tangent [2][nx] (zero unless the
+// storage is tangent-linear).
+constexpr int kWallSlotVals = 6;
 constexpr int kScheduleTile = 0;   // block-per-tile kernel with LDS-coupled phases
 constexpr int kScheduleMarch = 1;  // wave-per-strip row march with a register window
 constexpr int kSchedulePipe = 2;   // persistent blocks taking tiles by ticket, next tile's loads in flight
@@ -52,9 +55,10 @@ struct StepArgs {
     double rho0;              // storage shift (F16S/BF16S)
     CoefF32 cf;               // the coefficients above, rounded to FP32
     CoefTangent ct;           // their tangents (tangent-linear storage)
-    double* tau_w;            // [2][nx] wall shear of this step
+    double* tau_w;            // [2][nx] wall shear of this step (its slot of the wall ring)
     double* p_w;              // [2][nx] wall pressure of this step
-    double* partial;          // [2][nstrip][kPartialVals] this step's per-strip wall extremes
+    double* dtau_w;           // [2][nx] tangent of the wall shear of this step
+    double* ring;             // batch launches: base of the case's wall ring (slots of kWallSlotVals * nx)
     unsigned long long* tickets;  // kTicketGroups counters, kTicketStride apart (pipelined schedule)
     long long launch;         // launches since the counters were zeroed (pipelined schedule)
     int pipe_blocks;          // grid of the pipelined schedule
@@ -98,16 +102,16 @@ hipError_t launch_field_reduce(const double* rho, const double* vx, const double
 // Per column: minimum density over y and the centreline density.
 hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin, double* centre,
                               hipStream_t s);
-// Reduces the first `nsteps` slots of the per-strip partial ring (one wave per
-// step) into the history ring, then accumulates the running time integrals and
+// Reduces the first `nsteps` slots of the wall ring (one wave per step: extremes
+// and their columns, sums of squares) into the history ring, then accumulates the running time integrals and
 // running extremes acc[kWallAccVals] in step order.  scratch holds
 // kWallScratchVals doubles per step.
-hipError_t launch_wall_reduce(const double* partial_ring, int nsteps, int nstrip, int64_t first_step,
+hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t first_step,
                               lbm_stress_summary* hist, int hist_cap, double* scratch, double* acc, hipStream_t s);
 // The wall ring, history, scratch and accumulators of one lattice.
 struct WallFlush {
     const double* ring;
-    int nstrip;
+    int nx;
     lbm_stress_summary* hist;
     int hist_cap;
     double* scratch;

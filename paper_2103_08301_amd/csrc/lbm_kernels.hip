@@ -119,23 +119,25 @@ __device__ inline void comb_min(double& v, double& x, double ov, double ox) {
 
 __device__ void wall_step_reduce_body(const WallFlush& f, int t, int64_t first_step) {
     const int lane = threadIdx.x;
-    const int nstrip = f.nstrip;
-    const double* slot = f.ring + (long long)t * 2 * nstrip * kPartialVals;
+    const int nx = f.nx;
+    const double* slot = f.ring + (long long)t * kWallSlotVals * nx;  // tau [2][nx], p [2][nx], dtau [2][nx]
     lbm_stress_summary sm;
     sm.step = first_step + t;
     double pk = 0.0, s2 = 0.0, ds2 = 0.0;
     for (int w = 0; w < 2; ++w) {
-        const double* p = slot + (long long)w * nstrip * kPartialVals;
+        const double* tau = slot + (long long)w * nx;
+        const double* pw = slot + (long long)(2 + w) * nx;
+        const double* dtau = slot + (long long)(4 + w) * nx;
         double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
         double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0, wds = 0.0;
-        for (int st = lane; st < nstrip; st += 64) {
-            const double* q = p + (long long)st * kPartialVals;
-            comb_max(tmax, xtmax, q[0], q[1]);
-            comb_min(tmin, xtmin, q[2], q[3]);
-            comb_max(pmax, xpmax, q[4], q[5]);
-            comb_min(pmin, xpmin, q[6], q[7]);
-            ws += q[8];
-            wds += q[9];
+        for (int x = lane; x < nx; x += 64) {  // fixed order: lane-strided, then the butterfly below
+            const double tv = tau[x], pv = pw[x];
+            comb_max(tmax, xtmax, tv, double(x));
+            comb_min(tmin, xtmin, tv, double(x));
+            comb_max(pmax, xpmax, pv, double(x));
+            comb_min(pmin, xpmin, pv, double(x));
+            ws += tv * tv;
+            wds += 2.0 * tv * dtau[x];
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -310,10 +312,10 @@ hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin,
     return hipGetLastError();
 }
 
-hipError_t launch_wall_reduce(const double* ring, int nsteps, int nstrip, int64_t first_step, lbm_stress_summary* hist,
+hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t first_step, lbm_stress_summary* hist,
                               int hist_cap, double* scratch, double* acc, hipStream_t s) {
     if (nsteps <= 0) return hipSuccess;
-    const WallFlush f{ring, nstrip, hist, hist_cap, scratch, acc};
+    const WallFlush f{ring, nx, hist, hist_cap, scratch, acc};
     hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps), dim3(64), 0, s, f, first_step);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

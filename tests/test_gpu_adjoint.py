@@ -135,7 +135,7 @@ def test_autograd_function():
     J = WallShearObjective.apply(theta, spec)
     (3.0 * J).backward()
     J_ref, grad_ref, _ = adjoint(P)
-    assert float(J) == pytest.approx(J_ref, rel=1e-12)
+    assert float(J.detach()) == pytest.approx(J_ref, rel=1e-12)
     assert np.allclose(theta.grad.numpy(), 3.0 * grad_ref, rtol=1e-12, atol=0)
 
 
