@@ -320,6 +320,10 @@ struct lbm_ctx {
         if (p.graph_steps < 0 || schedule == lbm::kSchedulePipe) return 0;
         return p.graph_steps == 0 ? 64 : p.graph_steps;
     }
+    // steps per launch of lbm_step: 2 with the tile schedule's two-step kernel (on request)
+    int steps_per_launch() const {
+        return (schedule == lbm::kScheduleTile && p.storage != LBM_F64T && p.fused_steps == 2) ? 2 : 1;
+    }
 
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(dev + off); }
@@ -534,6 +538,7 @@ void lbm_params_default(lbm_params* p) {
     p->tile_waves = 0;
     p->pipe_blocks = 0;
     p->graph_steps = 0;
+    p->fused_steps = 0;
 }
 
 lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx** out) {
@@ -547,7 +552,8 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
         !(p->v_limit > 0) || p->history_cap < 1 || (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) ||
         p->storage < LBM_F64 || p->storage > LBM_F64T || (p->x_periodic != 0 && p->x_periodic != 1) ||
         (p->y_periodic != 0 && p->y_periodic != 1) || !std::isfinite(p->omega) ||
-        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || !schedule_ok(p) || !graph_steps_ok(p->graph_steps))
+        (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || !schedule_ok(p) || !graph_steps_ok(p->graph_steps) ||
+        p->fused_steps < 0 || p->fused_steps > 2)
         return LBM_EINVAL;
     const int pitch = (nx + 63) / 64 * 64;
     // the step kernel addresses a distribution buffer with 32-bit byte offsets
@@ -706,6 +712,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     }
     a.launch = 0;
     const int G = c->graph_steps();
+    const int L = c->steps_per_launch();  // steps per launch (1 or 2); G is a multiple of it
+    auto launch_k = [&](lbm::StepArgs& b, int in, int slot, int nsteps, bool emit, hipStream_t s) {
+        b.fin = c->dev + c->off_f[in];
+        b.fout = c->dev + c->off_f[1 - in];
+        set_wall_slot(b, c, slot);
+        return nsteps == 2 ? lbm::launch_step2(b, c->p.storage, c->p.eos, emit, s)
+                           : lbm::launch_step(b, c->p.storage, c->p.eos, emit, s);
+    };
     int64_t done = 0;
     while (done < n) {
         const int64_t next_check = (c->steps / c->p.check_every + 1) * c->p.check_every;
@@ -717,41 +731,37 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
                 lbm_status s = flush_wall(c);
                 if (s) return s;
             }
+            const int nl = G / L;  // launches in the graph; each flips the buffers once
             hipGraphExec_t& ge = c->graphs.exec[c->cur][c->ring_fill];
             if (!ge) {
                 const int par = c->cur, fill0 = c->ring_fill;
                 auto launch = [&](int j, hipStream_t s) {
                     lbm::StepArgs b = a;
-                    const int in = (par + j) & 1;
-                    b.fin = c->dev + c->off_f[in];
-                    b.fout = c->dev + c->off_f[1 - in];
-                    set_wall_slot(b, c, fill0 + j);
-                    return lbm::launch_step(b, c->p.storage, c->p.eos, false, s);
+                    return launch_k(b, (par + j) & 1, fill0 + L * j, L, false, s);
                 };
-                HIP_TRY(c, capture_graph(c->graphs, G, launch, &ge));
+                HIP_TRY(c, capture_graph(c->graphs, nl, launch, &ge));
             }
             HIP_TRY(c, hipGraphLaunch(ge, c->stream));
-            if (G & 1) c->cur = 1 - c->cur;
+            if (nl & 1) c->cur = 1 - c->cur;
             c->last_slot = c->ring_fill + G - 1;
             c->ring_fill += G;
             c->steps += G;
             k += G;
         }
-        for (; k < seg; ++k) {
-            if (c->ring_fill == kRingCap) {
+        while (k < seg) {
+            const int m = (L == 2 && seg - k - 1 >= 2) ? 2 : 1;  // the emitting step is a one-step launch
+            if (c->ring_fill + m > kRingCap) {
                 lbm_status s = flush_wall(c);
                 if (s) return s;
             }
-            const bool emit = (k == seg - 1);
-            a.fin = c->dev + c->off_f[c->cur];
-            a.fout = c->dev + c->off_f[1 - c->cur];
-            set_wall_slot(a, c, c->ring_fill);
-            HIP_TRY(c, lbm::launch_step(a, c->p.storage, c->p.eos, emit, c->stream));
+            const bool emit = (k + m == seg);
+            HIP_TRY(c, launch_k(a, c->cur, c->ring_fill, m, emit, c->stream));
             a.launch += 1;
             c->cur = 1 - c->cur;
-            c->last_slot = c->ring_fill;
-            c->ring_fill += 1;
-            c->steps += 1;
+            c->last_slot = c->ring_fill + m - 1;
+            c->ring_fill += m;
+            c->steps += m;
+            k += m;
         }
         lbm_status s = flush_wall(c);
         if (s) return s;

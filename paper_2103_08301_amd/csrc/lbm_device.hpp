@@ -1168,6 +1168,268 @@ __global__ __launch_bounds__(64 * NW) void pipe_kernel(const StepArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two steps per launch (temporal blocking).  A block of NW waves owns a
+// 64-column x (T + 10)-row tile: 54 output columns and T output rows plus a
+// 5-node halo, which is what two steps need (a step reads the state within one
+// node and the density within two more).  Step 1 runs from the state in global
+// memory on the tile minus its outer 2 nodes and keeps its post-collision
+// populations in LDS, encoded by the storage codec, so step 2 reads exactly
+// the values a store and a reload would give.  Step 2 pulls them from LDS and
+// collides the output nodes.  Every node is computed with tile_body's
+// expressions, so one launch equals two one-step launches bit for bit while
+// the state crosses HBM once per two steps.  Both steps write their wall
+// arrays: step 1 to tau_w/p_w/dtau_w, step 2 to the next wall-ring slot
+// (kWallSlotVals * nx further on).
+constexpr int kStrip2Out = 54;
+constexpr int kHalo2 = 5;
+
+template <class CD, int EOS, bool EMIT, int T, int NW>
+__device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v, void* fout_v, double* tau_w,
+                                           double* p_w, double* dtau_w, int bid) {
+    using S = typename CD::S;
+    using C = typename CD::C;
+    constexpr int H = T + 2 * kHalo2;  // tile rows including the halo
+    constexpr int H1 = H - 4;          // tile rows 2 .. H-3: step 1's collided nodes
+    constexpr int RPT = H / NW;
+    static_assert(H % NW == 0, "tile height must be a multiple of the waves per block");
+    __shared__ C sRho[H][64], sPhi[H][64], sLap[H][64];
+    __shared__ S sF[9][H1][64];
+    __shared__ C sWv[2][4][64], sWr[2][2][64], sWp[2][2][64];  // wall rows of step 1 and step 2
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tile = bid / a.nstrip;
+    const int strip = bid - tile * a.nstrip;
+    const int y0 = (a.ny >= T) ? min(tile * T, a.ny - T) : 0;
+    const int x0 = strip * kStrip2Out;
+    const int x = x0 - kHalo2 + lane;
+    const bool xin = x >= 0 && x < a.nx;
+    const bool xfl = a.xper || xin;  // a fluid column or a periodic image of one
+    const bool out_lane = lane >= kHalo2 && lane < kHalo2 + kStrip2Out && x < a.nx;
+    int xe = x;
+    if (!xin) xe = a.xper ? wrapi(x, a.nx) : clampi(x, 0, a.nx - 1);
+    // LDS lane of the node this lane stands for: itself, or for the copies beyond an
+    // extrapolated end, the end column's lane
+    const int lrep = xfl ? lane : xe - x0 + kHalo2;
+    const bool tile_inner = (x0 - kHalo2 - 1 >= 0) && (x0 - kHalo2 + 64 <= a.nx - 1) && (y0 - kHalo2 - 1 >= 0) &&
+                            (y0 + T + kHalo2 <= a.ny - 1);
+    const bool walls = !a.yper;
+    const bool wall_tile = walls && (y0 == 0 || y0 + T >= a.ny);  // block-uniform
+
+    const S* __restrict__ fin = static_cast<const S*>(fin_v);
+    S* __restrict__ fout = static_cast<S*>(fout_v);
+    const uint32_t plane_bytes = uint32_t(a.plane) * uint32_t(sizeof(S));
+    const C rho0 = LBM_COEF(C, rho0);
+    const C RT = LBM_COEF(C, RT), a_eff = LBM_COEF(C, a_eff), bb = LBM_COEF(C, b);
+    const C k2 = LBM_COEF(C, k2), kappa = LBM_COEF(C, kappa), g = LBM_COEF(C, g);
+    const C rho_w = LBM_COEF(C, rho_w);
+    const int lm = lane > 0 ? lane - 1 : 0, lp = lane < 63 ? lane + 1 : 63;  // edge lanes are halo: clamped, unused
+
+    // Laplacian of sRho on this thread's tile rows klo .. khi
+    auto laplacian = [&](int klo, int khi) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int k = wave + NW * j;
+            if (k >= klo && k <= khi) {
+                const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
+                const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
+                const Row3<C> n{sRho[k + 1][lane], sRho[k + 1][lp], sRho[k + 1][lm]};
+                sLap[k][lane] = lap3(s, m, n);
+            }
+        }
+    };
+    // Force and collision of the node at tile row k, pulled populations in fj (tile_body's
+    // phase C); wall rows of output lanes record v_x, rho and p_w of step st.
+    auto collide_at = [&](int k, int y, C (&fj)[9], int st, bool wall_lane, C& vx, C& vy) {
+        C gphx, gphy, glx, gly;
+        {
+            const Row3<C> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
+            const Row3<C> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
+            const Row3<C> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
+            grad3(s, m, n, gphx, gphy);
+        }
+        {
+            const Row3<C> s{sLap[k - 1][lane], sLap[k - 1][lp], sLap[k - 1][lm]};
+            const Row3<C> m{sLap[k][lane], sLap[k][lp], sLap[k][lm]};
+            const Row3<C> n{sLap[k + 1][lane], sLap[k + 1][lp], sLap[k + 1][lm]};
+            grad3(s, m, n, glx, gly);
+        }
+        const C rh = sRho[k][lane];
+        const C Fx = -gphx + kappa * rh * glx + g;
+        const C Fy = -gphy + kappa * rh * gly;
+        const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
+        const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
+        collide<C>(fj, rh, jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
+                   LBM_COEF(C, s_q), LBM_COEF(C, s_j), LBM_COEF(C, s_v), vx, vy);
+        if (wall_lane) {
+            if (y == 0 || y == a.ny - 1) {
+                // wall pressure: isotropic part of eq. 2.8 on the first fluid row
+                const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
+                const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
+                const Row3<C> n{sRho[k + 1][lane], sRho[k + 1][lp], sRho[k + 1][lm]};
+                C grx, gry;
+                grad3(s, m, n, grx, gry);
+                const int w = (y == 0) ? 0 : 1;
+                sWp[st][w][lane] = k2 * p0_of<EOS, C>(rh, RT, a_eff, bb) - kappa * rh * sLap[k][lane]
+                                 - C(0.5) * kappa * (grx * grx + gry * gry);
+                sWr[st][w][lane] = rh;
+            }
+            if (y == 0) sWv[st][0][lane] = vx;
+            if (y == 1) sWv[st][1][lane] = vx;
+            if (y == a.ny - 2) sWv[st][2][lane] = vx;
+            if (y == a.ny - 1) sWv[st][3][lane] = vx;
+        }
+    };
+    // Wall shear of step st from the recorded rows (waves 0 and 1; tile_body's phase D).
+    auto wall_shear = [&](int st, double* tw_out, double* pw_out, double* dtw_out) {
+        const bool has_bottom = (y0 == 0), has_top = (y0 + T >= a.ny);
+        if ((wave == 0 && has_bottom) || (wave == 1 && has_top)) {
+            const int w = wave;
+            // tau_w = rho nu dv/ds, quadratic through v(0)=0, v(1/2), v(3/2)
+            const C v_half = sWv[st][w == 0 ? 0 : 3][lane], v_3half = sWv[st][w == 0 ? 1 : 2][lane];
+            const C tw = sWr[st][w][lane] * LBM_COEF(C, nu) * (C(9) * v_half - v_3half) * C(1.0 / 3.0);
+            if (out_lane) {
+                tw_out[w * a.nx + x] = double(tw);
+                pw_out[w * a.nx + x] = double(sWp[st][w][lane]);
+                dtw_out[w * a.nx + x] = tangent_of(tw);
+            }
+        }
+    };
+    auto density = [](const C (&f)[9]) {
+        return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    };
+
+    // ---- step 1, phase A: pull from global memory, density, EOS field on all rows ------
+    {
+        C f[RPT][9];
+        if (tile_inner) {
+            uint32_t dir_off[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                dir_off[i] = uint32_t(i) * plane_bytes - uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(S));
+            const __amdgpu_buffer_rsrc_t rin = buffer_rsrc(const_cast<S*>(fin), 9u * plane_bytes);
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int r = y0 - kHalo2 + wave + NW * j;
+                pull_interior_buf<CD>(rin, dir_off, uint32_t(r * a.pitch + xe) * uint32_t(sizeof(S)), rho0, f[j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int r = y0 - kHalo2 + wave + NW * j;
+                if (a.yper || (r >= 0 && r < a.ny))
+                    pull_generic<CD>(fin, a, xe, a.yper ? wrapi(r, a.ny) : r, rho0, f[j]);
+                else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) f[j][i] = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int k = wave + NW * j;
+            const int r = y0 - kHalo2 + k;
+            const bool fluid = tile_inner || a.yper || (r >= 0 && r < a.ny);
+            const C rho = fluid ? density(f[j]) : rho_w;
+            sRho[k][lane] = rho;
+            sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+        }
+        __syncthreads();
+        // ---- step 1, phase B: Laplacian on rows 1 .. H-2 -------------------------------
+        laplacian(1, H - 2);
+        __syncthreads();
+        // ---- step 1, phase C: collide rows 2 .. H-3 and keep them (encoded) in LDS -----
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int k = wave + NW * j;
+            const int y = y0 - kHalo2 + k;
+            if (k < 2 || k > H - 3) continue;                          // wave-uniform
+            if (!(a.yper || (y >= 0 && y < a.ny)) || !xfl) continue;   // ghost rows and end copies: never read
+            C vx, vy;
+            const bool wall_lane = wall_tile && out_lane && k >= kHalo2 && k < kHalo2 + T;
+            collide_at(k, y, f[j], 0, wall_lane, vx, vy);
+#define LBM_KEEP(I) sF[I][k - 2][lane] = CD::template encode<I>(f[j][I], rho0);
+            LBM_KEEP(0) LBM_KEEP(1) LBM_KEEP(2) LBM_KEEP(3) LBM_KEEP(4) LBM_KEEP(5) LBM_KEEP(6) LBM_KEEP(7) LBM_KEEP(8)
+#undef LBM_KEEP
+        }
+    }
+    __syncthreads();
+    if (wall_tile) wall_shear(0, tau_w, p_w, dtau_w);
+
+    // ---- step 2, phase A: pull from LDS on rows 3 .. H-4 (lanes 3 .. 60), density, EOS ---
+    // Sources follow the one-step pull: beyond a wall the node's own opposite
+    // population, beyond an extrapolated end the end column, periodic images by lane.
+    C f2[RPT][9];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + NW * j;
+        const int r = y0 - kHalo2 + k;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f2[j][i] = 0;
+        if (k < 3 || k > H - 4) continue;  // wave-uniform
+        const bool fluid = a.yper || (r >= 0 && r < a.ny);
+        if (fluid && lane >= 3 && lane <= 60) {
+            const int yr = a.yper ? wrapi(r, a.ny) : r;
+#define LBM_PULL2(I)                                                                                          \
+    {                                                                                                         \
+        const int sy = yr - ey(I);                                                                            \
+        if (tile_inner) {                                                                                     \
+            f2[j][I] = CD::template decode<I>(sF[I][k - ey(I) - 2][lane - ex(I)], rho0);                      \
+        } else if (!a.yper && (sy < 0 || sy >= a.ny)) {                                                       \
+            f2[j][I] = CD::template decode<opp(I)>(sF[opp(I)][k - 2][lrep], rho0);                            \
+        } else {                                                                                              \
+            const int sx = xe - ex(I);                                                                        \
+            const int ls = (a.xper || (sx >= 0 && sx < a.nx)) ? lrep - ex(I) : clampi(sx, 0, a.nx - 1) - x0 + kHalo2; \
+            f2[j][I] = CD::template decode<I>(sF[I][k - ey(I) - 2][ls], rho0);                                \
+        }                                                                                                     \
+    }
+            LBM_PULL2(0) LBM_PULL2(1) LBM_PULL2(2) LBM_PULL2(3) LBM_PULL2(4) LBM_PULL2(5) LBM_PULL2(6) LBM_PULL2(7)
+            LBM_PULL2(8)
+#undef LBM_PULL2
+        }
+        const C rho = fluid ? density(f2[j]) : rho_w;
+        sRho[k][lane] = rho;
+        sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+    }
+    __syncthreads();
+    // ---- step 2, phase B: Laplacian on rows 4 .. H-5 -------------------------------------
+    laplacian(4, H - 5);
+    __syncthreads();
+    // ---- step 2, phase C: collide the output rows, store ---------------------------------
+    const __amdgpu_buffer_rsrc_t rout = buffer_rsrc(fout, 9u * plane_bytes);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int k = wave + NW * j;
+        const int y = y0 - kHalo2 + k;
+        if (k < kHalo2 || k >= kHalo2 + T || y >= a.ny) continue;  // wave-uniform
+        C vx, vy;
+        collide_at(k, y, f2[j], 1, wall_tile && out_lane, vx, vy);
+        if (out_lane) {
+            const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
+#define LBM_TSTORE(I) buffer_store(CD::template encode<I>(f2[j][I], rho0), rout, o, uint32_t(I) * plane_bytes);
+            LBM_TSTORE(0) LBM_TSTORE(1) LBM_TSTORE(2) LBM_TSTORE(3) LBM_TSTORE(4) LBM_TSTORE(5) LBM_TSTORE(6)
+            LBM_TSTORE(7) LBM_TSTORE(8)
+#undef LBM_TSTORE
+            if (EMIT) {
+                const long long c = (long long)y * a.nx + x;
+                a.rho_out[c] = double(sRho[k][lane]);
+                a.vx_out[c] = double(vx);
+                a.vy_out[c] = double(vy);
+            }
+        }
+    }
+    if (!wall_tile) return;  // block-uniform
+    __syncthreads();
+    const long long next = (long long)kWallSlotVals * a.nx;
+    wall_shear(1, tau_w + next, p_w + next, dtau_w + next);
+}
+
+template <class CD, int EOS, bool EMIT, int T, int NW>
+__global__ __launch_bounds__(64 * NW) void tile2_kernel(const StepArgs a) {
+    tile2_body<CD, EOS, EMIT, T, NW>(a, a.fin, a.fout, a.tau_w, a.p_w, a.dtau_w, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 template <class CD, int EOS, int TYO, int NW>
 hipError_t launch_tile(const StepArgs& a, bool emit, hipStream_t s) {
     const dim3 grid(a.nstrip * ((a.ny + TYO - 1) / TYO)), block(64 * NW);
@@ -1176,6 +1438,28 @@ hipError_t launch_tile(const StepArgs& a, bool emit, hipStream_t s) {
     else
         hipLaunchKernelGGL((tile_kernel<CD, EOS, false, TYO, NW>), grid, block, 0, s, a);
     return hipGetLastError();
+}
+
+// Two steps in one launch (tile2_kernel); a.nstrip is replaced by the 54-column strips.
+template <class CD, int EOS, int T, int NW>
+hipError_t launch_tile2(const StepArgs& a, bool emit, hipStream_t s) {
+    StepArgs b = a;
+    b.nstrip = (a.nx + kStrip2Out - 1) / kStrip2Out;
+    const dim3 grid(b.nstrip * ((a.ny + T - 1) / T)), block(64 * NW);
+    if (emit)
+        hipLaunchKernelGGL((tile2_kernel<CD, EOS, true, T, NW>), grid, block, 0, s, b);
+    else
+        hipLaunchKernelGGL((tile2_kernel<CD, EOS, false, T, NW>), grid, block, 0, s, b);
+    return hipGetLastError();
+}
+
+// Tile of the two-step kernel: 14 output rows and 8 waves with FP32 arithmetic,
+// 6 rows and 4 waves with FP64 arithmetic (LDS holds a step of populations).
+template <class CD>
+hipError_t launch_step2_c(const StepArgs& a, int eos, bool emit, hipStream_t s) {
+    constexpr bool f64 = sizeof(typename CD::C) == 8;
+    constexpr int T = f64 ? 6 : 14, NW = f64 ? 4 : 8;
+    return eos == LBM_EOS_CS ? launch_tile2<CD, LBM_EOS_CS, T, NW>(a, emit, s) : launch_tile2<CD, LBM_EOS_PR, T, NW>(a, emit, s);
 }
 
 template <class CD, int EOS, int TYO, int NW>
@@ -1314,5 +1598,8 @@ hipError_t pipe_grid_c(int eos, int ty, int waves, int* blocks) {
     }                                                                                                          \
     hipError_t pipe_grid_##NAME(int eos, int ty, int waves, int* blocks) {                                     \
         return pipe_grid_c<CODEC>(eos, ty, waves, blocks);                                                     \
+    }                                                                                                          \
+    hipError_t launch_step2_##NAME(const StepArgs& a, int eos, bool emit, hipStream_t s) {                    \
+        return launch_step2_c<CODEC>(a, eos, emit, s);                                                         \
     }                                                                                                          \
     }

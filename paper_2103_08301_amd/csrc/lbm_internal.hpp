@@ -75,7 +75,8 @@ hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipSt
     hipError_t launch_step_##NAME(const StepArgs& a, int eos, bool emit, hipStream_t s);                     \
     hipError_t launch_batch_##NAME(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, \
                                    int parity, int slot, int eos, int ty, int waves, bool emit, hipStream_t s); \
-    hipError_t pipe_grid_##NAME(int eos, int ty, int waves, int* blocks);
+    hipError_t pipe_grid_##NAME(int eos, int ty, int waves, int* blocks);                                     \
+    hipError_t launch_step2_##NAME(const StepArgs& a, int eos, bool emit, hipStream_t s);
 LBM_DECLARE_STORAGE_LAUNCHERS(f64)
 LBM_DECLARE_STORAGE_LAUNCHERS(f32)
 LBM_DECLARE_STORAGE_LAUNCHERS(f16s)
@@ -84,6 +85,11 @@ LBM_DECLARE_STORAGE_LAUNCHERS(f32d)
 LBM_DECLARE_STORAGE_LAUNCHERS(f32s)
 #undef LBM_DECLARE_STORAGE_LAUNCHERS
 hipError_t launch_step_f64t(const StepArgs& a, int eos, bool emit, hipStream_t s);
+// Two steps in one launch (temporal blocking, the tile schedule's two-step kernel):
+// reads a.fin, writes a.fout after two steps; the wall arrays of the first step
+// go to a.tau_w/p_w/dtau_w and those of the second kWallSlotVals * nx further on.
+// Not for F64T storage.
+hipError_t launch_step2(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s);
 // One step of many lattices in one launch (tile schedule): cases[c] holds case
 // c's arguments with both distribution buffers (f[0] as fin, f[1] as fout) and
 // the base of its wall ring; tile_start[c] is its first tile (device arrays).

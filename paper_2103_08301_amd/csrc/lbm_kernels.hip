@@ -235,6 +235,18 @@ __global__ __launch_bounds__(64) void wall_integrate_batch_kernel(const WallFlus
 
 }  // namespace
 
+hipError_t launch_step2(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s) {
+    switch (storage) {
+        case LBM_F64: return launch_step2_f64(a, eos, emit, s);
+        case LBM_F32: return launch_step2_f32(a, eos, emit, s);
+        case LBM_F16S: return launch_step2_f16s(a, eos, emit, s);
+        case LBM_BF16S: return launch_step2_bf16s(a, eos, emit, s);
+        case LBM_F32D: return launch_step2_f32d(a, eos, emit, s);
+        case LBM_F32S: return launch_step2_f32s(a, eos, emit, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s) {
     switch (storage) {
         case LBM_F64: return launch_step_f64(a, eos, emit, s);

@@ -49,6 +49,7 @@ class lbm_params(C.Structure):
         ("rho0_shift", C.c_double), ("check_every", C.c_int), ("v_limit", C.c_double),
         ("history_cap", C.c_int), ("tile_rows", C.c_int), ("schedule", C.c_int),
         ("tile_waves", C.c_int), ("pipe_blocks", C.c_int), ("graph_steps", C.c_int),
+        ("fused_steps", C.c_int),
     ]
 
 
