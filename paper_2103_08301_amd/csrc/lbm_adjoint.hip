@@ -120,8 +120,14 @@ __device__ inline C div3(const Row3<C>& sx, const Row3<C>& mx, const Row3<C>& nx
            C(1.0 / 3.0) * (ny_.c - sy.c) + C(1.0 / 12.0) * ((ny_.e + ny_.w) - (sy.e + sy.w));
 }
 
+// 8-row tiles with FP32 arithmetic: at least 6 waves per SIMD (three 8-wave blocks
+// per compute unit, at most 80 VGPRs, no spills), so the tiles of a 1024 x 256
+// grid run in one round.
+template <class CD, int TYO>
+constexpr int adj_min_waves() { return (sizeof(typename CD::C) == 4 && TYO == 8) ? 6 : 1; }
+
 template <class CD, int EOS, int TYO, int NW>
-__global__ __launch_bounds__(64 * NW) void adjoint_kernel(const AdjArgs A) {
+__global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_kernel(const AdjArgs A) {
     using S = typename CD::S;
     using C = typename CD::C;
     constexpr int H = TYO + 2 * kAdjHalo;
@@ -442,12 +448,22 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(const AdjArgs A) {
     }
 }
 
-// Sums n consecutive groups of 4 partials in a fixed order and adds them to
-// acc[0..3]: stage 1 reduces kAdjRedBlocks contiguous ranges (one block each)
-// into red[block][4], stage 2 sums those in block order.
+// Parameter sums of a run of adjoint launches (consecutive steps, in the order
+// they ran): stage 1 sums each launch's block partials in a fixed order (one
+// block per launch), stage 2 adds the launch totals to acc[0..3] one after
+// another.  acc therefore receives the same additions in the same order
+// whatever the grouping of launches into runs, so the result does not depend
+// on the checkpoint segment length.
 constexpr int kAdjRedThreads = 256;
-__device__ inline void block_sum4(double (&v)[4], double (*sh)[kAdjRedThreads]) {
+__global__ __launch_bounds__(kAdjRedThreads) void adjoint_reduce_stage1(const double* __restrict__ partial, int blocks,
+                                                                        double* __restrict__ red) {
+    __shared__ double sh[4][kAdjRedThreads];
     const int t = threadIdx.x;
+    const double* p = partial + (long long)blockIdx.x * blocks * 4;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = t; i < blocks; i += kAdjRedThreads)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += p[i * 4 + q];
 #pragma unroll
     for (int q = 0; q < 4; ++q) sh[q][t] = v[q];
     __syncthreads();
@@ -457,31 +473,15 @@ __device__ inline void block_sum4(double (&v)[4], double (*sh)[kAdjRedThreads]) 
             for (int q = 0; q < 4; ++q) sh[q][t] += sh[q][t + s];
         __syncthreads();
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = sh[q][0];
+    if (t < 4) red[blockIdx.x * 4 + t] = sh[t][0];
 }
 
-__global__ __launch_bounds__(kAdjRedThreads) void adjoint_reduce_stage1(const double* __restrict__ partial, long long n,
-                                                                        double* __restrict__ red) {
-    __shared__ double sh[4][kAdjRedThreads];
-    const long long lo = n * blockIdx.x / gridDim.x, hi = n * (blockIdx.x + 1) / gridDim.x;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long i = lo + threadIdx.x; i < hi; i += kAdjRedThreads)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += partial[i * 4 + q];
-    block_sum4(v, sh);
-    if (threadIdx.x < 4) red[blockIdx.x * 4 + threadIdx.x] = v[threadIdx.x];
-}
-
-__global__ __launch_bounds__(kAdjRedThreads) void adjoint_reduce_stage2(const double* __restrict__ red, int nb,
-                                                                        double* __restrict__ acc) {
-    __shared__ double sh[4][kAdjRedThreads];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nb; i += kAdjRedThreads)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += red[i * 4 + q];
-    block_sum4(v, sh);
-    if (threadIdx.x < 4) acc[threadIdx.x] += v[threadIdx.x];
+__global__ void adjoint_reduce_stage2(const double* __restrict__ red, int launches, double* __restrict__ acc) {
+    const int q = threadIdx.x;
+    if (q >= 4) return;
+    double a = acc[q];
+    for (int r = 0; r < launches; ++r) a += red[r * 4 + q];
+    acc[q] = a;
 }
 
 // dJ/df* of the initial state: the pull transpose of the last adjoint step's
@@ -530,12 +530,13 @@ hipError_t launch_adjoint(const AdjArgs& A, int storage, int eos, hipStream_t s)
     }
 }
 
-hipError_t launch_adjoint_reduce(const double* partial, long long ngroups, double* red, double* acc, hipStream_t s) {
-    if (ngroups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(adjoint_reduce_stage1, dim3(kAdjRedBlocks), dim3(kAdjRedThreads), 0, s, partial, ngroups, red);
+hipError_t launch_adjoint_reduce(const double* partial, int launches, int blocks, double* red, double* acc,
+                                 hipStream_t s) {
+    if (launches <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adjoint_reduce_stage1, dim3(launches), dim3(kAdjRedThreads), 0, s, partial, blocks, red);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(adjoint_reduce_stage2, dim3(1), dim3(kAdjRedThreads), 0, s, red, kAdjRedBlocks, acc);
+    hipLaunchKernelGGL(adjoint_reduce_stage2, dim3(1), dim3(64), 0, s, red, launches, acc);
     return hipGetLastError();
 }
 

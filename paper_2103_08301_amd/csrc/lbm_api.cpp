@@ -305,8 +305,26 @@ struct lbm_ctx {
         size_t state = 0, lam = 0;          // bytes of one state / one adjoint field (aligned)
         size_t off_ckpt = 0, off_seg = 0, off_lam[2]{}, off_tw = 0, off_part = 0, off_red = 0, off_acc = 0,
                off_pw = 0, off_g0 = 0, total = 0;
-        int blocks = 0, cur = 0, ty = 8;
+        int blocks = 0, cur = 0, ty = 8, ring_cap = 0;
         double J = 0, seed = 1;
+        hipGraphExec_t seg_graph[2] = {nullptr, nullptr};  // one full segment of the sweep, per adjoint parity
+        void drop_graphs() {
+            for (auto& g : seg_graph)
+                if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+        }
+        ~Adjoint() { drop_graphs(); }
+        Adjoint() = default;
+        Adjoint& operator=(const Adjoint& o) {  // layout only; the graphs belong to the bound workspace
+            drop_graphs();
+            dev = o.dev; bound = o.bound; recorded = o.recorded; swept = o.swept;
+            n = o.n; seg = o.seg; nckpt = o.nckpt; state = o.state; lam = o.lam;
+            off_ckpt = o.off_ckpt; off_seg = o.off_seg; off_lam[0] = o.off_lam[0]; off_lam[1] = o.off_lam[1];
+            off_tw = o.off_tw; off_part = o.off_part; off_red = o.off_red; off_acc = o.off_acc; off_pw = o.off_pw;
+            off_g0 = o.off_g0; total = o.total; blocks = o.blocks; cur = o.cur; ty = o.ty; ring_cap = o.ring_cap;
+            J = o.J; seed = o.seed;
+            return *this;
+        }
+        Adjoint(const Adjoint&) = delete;
     } adj;
     int cur = 0;
     int64_t steps = 0;
@@ -646,6 +664,7 @@ lbm_status lbm_bind(lbm_ctx* c, void* device_ptr, size_t bytes, void* hip_stream
     c->bound = true;
     c->initialized = false;
     c->graphs.drop();
+    c->adj.drop_graphs();
     return LBM_OK;
 }
 
@@ -700,10 +719,12 @@ lbm_status lbm_init_density(lbm_ctx* c, const double* rho) {
     return init_from_device_rho(c);
 }
 
-lbm_status lbm_step(lbm_ctx* c, int64_t n) {
-    if (!c || n < 0) return LBM_EINVAL;
-    if (c->in_batch) return fail(c, LBM_ESTATE, "this context belongs to a batch: step it with lbm_batch_step");
-    if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_step needs lbm_bind and an initialisation");
+namespace {
+
+// n steps.  Checks run at every multiple of check_every; `finish` adds the flush
+// of the wall ring and a check after the last step (lbm_step always finishes;
+// the recording run of the adjoint finishes only its last segment).
+lbm_status step_impl(lbm_ctx* c, int64_t n, bool finish) {
     lbm::StepArgs a = make_args(c);
     if (c->schedule == lbm::kSchedulePipe && n > 0) {
         // the ticket counters start from zero for this run of launches (all-zero bits)
@@ -748,13 +769,16 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
             c->steps += G;
             k += G;
         }
+        // a check follows this run of steps unless the run ends the call before a check
+        // boundary and the call does not finish
+        const bool check = finish || c->steps + (seg - k) == next_check;
         while (k < seg) {
             const int m = (L == 2 && seg - k - 1 >= 2) ? 2 : 1;  // the emitting step is a one-step launch
             if (c->ring_fill + m > kRingCap) {
                 lbm_status s = flush_wall(c);
                 if (s) return s;
             }
-            const bool emit = (k + m == seg);
+            const bool emit = check && (k + m == seg);
             HIP_TRY(c, launch_k(a, c->cur, c->ring_fill, m, emit, c->stream));
             a.launch += 1;
             c->cur = 1 - c->cur;
@@ -763,13 +787,23 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
             c->steps += m;
             k += m;
         }
+        done += seg;
+        if (!check) break;  // the end of the call, between checks
         lbm_status s = flush_wall(c);
         if (s) return s;
-        done += seg;
         s = run_check(c);
         if (s) return s;
     }
     return LBM_OK;
+}
+
+}  // namespace
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c || n < 0) return LBM_EINVAL;
+    if (c->in_batch) return fail(c, LBM_ESTATE, "this context belongs to a batch: step it with lbm_batch_step");
+    if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_step needs lbm_bind and an initialisation");
+    return step_impl(c, n, true);
 }
 
 lbm_status lbm_step_count(const lbm_ctx* c, int64_t* steps) {
@@ -1063,12 +1097,13 @@ lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm
     A.blocks = lbm::adjoint_blocks(c->nx, c->ny, A.ty);
     size_t o = 0;
     A.off_ckpt = o; o += (size_t)A.nckpt * A.state;
-    A.off_seg = o; o += (size_t)A.seg * A.state;
+    A.off_seg = o; o += (size_t)(A.seg + 1) * A.state;  // + the checkpoint copy a segment graph starts from
     A.off_lam[0] = o; o += A.lam;
     A.off_lam[1] = o; o += A.lam;
     A.off_tw = o; o += align256((size_t)A.seg * 2 * c->nx * sizeof(double));
-    A.off_part = o; o += align256((size_t)kAdjRing * A.blocks * 4 * sizeof(double));
-    A.off_red = o; o += align256((size_t)lbm::kAdjRedBlocks * 4 * sizeof(double));
+    A.ring_cap = (int)std::max<int64_t>(A.seg, kAdjRing);  // adjoint launches between reductions
+    A.off_part = o; o += align256((size_t)A.ring_cap * A.blocks * 4 * sizeof(double));
+    A.off_red = o; o += align256((size_t)A.ring_cap * 4 * sizeof(double));
     A.off_acc = o; o += 256;
     A.off_pw = o; o += align256((size_t)4 * c->nx * sizeof(double));
     A.off_g0 = o; o += align256((size_t)9 * c->nx * c->ny * sizeof(double));
@@ -1117,7 +1152,7 @@ lbm_status lbm_adjoint_forward(lbm_ctx* c, double* J) {
     for (int64_t k = 0; k < A.nckpt; ++k) {
         HIP_TRY(c, hipMemcpyAsync(A.dev + A.off_ckpt + (size_t)k * A.state, c->dev + c->off_f[c->cur], fbytes,
                                   hipMemcpyDeviceToDevice, c->stream));
-        s = lbm_step(c, std::min(A.seg, A.n - k * A.seg));
+        s = step_impl(c, std::min(A.seg, A.n - k * A.seg), k == A.nckpt - 1);  // checks at their cadence only
         if (s) return s;
     }
     HIP_TRY(c, hipMemcpyAsync(acc1, c->dev + c->off_acc, sizeof acc1, hipMemcpyDeviceToHost, c->stream));
@@ -1134,8 +1169,11 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     if (!A.bound || !A.recorded) return fail(c, LBM_ESTATE, "lbm_adjoint_backward needs lbm_adjoint_forward first");
     const int storage = c->p.storage, eos = c->p.eos;
     lbm::StepArgs base = make_args(c);
-    auto state = [&](int64_t ck, int64_t start, int64_t k) -> char* {  // state after step k of segment ck
-        return k == start ? A.dev + A.off_ckpt + (size_t)ck * A.state : A.dev + A.off_seg + (size_t)(k - start - 1) * A.state;
+    // state after step k of segment ck: the checkpoint, or a recomputed state in the segment buffer
+    // (slot 0 of which holds a copy of the checkpoint when the segment runs as a captured graph)
+    auto state = [&](int64_t ck, int64_t start, int64_t k, bool copied) -> char* {
+        if (k == start && !copied) return A.dev + A.off_ckpt + (size_t)ck * A.state;
+        return A.dev + A.off_seg + (size_t)(k - start) * A.state;
     };
     double* tw = reinterpret_cast<double*>(A.dev + A.off_tw);
     double* part = reinterpret_cast<double*>(A.dev + A.off_part);
@@ -1152,29 +1190,64 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     aa.nstrip = (c->nx + lbm::kAdjStripOut - 1) / lbm::kAdjStripOut;
     aa.ty = A.ty;
     int ring = 0;
-    for (int64_t ck = A.nckpt - 1; ck >= 0; --ck) {
-        const int64_t start = ck * A.seg, end = std::min(start + A.seg, A.n);
-        for (int64_t k = start + 1; k <= end; ++k) {
-            fa.fin = state(ck, start, k - 1);
-            fa.fout = state(ck, start, k);
-            fa.tau_w = tw + (size_t)(k - start - 1) * 2 * c->nx;
-            HIP_TRY(c, lbm::launch_step(fa, storage, eos, false, c->stream));
+    // One segment: recompute its states, then the adjoint steps from its last step down.
+    // Launch j of 2 (end - start) + 1 (recomputes, adjoints, the final reduction when
+    // `reduce_at_end`); cur0 is the adjoint parity at the segment's start.
+    auto segment_launch = [&](int64_t ck, int64_t start, int64_t end, bool copied, int cur0, int ring0, int64_t j,
+                              hipStream_t s) -> hipError_t {
+        const int64_t len = end - start;
+        if (j < len) {
+            const int64_t k = start + 1 + j;
+            lbm::StepArgs b = fa;
+            b.fin = state(ck, start, k - 1, copied);
+            b.fout = state(ck, start, k, true);
+            b.tau_w = tw + (size_t)(k - start - 1) * 2 * c->nx;
+            return lbm::launch_step(b, storage, eos, false, s);
         }
-        for (int64_t k = end; k > start; --k) {
-            aa.s.fin = state(ck, start, k - 1);
-            aa.lam_in = A.dev + A.off_lam[A.cur];
-            aa.lam_out = A.dev + A.off_lam[1 - A.cur];
-            aa.tau_w = tw + (size_t)(k - start - 1) * 2 * c->nx;
-            aa.partial = part + (size_t)ring * A.blocks * 4;
-            HIP_TRY(c, lbm::launch_adjoint(aa, storage, eos, c->stream));
-            A.cur = 1 - A.cur;
-            if (++ring == kAdjRing) {
-                HIP_TRY(c, lbm::launch_adjoint_reduce(part, (long long)ring * A.blocks, red, acc, c->stream));
+        if (j < 2 * len) {
+            const int64_t m = j - len, k = end - m;  // m-th adjoint launch of the segment
+            const int par = (cur0 + (int)m) & 1;
+            lbm::AdjArgs b = aa;
+            b.s.fin = state(ck, start, k - 1, copied);
+            b.lam_in = A.dev + A.off_lam[par];
+            b.lam_out = A.dev + A.off_lam[1 - par];
+            b.tau_w = tw + (size_t)(k - start - 1) * 2 * c->nx;
+            b.partial = part + (size_t)(ring0 + m) * A.blocks * 4;
+            return lbm::launch_adjoint(b, storage, eos, s);
+        }
+        return lbm::launch_adjoint_reduce(part, (int)(ring0 + len), A.blocks, red, acc, s);
+    };
+    for (int64_t ck = A.nckpt - 1; ck >= 0; --ck) {
+        const int64_t start = ck * A.seg, end = std::min(start + A.seg, A.n), len = end - start;
+        if (len == A.seg && c->graph_steps() > 0) {
+            // a full segment: copy its checkpoint to the segment buffer and replay the captured sweep
+            if (ring > 0) {
+                HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
                 ring = 0;
             }
+            HIP_TRY(c, hipMemcpyAsync(A.dev + A.off_seg, A.dev + A.off_ckpt + (size_t)ck * A.state, A.state,
+                                      hipMemcpyDeviceToDevice, c->stream));
+            hipGraphExec_t& ge = A.seg_graph[A.cur];
+            if (!ge) {
+                const int cur0 = A.cur;
+                auto launch = [&](int j, hipStream_t s) { return segment_launch(ck, start, end, true, cur0, 0, j, s); };
+                HIP_TRY(c, capture_graph(c->graphs, (int)(2 * len + 1), launch, &ge));
+            }
+            HIP_TRY(c, hipGraphLaunch(ge, c->stream));
+            A.cur = (A.cur + (int)len) & 1;
+            continue;
         }
+        // the last (shorter) segment, or every segment without graphs: direct launches
+        if (ring + len > A.ring_cap) {
+            HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
+            ring = 0;
+        }
+        for (int64_t j = 0; j < 2 * len; ++j)
+            HIP_TRY(c, segment_launch(ck, start, end, false, A.cur, ring, j, c->stream));
+        A.cur = (A.cur + (int)len) & 1;
+        ring += (int)len;
     }
-    if (ring > 0) HIP_TRY(c, lbm::launch_adjoint_reduce(part, (long long)ring * A.blocks, red, acc, c->stream));
+    if (ring > 0) HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
     double sums[4];
     HIP_TRY(c, hipMemcpyAsync(sums, acc, sizeof sums, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

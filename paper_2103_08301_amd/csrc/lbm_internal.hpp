@@ -140,10 +140,11 @@ struct AdjArgs {
     int ty;                // output rows per tile: 8 or 16
 };
 hipError_t launch_adjoint(const AdjArgs& A, int storage, int eos, hipStream_t s);
-// acc[0..3] += the sums of ngroups groups of 4 partials (fixed order); red is
-// scratch of kAdjRedBlocks x 4 doubles.
-constexpr int kAdjRedBlocks = 256;
-hipError_t launch_adjoint_reduce(const double* partial, long long ngroups, double* red, double* acc, hipStream_t s);
+// acc[0..3] += the parameter sums of `launches` consecutive adjoint launches
+// (partial: [launches][blocks][4]), launch totals added in launch order; red is
+// scratch of launches x 4 doubles.
+hipError_t launch_adjoint_reduce(const double* partial, int launches, int blocks, double* red, double* acc,
+                                 hipStream_t s);
 // dJ/df* of a state from the adjoint of the step that read it, as FP64 [9][ny][nx].
 hipError_t launch_adjoint_gather(const void* lam, const StepArgs& a, int storage, double* out, hipStream_t s);
 int adjoint_blocks(int nx, int ny, int ty);
