@@ -117,20 +117,24 @@ __device__ inline void comb_min(double& v, double& x, double ov, double ox) {
     if (ov < v || (ov == v && ox < x)) { v = ov; x = ox; }
 }
 
+constexpr int kWallThreads = 256;  // threads of the wall reduction blocks (4 waves)
+
+// One step of the wall ring (block per step): extremes of tau_w and p_w per wall
+// with their columns (the smallest column on ties) and the sums of tau_w^2 and
+// of its tangent, reduced lane-strided, then by wave butterflies, then over the
+// 4 waves in order.
 __device__ void wall_step_reduce_body(const WallFlush& f, int t, int64_t first_step) {
-    const int lane = threadIdx.x;
+    __shared__ double sh[4][2][10];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nx = f.nx;
     const double* slot = f.ring + (long long)t * kWallSlotVals * nx;  // tau [2][nx], p [2][nx], dtau [2][nx]
-    lbm_stress_summary sm;
-    sm.step = first_step + t;
-    double pk = 0.0, s2 = 0.0, ds2 = 0.0;
     for (int w = 0; w < 2; ++w) {
         const double* tau = slot + (long long)w * nx;
         const double* pw = slot + (long long)(2 + w) * nx;
         const double* dtau = slot + (long long)(4 + w) * nx;
         double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
         double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0, wds = 0.0;
-        for (int x = lane; x < nx; x += 64) {  // fixed order: lane-strided, then the butterfly below
+        for (int x = threadIdx.x; x < nx; x += kWallThreads) {
             const double tv = tau[x], pv = pw[x];
             comb_max(tmax, xtmax, tv, double(x));
             comb_min(tmin, xtmin, tv, double(x));
@@ -148,89 +152,121 @@ __device__ void wall_step_reduce_body(const WallFlush& f, int t, int64_t first_s
             ws += __shfl_xor(ws, off, 64);
             wds += __shfl_xor(wds, off, 64);
         }
-        ds2 += wds;
-        sm.tau_max[w] = tmax; sm.tau_min[w] = tmin; sm.p_max[w] = pmax; sm.p_min[w] = pmin;
-        sm.x_tau_max[w] = int32_t(xtmax); sm.x_tau_min[w] = int32_t(xtmin);
-        sm.x_p_max[w] = int32_t(xpmax); sm.x_p_min[w] = int32_t(xpmin);
-        pk = fmax(pk, fmax(tmax * tmax, tmin * tmin));
-        s2 += ws;
-    }
-    if (lane == 0) {
-        sm.sum_tau2 = s2;
-        sm.d_sum_tau2 = ds2;
-        sm.int_peak_tau2 = 0.0;
-        sm.int_tau2 = 0.0;
-        sm.d_int_tau2 = 0.0;
-        f.hist[(sm.step - 1) % f.hist_cap] = sm;
-        double* o = f.scratch + (long long)t * kWallScratchVals;
-        o[0] = pk;
-        o[1] = s2;
-        for (int w = 0; w < 2; ++w) {
-            o[2 + w] = sm.tau_max[w];
-            o[4 + w] = sm.tau_min[w];
-            o[6 + w] = sm.p_max[w];
-            o[8 + w] = sm.p_min[w];
+        if (lane == 0) {
+            double* o = sh[wave][w];
+            o[0] = tmax; o[1] = xtmax; o[2] = tmin; o[3] = xtmin;
+            o[4] = pmax; o[5] = xpmax; o[6] = pmin; o[7] = xpmin; o[8] = ws; o[9] = wds;
         }
-        o[10] = ds2;
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    lbm_stress_summary sm;
+    sm.step = first_step + t;
+    double pk = 0.0, s2 = 0.0, ds2 = 0.0;
+    for (int w = 0; w < 2; ++w) {
+        double r[10];
+        for (int q = 0; q < 10; ++q) r[q] = sh[0][w][q];
+        for (int v = 1; v < 4; ++v) {
+            const double* o = sh[v][w];
+            comb_max(r[0], r[1], o[0], o[1]);
+            comb_min(r[2], r[3], o[2], o[3]);
+            comb_max(r[4], r[5], o[4], o[5]);
+            comb_min(r[6], r[7], o[6], o[7]);
+            r[8] += o[8];
+            r[9] += o[9];
+        }
+        sm.tau_max[w] = r[0]; sm.tau_min[w] = r[2]; sm.p_max[w] = r[4]; sm.p_min[w] = r[6];
+        sm.x_tau_max[w] = int32_t(r[1]); sm.x_tau_min[w] = int32_t(r[3]);
+        sm.x_p_max[w] = int32_t(r[5]); sm.x_p_min[w] = int32_t(r[7]);
+        pk = fmax(pk, fmax(r[0] * r[0], r[2] * r[2]));
+        s2 += r[8];
+        ds2 += r[9];
+    }
+    sm.sum_tau2 = s2;
+    sm.d_sum_tau2 = ds2;
+    sm.int_peak_tau2 = 0.0;
+    sm.int_tau2 = 0.0;
+    sm.d_int_tau2 = 0.0;
+    f.hist[(sm.step - 1) % f.hist_cap] = sm;
+    double* o = f.scratch + (long long)t * kWallScratchVals;
+    o[0] = pk;
+    o[1] = s2;
+    for (int w = 0; w < 2; ++w) {
+        o[2 + w] = sm.tau_max[w];
+        o[4 + w] = sm.tau_min[w];
+        o[6 + w] = sm.p_max[w];
+        o[8 + w] = sm.p_min[w];
+    }
+    o[10] = ds2;
 }
 
-// Running time integrals and running extremes, in step order (single thread).
+// Running time integrals and running extremes of nsteps <= kWallThreads steps:
+// an inclusive scan over the steps (thread per step, Hillis-Steele in LDS, a
+// fixed tree), added to the totals so far.
 // acc: [0] int peak tau^2, [1] int sum tau^2, [2 + 2q + w] running extreme q
 // (tau max, tau min, p max, p min) of wall w, [10] tangent of int sum tau^2.
 __device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t first_step) {
-    const double* __restrict__ scratch = f.scratch;
-    lbm_stress_summary* hist = f.hist;
-    const int hist_cap = f.hist_cap;
-    double* acc = f.acc;
-    double ip = acc[0], is = acc[1], dis = acc[10];
-    double run[8];
-    for (int q = 0; q < 8; ++q) run[q] = acc[2 + q];
-    for (int k = 0; k < nsteps; ++k) {
-        const double* o = scratch + (long long)k * kWallScratchVals;
-        ip += o[0];
-        is += o[1];
-        dis += o[10];
-        for (int w = 0; w < 2; ++w) {
-            run[w] = fmax(run[w], o[2 + w]);
-            run[2 + w] = fmin(run[2 + w], o[4 + w]);
-            run[4 + w] = fmax(run[4 + w], o[6 + w]);
-            run[6 + w] = fmin(run[6 + w], o[8 + w]);
-        }
-        lbm_stress_summary* h = &hist[(first_step + k - 1) % hist_cap];
-        h->int_peak_tau2 = ip;
-        h->int_tau2 = is;
-        h->d_int_tau2 = dis;
-        for (int w = 0; w < 2; ++w) {
-            h->run_tau_max[w] = run[w];
-            h->run_tau_min[w] = run[2 + w];
-            h->run_p_max[w] = run[4 + w];
-            h->run_p_min[w] = run[6 + w];
-        }
+    __shared__ double sh[kWallScratchVals][kWallThreads];
+    const int t = threadIdx.x;
+    // per scratch value: 0 sum, 1 max, 2 min
+    auto kind = [](int q) { return (q == 0 || q == 1 || q == 10) ? 0 : ((q - 2) / 2 % 2 == 0 ? 1 : 2); };
+    double v[kWallScratchVals], prev[kWallScratchVals];
+    for (int q = 0; q < kWallScratchVals; ++q) {
+        const int kq = kind(q);
+        v[q] = t < nsteps ? f.scratch[(long long)t * kWallScratchVals + q] : (kq == 0 ? 0.0 : (kq == 1 ? -INFINITY : INFINITY));
+        prev[q] = f.acc[q];  // acc uses the scratch layout's order: 0, 1, 2 + 2q + w, 10
+        sh[q][t] = v[q];
     }
-    acc[0] = ip;
-    acc[1] = is;
-    acc[10] = dis;
-    for (int q = 0; q < 8; ++q) acc[2 + q] = run[q];
+    __syncthreads();
+    for (int off = 1; off < kWallThreads; off <<= 1) {
+        double o[kWallScratchVals];
+        for (int q = 0; q < kWallScratchVals; ++q) o[q] = t >= off ? sh[q][t - off] : 0.0;
+        __syncthreads();
+        if (t >= off)
+            for (int q = 0; q < kWallScratchVals; ++q) {
+                const int kq = kind(q);
+                v[q] = kq == 0 ? o[q] + v[q] : (kq == 1 ? fmax(o[q], v[q]) : fmin(o[q], v[q]));
+                sh[q][t] = v[q];
+            }
+        __syncthreads();
+    }
+    if (t >= nsteps) return;
+    double tot[kWallScratchVals];
+    for (int q = 0; q < kWallScratchVals; ++q) {
+        const int kq = kind(q);
+        tot[q] = kq == 0 ? prev[q] + v[q] : (kq == 1 ? fmax(prev[q], v[q]) : fmin(prev[q], v[q]));
+    }
+    lbm_stress_summary* h = &f.hist[(first_step + t - 1) % f.hist_cap];
+    h->int_peak_tau2 = tot[0];
+    h->int_tau2 = tot[1];
+    h->d_int_tau2 = tot[10];
+    for (int w = 0; w < 2; ++w) {
+        h->run_tau_max[w] = tot[2 + w];
+        h->run_tau_min[w] = tot[4 + w];
+        h->run_p_max[w] = tot[6 + w];
+        h->run_p_min[w] = tot[8 + w];
+    }
+    if (t == nsteps - 1)
+        for (int q = 0; q < kWallScratchVals; ++q) f.acc[q] = tot[q];
 }
 
-// One lattice: one wave per step, then the step-ordered integration.
-__global__ __launch_bounds__(64) void wall_step_reduce_kernel(const WallFlush f, int64_t first_step) {
+// One lattice: a block per step, then the scan over the steps.
+__global__ __launch_bounds__(kWallThreads) void wall_step_reduce_kernel(const WallFlush f, int64_t first_step) {
     wall_step_reduce_body(f, blockIdx.x, first_step);
 }
-__global__ void wall_integrate_kernel(const WallFlush f, int nsteps, int64_t first_step) {
+__global__ __launch_bounds__(kWallThreads) void wall_integrate_kernel(const WallFlush f, int nsteps, int64_t first_step) {
     wall_integrate_body(f, nsteps, first_step);
 }
 
-// Many lattices stepped together (same steps): blockIdx.y is the case.
-__global__ __launch_bounds__(64) void wall_step_reduce_batch_kernel(const WallFlush* __restrict__ tbl,
-                                                                    int64_t first_step) {
+// Many lattices stepped together (same steps): blockIdx.y (reduction) or
+// blockIdx.x (scan) is the case.
+__global__ __launch_bounds__(kWallThreads) void wall_step_reduce_batch_kernel(const WallFlush* __restrict__ tbl,
+                                                                              int64_t first_step) {
     wall_step_reduce_body(tbl[blockIdx.y], blockIdx.x, first_step);
 }
-__global__ __launch_bounds__(64) void wall_integrate_batch_kernel(const WallFlush* __restrict__ tbl, int ncases,
-                                                                  int nsteps, int64_t first_step) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < ncases) wall_integrate_body(tbl[c], nsteps, first_step);
+__global__ __launch_bounds__(kWallThreads) void wall_integrate_batch_kernel(const WallFlush* __restrict__ tbl,
+                                                                            int nsteps, int64_t first_step) {
+    wall_integrate_body(tbl[blockIdx.x], nsteps, first_step);
 }
 
 }  // namespace
@@ -328,20 +364,21 @@ hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t fi
                               int hist_cap, double* scratch, double* acc, hipStream_t s) {
     if (nsteps <= 0) return hipSuccess;
     const WallFlush f{ring, nx, hist, hist_cap, scratch, acc};
-    hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps), dim3(64), 0, s, f, first_step);
+    if (nsteps > kWallThreads) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps), dim3(kWallThreads), 0, s, f, first_step);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(wall_integrate_kernel, dim3(1), dim3(1), 0, s, f, nsteps, first_step);
+    hipLaunchKernelGGL(wall_integrate_kernel, dim3(1), dim3(kWallThreads), 0, s, f, nsteps, first_step);
     return hipGetLastError();
 }
 
 hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, int64_t first_step, hipStream_t s) {
     if (nsteps <= 0 || ncases <= 0) return hipSuccess;
-    hipLaunchKernelGGL(wall_step_reduce_batch_kernel, dim3(nsteps, ncases), dim3(64), 0, s, tbl, first_step);
+    if (nsteps > kWallThreads) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wall_step_reduce_batch_kernel, dim3(nsteps, ncases), dim3(kWallThreads), 0, s, tbl, first_step);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(wall_integrate_batch_kernel, dim3((ncases + 63) / 64), dim3(64), 0, s, tbl, ncases, nsteps,
-                       first_step);
+    hipLaunchKernelGGL(wall_integrate_batch_kernel, dim3(ncases), dim3(kWallThreads), 0, s, tbl, nsteps, first_step);
     return hipGetLastError();
 }
 
