@@ -79,25 +79,68 @@ def time_steps(w: dict, steps: int, warmup: int):
     return start.elapsed_time(stop) / 1e3, wall, lat
 
 
-def cpu_baseline(w: dict, budget_s: float) -> dict:
-    """The oracle as it stands, on a bounded sample of the same workload."""
-    import oracle
+_ORACLE_SAMPLE = r"""
+import json, os, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+w = json.loads(sys.argv[2])
+budget = float(sys.argv[3])
+keys = {"T_over_Tc", "dp"}
+p = oracle.params(tau=w["tau"], **{k: v for k, v in w["params"].items() if k in keys})
+sim = oracle.Sim(w["nx"], w["ny"], p)
+pl = w["plug"]
+sim.init_plug(pl["plug_len"], pl["film"], float("nan") if pl["x_center"] is None else pl["x_center"],
+              pl["noise_amp"], pl["seed"])
+t0 = time.perf_counter()
+sim.step(1)
+one = time.perf_counter() - t0
+n = max(1, min(1000, int(budget / max(one, 1e-6))))
+t0 = time.perf_counter()
+sim.step(n)
+dt = time.perf_counter() - t0
+print(json.dumps({"steps": n, "seconds": dt, "threads": oracle.threads()}))
+"""
 
-    keys = {"T_over_Tc", "dp"}
-    p = oracle.params(tau=w["tau"], **{k: v for k, v in w["params"].items() if k in keys})
-    sim = oracle.Sim(w["nx"], w["ny"], p)
-    pl = w["plug"]
-    sim.init_plug(pl["plug_len"], pl["film"], pl["x_center"], pl["noise_amp"], pl["seed"])
-    t0 = time.perf_counter()
-    sim.step(1)
-    one = time.perf_counter() - t0
-    n = max(1, min(1000, int(budget_s / max(one, 1e-6))))
-    t0 = time.perf_counter()
-    sim.step(n)
-    dt = time.perf_counter() - t0
-    return {"value": round(w["nx"] * w["ny"] * n / dt / 1e6, 2), "unit": "MLUPS", "cores": oracle.threads(),
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w: dict, budget_s: float) -> dict:
+    """The oracle as it stands, on a bounded sample of the same workload, with all host threads and with one
+    (each in a child process, so that OMP_NUM_THREADS takes effect)."""
+    import subprocess
+
+    spec = json.dumps({k: (None if isinstance(v, float) and v != v else v) for k, v in w.items() if k != "params"}
+                      | {"params": w["params"], "plug": {k: (None if isinstance(v, float) and v != v else v)
+                                                         for k, v in w["plug"].items()}})
+    runs = {}
+    for label, nthreads in (("all", None), ("one", 1)):
+        env = dict(os.environ)
+        if nthreads:
+            env["OMP_NUM_THREADS"] = str(nthreads)
+        out = subprocess.run([sys.executable, "-c", _ORACLE_SAMPLE, ROOT, spec,
+                              str(budget_s if nthreads is None else budget_s / 2)],
+                             capture_output=True, text=True, env=env, timeout=600)
+        if out.returncode != 0:
+            raise RuntimeError(f"oracle sample failed: {out.stderr[-2000:]}")
+        runs[label] = json.loads(out.stdout.strip().splitlines()[-1])
+    nodes = w["nx"] * w["ny"]
+    a, o = runs["all"], runs["one"]
+    return {"value": round(nodes * a["steps"] / a["seconds"] / 1e6, 2), "unit": "MLUPS", "cores": a["threads"],
             "kind": "oracle",
-            "sample": f"{n} steps of the {w['nx']}x{w['ny']} workload, FP64 oracle on the host ({dt:.1f} s)"}
+            "sample": f"{a['steps']} steps of the {w['nx']}x{w['ny']} workload, FP64 oracle on the host "
+                      f"({a['seconds']:.1f} s, {a['threads']} threads)",
+            "one_thread": {"value": round(nodes * o["steps"] / o["seconds"] / 1e6, 2), "unit": "MLUPS",
+                           "sample": f"{o['steps']} steps ({o['seconds']:.1f} s)"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def finite(v):
@@ -111,9 +154,9 @@ def finite(v):
     return v
 
 
-def measured_traffic(storage: str):
-    """HBM bytes per launch from the committed counter profile, if it was taken on this kernel source."""
-    if storage != "f32" or not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(storage: str, shape=(8, 4)):
+    """HBM bytes per launch from the committed counter profile, if it was taken on this kernel source and shape."""
+    if storage != "f32" or tuple(shape) != (8, 4) or not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
@@ -393,6 +436,7 @@ def main() -> int:
     achieved = bpn * nodes / (gpu_s / args.steps) / 1e9
     log(f"{mlups:.0f} MLUPS, {ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s algorithmic "
         f"(wall {wall_s:.3f} s); check: {chk}")
+    traffic = measured_traffic(args.storage, (lat.tuned["tile_rows"], lat.tuned["tile_waves"]) if lat.tuned else (8, 4))
     hist = lat.history(1)
     peak = None
     if hist:
@@ -417,8 +461,11 @@ def main() -> int:
                                 if lat.tuned else ("tile 60x8" if args.storage not in ("f64", "f32d") else "tile 60x12")),
                    "graph_steps": GRAPH_STEPS},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.storage),
-                     "bytes_per_node": bpn, "kernel": "tile_kernel (fused pull-stream/force/MRT/wall diagnostics)"},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_node": bpn,
+                     "fabric_bytes_per_node": round(traffic / nodes, 2) if traffic else None,
+                     "fabric_GBps": round(traffic / (gpu_s / args.steps) / 1e9, 1) if traffic else None,
+                     "kernel": "tile_kernel (fused pull-stream/force/MRT/wall diagnostics)"},
         "physics": {"unstable_step": chk["unstable_step"], "vmax": round(chk["vmax"], 5),
                     "nan_cells": chk["nan_count"], "liquid_columns": chk["liquid_columns"],
                     "x_rear": chk["x_rear"], "x_front": chk["x_front"], "wall_tau_peak_last_step": peak},
