@@ -238,7 +238,9 @@ bool schedule_ok(const lbm_params* p) {
     }
 }
 
-bool graph_steps_ok(int g) { return g == -1 || g == 0 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+bool graph_steps_ok(int g) {
+    return g == -1 || g == 0 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64 || g == 128 || g == 256;
+}
 
 // Captured HIP graphs of consecutive step launches, one per (parity of the
 // input buffer, first wall-ring slot), made when first needed: replaying a
