@@ -289,23 +289,7 @@ __device__ inline void grad3(const Row3<C>& s, const Row3<C>& m, const Row3<C>& 
     gy = C(1.0 / 3.0) * (n.c - s.c) + C(1.0 / 12.0) * ((n.e + n.w) - (s.e + s.w));
 }
 
-// Wave-wide reductions (64 lanes) used for the per-strip wall extremes.
-__device__ inline void wave_argmax(double& v, int& x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        double ov = __shfl_xor(v, off, 64);
-        int ox = __shfl_xor(x, off, 64);
-        if (ov > v || (ov == v && ox < x)) { v = ov; x = ox; }
-    }
-}
-__device__ inline void wave_argmin(double& v, int& x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        double ov = __shfl_xor(v, off, 64);
-        int ox = __shfl_xor(x, off, 64);
-        if (ov < v || (ov == v && ox < x)) { v = ov; x = ox; }
-    }
-}
+// Wave-wide sum (64 lanes).
 __device__ inline double wave_sum(double v) {
     // fixed butterfly: every lane ends with the same, order-deterministic sum
 #pragma unroll

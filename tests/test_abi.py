@@ -81,7 +81,8 @@ def test_defaults(L):
     dict(tile_waves=8, tile_rows=8), dict(schedule=0, tile_rows=16), dict(schedule=3), dict(schedule=2, tile_rows=20),
     dict(schedule=2, tile_waves=8, tile_rows=12), dict(schedule=2, pipe_blocks=4), dict(pipe_blocks=64),
     dict(schedule=1, tile_waves=4), dict(storage=6, schedule=1), dict(storage=6, tile_rows=8),
-    dict(storage=6, tile_waves=4),
+    dict(storage=6, tile_waves=4), dict(graph_steps=3), dict(graph_steps=512), dict(graph_steps=-2),
+    dict(fused_steps=3), dict(fused_steps=-1),
 ])
 def test_create_rejects_invalid_parameters(L, bad):
     with pytest.raises(L.LbmError) as e:
@@ -144,3 +145,49 @@ def test_batch_create_validates_cases(L):
                 [p(), p(check_every=10)], [p(), p(schedule=1)], [p(), p(T_over_Tc=-1.0)]):
         st, _ = create(bad)
         assert st == L.LBM_EINVAL
+
+
+def test_adjoint_workspace_layout_and_rules(L):
+    """Host-side arithmetic of the adjoint workspace (no device needed): ceil(N/S) checkpoints plus S + 1 segment
+    states, two adjoint fields, the recomputed wall shears, the per-launch partials and the FP64 state gradient."""
+    def align(v):
+        return (v + 255) // 256 * 256
+
+    nx, ny = 200, 40
+    pitch = (nx + 63) // 64 * 64
+    for storage, sb, ab in (("f32", 4, 4), ("f64", 8, 8), ("f32d", 4, 8)):
+        ctx = L.lbm_create(nx, ny, 1.0, L.lbm_params_default(storage=storage))
+        for n, seg in ((1000, 0), (1000, 10), (7, 7), (1, 1)):
+            s = seg or math.ceil(math.sqrt(n))
+            k = (n + s - 1) // s
+            ty = 8
+            blocks = ((nx + 55) // 56) * ((ny + ty - 1) // ty)
+            ring = max(s, 64)
+            want = (k * align(pitch * ny * 9 * sb) + (s + 1) * align(pitch * ny * 9 * sb) + 2 * align(pitch * ny * 9 * ab)
+                    + align(s * 2 * nx * 8) + align(ring * blocks * 4 * 8) + align(ring * 4 * 8) + 256
+                    + align(4 * nx * 8) + align(9 * nx * ny * 8))
+            assert L.lbm_adjoint_workspace(ctx, n, seg) == want, (storage, n, seg)
+        for n, seg in ((0, 0), (10, 11), (10, -1)):
+            with pytest.raises(L.LbmError):
+                L.lbm_adjoint_workspace(ctx, n, seg)
+        L.lbm_destroy(ctx)
+    for bad in (dict(storage="f16s"), dict(storage="bf16s"), dict(storage="f64t"), dict(schedule=1),
+                dict(schedule=2)):
+        ctx = L.lbm_create(nx, ny, 1.0, L.lbm_params_default(**bad))
+        with pytest.raises(L.LbmError):
+            L.lbm_adjoint_workspace(ctx, 100, 0)
+        L.lbm_destroy(ctx)
+
+
+def test_calls_before_binding_the_adjoint_are_rejected(L):
+    import ctypes as C
+
+    ctx = L.lbm_create(64, 32, 1.0, L.lbm_params_default(storage="f64"))
+    J = C.c_double()
+    g = (C.c_double * 4)()
+    assert L.library().lbm_adjoint_forward(ctx, C.byref(J)) == L.LBM_ESTATE
+    assert L.library().lbm_adjoint_backward(ctx, 1.0, g) == L.LBM_ESTATE
+    assert L.library().lbm_adjoint_state_gradient(ctx, g) == L.LBM_ESTATE
+    assert L.library().lbm_autotune(ctx, 10, None, None, None) == L.LBM_ESTATE
+    assert L.library().lbm_adjoint_backward(ctx, math.nan, g) == L.LBM_EINVAL
+    L.lbm_destroy(ctx)
