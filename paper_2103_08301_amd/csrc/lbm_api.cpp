@@ -1080,10 +1080,14 @@ constexpr int kAdjRing = 64;  // adjoint launches whose parameter partials are r
 
 size_t adjoint_arith_bytes(int storage) { return storage == LBM_F32 ? 4 : 8; }
 
-// Output rows per adjoint tile.  Measured (FP32 and FP64): 8-row tiles are faster
-// on the 1024x256 channel (more blocks to fill the chip), 16-row tiles on
-// 4096x512 (less halo recomputation once the grid fills it).
-int adjoint_tile_rows(const lbm_ctx* c) { return (long long)c->nx * c->ny >= (1LL << 20) ? 16 : 8; }
+// Output rows per adjoint tile.  Measured: with FP32 arithmetic 8-row tiles at six
+// waves per SIMD are faster at every size (4096x512: 78 vs 88 us per step); with
+// FP64 arithmetic (three waves per SIMD) 8-row tiles win on the 1024x256 channel
+// (more blocks to fill the chip) and 16-row tiles on 4096x512 (less recomputed halo).
+int adjoint_tile_rows(const lbm_ctx* c) {
+    if (adjoint_arith_bytes(c->p.storage) == 4) return 8;
+    return (long long)c->nx * c->ny >= (1LL << 20) ? 16 : 8;
+}
 
 lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm_ctx::Adjoint& A) {
     if (c->p.storage != LBM_F64 && c->p.storage != LBM_F32 && c->p.storage != LBM_F32D) return LBM_EINVAL;
