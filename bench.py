@@ -258,7 +258,7 @@ def adjoint_cost(storage: str, steps: int, segment: int, large: bool) -> int:
     seg = segment or math.ceil(math.sqrt(steps))
     recompute_steps = steps  # every step is recomputed once from its segment's checkpoint
     t_adj_kernel = max(t_bwd - recompute_steps * t_fwd / steps, 0.0) / steps
-    bpn = 9 * (BYTES_PER_NODE[storage] // 18) + 18 * (4 if storage == "f32" else 8)  # state read, adjoint read+write
+    bpn = 23 * (4 if storage == "f32" else 8)  # 5 forward fields and 9 adjoint reads, 9 adjoint writes
     out = {"metric": "adjoint/fwd time (gradient of int sum tau_w^2 w.r.t. dp, a, b, T)", "workload": w["name"],
            "storage": storage, "steps": steps, "segment": seg, "checkpoints": math.ceil(steps / seg),
            "forward_s": round(t_fwd, 4), "record_s": round(t_rec, 4), "backward_s": round(t_bwd, 4),

@@ -21,14 +21,16 @@
 // into the copied column, and the pull transposes to a gather of lam_in from
 // the downstream neighbours x + e_i (bounce-back from the node itself).
 //
-// A tile of 64 columns (56 outputs and a 4-column halo on each side) by TYO + 8
-// rows recomputes the forward quantities it needs from step n's input state:
-// the force adjoint at a node needs lam and the forward force within 2 nodes,
-// which need rho within 4.  Phases, with barriers between them:
-//   A  pull the state, rho/phi to LDS (radius 4), gather lam (radius 2)
-//   B  Laplacian of rho (radius 3)
-//   C  force, velocity shift, wall seeds, the collision's vector-Jacobian
-//      product: the local part of dJ/df and the force adjoint F~ (radius 2)
+// The backward sweep recomputes each checkpoint segment forwards with a step
+// kernel that also writes the forward quantities this adjoint needs (rho, u =
+// (j + tau F)/rho, grad lap rho, and v_x on the wall rows), so the adjoint
+// recomputes none of the step.  A tile of 64 columns (60 outputs and a 2-column
+// halo on each side) by TYO + 4 rows: the force adjoint is needed within 1 node
+// of the outputs' density adjoint and within 2 nodes of the outputs, and at a
+// node it depends only on lam and that node's forward fields.  Phases, with
+// barriers between them:
+//   A  gather lam, the collision's vector-Jacobian product: the local part of
+//      dJ/df (output rows) and the force adjoint F~ (all rows), rho and F~ to LDS
 //   D  phi~ = div F~ and L~ = -div(kappa rho F~) (radius 1)
 //   E  rho~ = lap L~ + phi'(rho) phi~ (+ ghost columns), store dJ/df, and the
 //      parameter sums sum F~_x, sum phi~ dphi/d(RT, a_eff, b)
@@ -38,7 +40,7 @@
 namespace lbm {
 namespace {
 
-constexpr int kAdjHalo = 4;
+constexpr int kAdjHalo = 2;
 
 // dphi/drho and dphi/d(RT, a_eff, b) of phi = k^2 p0(rho) - rho/3 at one density
 // (the same p0 as phi_of: eq. A9 with the van der Waals attraction, eq. A8).
@@ -120,20 +122,13 @@ __device__ inline C div3(const Row3<C>& sx, const Row3<C>& mx, const Row3<C>& nx
            C(1.0 / 3.0) * (ny_.c - sy.c) + C(1.0 / 12.0) * ((ny_.e + ny_.w) - (sy.e + sy.w));
 }
 
-// 8-row tiles with FP32 arithmetic: at least 6 waves per SIMD (three 8-wave blocks
-// per compute unit, at most 80 VGPRs, no spills), so the tiles of a 1024 x 256
-// grid run in one round.
-template <class CD, int TYO>
-constexpr int adj_min_waves() { return (sizeof(typename CD::C) == 4 && TYO == 8) ? 6 : 1; }
-
 template <class CD, int EOS, int TYO, int NW>
-__global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_kernel(const AdjArgs A) {
-    using S = typename CD::S;
+__global__ __launch_bounds__(64 * NW) void adjoint_kernel(const AdjArgs A) {
     using C = typename CD::C;
     constexpr int H = TYO + 2 * kAdjHalo;
     constexpr int RPT = H / NW;
     static_assert(H % NW == 0, "tile height must be a multiple of the waves per block");
-    __shared__ C sRho[H][64], sPhi[H][64], sLap[H][64], sFx[H][64], sFy[H][64];
+    __shared__ C sRho[H][64], sFx[H][64], sFy[H][64], sPhi[H][64], sLap[H][64];
     __shared__ double sRed[NW][4];
 
     const StepArgs& a = A.s;
@@ -143,7 +138,11 @@ __global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_k
     const int tile = bid / A.nstrip;
     const int strip = bid - tile * A.nstrip;
     const int y0 = (a.ny >= TYO) ? min(tile * TYO, a.ny - TYO) : 0;
-    const int x = strip * kAdjStripOut - kAdjHalo + lane;
+    // the last tile is moved down to end at row ny - 1: its rows below tile * TYO are
+    // the previous tile's too, and only that tile adds them to the parameter sums
+    const int y_sum = tile * TYO;
+    const int x0 = strip * kAdjStripOut;
+    const int x = x0 - kAdjHalo + lane;
     const bool xin = x >= 0 && x < a.nx;
     const bool xfl = a.xper || xin;
     int xe = x;
@@ -151,122 +150,30 @@ __global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_k
     const bool out_lane = lane >= kAdjHalo && lane < 64 - kAdjHalo && xin;
     const int lm = lane > 0 ? lane - 1 : 0, lp = lane < 63 ? lane + 1 : 63;  // edge lanes are halo: clamped, unused
 
-    const S* __restrict__ fin = static_cast<const S*>(a.fin);
     const C* __restrict__ lb = static_cast<const C*>(A.lam_in);
     C* __restrict__ lout = static_cast<C*>(A.lam_out);
-    const C rho0 = LBM_COEF(C, rho0);
     const C RT = LBM_COEF(C, RT), a_eff = LBM_COEF(C, a_eff), bb = LBM_COEF(C, b);
-    const C k2 = LBM_COEF(C, k2), kappa = LBM_COEF(C, kappa), g = LBM_COEF(C, g);
+    const C k2 = LBM_COEF(C, k2), kappa = LBM_COEF(C, kappa);
     const C rho_w = LBM_COEF(C, rho_w), tau = LBM_COEF(C, tau), nu = LBM_COEF(C, nu);
     const C s_e = LBM_COEF(C, s_e), s_eps = LBM_COEF(C, s_eps), s_q = LBM_COEF(C, s_q);
     const C s_j = LBM_COEF(C, s_j), s_v = LBM_COEF(C, s_v);
+    const bool walls = !a.yper;
 
-    // ---- phase A: pull, density, EOS field; gather lam -------------------------
-    // Interior tiles (every pulled source and every gathered target in range, no
-    // wall or end rule) load through buffer resources with uniform offsets.
-    const int x0 = strip * kAdjStripOut;
+    // Field and adjoint loads through buffer resources (uniform plane offsets in
+    // SGPRs).  Interior tiles (every gathered target in range, no wall or end
+    // rule) gather lam with uniform offsets too.
+    const uint32_t esz = uint32_t(sizeof(C));
+    const uint32_t plane_c = uint32_t(a.plane) * esz;
+    const __amdgpu_buffer_rsrc_t rfl =
+        buffer_rsrc(const_cast<void*>(A.fld), uint32_t(kAdjFieldPlanes) * plane_c + uint32_t(4 * a.nx) * esz);
+    const __amdgpu_buffer_rsrc_t rlb = buffer_rsrc(const_cast<C*>(lb), 9u * plane_c);
     const bool tile_inner = (x0 - kAdjHalo - 1 >= 0) && (x0 + 64 - kAdjHalo <= a.nx - 1) &&
                             (y0 - kAdjHalo - 1 >= 0) && (y0 + TYO + kAdjHalo <= a.ny - 1);
-    C jx[RPT], jy[RPT], lam[RPT][9];
-    C rho_r[RPT];
-    if (tile_inner) {
-        const uint32_t plane_s = uint32_t(a.plane) * uint32_t(sizeof(S)), plane_c = uint32_t(a.plane) * uint32_t(sizeof(C));
-        uint32_t dir_off[9], gat_off[9];
+    uint32_t gat_off[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            dir_off[i] = uint32_t(i) * plane_s - uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(S));
-            gat_off[i] = uint32_t(i) * plane_c + uint32_t(ey(i) * a.pitch + ex(i)) * uint32_t(sizeof(C));
-        }
-        const __amdgpu_buffer_rsrc_t rin = buffer_rsrc(const_cast<S*>(fin), 9u * plane_s);
-        const __amdgpu_buffer_rsrc_t rlb = buffer_rsrc(const_cast<C*>(lb), 9u * plane_c);
-        C f[RPT][9];
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int k = wave + NW * j;
-            const int r = y0 - kAdjHalo + k;
-            pull_interior_buf<CD>(rin, dir_off, uint32_t(r * a.pitch + xe) * uint32_t(sizeof(S)), rho0, f[j]);
-            if (k >= 2 && k <= H - 3)
-                gather_lambda_buf<C>(rlb, gat_off, uint32_t(r * a.pitch + xe) * uint32_t(sizeof(C)), lam[j]);
-            else
-#pragma unroll
-                for (int i = 0; i < 9; ++i) lam[j][i] = C(0);
-        }
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            rho_r[j] = ((f[j][0] + f[j][1]) + (f[j][2] + f[j][3])) + ((f[j][4] + f[j][5]) + (f[j][6] + f[j][7])) + f[j][8];
-            jx[j] = (f[j][1] - f[j][3]) + (f[j][5] - f[j][6]) + (f[j][8] - f[j][7]);
-            jy[j] = (f[j][2] - f[j][4]) + (f[j][5] - f[j][8]) + (f[j][6] - f[j][7]);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int k = wave + NW * j;
-            const int r = y0 - kAdjHalo + k;
-            const bool yfl = a.yper || (r >= 0 && r < a.ny);
-            const int yr = a.yper ? wrapi(r, a.ny) : r;
-            rho_r[j] = rho_w;
-            jx[j] = C(0);
-            jy[j] = C(0);
-            if (yfl) {
-                C f[9];
-                pull_generic<CD>(fin, a, xe, yr, rho0, f);
-                rho_r[j] = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-                jx[j] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-                jy[j] = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
-            }
-            if (k >= 2 && k <= H - 3 && yfl && xfl) {
-                gather_lambda<C>(lb, a, xe, yr, lam[j]);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) lam[j][i] = C(0);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int k = wave + NW * j;
-        sRho[k][lane] = rho_r[j];
-        sPhi[k][lane] = phi_of<EOS, C>(rho_r[j], RT, a_eff, bb, k2);
-        sFx[k][lane] = C(0);
-        sFy[k][lane] = C(0);
-    }
-    __syncthreads();
+    for (int i = 0; i < 9; ++i) gat_off[i] = uint32_t(i) * plane_c + uint32_t(ey(i) * a.pitch + ex(i)) * esz;
 
-    // ---- phase B: Laplacian of rho on rows 1 .. H-2 ------------------------------
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int k = wave + NW * j;
-        if (k >= 1 && k <= H - 2) {
-            const Row3<C> s{sRho[k - 1][lane], sRho[k - 1][lp], sRho[k - 1][lm]};
-            const Row3<C> m{sRho[k][lane], sRho[k][lp], sRho[k][lm]};
-            const Row3<C> n{sRho[k + 1][lane], sRho[k + 1][lp], sRho[k + 1][lm]};
-            sLap[k][lane] = lap3(s, m, n);
-        }
-    }
-    __syncthreads();
-
-    // Force at tile row k of this lane (rows 2 .. H-3), with the forward step's expressions.
-    auto force = [&](int k, C& Fx, C& Fy, C& glx, C& gly) {
-        C gphx, gphy;
-        {
-            const Row3<C> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
-            const Row3<C> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
-            const Row3<C> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
-            grad3(s, m, n, gphx, gphy);
-        }
-        {
-            const Row3<C> s{sLap[k - 1][lane], sLap[k - 1][lp], sLap[k - 1][lm]};
-            const Row3<C> m{sLap[k][lane], sLap[k][lp], sLap[k][lm]};
-            const Row3<C> n{sLap[k + 1][lane], sLap[k + 1][lp], sLap[k + 1][lm]};
-            grad3(s, m, n, glx, gly);
-        }
-        const C rh = sRho[k][lane];
-        Fx = -gphx + kappa * rh * glx + g;
-        Fy = -gphy + kappa * rh * gly;
-    };
-
-    // ---- phase C: the collision's vector-Jacobian product --------------------------
-    const bool walls = !a.yper;
+    // ---- phase A: gather lam, the collision's vector-Jacobian product ----------------
     double acc_g = 0.0;
     C fb[RPT][9];
 #pragma unroll
@@ -274,90 +181,97 @@ __global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_k
         const int k = wave + NW * j;
         const int y = y0 - kAdjHalo + k;
         const bool yfl = a.yper || (y >= 0 && y < a.ny);
+        const int yr = a.yper ? wrapi(y, a.ny) : y;
 #pragma unroll
         for (int i = 0; i < 9; ++i) fb[j][i] = C(0);
-        if (k < 2 || k > H - 3 || !yfl || !xfl) continue;
-        C Fx, Fy, glx, gly;
-        force(k, Fx, Fy, glx, gly);
-        const C rh = sRho[k][lane];
-        const C inv = recip(rh);
-        const C Px = jx[j] + tau * Fx, Py = jy[j] + tau * Fy;
-        const C ux = Px * inv, uy = Py * inv;
-        // seeds of J = sum tau_w^2 on the two rows next to each wall: dJ/dtau_w = 2 tau_w, with
-        // tau_w = rho_w nu (9 v_x(1/2) - v_x(3/2)) / 3 of this step (written by its forward recompute)
-        C vbx = C(0), rbw = C(0);
-        if (walls && (y <= 1 || y >= a.ny - 2)) {
-            const bool bottom = y <= 1;
-            const int kw = bottom ? (y == 0 ? k : k - 1) : (y == a.ny - 1 ? k : k + 1);  // row next to the wall
-            const C rw = sRho[kw][lane];
-            const C tw = C(A.tau_w[(bottom ? 0 : a.nx) + xe]);
-            const C tb = C(2) * tw;
-            if (y == 0 || y == a.ny - 1) {
-                rbw = tb * tw * recip(rw);  // d tau_w / d rho_w = tau_w / rho_w
-                vbx = tb * rw * nu * C(3);
-            } else {
-                vbx = -(tb * rw * nu * C(1.0 / 3.0));
+        C rho = rho_w, Fbx = C(0), Fby = C(0);
+        if (yfl) {
+            const uint32_t no = uint32_t(yr * a.pitch + xe) * esz;
+            rho = buffer_load<C>(rfl, no, 0);
+            if (xfl) {
+                const C ux = buffer_load<C>(rfl, no, plane_c), uy = buffer_load<C>(rfl, no, 2 * plane_c);
+                const C glx = buffer_load<C>(rfl, no, 3 * plane_c), gly = buffer_load<C>(rfl, no, 4 * plane_c);
+                C l[9];
+                if (tile_inner)
+                    gather_lambda_buf<C>(rlb, gat_off, no, l);
+                else
+                    gather_lambda<C>(lb, a, xe, yr, l);
+                // seeds of J = sum tau_w^2 on the two rows next to each wall: dJ/dtau_w = 2 tau_w, with
+                // tau_w = rho_w nu (9 v_x(1/2) - v_x(3/2)) / 3 of this step (written by its forward recompute)
+                C vbx = C(0), rbw = C(0), vx = C(0), inv = C(0);
+                if (walls && (y <= 1 || y >= a.ny - 2)) {
+                    const bool bottom = y <= 1;
+                    const int yw = bottom ? 0 : a.ny - 1;  // the row next to the wall
+                    const int w = bottom ? y : 3 - (a.ny - 1 - y);
+                    const C rw = buffer_load<C>(rfl, uint32_t(yw * a.pitch + xe) * esz, 0);
+                    vx = buffer_load<C>(rfl, uint32_t(w * a.nx + xe) * esz, uint32_t(kAdjFieldPlanes) * plane_c);
+                    inv = recip(rho);
+                    const C tw = C(A.tau_w[(bottom ? 0 : a.nx) + xe]);
+                    const C tb = C(2) * tw;
+                    if (y == yw) {
+                        rbw = tb * tw * recip(rw);  // d tau_w / d rho_w = tau_w / rho_w
+                        vbx = tb * rw * nu * C(3);
+                    } else {
+                        vbx = -(tb * rw * nu * C(1.0 / 3.0));
+                    }
+                }
+                // moments of lam, scaled by the relaxation rates over the squared row norms
+                const C A4 = (l[1] + l[2]) + (l[3] + l[4]);
+                const C D4 = (l[5] + l[6]) + (l[7] + l[8]);
+                const C ne = s_e * C(1.0 / 36.0) * (C(-4) * l[0] - A4 + C(2) * D4);
+                const C neps = s_eps * C(1.0 / 36.0) * (C(4) * l[0] - C(2) * A4 + D4);
+                const C njx = s_j * C(1.0 / 6.0) * ((l[1] - l[3]) + (l[5] - l[6]) + (l[8] - l[7]));
+                const C nqx = s_q * C(1.0 / 12.0) * (C(2) * (l[3] - l[1]) + ((l[5] - l[6]) - (l[7] - l[8])));
+                const C njy = s_j * C(1.0 / 6.0) * ((l[2] - l[4]) + (l[5] - l[8]) + (l[6] - l[7]));
+                const C nqy = s_q * C(1.0 / 12.0) * (C(2) * (l[4] - l[2]) + ((l[5] + l[6]) - (l[7] + l[8])));
+                const C nxx = s_v * C(0.25) * ((l[1] + l[3]) - (l[2] + l[4]));
+                const C nxy = s_v * C(0.25) * ((l[5] + l[7]) - (l[6] + l[8]));
+                // m_eq = (rho, 3|P|^2/rho - 2 rho, rho - 3|P|^2/rho, Px, -Px, Py, -Py, (Px^2 - Py^2)/rho, Px Py/rho)
+                const C u2 = ux * ux + uy * uy;
+                C rb = ne * (C(-2) - C(3) * u2) + neps * (C(1) + C(3) * u2) - nxx * (ux * ux - uy * uy) - nxy * (ux * uy);
+                const C dee = C(6) * (ne - neps);
+                const C Pbx = dee * ux + (njx - nqx) + C(2) * nxx * ux + nxy * uy;
+                const C Pby = dee * uy + (njy - nqy) - C(2) * nxx * uy + nxy * ux;
+                // P = j + tau F; v = (j + F/2)/rho
+                const C jbx = Pbx + vbx * inv, jby = Pby;
+                Fbx = tau * Pbx + C(0.5) * vbx * inv;
+                Fby = tau * Pby;
+                rb += rbw - vbx * vx * inv;
+                rb += kappa * (glx * Fbx + gly * Fby);  // F contains kappa rho grad L
+                if (k >= kAdjHalo && k < kAdjHalo + TYO && out_lane && y < a.ny) {
+                    if (y >= y_sum) acc_g += double(Fbx);
+                    // f~ = lam - M^T (D M lam) + rho~ + e . j~ (rho~ gets the stencil terms in phase E)
+                    const C c0 = -ne - C(2) * neps, c1 = C(2) * ne + neps;
+                    const C X = njx - C(2) * nqx, Y = njy - C(2) * nqy, Xd = njx + nqx, Yd = njy + nqy;
+                    fb[j][0] = l[0] - C(4) * (neps - ne) + rb;
+                    fb[j][1] = l[1] - (c0 + X + nxx) + rb + jbx;
+                    fb[j][3] = l[3] - (c0 - X + nxx) + rb - jbx;
+                    fb[j][2] = l[2] - (c0 + Y - nxx) + rb + jby;
+                    fb[j][4] = l[4] - (c0 - Y - nxx) + rb - jby;
+                    fb[j][5] = l[5] - (c1 + Xd + Yd + nxy) + rb + jbx + jby;
+                    fb[j][7] = l[7] - (c1 - Xd - Yd + nxy) + rb - jbx - jby;
+                    fb[j][6] = l[6] - (c1 - Xd + Yd - nxy) + rb - jbx + jby;
+                    fb[j][8] = l[8] - (c1 + Xd - Yd - nxy) + rb + jbx - jby;
+                }
             }
         }
-        const C vx = (jx[j] + C(0.5) * Fx) * inv;
-        C* l = lam[j];
-        // moments of lam, scaled by the relaxation rates over the squared row norms
-        const C A4 = (l[1] + l[2]) + (l[3] + l[4]);
-        const C D4 = (l[5] + l[6]) + (l[7] + l[8]);
-        const C ne = s_e * C(1.0 / 36.0) * (C(-4) * l[0] - A4 + C(2) * D4);
-        const C neps = s_eps * C(1.0 / 36.0) * (C(4) * l[0] - C(2) * A4 + D4);
-        const C njx = s_j * C(1.0 / 6.0) * ((l[1] - l[3]) + (l[5] - l[6]) + (l[8] - l[7]));
-        const C nqx = s_q * C(1.0 / 12.0) * (C(2) * (l[3] - l[1]) + ((l[5] - l[6]) - (l[7] - l[8])));
-        const C njy = s_j * C(1.0 / 6.0) * ((l[2] - l[4]) + (l[5] - l[8]) + (l[6] - l[7]));
-        const C nqy = s_q * C(1.0 / 12.0) * (C(2) * (l[4] - l[2]) + ((l[5] + l[6]) - (l[7] + l[8])));
-        const C nxx = s_v * C(0.25) * ((l[1] + l[3]) - (l[2] + l[4]));
-        const C nxy = s_v * C(0.25) * ((l[5] + l[7]) - (l[6] + l[8]));
-        // m_eq = (rho, 3|P|^2/rho - 2 rho, rho - 3|P|^2/rho, Px, -Px, Py, -Py, (Px^2 - Py^2)/rho, Px Py/rho)
-        const C u2 = ux * ux + uy * uy;
-        C rb = ne * (C(-2) - C(3) * u2) + neps * (C(1) + C(3) * u2) - nxx * (ux * ux - uy * uy) - nxy * (ux * uy);
-        const C dee = C(6) * (ne - neps);
-        const C Pbx = dee * ux + (njx - nqx) + C(2) * nxx * ux + nxy * uy;
-        const C Pby = dee * uy + (njy - nqy) - C(2) * nxx * uy + nxy * ux;
-        // P = j + tau F; v = (j + F/2)/rho
-        const C jbx = Pbx + vbx * inv, jby = Pby;
-        const C Fbx = tau * Pbx + C(0.5) * vbx * inv, Fby = tau * Pby;
-        rb += rbw - vbx * vx * inv;
-        rb += kappa * (glx * Fbx + gly * Fby);  // F contains kappa rho grad L
-        sFx[k][lane] = Fbx;
+        sRho[k][lane] = rho;  // ghost rows hold rho_w, ghost columns the copied end column
+        sFx[k][lane] = Fbx;   // zero off the fluid
         sFy[k][lane] = Fby;
-        if (k >= kAdjHalo && k < kAdjHalo + TYO && out_lane && y < a.ny) {
-            acc_g += double(Fbx);
-            // f~ = lam - M^T (D M lam) + rho~ + e . j~ (rho~ gets the stencil terms in phase E)
-            const C c0 = -ne - C(2) * neps, c1 = C(2) * ne + neps;
-            const C X = njx - C(2) * nqx, Y = njy - C(2) * nqy, Xd = njx + nqx, Yd = njy + nqy;
-            fb[j][0] = l[0] - C(4) * (neps - ne) + rb;
-            fb[j][1] = l[1] - (c0 + X + nxx) + rb + jbx;
-            fb[j][3] = l[3] - (c0 - X + nxx) + rb - jbx;
-            fb[j][2] = l[2] - (c0 + Y - nxx) + rb + jby;
-            fb[j][4] = l[4] - (c0 - Y - nxx) + rb - jby;
-            fb[j][5] = l[5] - (c1 + Xd + Yd + nxy) + rb + jbx + jby;
-            fb[j][7] = l[7] - (c1 - Xd - Yd + nxy) + rb - jbx - jby;
-            fb[j][6] = l[6] - (c1 - Xd + Yd - nxy) + rb - jbx + jby;
-            fb[j][8] = l[8] - (c1 + Xd - Yd - nxy) + rb + jbx - jby;
-        }
     }
     __syncthreads();
 
     // ---- phase D: phi~ = div F~, L~ = -div(kappa rho F~) on rows 1 .. H-2 -----------
-    // Both overwrite their forward fields (phi, L), which nothing reads any more.
-    C phib[RPT], lapb[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int k = wave + NW * j;
-        phib[j] = C(0);
-        lapb[j] = C(0);
         if (k < 1 || k > H - 2) continue;
         const Row3<C> sx{sFx[k - 1][lane], sFx[k - 1][lp], sFx[k - 1][lm]};
         const Row3<C> mx{sFx[k][lane], sFx[k][lp], sFx[k][lm]};
         const Row3<C> nx_{sFx[k + 1][lane], sFx[k + 1][lp], sFx[k + 1][lm]};
         const Row3<C> sy{sFy[k - 1][lane], sFy[k - 1][lp], sFy[k - 1][lm]};
         const Row3<C> ny_{sFy[k + 1][lane], sFy[k + 1][lp], sFy[k + 1][lm]};
-        phib[j] = div3(sx, mx, nx_, sy, ny_);
+        sPhi[k][lane] = div3(sx, mx, nx_, sy, ny_);
 #define LBM_G(F, kk, ll) (kappa * sRho[kk][ll] * F[kk][ll])
         const Row3<C> gsx{LBM_G(sFx, k - 1, lane), LBM_G(sFx, k - 1, lp), LBM_G(sFx, k - 1, lm)};
         const Row3<C> gmx{LBM_G(sFx, k, lane), LBM_G(sFx, k, lp), LBM_G(sFx, k, lm)};
@@ -365,25 +279,20 @@ __global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_k
         const Row3<C> gsy{LBM_G(sFy, k - 1, lane), LBM_G(sFy, k - 1, lp), LBM_G(sFy, k - 1, lm)};
         const Row3<C> gny{LBM_G(sFy, k + 1, lane), LBM_G(sFy, k + 1, lp), LBM_G(sFy, k + 1, lm)};
 #undef LBM_G
-        lapb[j] = -div3(gsx, gmx, gnx, gsy, gny);
-    }
-    // every read of phi and L (phases A-C) is behind the barrier above
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int k = wave + NW * j;
-        if (k < 1 || k > H - 2) continue;
-        sPhi[k][lane] = phib[j];
-        sLap[k][lane] = lapb[j];
+        sLap[k][lane] = -div3(gsx, gmx, gnx, gsy, gny);
     }
     __syncthreads();
 
     // ---- phase E: rho~, dJ/df of the outputs, parameter sums ------------------------
     double acc_rt = 0.0, acc_a = 0.0, acc_b = 0.0;
     auto rho_bar_at = [&](int k, int l2, C& dRT, C& dA, C& dB) {
-        // lap(L~) + phi'(rho) phi~ at tile position (k, l2); returns the EOS partials too
-        const Row3<C> s{sLap[k - 1][l2], sLap[k - 1][l2 + 1], sLap[k - 1][l2 - 1]};
-        const Row3<C> m{sLap[k][l2], sLap[k][l2 + 1], sLap[k][l2 - 1]};
-        const Row3<C> n{sLap[k + 1][l2], sLap[k + 1][l2 + 1], sLap[k + 1][l2 - 1]};
+        // lap(L~) + phi'(rho) phi~ at tile position (k, l2); returns the EOS partials too.  Past
+        // the tile's edge lanes (only reached from a ghost column two nodes beyond an
+        // extrapolated end) L~ is zero, as it is in the clamped edge lane.
+        const int l2m = l2 > 0 ? l2 - 1 : 0, l2p = l2 < 63 ? l2 + 1 : 63;
+        const Row3<C> s{sLap[k - 1][l2], sLap[k - 1][l2p], sLap[k - 1][l2m]};
+        const Row3<C> m{sLap[k][l2], sLap[k][l2p], sLap[k][l2m]};
+        const Row3<C> n{sLap[k + 1][l2], sLap[k + 1][l2p], sLap[k + 1][l2m]};
         C dr;
         phi_partials<EOS, C>(sRho[k][l2], RT, a_eff, bb, k2, dr, dRT, dA, dB);
         return lap3(s, m, n) + dr * sPhi[k][l2];
@@ -396,9 +305,12 @@ __global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_k
         C dRT, dA, dB;
         C rb = rho_bar_at(k, lane, dRT, dA, dB);
         const C ph = sPhi[k][lane];
-        acc_rt += double(ph * dRT);
-        acc_a += double(ph * dA);
-        acc_b += double(ph * dB);
+        const bool sums = y >= y_sum;
+        if (sums) {
+            acc_rt += double(ph * dRT);
+            acc_a += double(ph * dA);
+            acc_b += double(ph * dB);
+        }
         if (!a.xper && (x == 0 || x == a.nx - 1)) {
             // ghost columns copy this end column: their adjoints add back here
             const int sgn = x == 0 ? -1 : 1;
@@ -406,7 +318,7 @@ __global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_k
             rb += rho_bar_at(k, lane + sgn, t0, t1, t2);
             rb += rho_bar_at(k, lane + 2 * sgn, t0, t1, t2);
         }
-        const bool edge = (!a.yper && (y == 0 || y == a.ny - 1)) || (!a.xper && (x == 0 || x == a.nx - 1));
+        const bool edge = sums && ((!a.yper && (y == 0 || y == a.ny - 1)) || (!a.xper && (x == 0 || x == a.nx - 1)));
         if (edge) {
             // ghost positions next to the domain whose nearest node is this one: their phi
             // depends on the parameters (wall rows at the fixed rho_w, end columns at copies)
@@ -507,11 +419,31 @@ hipError_t launch_adj_t(const AdjArgs& A, hipStream_t s) {
 
 template <class CD, int EOS>
 hipError_t launch_adj_e(const AdjArgs& A, hipStream_t s) {
+    if (A.waves != 8) return hipErrorInvalidValue;
     switch (A.ty) {
-        case 8: return launch_adj_t<CD, EOS, 8, 8>(A, s);
-        case 16: return launch_adj_t<CD, EOS, 16, 8>(A, s);
+        case 4: return launch_adj_t<CD, EOS, 4, 8>(A, s);
+        case 12: return launch_adj_t<CD, EOS, 12, 8>(A, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// The forward step of the backward sweep's recompute: the tile step (8-row,
+// 4-wave tiles) that also writes the adjoint's fields of the step.
+template <class CD, int EOS>
+__global__ __launch_bounds__(256) void tile_save_kernel(const StepArgs a) {
+    tile_body<CD, EOS, false, 8, 4, true>(a, a.fin, a.fout, a.tau_w, a.p_w, a.dtau_w, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <class CD>
+hipError_t launch_save_c(const StepArgs& a, int eos, hipStream_t s) {
+    StepArgs b = a;
+    b.nstrip = (a.nx + kStripOut - 1) / kStripOut;
+    const dim3 grid(b.nstrip * ((a.ny + 7) / 8)), block(256);
+    if (eos == LBM_EOS_CS)
+        hipLaunchKernelGGL((tile_save_kernel<CD, LBM_EOS_CS>), grid, block, 0, s, b);
+    else
+        hipLaunchKernelGGL((tile_save_kernel<CD, LBM_EOS_PR>), grid, block, 0, s, b);
+    return hipGetLastError();
 }
 
 template <class CD>
@@ -526,6 +458,16 @@ hipError_t launch_adjoint(const AdjArgs& A, int storage, int eos, hipStream_t s)
         case LBM_F64: return launch_adj_c<CodecF64>(A, eos, s);
         case LBM_F32: return launch_adj_c<CodecF32>(A, eos, s);
         case LBM_F32D: return launch_adj_c<CodecF32D>(A, eos, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_save(const StepArgs& a, int storage, int eos, hipStream_t s) {
+    if (!a.save) return hipErrorInvalidValue;
+    switch (storage) {
+        case LBM_F64: return launch_save_c<CodecF64>(a, eos, s);
+        case LBM_F32: return launch_save_c<CodecF32>(a, eos, s);
+        case LBM_F32D: return launch_save_c<CodecF32D>(a, eos, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -304,10 +304,10 @@ struct lbm_ctx {
         char* dev = nullptr;
         bool bound = false, recorded = false, swept = false;
         int64_t n = 0, seg = 0, nckpt = 0;  // recorded steps, segment length, checkpoints
-        size_t state = 0, lam = 0;          // bytes of one state / one adjoint field (aligned)
-        size_t off_ckpt = 0, off_seg = 0, off_lam[2]{}, off_tw = 0, off_part = 0, off_red = 0, off_acc = 0,
-               off_pw = 0, off_g0 = 0, total = 0;
-        int blocks = 0, cur = 0, ty = 8, ring_cap = 0;
+        size_t state = 0, lam = 0, fld = 0;  // bytes of one state / adjoint field / step's forward fields (aligned)
+        size_t off_ckpt = 0, off_pp = 0, off_fld = 0, off_lam[2]{}, off_tw = 0, off_part = 0, off_red = 0,
+               off_acc = 0, off_pw = 0, off_g0 = 0, total = 0;
+        int blocks = 0, cur = 0, ty = 8, waves = 4, ring_cap = 0;
         double J = 0, seed = 1;
         hipGraphExec_t seg_graph[2] = {nullptr, nullptr};  // one full segment of the sweep, per adjoint parity
         void drop_graphs() {
@@ -319,10 +319,12 @@ struct lbm_ctx {
         Adjoint& operator=(const Adjoint& o) {  // layout only; the graphs belong to the bound workspace
             drop_graphs();
             dev = o.dev; bound = o.bound; recorded = o.recorded; swept = o.swept;
-            n = o.n; seg = o.seg; nckpt = o.nckpt; state = o.state; lam = o.lam;
-            off_ckpt = o.off_ckpt; off_seg = o.off_seg; off_lam[0] = o.off_lam[0]; off_lam[1] = o.off_lam[1];
+            n = o.n; seg = o.seg; nckpt = o.nckpt; state = o.state; lam = o.lam; fld = o.fld;
+            off_ckpt = o.off_ckpt; off_pp = o.off_pp; off_fld = o.off_fld;
+            off_lam[0] = o.off_lam[0]; off_lam[1] = o.off_lam[1];
             off_tw = o.off_tw; off_part = o.off_part; off_red = o.off_red; off_acc = o.off_acc; off_pw = o.off_pw;
-            off_g0 = o.off_g0; total = o.total; blocks = o.blocks; cur = o.cur; ty = o.ty; ring_cap = o.ring_cap;
+            off_g0 = o.off_g0; total = o.total; blocks = o.blocks; cur = o.cur; ty = o.ty; waves = o.waves;
+            ring_cap = o.ring_cap;
             J = o.J; seed = o.seed;
             return *this;
         }
@@ -1080,13 +1082,12 @@ constexpr int kAdjRing = 64;  // adjoint launches whose parameter partials are r
 
 size_t adjoint_arith_bytes(int storage) { return storage == LBM_F32 ? 4 : 8; }
 
-// Output rows per adjoint tile.  Measured: with FP32 arithmetic 8-row tiles at six
-// waves per SIMD are faster at every size (4096x512: 78 vs 88 us per step); with
-// FP64 arithmetic (three waves per SIMD) 8-row tiles win on the 1024x256 channel
-// (more blocks to fill the chip) and 16-row tiles on 4096x512 (less recomputed halo).
-int adjoint_tile_rows(const lbm_ctx* c) {
-    if (adjoint_arith_bytes(c->p.storage) == 4) return 8;
-    return (long long)c->nx * c->ny >= (1LL << 20) ? 16 : 8;
+// Adjoint tile: output rows and waves per block.  Measured on the 1024x256 and
+// 4096x512 channels (FP32 and FP64): 4-row tiles (one row per wave, the most
+// blocks) are fastest below 1M nodes, 12-row tiles (less halo) above.
+void adjoint_tile_shape(const lbm_ctx* c, int* ty, int* waves) {
+    *ty = (long long)c->nx * c->ny >= (1LL << 20) ? 12 : 4;
+    *waves = 8;
 }
 
 lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm_ctx::Adjoint& A) {
@@ -1095,15 +1096,18 @@ lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm
     A.n = nsteps;
     A.seg = segment > 0 ? segment : (int64_t)std::ceil(std::sqrt((double)nsteps));
     A.nckpt = (nsteps + A.seg - 1) / A.seg;
+    const size_t ab = adjoint_arith_bytes(c->p.storage);
     A.state = align256((size_t)c->plane * 9 * storage_bytes(c->p.storage));
     // adjoint fields are addressed with 32-bit byte offsets like the distributions
-    if ((unsigned long long)c->plane * 9 * adjoint_arith_bytes(c->p.storage) >= (1ULL << 32)) return LBM_EINVAL;
-    A.lam = align256((size_t)c->plane * 9 * adjoint_arith_bytes(c->p.storage));
-    A.ty = adjoint_tile_rows(c);
+    if ((unsigned long long)c->plane * 9 * ab >= (1ULL << 32)) return LBM_EINVAL;
+    A.lam = align256((size_t)c->plane * 9 * ab);
+    A.fld = align256((size_t)lbm::adjoint_field_elems(c->plane, c->nx) * ab);
+    adjoint_tile_shape(c, &A.ty, &A.waves);
     A.blocks = lbm::adjoint_blocks(c->nx, c->ny, A.ty);
     size_t o = 0;
     A.off_ckpt = o; o += (size_t)A.nckpt * A.state;
-    A.off_seg = o; o += (size_t)(A.seg + 1) * A.state;  // + the checkpoint copy a segment graph starts from
+    A.off_pp = o; o += 2 * A.state;               // the recompute's two states
+    A.off_fld = o; o += (size_t)A.seg * A.fld;    // forward fields of each step of a segment
     A.off_lam[0] = o; o += A.lam;
     A.off_lam[1] = o; o += A.lam;
     A.off_tw = o; o += align256((size_t)A.seg * 2 * c->nx * sizeof(double));
@@ -1175,16 +1179,12 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     if (!A.bound || !A.recorded) return fail(c, LBM_ESTATE, "lbm_adjoint_backward needs lbm_adjoint_forward first");
     const int storage = c->p.storage, eos = c->p.eos;
     lbm::StepArgs base = make_args(c);
-    // state after step k of segment ck: the checkpoint, or a recomputed state in the segment buffer
-    // (slot 0 of which holds a copy of the checkpoint when the segment runs as a captured graph)
-    auto state = [&](int64_t ck, int64_t start, int64_t k, bool copied) -> char* {
-        if (k == start && !copied) return A.dev + A.off_ckpt + (size_t)ck * A.state;
-        return A.dev + A.off_seg + (size_t)(k - start) * A.state;
-    };
     double* tw = reinterpret_cast<double*>(A.dev + A.off_tw);
     double* part = reinterpret_cast<double*>(A.dev + A.off_part);
     double* acc = reinterpret_cast<double*>(A.dev + A.off_acc);
     double* red = reinterpret_cast<double*>(A.dev + A.off_red);
+    auto pp = [&](int64_t i) { return A.dev + A.off_pp + (size_t)(i & 1) * A.state; };
+    auto fld = [&](int64_t i) { return A.dev + A.off_fld + (size_t)i * A.fld; };
     HIP_TRY(c, lbm::launch_fill(reinterpret_cast<double*>(A.dev + A.off_lam[0]), 0.0, (long long)(A.lam / 8), c->stream));
     HIP_TRY(c, lbm::launch_fill(acc, 0.0, 4, c->stream));
     A.cur = 0;
@@ -1195,29 +1195,29 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     aa.s = base;
     aa.nstrip = (c->nx + lbm::kAdjStripOut - 1) / lbm::kAdjStripOut;
     aa.ty = A.ty;
+    aa.waves = A.waves;
     int ring = 0;
-    // One segment: recompute its states, then the adjoint steps from its last step down.
-    // Launch j of 2 (end - start) + 1 (recomputes, adjoints, the final reduction when
-    // `reduce_at_end`); cur0 is the adjoint parity at the segment's start.
-    auto segment_launch = [&](int64_t ck, int64_t start, int64_t end, bool copied, int cur0, int ring0, int64_t j,
-                              hipStream_t s) -> hipError_t {
-        const int64_t len = end - start;
+    // One segment, its checkpoint copied to the first recompute state: launch j of
+    // 2 len + 1 recomputes step start + 1 + j (j < len), writing its forward fields
+    // to slot j, then runs the adjoint steps from the segment's last step down, then
+    // (with `reduce_at_end`) the reduction; cur0 is the adjoint parity at the start.
+    auto segment_launch = [&](int64_t len, int cur0, int ring0, int64_t j, hipStream_t s) -> hipError_t {
         if (j < len) {
-            const int64_t k = start + 1 + j;
             lbm::StepArgs b = fa;
-            b.fin = state(ck, start, k - 1, copied);
-            b.fout = state(ck, start, k, true);
-            b.tau_w = tw + (size_t)(k - start - 1) * 2 * c->nx;
-            return lbm::launch_step(b, storage, eos, false, s);
+            b.fin = pp(j);
+            b.fout = pp(j + 1);
+            b.save = fld(j);
+            b.tau_w = tw + (size_t)j * 2 * c->nx;
+            return lbm::launch_step_save(b, storage, eos, s);
         }
         if (j < 2 * len) {
-            const int64_t m = j - len, k = end - m;  // m-th adjoint launch of the segment
+            const int64_t m = j - len, i = len - 1 - m;  // m-th adjoint launch: step start + 1 + i
             const int par = (cur0 + (int)m) & 1;
             lbm::AdjArgs b = aa;
-            b.s.fin = state(ck, start, k - 1, copied);
+            b.fld = fld(i);
             b.lam_in = A.dev + A.off_lam[par];
             b.lam_out = A.dev + A.off_lam[1 - par];
-            b.tau_w = tw + (size_t)(k - start - 1) * 2 * c->nx;
+            b.tau_w = tw + (size_t)i * 2 * c->nx;
             b.partial = part + (size_t)(ring0 + m) * A.blocks * 4;
             return lbm::launch_adjoint(b, storage, eos, s);
         }
@@ -1225,18 +1225,18 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     };
     for (int64_t ck = A.nckpt - 1; ck >= 0; --ck) {
         const int64_t start = ck * A.seg, end = std::min(start + A.seg, A.n), len = end - start;
+        HIP_TRY(c, hipMemcpyAsync(pp(0), A.dev + A.off_ckpt + (size_t)ck * A.state, A.state, hipMemcpyDeviceToDevice,
+                                  c->stream));
         if (len == A.seg && c->graph_steps() > 0) {
-            // a full segment: copy its checkpoint to the segment buffer and replay the captured sweep
+            // a full segment: replay the captured sweep
             if (ring > 0) {
                 HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
                 ring = 0;
             }
-            HIP_TRY(c, hipMemcpyAsync(A.dev + A.off_seg, A.dev + A.off_ckpt + (size_t)ck * A.state, A.state,
-                                      hipMemcpyDeviceToDevice, c->stream));
             hipGraphExec_t& ge = A.seg_graph[A.cur];
             if (!ge) {
                 const int cur0 = A.cur;
-                auto launch = [&](int j, hipStream_t s) { return segment_launch(ck, start, end, true, cur0, 0, j, s); };
+                auto launch = [&](int j, hipStream_t s) { return segment_launch(len, cur0, 0, j, s); };
                 HIP_TRY(c, capture_graph(c->graphs, (int)(2 * len + 1), launch, &ge));
             }
             HIP_TRY(c, hipGraphLaunch(ge, c->stream));
@@ -1248,8 +1248,7 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
             HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
             ring = 0;
         }
-        for (int64_t j = 0; j < 2 * len; ++j)
-            HIP_TRY(c, segment_launch(ck, start, end, false, A.cur, ring, j, c->stream));
+        for (int64_t j = 0; j < 2 * len; ++j) HIP_TRY(c, segment_launch(len, A.cur, ring, j, c->stream));
         A.cur = (A.cur + (int)len) & 1;
         ring += (int)len;
     }

@@ -680,8 +680,9 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
 // (rows covered by two tiles are computed identically by both).
 // One tile of one lattice: `bid` is the tile index in tile-row-major order,
 // fin/fout the distribution buffers of this step and tau_w/p_w/dtau_w its wall
-// arrays (the kernels below pick them).
-template <class CD, int EOS, bool EMIT, int TYO, int NW>
+// arrays (the kernels below pick them).  SAVE also writes the forward fields
+// the adjoint of this step reads (a.save; layout of adjoint_field_elems).
+template <class CD, int EOS, bool EMIT, int TYO, int NW, bool SAVE = false>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, void* fout_v, double* tau_w,
                                           double* p_w, double* dtau_w, int bid) {
     using S = typename CD::S;
@@ -808,6 +809,20 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
                 a.rho_out[c] = double(rh);
                 a.vx_out[c] = double(vx);
                 a.vy_out[c] = double(vy);
+            }
+            if (SAVE) {
+                C* __restrict__ sv = static_cast<C*>(a.save);
+                const long long o = (long long)y * a.pitch + x;
+                const C inv = recip(rh), tau = LBM_COEF(C, tau);
+                sv[o] = rh;
+                sv[a.plane + o] = (jx + tau * Fx) * inv;
+                sv[2 * a.plane + o] = (jy + tau * Fy) * inv;
+                sv[3 * a.plane + o] = glx;
+                sv[4 * a.plane + o] = gly;
+                if (walls && (y <= 1 || y >= a.ny - 2)) {
+                    const int w = y <= 1 ? y : 3 - (a.ny - 1 - y);
+                    sv[5 * a.plane + (long long)w * a.nx + x] = vx;
+                }
             }
         }
         if (wall_tile) {

@@ -65,6 +65,7 @@ struct StepArgs {
     double* rho_out;          // emitted fields [ny][nx] (only read when emitting)
     double* vx_out;
     double* vy_out;
+    void* save;               // the adjoint's fields of this step (launch_step_save only)
 };
 
 hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s);
@@ -127,17 +128,29 @@ struct WallFlush {
 // they have stepped together, so nsteps and first_step are shared.
 hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, int64_t first_step, hipStream_t s);
 
-// Reverse-mode (adjoint) step (lbm_adjoint.hip).  Tiles of 64 columns give 56
-// outputs (a 4-column halo on each side) and ty output rows.
-constexpr int kAdjStripOut = 56;
+// Reverse-mode (adjoint) step (lbm_adjoint.hip).  Tiles of 64 columns give 60
+// outputs (a 2-column halo on each side) and ty output rows.
+constexpr int kAdjStripOut = 60;
+// Forward quantities of one step that its adjoint reads, written by the step
+// itself during the backward sweep's recompute (arithmetic type, planes of
+// `plane` elements at the distributions' row pitch): rho, u = (j + tau F)/rho
+// (two planes), grad lap rho (two planes); then the velocity shift
+// v_x = (j_x + F_x/2)/rho of the wall rows 0, 1, ny - 2, ny - 1 as 4 x nx.
+constexpr int kAdjFieldPlanes = 5;
+inline long long adjoint_field_elems(long long plane, int nx) { return kAdjFieldPlanes * plane + 4LL * nx; }
+// One step of the tile schedule (fixed 8-row, 4-wave tiles) that also writes
+// the adjoint's fields of the step to a.save.  F64, F32 and F32D storage.
+hipError_t launch_step_save(const StepArgs& a, int storage, int eos, hipStream_t s);
 struct AdjArgs {
-    StepArgs s;            // the step's coefficients; s.fin is the state the step started from
+    StepArgs s;            // the step's coefficients and geometry
+    const void* fld;       // the step's forward fields (layout above)
     const void* lam_in;    // dJ/df of the next step's pulled populations [9][ny][pitch] (arithmetic type)
     void* lam_out;         // the same for this step
     const double* tau_w;   // [2][nx] this step's wall shear (from its forward recompute)
     double* partial;       // [blocks][4]: sum F~_x, sum phi~ dphi/dRT, dphi/da_eff, dphi/db
-    int nstrip;            // 56-column strips
-    int ty;                // output rows per tile: 8 or 16
+    int nstrip;            // 60-column strips
+    int ty;                // output rows per tile (adjoint_tile_shape)
+    int waves;             // waves per tile block
 };
 hipError_t launch_adjoint(const AdjArgs& A, int storage, int eos, hipStream_t s);
 // acc[0..3] += the parameter sums of `launches` consecutive adjoint launches

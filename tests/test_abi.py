@@ -148,8 +148,9 @@ def test_batch_create_validates_cases(L):
 
 
 def test_adjoint_workspace_layout_and_rules(L):
-    """Host-side arithmetic of the adjoint workspace (no device needed): ceil(N/S) checkpoints plus S + 1 segment
-    states, two adjoint fields, the recomputed wall shears, the per-launch partials and the FP64 state gradient."""
+    """Host-side arithmetic of the adjoint workspace (no device needed): ceil(N/S) checkpoints, the recompute's two
+    states, S steps of forward fields (five planes and four wall rows of the arithmetic type), two adjoint fields,
+    the recomputed wall shears, the per-launch partials and the FP64 state gradient."""
     def align(v):
         return (v + 255) // 256 * 256
 
@@ -161,9 +162,10 @@ def test_adjoint_workspace_layout_and_rules(L):
             s = seg or math.ceil(math.sqrt(n))
             k = (n + s - 1) // s
             ty = 8
-            blocks = ((nx + 55) // 56) * ((ny + ty - 1) // ty)
+            blocks = ((nx + 59) // 60) * ((ny + ty - 1) // ty)
             ring = max(s, 64)
-            want = (k * align(pitch * ny * 9 * sb) + (s + 1) * align(pitch * ny * 9 * sb) + 2 * align(pitch * ny * 9 * ab)
+            want = (k * align(pitch * ny * 9 * sb) + 2 * align(pitch * ny * 9 * sb)
+                    + s * align((5 * pitch * ny + 4 * nx) * ab) + 2 * align(pitch * ny * 9 * ab)
                     + align(s * 2 * nx * 8) + align(ring * blocks * 4 * 8) + align(ring * 4 * 8) + 256
                     + align(4 * nx * 8) + align(9 * nx * ny * 8))
             assert L.lbm_adjoint_workspace(ctx, n, seg) == want, (storage, n, seg)

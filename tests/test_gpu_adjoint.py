@@ -161,8 +161,41 @@ def test_adjoint_api_rules():
     assert np.array_equal(g2, -2.0 * g1)
 
 
-def test_large_grid_16_row_tiles_equal_tangent():
-    """Grids of 1M nodes and more take the 16-row adjoint tiles: same check against the tangents."""
+@pytest.mark.parametrize("xper", [0, 1])
+def test_ragged_tiles_equal_tangent(xper):
+    """42 rows are not a multiple of the 4-row adjoint tiles and 100 columns leave a part strip: the last tile row
+    overlaps the one before it, whose rows must enter the parameter sums once."""
+    cfg = dict(CS)
+    P = Problem(cfg, nx=100, ny=42, steps=120)
+
+    def make(storage):
+        lat = Lattice(P.nx, P.ny, cfg["tau"], storage=storage, x_periodic=xper, a=cfg["a"], b=cfg["b"], dp=cfg["dp"],
+                      k=cfg["k"], kappa=cfg["kappa"], T_over_Tc=cfg["Tr"], rho_wall=P.rho_w, v_limit=1.0,
+                      check_every=10 ** 6)
+        return lat
+
+    lat = make("f64")
+    lat.init_density(P.rho_init)
+    lat.adjoint_bind(P.steps, 11)
+    st, J = lat.adjoint_forward()
+    assert st == 0
+    grad = lat.adjoint_backward()
+    for k in (0, 1, 2, 3):
+        tl = make("f64t")
+        e = [0.0] * 4
+        e[k] = 1.0
+        tl.set_tangent(*e)
+        tl.init_density(P.rho_init)
+        assert tl.step(P.steps) == 0
+        h = tl.history(1)[-1]
+        log(f"ragged xper {xper} dJ/d{NAMES[k]}: adjoint {grad[k]:.12e} tangent {h['d_int_tau2']:.12e}")
+        assert h["int_tau2"] == pytest.approx(J, rel=1e-12)
+        assert grad[k] == pytest.approx(h["d_int_tau2"], rel=1e-9)
+
+
+def test_large_grid_12_row_tiles_equal_tangent():
+    """Grids of 1M nodes and more take the 12-row adjoint tiles (512 rows: the last tile overlaps): same check
+    against the tangents."""
     nx, ny, steps = 2048, 512, 24
     kw = dict(T_over_Tc=0.9, dp=1e-3, v_limit=1.0, check_every=10 ** 6, rho_wall=0.3)
     lat = Lattice(nx, ny, 1.0, storage="f64", **kw)
