@@ -161,7 +161,7 @@ def test_adjoint_workspace_layout_and_rules(L):
         for n, seg in ((1000, 0), (1000, 10), (7, 7), (1, 1)):
             s = seg or math.ceil(math.sqrt(n))
             k = (n + s - 1) // s
-            ty = 8
+            ty = 4  # adjoint tile rows below 1M nodes
             blocks = ((nx + 59) // 60) * ((ny + ty - 1) // ty)
             ring = max(s, 64)
             want = (k * align(pitch * ny * 9 * sb) + 2 * align(pitch * ny * 9 * sb)
