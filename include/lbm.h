@@ -234,9 +234,11 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int trial_steps, int* tile_rows, int* tile
 
    Memory: nsteps steps are recorded with one checkpoint of the state every
    `segment` steps (0 picks ceil(sqrt(nsteps))); the backward sweep recomputes
-   each segment's states from its checkpoint.  The adjoint workspace holds
-   ceil(nsteps/segment) + segment states, two adjoint fields of the arithmetic
-   type, segment x 2 x nx FP64 wall shears and small scratch; it is
+   each segment from its checkpoint, storing per step the forward fields the
+   adjoint step reads.  The adjoint workspace holds ceil(nsteps/segment) + 2
+   states, segment x (5 x ny x pitch + 4 x nx) values and two adjoint fields
+   (9 x ny x pitch) of the arithmetic type, segment x 2 x nx FP64 wall shears
+   and small scratch; it is
    caller-owned device memory like the main workspace, 256-byte aligned, and
    bound once.  Storage F64, F32 or F32D with the tile schedule; otherwise
    LBM_EINVAL. */
