@@ -68,9 +68,17 @@ typedef enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 } lbm_eos_kind;
    and its FP64 tangent along a direction of the parameters (lbm_set_tangent):
    the step then runs in tangent-linear arithmetic and the wall summaries carry
    the derivative of the squared wall shear (forward-mode sensitivities).  F64T
-   runs on the tile schedule with 12-row, 8-wave tiles, CS or PR. */
+   runs on the tile schedule with 12-row, 8-wave tiles, CS or PR.
+   F16R: f_i - w_i rho0_shift in FP16 with stochastic rounding, FP32
+   arithmetic: each stored value rounds up or down to a neighbouring FP16 value
+   with probabilities that make the expected rounding error zero, the random
+   bits coming from an integer hash of (step counter, node, direction), so runs
+   are reproducible.  Round-to-nearest FP16 storage (F16S) repeats the same
+   error every step where the populations are steady, which acts as a mass
+   source; F16R averages it out.  Tile schedule (one step per launch) and
+   batches; no adjoint. */
 typedef enum {
-    LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_F32D = 4, LBM_F32S = 5, LBM_F64T = 6
+    LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_F32D = 4, LBM_F32S = 5, LBM_F64T = 6, LBM_F16R = 7
 } lbm_storage;
 
 typedef struct {

@@ -431,7 +431,8 @@ hipError_t launch_adj_e(const AdjArgs& A, hipStream_t s) {
 // 4-wave tiles) that also writes the adjoint's fields of the step.
 template <class CD, int EOS>
 __global__ __launch_bounds__(256) void tile_save_kernel(const StepArgs a) {
-    tile_body<CD, EOS, false, 8, 4, true>(a, a.fin, a.fout, a.tau_w, a.p_w, a.dtau_w, xcd_remap(blockIdx.x, gridDim.x));
+    tile_body<CD, EOS, false, 8, 4, true>(a, a.fin, a.fout, a.tau_w, a.p_w, a.dtau_w, xcd_remap(blockIdx.x, gridDim.x),
+                                          0);
 }
 
 template <class CD>

@@ -224,6 +224,7 @@ bool schedule_ok(const lbm_params* p) {
     const int r = p->tile_rows, w = p->tile_waves;
     if (w != 0 && w != 4 && w != 8) return false;
     if (p->pipe_blocks != 0 && (p->schedule != lbm::kSchedulePipe || p->pipe_blocks < 8)) return false;
+    if (p->storage == LBM_F16R && p->schedule != lbm::kScheduleTile) return false;  // stochastic rounding: tiles only
     if (p->storage == LBM_F64T)  // tangent-linear runs: the tile schedule with 12-row, 8-wave tiles
         return p->schedule == lbm::kScheduleTile && (r == 0 || r == 12) && (w == 0 || w == 8);
     switch (p->schedule) {
@@ -292,7 +293,7 @@ struct lbm_ctx {
     // workspace layout (byte offsets)
     size_t off_f[2]{}, off_rho = 0, off_vx = 0, off_vy = 0, off_ring = 0, off_hist = 0,
            off_acc = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, off_tickets = 0,
-           total = 0;
+           off_sr = 0, total = 0;
     char* dev = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -380,6 +381,7 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     for (int q = 0; q < 4; ++q)  // running maxima start at -inf, minima at +inf
         HIP_TRY(c, lbm::launch_fill(acc + 2 + 2 * q, (q % 2 == 0) ? -INFINITY : INFINITY, 2, c->stream));
     HIP_TRY(c, lbm::launch_fill(acc + 10, 0.0, 1, c->stream));  // tangent of the sum-of-squares integral
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_sr), 0.0, 1, c->stream));  // stochastic-rounding step counters
     c->steps = 0;
     c->ring_fill = 0;
     c->last_slot = -1;
@@ -524,6 +526,8 @@ lbm::StepArgs make_args(const lbm_ctx* c) {
     }
     a.tickets = c->at<unsigned long long>(c->off_tickets);
     a.pipe_blocks = c->pipe_blocks;
+    a.sr = c->at<uint32_t>(c->off_sr);
+    a.sr_par = c->cur;
     return a;
 }
 
@@ -572,10 +576,10 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
         !std::isfinite(p->T_over_Tc) || !(p->k > 0) || !(p->kappa >= 0) || !rate_ok(p->s_e) || !rate_ok(p->s_eps) ||
         !rate_ok(p->s_q) || !(p->s_j <= 0 || rate_ok(p->s_j)) || !std::isfinite(p->dp) || p->check_every < 1 ||
         !(p->v_limit > 0) || p->history_cap < 1 || (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) ||
-        p->storage < LBM_F64 || p->storage > LBM_F64T || (p->x_periodic != 0 && p->x_periodic != 1) ||
+        p->storage < LBM_F64 || p->storage > LBM_F16R || (p->x_periodic != 0 && p->x_periodic != 1) ||
         (p->y_periodic != 0 && p->y_periodic != 1) || !std::isfinite(p->omega) ||
         (!std::isnan(p->rho_wall) && !(p->rho_wall > 0)) || !schedule_ok(p) || !graph_steps_ok(p->graph_steps) ||
-        p->fused_steps < 0 || p->fused_steps > 2)
+        p->fused_steps < 0 || p->fused_steps > 2 || (p->storage == LBM_F16R && p->fused_steps == 2))
         return LBM_EINVAL;
     const int pitch = (nx + 63) / 64 * 64;
     // the step kernel addresses a distribution buffer with 32-bit byte offsets
@@ -637,6 +641,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->off_colmin = o; o += align256((size_t)nx * sizeof(double));
     c->off_centre = o; o += align256((size_t)nx * sizeof(double));
     c->off_tickets = o; o += (size_t)lbm::kTicketGroups * lbm::kTicketStride * sizeof(unsigned long long);
+    c->off_sr = o; o += 256;
     c->total = o;
     c->check.rupture_step = -1;
     c->check.unstable_step = -1;
@@ -741,6 +746,7 @@ lbm_status step_impl(lbm_ctx* c, int64_t n, bool finish) {
     auto launch_k = [&](lbm::StepArgs& b, int in, int slot, int nsteps, bool emit, hipStream_t s) {
         b.fin = c->dev + c->off_f[in];
         b.fout = c->dev + c->off_f[1 - in];
+        b.sr_par = in;
         set_wall_slot(b, c, slot);
         return nsteps == 2 ? lbm::launch_step2(b, c->p.storage, c->p.eos, emit, s)
                            : lbm::launch_step(b, c->p.storage, c->p.eos, emit, s);
@@ -901,7 +907,8 @@ lbm_status lbm_get_f(lbm_ctx* c, double* f) {
                     case LBM_F32:
                     case LBM_F32D: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = t; break; }
                     case LBM_F32S: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = (double)std::fmaf(host_weight(i), r0, t); break; }
-                    case LBM_F16S: {
+                    case LBM_F16S:
+                    case LBM_F16R: {
                         _Float16 h;
                         std::memcpy(&h, raw.data() + src * 2, 2);
                         v = (double)std::fmaf(host_weight(i), r0, (float)h);
@@ -938,7 +945,8 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
                     case LBM_F32:
                     case LBM_F32D: { const float t = (float)v; std::memcpy(raw.data() + dst * 4, &t, 4); break; }
                     case LBM_F32S: { const float t = std::fmaf(-host_weight(i), r0, (float)v); std::memcpy(raw.data() + dst * 4, &t, 4); break; }
-                    case LBM_F16S: {
+                    case LBM_F16S:
+                    case LBM_F16R: {
                         const _Float16 h = (_Float16)std::fmaf(-host_weight(i), r0, (float)v);
                         std::memcpy(raw.data() + dst * 2, &h, 2);
                         break;

@@ -132,6 +132,54 @@ struct CodecF16S {
     __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
 };
 
+// Integer hash of 32 bits (Wellons' "lowbias32" from his hash-prospector search:
+// two xorshift-multiply rounds and a final xorshift).
+__device__ inline uint32_t hash32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Stochastic rounding of v to FP16 by dithering: with s the FP16 spacing at |v|
+// (2^-24 below 2^-14), v + D, D = ((2r + 1)/2048 - 1/2) s for 10 uniform random
+// bits r, is rounded to nearest.  When v lies a fraction t of the way from one
+// FP16 neighbour to the next, the result is the upper one for a fraction of the
+// 1024 values of r within 1/2048 of t, so the expected rounding error is zero to
+// within s/2048 (over 10^5 steps a steady value gathers at most ~50 s of bias,
+// against ~160 s of random walk).  v + D is exact in FP32: D is a multiple of
+// s/2048, coarser than the FP32 spacing at v.
+__device__ inline _Float16 f16_stochastic(float v, uint32_t r) {
+    int e = int((__float_as_uint(v) >> 23) & 0xffu) - 127;  // 2^e <= |v| < 2^(e+1); 0 and FP32 subnormals: -127
+    e = e < -14 ? -14 : e;
+    const float d = __builtin_ldexpf(float(int(2u * r) - 1023), e - 10 - 11);
+    return static_cast<_Float16>(v + d);
+}
+
+// 10 random bits for population I: bits 10 (I mod 3) .. of word I / 3.
+template <int I>
+__device__ inline uint32_t sr_bits(const uint32_t (&h)[3]) {
+    return (h[I / 3] >> (10 * (I % 3))) & 1023u;
+}
+
+// FP16 storage of f_i - w_i rho0 with stochastic rounding (the step kernel
+// passes the random bits).  Round-to-nearest repeats the same error every step
+// wherever the populations are steady, which adds up to a mass source; rounding
+// up or down at random makes the errors average out instead.  encode (used by
+// the initialisation) rounds to nearest.
+struct CodecF16R : CodecF16S {
+    template <int I>
+    __device__ static S encode_sr(C v, C rho0, uint32_t r) {
+        return f16_stochastic(__builtin_fmaf(-wgt<float>(I), rho0, v), r);
+    }
+};
+template <class CD>
+constexpr bool stochastic_codec() { return false; }
+template <>
+constexpr bool stochastic_codec<CodecF16R>() { return true; }
+
 // BF16 storage of f_i - w_i rho0, FP32 arithmetic, round-to-nearest-even.
 struct CodecBF16S {
     using S = uint16_t;
@@ -682,9 +730,10 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
 // fin/fout the distribution buffers of this step and tau_w/p_w/dtau_w its wall
 // arrays (the kernels below pick them).  SAVE also writes the forward fields
 // the adjoint of this step reads (a.save; layout of adjoint_field_elems).
+// par is the step-counter parity of stochastic-rounding storage (unused otherwise).
 template <class CD, int EOS, bool EMIT, int TYO, int NW, bool SAVE = false>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, void* fout_v, double* tau_w,
-                                          double* p_w, double* dtau_w, int bid) {
+                                          double* p_w, double* dtau_w, int bid, int par) {
     using S = typename CD::S;
     using C = typename CD::C;
     constexpr int H = TYO + 4;    // tile rows including the halo
@@ -720,6 +769,14 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
     const C RT = LBM_COEF(C, RT), a_eff = LBM_COEF(C, a_eff), bb = LBM_COEF(C, b);
     const C k2 = LBM_COEF(C, k2), kappa = LBM_COEF(C, kappa), g = LBM_COEF(C, g);
     const C rho_w = LBM_COEF(C, rho_w);
+    // stochastic rounding: this step's counter seeds the random bits of every store;
+    // one lane advances the counter of the next step (read by no block of this launch)
+    uint32_t sr_seed = 0;
+    if constexpr (stochastic_codec<CD>()) {
+        const uint32_t step = a.sr[par];
+        if (bid == 0 && threadIdx.x == 0) a.sr[1 - par] = step + 1u;
+        sr_seed = hash32(step * 0x9e3779b9u + 0x632be5abu);
+    }
 
     // ---- phase A: pull, density, EOS field -------------------------------------
     C f[RPT][9];
@@ -800,10 +857,25 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
                    LBM_COEF(C, s_q), LBM_COEF(C, s_j), LBM_COEF(C, s_v), vx, vy);
         if (out_lane) {
             const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
+            if constexpr (stochastic_codec<CD>()) {
+                // 96 random bits per node and step: three hashes of (node, step), 10 bits per
+                // population.  (Deriving two of the words from the first by xorshift steps
+                // leaves only 32 bits of entropy per node; measured on the periodic plug
+                // channel, its interfaces lag the FP64 ones by 1.3-1.7 lattice units after
+                // 20000 steps against 0.9-1.4 with three hashes.)
+                const uint32_t nd = uint32_t(y * a.pitch + x) * 3u;
+                const uint32_t h[3] = {hash32(sr_seed ^ nd), hash32(sr_seed ^ (nd + 1u)), hash32(sr_seed ^ (nd + 2u))};
+#define LBM_SSTORE(I) \
+    buffer_store(CD::template encode_sr<I>(f[j][I], rho0, sr_bits<I>(h)), rout, o, uint32_t(I) * plane_bytes);
+                LBM_SSTORE(0) LBM_SSTORE(1) LBM_SSTORE(2) LBM_SSTORE(3) LBM_SSTORE(4) LBM_SSTORE(5) LBM_SSTORE(6)
+                LBM_SSTORE(7) LBM_SSTORE(8)
+#undef LBM_SSTORE
+            } else {
 #define LBM_TSTORE(I) buffer_store(CD::template encode<I>(f[j][I], rho0), rout, o, uint32_t(I) * plane_bytes);
-            LBM_TSTORE(0) LBM_TSTORE(1) LBM_TSTORE(2) LBM_TSTORE(3) LBM_TSTORE(4) LBM_TSTORE(5) LBM_TSTORE(6)
-            LBM_TSTORE(7) LBM_TSTORE(8)
+                LBM_TSTORE(0) LBM_TSTORE(1) LBM_TSTORE(2) LBM_TSTORE(3) LBM_TSTORE(4) LBM_TSTORE(5) LBM_TSTORE(6)
+                LBM_TSTORE(7) LBM_TSTORE(8)
 #undef LBM_TSTORE
+            }
             if (EMIT) {
                 const long long c = (long long)y * a.nx + x;
                 a.rho_out[c] = double(rh);
@@ -864,7 +936,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
 
 template <class CD, int EOS, bool EMIT, int TYO, int NW>
 __global__ __launch_bounds__(64 * NW) void tile_kernel(const StepArgs a) {
-    tile_body<CD, EOS, EMIT, TYO, NW>(a, a.fin, a.fout, a.tau_w, a.p_w, a.dtau_w, xcd_remap(blockIdx.x, gridDim.x));
+    tile_body<CD, EOS, EMIT, TYO, NW>(a, a.fin, a.fout, a.tau_w, a.p_w, a.dtau_w, xcd_remap(blockIdx.x, gridDim.x),
+                                      a.sr_par);
 }
 
 // Many lattices in one launch: the tiles of case c are blocks
@@ -886,7 +959,7 @@ __global__ __launch_bounds__(64 * NW) void tile_batch_kernel(const StepArgs* __r
     const void* fin = parity ? a.fout : a.fin;
     void* fout = parity ? const_cast<void*>(a.fin) : a.fout;
     double* w = a.ring + (long long)slot * kWallSlotVals * a.nx;
-    tile_body<CD, EOS, EMIT, TYO, NW>(a, fin, fout, w, w + 2 * a.nx, w + 4 * a.nx, bid - tile_start[lo]);
+    tile_body<CD, EOS, EMIT, TYO, NW>(a, fin, fout, w, w + 2 * a.nx, w + 4 * a.nx, bid - tile_start[lo], parity);
 }
 
 // ---------------------------------------------------------------------------

@@ -66,6 +66,8 @@ struct StepArgs {
     double* vx_out;
     double* vy_out;
     void* save;               // the adjoint's fields of this step (launch_step_save only)
+    uint32_t* sr;             // F16R: two step counters; a launch reads sr[sr_par] and writes sr[1 - sr_par]
+    int sr_par;               // (batch launches take the parity from their own argument)
 };
 
 hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s);
@@ -86,6 +88,11 @@ LBM_DECLARE_STORAGE_LAUNCHERS(f32d)
 LBM_DECLARE_STORAGE_LAUNCHERS(f32s)
 #undef LBM_DECLARE_STORAGE_LAUNCHERS
 hipError_t launch_step_f64t(const StepArgs& a, int eos, bool emit, hipStream_t s);
+// FP16 storage with stochastic rounding (lbm_step_f16r.hip): the tile schedule
+// and batches only.
+hipError_t launch_step_f16r(const StepArgs& a, int eos, bool emit, hipStream_t s);
+hipError_t launch_batch_f16r(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                             int slot, int eos, int ty, int waves, bool emit, hipStream_t s);
 // Two steps in one launch (temporal blocking, the tile schedule's two-step kernel):
 // reads a.fin, writes a.fout after two steps; the wall arrays of the first step
 // go to a.tau_w/p_w/dtau_w and those of the second kWallSlotVals * nx further on.

@@ -292,6 +292,7 @@ hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipSt
         case LBM_F32D: return launch_step_f32d(a, eos, emit, s);
         case LBM_F32S: return launch_step_f32s(a, eos, emit, s);
         case LBM_F64T: return launch_step_f64t(a, eos, emit, s);
+        case LBM_F16R: return launch_step_f16r(a, eos, emit, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -306,6 +307,7 @@ hipError_t launch_step_batch(const StepArgs* cases, const int* tile_start, int n
         case LBM_BF16S: return launch_batch_bf16s(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
         case LBM_F32D: return launch_batch_f32d(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
         case LBM_F32S: return launch_batch_f32s(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
+        case LBM_F16R: return launch_batch_f16r(cases, tile_start, ncases, total_tiles, parity, slot, eos, ty, waves, emit, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -334,6 +336,7 @@ hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, lo
         case LBM_F32D: hipLaunchKernelGGL(init_kernel<CodecF32D>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
         case LBM_F32S: hipLaunchKernelGGL(init_kernel<CodecF32S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
         case LBM_F64T: hipLaunchKernelGGL(init_kernel<CodecF64T>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        case LBM_F16R: hipLaunchKernelGGL(init_kernel<CodecF16R>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_EOS_CS, LBM_EOS_PR = 0, 1
-LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F32D, LBM_F32S, LBM_F64T = 0, 1, 2, 3, 4, 5, 6
+LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F32D, LBM_F32S, LBM_F64T, LBM_F16R = 0, 1, 2, 3, 4, 5, 6, 7
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S, "f32d": LBM_F32D,
-           "f32s": LBM_F32S, "f64t": LBM_F64T}
+           "f32s": LBM_F32S, "f64t": LBM_F64T, "f16r": LBM_F16R}
 
 EXPORTED = [
     "lbm_params_default", "lbm_create", "lbm_workspace", "lbm_bind", "lbm_state", "lbm_init_plug",

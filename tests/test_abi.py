@@ -76,7 +76,7 @@ def test_defaults(L):
 
 @pytest.mark.parametrize("bad", [
     dict(T_over_Tc=0.0), dict(a=-1.0), dict(b=0.0), dict(k=0.0), dict(kappa=-1.0), dict(s_e=2.0),
-    dict(s_q=0.0), dict(check_every=0), dict(v_limit=0.0), dict(history_cap=0), dict(storage=7),
+    dict(s_q=0.0), dict(check_every=0), dict(v_limit=0.0), dict(history_cap=0), dict(storage=8),
     dict(eos=3), dict(x_periodic=2), dict(rho_wall=-1.0), dict(dp=math.inf), dict(tile_waves=6),
     dict(tile_waves=8, tile_rows=8), dict(schedule=0, tile_rows=16), dict(schedule=3), dict(schedule=2, tile_rows=20),
     dict(schedule=2, tile_waves=8, tile_rows=12), dict(schedule=2, pipe_blocks=4), dict(pipe_blocks=64),
@@ -173,8 +173,8 @@ def test_adjoint_workspace_layout_and_rules(L):
             with pytest.raises(L.LbmError):
                 L.lbm_adjoint_workspace(ctx, n, seg)
         L.lbm_destroy(ctx)
-    for bad in (dict(storage="f16s"), dict(storage="bf16s"), dict(storage="f64t"), dict(schedule=1),
-                dict(schedule=2)):
+    for bad in (dict(storage="f16s"), dict(storage="bf16s"), dict(storage="f64t"), dict(storage="f16r"),
+                dict(schedule=1), dict(schedule=2)):
         ctx = L.lbm_create(nx, ny, 1.0, L.lbm_params_default(**bad))
         with pytest.raises(L.LbmError):
             L.lbm_adjoint_workspace(ctx, 100, 0)
@@ -193,3 +193,13 @@ def test_calls_before_binding_the_adjoint_are_rejected(L):
     assert L.library().lbm_autotune(ctx, 10, None, None, None) == L.LBM_ESTATE
     assert L.library().lbm_adjoint_backward(ctx, math.nan, g) == L.LBM_EINVAL
     L.lbm_destroy(ctx)
+
+
+def test_stochastic_fp16_storage_rules(L):
+    """F16R runs on the tile schedule with one step per launch; other schedules and two-step launches are refused."""
+    ctx = L.lbm_create(64, 16, 1.0, L.lbm_params_default(storage="f16r"))
+    assert L.lbm_workspace(ctx) > 2 * 9 * 64 * 16 * 2
+    L.lbm_destroy(ctx)
+    for bad in (dict(schedule=1), dict(schedule=2), dict(fused_steps=2)):
+        with pytest.raises(L.LbmError):
+            L.lbm_create(64, 16, 1.0, L.lbm_params_default(storage="f16r", **bad))

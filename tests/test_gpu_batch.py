@@ -53,7 +53,7 @@ def plug(case):
 
 
 @pytest.mark.parametrize("check_every", [50, 300])  # 300: captured graphs and several wall-ring flushes
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16r"])
 def test_batch_matches_single_runs_bitwise(storage, check_every):
     # the long run leaves out the rho_wall = 0.2 case, which goes unstable after 200 steps (oracle too)
     cases = CASES if check_every == 50 else [c for i, c in enumerate(CASES) if i != 4]

@@ -34,7 +34,7 @@ CALLS = [1, 70, 3, 300, 129, 64, 65, 400]  # odd ring offsets, both parities, fl
 
 
 @pytest.mark.parametrize("storage,schedule,tile_rows", [("f64", 0, 12), ("f32", 0, 8), ("f32", 1, 16),
-                                                        ("f16s", 0, 8)])
+                                                        ("f16s", 0, 8), ("f16r", 0, 8)])
 @pytest.mark.parametrize("graph_steps", [0, 16, 2, 256])
 def test_graph_replays_equal_direct_launches(storage, schedule, tile_rows, graph_steps):
     ref = run(-1, storage, schedule, tile_rows, CALLS)
