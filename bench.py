@@ -482,13 +482,16 @@ def main() -> int:
                     "x_rear": chk["x_rear"], "x_front": chk["x_front"], "wall_tau_peak_last_step": peak},
     }
     if not args.no_variants and args.workload == "large-stable":
-        wh = make("f16s")
-        hs, _, hl = time_steps(wh, args.steps, args.warmup)
-        hc = hl.check()
-        out["fp16_store"] = {"value": round(nodes * args.steps / hs / 1e6, 1), "unit": "MLUPS",
-                             "roofline_frac": round(36 * nodes / (hs / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
-                             "x_rear": hc["x_rear"], "x_front": hc["x_front"], "unstable_step": hc["unstable_step"]}
-        log(f"fp16 store: {out['fp16_store']}")
+        for key, st in (("fp16_store", "f16s"), ("fp16_store_stochastic", "f16r")):
+            wh = make(st)
+            hs, _, hl = time_steps(wh, args.steps, args.warmup)
+            hc = hl.check()
+            out[key] = {"value": round(nodes * args.steps / hs / 1e6, 1), "unit": "MLUPS",
+                        "roofline_frac": round(36 * nodes / (hs / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+                        "x_rear": hc["x_rear"], "x_front": hc["x_front"], "liquid_columns": hc["liquid_columns"],
+                        "unstable_step": hc["unstable_step"]}
+            log(f"{key}: {out[key]}")
+            del wh, hl
         lit = workloads.plug_large(args.storage)
         ll = make_lattice(lit, check_every=50)
         ll.step(400)
