@@ -207,6 +207,11 @@ lbm_status lbm_step_count(const lbm_ctx* ctx, int64_t* steps);
    host arrays [ny][nx] (FP64).  Any pointer may be NULL. */
 lbm_status lbm_fields(lbm_ctx* ctx, double* rho, double* vx, double* vy);
 
+/* The fields of lbm_fields copied to caller-owned device arrays [ny][nx] on the
+   bound stream (asynchronously; e.g. torch tensors): FP64 when fp64 != 0, else
+   FP32 (rounded to nearest).  Any pointer may be NULL. */
+lbm_status lbm_fields_device(lbm_ctx* ctx, void* rho, void* vx, void* vy, int fp64);
+
 /* Wall shear stress and wall pressure of the last step along both walls
    (host arrays of nx doubles, any may be NULL) and that step's summary
    (may be NULL).  Before the first step they are zero. */
@@ -337,6 +342,22 @@ lbm_status lbm_get_f(lbm_ctx* ctx, double* f);
 lbm_status lbm_set_f(lbm_ctx* ctx, const double* f);
 
 /* Frees a context (a no-op for a context owned by a batch). */
+/* Checkpoint and resume (a run split over jobs, as the 100000-step runs of
+   Sec. 3 may need).  lbm_save writes the current distributions, the step
+   count, the latest check, the fields of the last step, the wall-stress time
+   integrals and running extremes (after flushing the pending steps), the F16R
+   step counter and the F64T tangent direction to `path`, with an FNV-1a hash
+   of the content.  lbm_load reads such a file into a bound context created
+   with the same nx, ny, tau and parameters (else LBM_EINVAL, also for a
+   missing, short or corrupt file) and continues from there: stepping the
+   loaded context gives bit for bit the states, checks and time integrals the
+   saved run would have given.  Not kept: the per-step history and the wall
+   arrays of the saved steps (the history restarts with the next step; the wall
+   arrays read zero until then) and any adjoint record.  Batch cases are not
+   saved or loaded on their own (LBM_ESTATE).  Both block until done. */
+lbm_status lbm_save(lbm_ctx* ctx, const char* path);
+lbm_status lbm_load(lbm_ctx* ctx, const char* path);
+
 void lbm_destroy(lbm_ctx* ctx);
 const char* lbm_last_error(const lbm_ctx* ctx);
 

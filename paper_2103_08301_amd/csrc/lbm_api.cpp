@@ -336,6 +336,7 @@ struct lbm_ctx {
     int ring_fill = 0;
     int last_slot = -1;  // wall-ring slot of the latest step (its wall arrays)
     int64_t ring_first_step = 1;
+    int64_t hist_first = 1;  // first step whose summary is in the history ring (after lbm_load: the next step)
     lbm_check_result check{};
     std::string err;
     StepGraphs graphs;  // captured step loops (invalidated when the launch arguments change)
@@ -386,6 +387,7 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     c->ring_fill = 0;
     c->last_slot = -1;
     c->ring_first_step = 1;
+    c->hist_first = 1;
     c->check = lbm_check_result{};
     c->check.rupture_step = -1;
     c->check.unstable_step = -1;
@@ -850,7 +852,7 @@ lbm_status lbm_wall_stress(lbm_ctx* c, double* tau_bot, double* tau_top, double*
     }
     if (s) {
         std::memset(s, 0, sizeof *s);
-        if (c->steps > 0 && !c->p.y_periodic) {
+        if (c->steps >= c->hist_first && !c->p.y_periodic) {
             const size_t idx = (size_t)((c->steps - 1) % c->p.history_cap);
             HIP_TRY(c, hipMemcpyAsync(s, c->dev + c->off_hist + idx * sizeof(lbm_stress_summary),
                                       sizeof(lbm_stress_summary), hipMemcpyDeviceToHost, c->stream));
@@ -863,7 +865,7 @@ lbm_status lbm_wall_stress(lbm_ctx* c, double* tau_bot, double* tau_top, double*
 lbm_status lbm_stress_history(lbm_ctx* c, lbm_stress_summary* buf, int64_t cap, int64_t* n_out) {
     if (!c || !n_out || cap < 0 || (cap > 0 && !buf)) return LBM_EINVAL;
     if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
-    const int64_t have = c->p.y_periodic ? 0 : std::min<int64_t>(c->steps, c->p.history_cap);
+    const int64_t have = c->p.y_periodic ? 0 : std::min<int64_t>(c->steps - c->hist_first + 1, c->p.history_cap);
     const int64_t n = std::min(have, cap);
     std::vector<lbm_stress_summary> ring(c->p.history_cap);
     if (n > 0) {
@@ -1309,6 +1311,160 @@ lbm_status lbm_components(lbm_ctx* c, double threshold, int connectivity, lbm_co
                                          threshold, rho_g, connectivity, out, cap, n_out, summary);
     if (s) return fail(c, s, "lbm_components: connectivity must be 4 or 8 and cap >= 0");
     if (summary) summary->step = c->steps;
+    return LBM_OK;
+}
+
+// ---- checkpoint / resume ---------------------------------------------------------
+//
+// File: the 8-byte magic "LBMCKPT1", then the fields below in this order (native
+// byte order, as the library's own structs), then the current distribution
+// buffer [9][ny][pitch] in the storage type and the emitted fields rho, vx, vy
+// [ny][nx] FP64, then an FNV-1a 64-bit hash of every preceding byte.
+namespace {
+constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
+struct CkptHeader {
+    int32_t nx, ny;
+    double tau;
+    lbm_params p;
+    int64_t steps;
+    lbm_check_result check;
+    double acc[lbm::kWallAccVals];  // time integrals and running extremes of the wall stresses
+    double dtheta[4];               // F64T tangent direction
+    uint32_t sr;                    // F16R: counter of the next step
+    uint32_t pad;
+    uint64_t f_bytes;
+};
+struct Fnv64 {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    }
+};
+bool params_equal(const lbm_params& a, const lbm_params& b) {
+    // field by field (the struct has padding); NaN defaults compare equal
+    auto same = [](double x, double y) { return x == y || (std::isnan(x) && std::isnan(y)); };
+    return a.eos == b.eos && same(a.a, b.a) && same(a.b, b.b) && same(a.R, b.R) && same(a.omega, b.omega) &&
+           same(a.T_over_Tc, b.T_over_Tc) && same(a.k, b.k) && same(a.kappa, b.kappa) && same(a.s_e, b.s_e) &&
+           same(a.s_eps, b.s_eps) && same(a.s_q, b.s_q) && same(a.s_j, b.s_j) && same(a.rho_wall, b.rho_wall) &&
+           same(a.dp, b.dp) && a.x_periodic == b.x_periodic && a.y_periodic == b.y_periodic &&
+           a.storage == b.storage && same(a.rho0_shift, b.rho0_shift) && same(a.v_limit, b.v_limit);
+}
+}  // namespace
+
+lbm_status lbm_save(lbm_ctx* c, const char* path) {
+    if (!c || !path) return LBM_EINVAL;
+    if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_save needs an initialised lattice");
+    if (c->in_batch) return fail(c, LBM_ESTATE, "a batch case is not saved on its own");
+    lbm_status st = flush_wall(c);  // the accumulators then hold every step so far
+    if (st) return st;
+    CkptHeader h{};
+    h.nx = c->nx;
+    h.ny = c->ny;
+    h.tau = c->tau;
+    h.p = c->p;
+    h.steps = c->steps;
+    h.check = c->check;
+    for (int q = 0; q < 4; ++q) h.dtheta[q] = c->dtheta[q];
+    h.f_bytes = (uint64_t)c->plane * 9 * storage_bytes(c->p.storage);
+    const size_t nxy = (size_t)c->nx * c->ny;
+    std::vector<unsigned char> f((size_t)h.f_bytes);
+    std::vector<double> fields(3 * nxy);
+    uint32_t sr[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(h.acc, c->dev + c->off_acc, sizeof h.acc, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(sr, c->dev + c->off_sr, sizeof sr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(f.data(), c->dev + c->off_f[c->cur], f.size(), hipMemcpyDeviceToHost, c->stream));
+    const size_t off_fields[3] = {c->off_rho, c->off_vx, c->off_vy};
+    for (int q = 0; q < 3; ++q)
+        HIP_TRY(c, hipMemcpyAsync(fields.data() + q * nxy, c->dev + off_fields[q], nxy * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    h.sr = sr[c->cur];
+    Fnv64 hash;
+    hash.add(kCkptMagic, sizeof kCkptMagic);
+    hash.add(&h, sizeof h);
+    hash.add(f.data(), f.size());
+    hash.add(fields.data(), fields.size() * sizeof(double));
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail(c, LBM_EINVAL, "lbm_save: cannot open %s for writing", path);
+    bool ok = std::fwrite(kCkptMagic, sizeof kCkptMagic, 1, fp) == 1 && std::fwrite(&h, sizeof h, 1, fp) == 1 &&
+              std::fwrite(f.data(), 1, f.size(), fp) == f.size() &&
+              std::fwrite(fields.data(), sizeof(double), fields.size(), fp) == fields.size() &&
+              std::fwrite(&hash.h, sizeof hash.h, 1, fp) == 1;
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return fail(c, LBM_EINVAL, "lbm_save: writing %s failed", path);
+    return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx* c, const char* path) {
+    if (!c || !path) return LBM_EINVAL;
+    if (!c->bound) return fail(c, LBM_ESTATE, "lbm_bind must come first");
+    if (c->in_batch) return fail(c, LBM_ESTATE, "a batch case is not loaded on its own");
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(c, LBM_EINVAL, "lbm_load: cannot open %s", path);
+    char magic[8];
+    CkptHeader h{};
+    bool ok = std::fread(magic, sizeof magic, 1, fp) == 1 && std::memcmp(magic, kCkptMagic, sizeof magic) == 0 &&
+              std::fread(&h, sizeof h, 1, fp) == 1;
+    const size_t nxy = (size_t)c->nx * c->ny;
+    const uint64_t f_bytes = (uint64_t)c->plane * 9 * storage_bytes(c->p.storage);
+    ok = ok && h.nx == c->nx && h.ny == c->ny && h.tau == c->tau && h.f_bytes == f_bytes && params_equal(h.p, c->p);
+    std::vector<unsigned char> f;
+    std::vector<double> fields;
+    uint64_t stored = 0;
+    if (ok) {
+        f.resize((size_t)f_bytes);
+        fields.resize(3 * nxy);
+        ok = std::fread(f.data(), 1, f.size(), fp) == f.size() &&
+             std::fread(fields.data(), sizeof(double), fields.size(), fp) == fields.size() &&
+             std::fread(&stored, sizeof stored, 1, fp) == 1;
+    }
+    std::fclose(fp);
+    if (!ok)
+        return fail(c, LBM_EINVAL, "lbm_load: %s is not a checkpoint of a lattice with these sizes, tau and "
+                                   "parameters", path);
+    Fnv64 hash;
+    hash.add(kCkptMagic, sizeof kCkptMagic);
+    hash.add(&h, sizeof h);
+    hash.add(f.data(), f.size());
+    hash.add(fields.data(), fields.size() * sizeof(double));
+    if (hash.h != stored) return fail(c, LBM_EINVAL, "lbm_load: %s is corrupt (hash mismatch)", path);
+    c->cur = 0;
+    const uint32_t sr[2] = {h.sr, 0};
+    HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_f[0], f.data(), f.size(), hipMemcpyHostToDevice, c->stream));
+    const size_t off_fields[3] = {c->off_rho, c->off_vx, c->off_vy};
+    for (int q = 0; q < 3; ++q)
+        HIP_TRY(c, hipMemcpyAsync(c->dev + off_fields[q], fields.data() + q * nxy, nxy * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_acc, h.acc, sizeof h.acc, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_sr, sr, sizeof sr, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->steps = h.steps;
+    c->check = h.check;
+    for (int q = 0; q < 4; ++q) c->dtheta[q] = h.dtheta[q];
+    c->ring_fill = 0;
+    c->last_slot = -1;
+    c->ring_first_step = h.steps + 1;
+    c->hist_first = h.steps + 1;
+    c->initialized = true;
+    c->adj.recorded = c->adj.swept = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_fields_device(lbm_ctx* c, void* rho, void* vx, void* vy, int fp64) {
+    if (!c) return LBM_EINVAL;
+    if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    const long long n = (long long)c->nx * c->ny;
+    void* outs[3] = {rho, vx, vy};
+    const size_t off_fields[3] = {c->off_rho, c->off_vx, c->off_vy};
+    for (int q = 0; q < 3; ++q) {
+        if (!outs[q]) continue;
+        const double* src = c->at<double>(off_fields[q]);
+        if (fp64)
+            HIP_TRY(c, hipMemcpyAsync(outs[q], src, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        else
+            HIP_TRY(c, lbm::launch_to_f32(src, static_cast<float*>(outs[q]), n, c->stream));
+    }
     return LBM_OK;
 }
 

@@ -109,6 +109,8 @@ hipError_t pipe_grid(int storage, int eos, int ty, int waves, int* blocks);
 hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, long long plane,
                        int storage, double rho0, hipStream_t s);
 hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
+// out[i] = (float)in[i], i < n.
+hipError_t launch_to_f32(const double* in, float* out, long long n, hipStream_t s);
 // Stage 1+2 FP64 reduction over the emitted fields into out[5]:
 // sum rho, sum rho vx, sum rho vy, max |v|^2, NaN count.
 hipError_t launch_field_reduce(const double* rho, const double* vx, const double* vy, long long n,

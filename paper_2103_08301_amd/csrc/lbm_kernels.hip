@@ -34,6 +34,11 @@ __global__ void fill_kernel(double* p, double v, long long n) {
         p[c] = v;
 }
 
+__global__ void to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, long long n) {
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x)
+        out[c] = float(in[c]);
+}
+
 // Deterministic two-stage FP64 reduction.  Stage 1: block b reduces the
 // contiguous range [b n/B, (b+1) n/B) with a fixed thread/LDS tree.
 constexpr int kRedThreads = 256;
@@ -339,6 +344,13 @@ hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, lo
         case LBM_F16R: hipLaunchKernelGGL(init_kernel<CodecF16R>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* in, float* out, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = int((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+    hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, s, in, out, n);
     return hipGetLastError();
 }
 

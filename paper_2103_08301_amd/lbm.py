@@ -31,6 +31,7 @@ EXPORTED = [
     "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_set_tangent", "lbm_get_f_tangent",
     "lbm_reset_stress_extremes", "lbm_adjoint_workspace", "lbm_adjoint_bind", "lbm_adjoint_forward",
     "lbm_adjoint_backward", "lbm_adjoint_state_gradient", "lbm_autotune", "lbm_batch_autotune",
+    "lbm_fields_device", "lbm_save", "lbm_load",
 ]
 
 
@@ -121,6 +122,9 @@ def library():
             "lbm_step": (C.c_int, [_P, C.c_int64]),
             "lbm_step_count": (C.c_int, [_P, C.POINTER(C.c_int64)]),
             "lbm_fields": (C.c_int, [_P, _D, _D, _D]),
+            "lbm_fields_device": (C.c_int, [_P, _P, _P, _P, C.c_int]),
+            "lbm_save": (C.c_int, [_P, C.c_char_p]),
+            "lbm_load": (C.c_int, [_P, C.c_char_p]),
             "lbm_wall_stress": (C.c_int, [_P, _D, _D, _D, _D, C.POINTER(lbm_stress_summary)]),
             "lbm_stress_history": (C.c_int, [_P, C.POINTER(lbm_stress_summary), C.c_int64,
                                              C.POINTER(C.c_int64)]),
@@ -234,6 +238,19 @@ def lbm_step_count(ctx) -> int:
 
 def lbm_fields(ctx, rho, vx, vy):
     _check(ctx, library().lbm_fields(ctx, _ptr(rho), _ptr(vx), _ptr(vy)))
+
+
+def lbm_fields_device(ctx, rho_ptr: int, vx_ptr: int, vy_ptr: int, fp64: bool):
+    """Device pointers (ints, 0 for none) of caller-owned [ny][nx] arrays."""
+    _check(ctx, library().lbm_fields_device(ctx, rho_ptr or None, vx_ptr or None, vy_ptr or None, int(fp64)))
+
+
+def lbm_save(ctx, path: str):
+    _check(ctx, library().lbm_save(ctx, os.fsencode(path)))
+
+
+def lbm_load(ctx, path: str):
+    _check(ctx, library().lbm_load(ctx, os.fsencode(path)))
 
 
 def lbm_wall_stress(ctx, tau_bot, tau_top, p_bot, p_top) -> dict:
@@ -415,6 +432,27 @@ class Lattice:
         vy = np.empty_like(r)
         lbm_fields(self._ctx, r, vx, vy)
         return r, vx, vy
+
+    def fields_device(self, dtype=None):
+        """rho, vx, vy of the last step as device tensors [ny][nx] (float64, or float32), written on the
+        lattice's stream."""
+        import torch
+
+        dtype = torch.float64 if dtype is None else dtype
+        if dtype not in (torch.float64, torch.float32):
+            raise ValueError("dtype must be torch.float64 or torch.float32")
+        with torch.cuda.stream(self.stream):
+            out = [torch.empty((self.ny, self.nx), dtype=dtype, device=self.device) for _ in range(3)]
+        lbm_fields_device(self._ctx, *(t.data_ptr() for t in out), dtype == torch.float64)
+        return tuple(out)
+
+    def save(self, path: str):
+        """Checkpoint of the run (lbm_save)."""
+        lbm_save(self._ctx, path)
+
+    def load(self, path: str):
+        """Continue a run saved by a lattice with the same sizes, tau and parameters (lbm_load)."""
+        lbm_load(self._ctx, path)
 
     def wall(self):
         a = [np.empty(self.nx) for _ in range(4)]

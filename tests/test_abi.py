@@ -203,3 +203,16 @@ def test_stochastic_fp16_storage_rules(L):
     for bad in (dict(schedule=1), dict(schedule=2), dict(fused_steps=2)):
         with pytest.raises(L.LbmError):
             L.lbm_create(64, 16, 1.0, L.lbm_params_default(storage="f16r", **bad))
+
+
+def test_checkpoint_and_device_fields_need_a_bound_lattice(L, tmp_path):
+    """lbm_save, lbm_load and lbm_fields_device before binding or initialisation: LBM_ESTATE, no device access."""
+    ctx = L.lbm_create(64, 16, 1.0, L.lbm_params_default())
+    lib = L.library()
+    path = str(tmp_path / "x.ckpt").encode()
+    assert lib.lbm_save(ctx, path) == L.LBM_ESTATE
+    assert lib.lbm_load(ctx, path) == L.LBM_ESTATE
+    assert lib.lbm_fields_device(ctx, None, None, None, 1) == L.LBM_ESTATE
+    assert lib.lbm_save(None, path) == L.LBM_EINVAL
+    assert not (tmp_path / "x.ckpt").exists()
+    L.lbm_destroy(ctx)
