@@ -227,12 +227,23 @@ lbm_status lbm_check_state(const lbm_ctx* ctx, lbm_check_result* out);
 /* Tile autotuner of the tile schedule: times trial_steps launches of every
    tile shape (output rows x waves per block: 8x4, 12x4, 20x4, 28x4, 12x8,
    20x8, 28x8) on the current state and keeps the fastest for later steps.
-   Trials read the current state and write only scratch (the other
-   distribution buffer and the flushed wall ring), so the state, fields and
-   wall diagnostics are unchanged, and results do not depend on the shape.
-   Outputs (any may be NULL): the chosen shape and its mean time per step in
-   microseconds.  Blocks until done.  LBM_EINVAL for other schedules or F64T. */
+   It also times two steps per launch (fused_steps = 2; not for F16R) and
+   keeps them when they take less time per step, as on grids too small to fill
+   the chip; otherwise it sets one step per launch.  Trials read the current
+   state and write only scratch (the other distribution buffer and flushed
+   wall-ring slots), so the state, fields and wall diagnostics are unchanged,
+   and results do not depend on the choice (the kernels are bit-identical).
+   Outputs (any may be NULL): the chosen one-step shape (also used for the
+   single steps a two-step run needs) and the mean time per step in
+   microseconds of the chosen configuration; lbm_launch_config reports
+   whether two steps per launch were chosen.  Blocks until done.  LBM_EINVAL
+   for other schedules or F64T. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int trial_steps, int* tile_rows, int* tile_waves, double* us_per_step);
+
+/* The launch configuration in use: tile shape, steps per launch (1 or 2) and
+   steps per captured graph (0: graphs off).  Any pointer may be NULL. */
+lbm_status lbm_launch_config(const lbm_ctx* ctx, int* tile_rows, int* tile_waves, int* fused_steps,
+                             int* graph_steps);
 
 /* Reverse-mode sensitivities (adjoint) of the wall-shear objective
    J = sum over steps, walls and columns of tau_w^2 (the time integral of

@@ -1056,6 +1056,15 @@ hipError_t time_launches(hipStream_t s, int trials, F&& launch, double* us) {
 
 extern "C" {
 
+lbm_status lbm_launch_config(const lbm_ctx* c, int* tile_rows, int* tile_waves, int* fused_steps, int* graph_steps) {
+    if (!c) return LBM_EINVAL;
+    if (tile_rows) *tile_rows = c->ty;
+    if (tile_waves) *tile_waves = c->tile_waves;
+    if (fused_steps) *fused_steps = c->steps_per_launch();
+    if (graph_steps) *graph_steps = c->graph_steps();
+    return LBM_OK;
+}
+
 lbm_status lbm_autotune(lbm_ctx* c, int trial_steps, int* tile_rows, int* tile_waves, double* us_per_step) {
     if (!c || trial_steps < 1) return LBM_EINVAL;
     if (c->in_batch) return fail(c, LBM_ESTATE, "a batch case is tuned with lbm_batch_autotune");
@@ -1075,10 +1084,25 @@ lbm_status lbm_autotune(lbm_ctx* c, int trial_steps, int* tile_rows, int* tile_w
                                  [&] { return lbm::launch_step(a, c->p.storage, c->p.eos, false, c->stream); }, &us));
         if (us < best) { best = us; pick = t; }
     }
+    // two steps per launch, where the storage has the two-step kernel; their two wall
+    // arrays go to two consecutive ring slots, neither of them the latest step's
+    int fused = 1;
+    if (c->p.storage != LBM_F16R) {
+        lbm::StepArgs a = trial_args(c);
+        set_wall_slot(a, c, c->last_slot + 1 <= kRingCap - 2 ? c->last_slot + 1 : 0);
+        double us = 0;
+        HIP_TRY(c, time_launches(c->stream, (trial_steps + 1) / 2,
+                                 [&] { return lbm::launch_step2(a, c->p.storage, c->p.eos, false, c->stream); }, &us));
+        if (0.5 * us < best) {
+            best = 0.5 * us;
+            fused = 2;
+        }
+    }
     c->ty = c->p.tile_rows = pick.rows;
     c->tile_waves = c->p.tile_waves = pick.waves;
+    c->p.fused_steps = fused;
     c->nchunk = std::max(1, c->ny / c->ty);
-    c->graphs.drop();  // the tile shape is part of the captured launches
+    c->graphs.drop();  // the launch configuration is part of the captured launches
     if (tile_rows) *tile_rows = pick.rows;
     if (tile_waves) *tile_waves = pick.waves;
     if (us_per_step) *us_per_step = best;

@@ -31,7 +31,7 @@ EXPORTED = [
     "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_set_tangent", "lbm_get_f_tangent",
     "lbm_reset_stress_extremes", "lbm_adjoint_workspace", "lbm_adjoint_bind", "lbm_adjoint_forward",
     "lbm_adjoint_backward", "lbm_adjoint_state_gradient", "lbm_autotune", "lbm_batch_autotune",
-    "lbm_fields_device", "lbm_save", "lbm_load",
+    "lbm_fields_device", "lbm_save", "lbm_load", "lbm_launch_config",
 ]
 
 
@@ -124,6 +124,8 @@ def library():
             "lbm_fields": (C.c_int, [_P, _D, _D, _D]),
             "lbm_fields_device": (C.c_int, [_P, _P, _P, _P, C.c_int]),
             "lbm_save": (C.c_int, [_P, C.c_char_p]),
+            "lbm_launch_config": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                            C.POINTER(C.c_int)]),
             "lbm_load": (C.c_int, [_P, C.c_char_p]),
             "lbm_wall_stress": (C.c_int, [_P, _D, _D, _D, _D, C.POINTER(lbm_stress_summary)]),
             "lbm_stress_history": (C.c_int, [_P, C.POINTER(lbm_stress_summary), C.c_int64,
@@ -311,7 +313,14 @@ def lbm_get_f_tangent(ctx, df: np.ndarray):
 def lbm_autotune(ctx, trial_steps: int = 50) -> dict:
     r, w, us = C.c_int(), C.c_int(), C.c_double()
     _check(ctx, library().lbm_autotune(ctx, trial_steps, C.byref(r), C.byref(w), C.byref(us)))
-    return dict(tile_rows=r.value, tile_waves=w.value, us_per_step=us.value)
+    return dict(tile_rows=r.value, tile_waves=w.value, us_per_step=us.value,
+                fused_steps=lbm_launch_config(ctx)["fused_steps"])
+
+
+def lbm_launch_config(ctx) -> dict:
+    v = [C.c_int() for _ in range(4)]
+    _check(ctx, library().lbm_launch_config(ctx, *(C.byref(x) for x in v)))
+    return dict(zip(["tile_rows", "tile_waves", "fused_steps", "graph_steps"], (x.value for x in v)))
 
 
 def lbm_adjoint_workspace(ctx, nsteps: int, segment: int = 0) -> int:
@@ -493,8 +502,12 @@ class Lattice:
         lbm_set_f(self._ctx, f)
 
     def autotune(self, trial_steps: int = 50) -> dict:
-        """Times every tile shape of the tile schedule on the current state and keeps the fastest."""
+        """Times every tile shape of the tile schedule, and two steps per launch, on the current state and keeps
+        the fastest."""
         return lbm_autotune(self._ctx, trial_steps)
+
+    def launch_config(self) -> dict:
+        return lbm_launch_config(self._ctx)
 
     def adjoint_bind(self, nsteps: int, segment: int = 0):
         """Device workspace for recording nsteps steps with a checkpoint every `segment` steps."""
