@@ -282,6 +282,10 @@ hipError_t capture_graph(StepGraphs& g, int steps, F&& launch, hipGraphExec_t* o
 }  // namespace
 
 struct lbm_ctx {
+    double* check_host = nullptr;  // pinned host copy of a check's device results: 5 sums, colmin[nx], centre[nx]
+    ~lbm_ctx() {
+        if (check_host) (void)hipHostFree(check_host);
+    }
     int nx = 0, ny = 0;
     double tau = 1.0;
     lbm_params p{};
@@ -420,22 +424,35 @@ lbm_status flush_wall(lbm_ctx* c) {
     return LBM_OK;
 }
 
-// Mass, momentum, |v|max and NaNs of the emitted fields, interface positions and rupture.
-lbm_status run_check(lbm_ctx* c) {
+// A check in two halves, so that a batch can launch every case's before waiting once:
+// check_launch queues the reductions of the emitted fields and their copies to the
+// pinned host buffer; check_finish (after the stream has been synchronised) derives
+// mass, momentum, |v|max, NaNs, interface positions and rupture.
+lbm_status check_launch(lbm_ctx* c) {
+    if (!c->check_host) {
+        void* h = nullptr;
+        HIP_TRY(c, hipHostMalloc(&h, (5 + 2 * (size_t)c->nx) * sizeof(double), hipHostMallocDefault));
+        c->check_host = static_cast<double*>(h);
+    }
     const long long nxy = (long long)c->nx * c->ny;
     HIP_TRY(c, lbm::launch_field_reduce(c->at<double>(c->off_rho), c->at<double>(c->off_vx), c->at<double>(c->off_vy),
                                         nxy, c->at<double>(c->off_red), lbm::kFieldReduceBlocks,
                                         c->at<double>(c->off_redout), c->stream));
     HIP_TRY(c, lbm::launch_column_scan(c->at<double>(c->off_rho), c->nx, c->ny, c->at<double>(c->off_colmin),
                                        c->at<double>(c->off_centre), c->stream));
-    double red[5];
-    std::vector<double> colmin(c->nx), centre(c->nx);
-    HIP_TRY(c, hipMemcpyAsync(red, c->dev + c->off_redout, sizeof red, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(colmin.data(), c->dev + c->off_colmin, c->nx * sizeof(double), hipMemcpyDeviceToHost,
+    double* h = c->check_host;
+    HIP_TRY(c, hipMemcpyAsync(h, c->dev + c->off_redout, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(h + 5, c->dev + c->off_colmin, c->nx * sizeof(double), hipMemcpyDeviceToHost,
                               c->stream));
-    HIP_TRY(c, hipMemcpyAsync(centre.data(), c->dev + c->off_centre, c->nx * sizeof(double), hipMemcpyDeviceToHost,
+    HIP_TRY(c, hipMemcpyAsync(h + 5 + c->nx, c->dev + c->off_centre, c->nx * sizeof(double), hipMemcpyDeviceToHost,
                               c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status check_finish(lbm_ctx* c) {
+    const double* red = c->check_host;
+    const double* colmin = red + 5;
+    const double* centre = red + 5 + c->nx;
     lbm_check_result& k = c->check;
     k.step = c->steps;
     k.mass = red[0];
@@ -472,6 +489,13 @@ lbm_status run_check(lbm_ctx* c) {
     }
     if (bad) return fail(c, LBM_EUNSTABLE, "state is unstable since step %lld", (long long)k.unstable_step);
     return LBM_OK;
+}
+
+lbm_status run_check(lbm_ctx* c) {
+    lbm_status s = check_launch(c);
+    if (s) return s;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return check_finish(c);
 }
 
 // Points the wall arrays of a step's arguments at a slot of the wall ring.
@@ -1705,8 +1729,14 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
         lbm_status fs = flush_all();
         if (fs) return fs;
         done += seg;
+        // every case's check queued on the batch stream, one wait, then the host halves in case order
         for (int k = 0; k < ncases; ++k) {
-            lbm_status s = run_check(b->cases[(size_t)k]);
+            lbm_status s = check_launch(b->cases[(size_t)k]);
+            if (s) return bfail(b, s, "case " + std::to_string(k) + ": " + b->cases[(size_t)k]->err);
+        }
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, LBM_EDEVICE, "batch check: stream error");
+        for (int k = 0; k < ncases; ++k) {
+            lbm_status s = check_finish(b->cases[(size_t)k]);
             if (s) {
                 if (failed_case) *failed_case = k;
                 return bfail(b, s, "case " + std::to_string(k) + ": " + b->cases[(size_t)k]->err);

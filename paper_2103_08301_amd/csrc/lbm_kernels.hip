@@ -99,13 +99,31 @@ __global__ __launch_bounds__(kRedThreads) void field_reduce_stage2(const double*
         for (int k = 0; k < 5; ++k) out[k] = v[k];
 }
 
-__global__ void column_scan_kernel(const double* __restrict__ rho, int nx, int ny, double* __restrict__ colmin,
-                                   double* __restrict__ centre) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
-    double m = rho[x];
-    for (int y = 1; y < ny; ++y) m = fmin(m, rho[(long long)y * nx + x]);
-    colmin[x] = m;
+// Per column: the minimum density over y and the centreline density.  A block
+// takes 64 columns; its kColScanWaves waves take every kColScanWaves-th row
+// (four loads in flight per lane), and wave 0 combines the partial minima (fmin
+// is exact and order-free: it skips NaNs, and gives NaN only if every value is).
+constexpr int kColScanWaves = 8;
+__global__ __launch_bounds__(64 * kColScanWaves) void column_scan_kernel(const double* __restrict__ rho, int nx, int ny,
+                                                                         double* __restrict__ colmin,
+                                                                         double* __restrict__ centre) {
+    __shared__ double sh[kColScanWaves][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = blockIdx.x * 64 + lane;
+    const int xc = x < nx ? x : nx - 1;  // lanes past the last column read a valid column and store nothing
+    const double none = __builtin_nan("");  // fmin's identity: an all-NaN column stays NaN
+    double m[4] = {none, none, none, none};
+    int y = wave;
+    for (; y + 3 * kColScanWaves < ny; y += 4 * kColScanWaves)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m[u] = fmin(m[u], rho[(long long)(y + u * kColScanWaves) * nx + xc]);
+    for (; y < ny; y += kColScanWaves) m[0] = fmin(m[0], rho[(long long)y * nx + xc]);
+    sh[wave][lane] = fmin(fmin(m[0], m[1]), fmin(m[2], m[3]));
+    __syncthreads();
+    if (wave != 0 || x >= nx) return;
+    double r = sh[0][lane];
+    for (int w = 1; w < kColScanWaves; ++w) r = fmin(r, sh[w][lane]);
+    colmin[x] = r;
     if (ny % 2 == 0)
         centre[x] = 0.5 * (rho[(long long)(ny / 2 - 1) * nx + x] + rho[(long long)(ny / 2) * nx + x]);
     else
@@ -371,7 +389,8 @@ hipError_t launch_field_reduce(const double* rho, const double* vx, const double
 }
 
 hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin, double* centre, hipStream_t s) {
-    hipLaunchKernelGGL(column_scan_kernel, dim3((nx + 255) / 256), dim3(256), 0, s, rho, nx, ny, colmin, centre);
+    hipLaunchKernelGGL(column_scan_kernel, dim3((nx + 63) / 64), dim3(64 * kColScanWaves), 0, s, rho, nx, ny, colmin,
+                       centre);
     return hipGetLastError();
 }
 
