@@ -122,8 +122,15 @@ __device__ inline C div3(const Row3<C>& sx, const Row3<C>& mx, const Row3<C>& nx
            C(1.0 / 3.0) * (ny_.c - sy.c) + C(1.0 / 12.0) * ((ny_.e + ny_.w) - (sy.e + sy.w));
 }
 
+// 4-row tiles with FP32 arithmetic: 8 waves per SIMD (four blocks per compute unit), so
+// a 1024 x 256 grid's 1152 blocks take little more than one round.  Without the bound
+// the compiler's 102 SGPRs allow seven; with it a few SGPRs move to VGPR lanes
+// (measured: the gradient's backward sweep 0.477 -> 0.455 s on that grid).
+template <class CD, int TYO>
+constexpr int adj_min_waves() { return (sizeof(typename CD::C) == 4 && TYO == 4) ? 8 : 1; }
+
 template <class CD, int EOS, int TYO, int NW>
-__global__ __launch_bounds__(64 * NW) void adjoint_kernel(const AdjArgs A) {
+__global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_kernel(const AdjArgs A) {
     using C = typename CD::C;
     constexpr int H = TYO + 2 * kAdjHalo;
     constexpr int RPT = H / NW;
