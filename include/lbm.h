@@ -259,10 +259,11 @@ lbm_status lbm_launch_config(const lbm_ctx* ctx, int* tile_rows, int* tile_waves
    Memory: nsteps steps are recorded with one checkpoint of the state every
    `segment` steps (0 picks ceil(sqrt(nsteps))); the backward sweep recomputes
    each segment from its checkpoint, storing per step the forward fields the
-   adjoint step reads.  The adjoint workspace holds ceil(nsteps/segment) + 2
-   states, segment x (5 x ny x pitch + 4 x nx) values and two adjoint fields
-   (9 x ny x pitch) of the arithmetic type, segment x 2 x nx FP64 wall shears
-   and small scratch; it is
+   adjoint step reads (two segments' worth, so that one is recomputed while
+   the other is swept).  The adjoint workspace holds ceil(nsteps/segment) + 2
+   states, 2 x segment x (5 x ny x pitch + 4 x nx) values and two adjoint
+   fields (9 x ny x pitch) of the arithmetic type, 2 x segment x 2 x nx FP64
+   wall shears and small scratch; it is
    caller-owned device memory like the main workspace, 256-byte aligned, and
    bound once.  Storage F64, F32 or F32D with the tile schedule; otherwise
    LBM_EINVAL. */

@@ -314,14 +314,27 @@ struct lbm_ctx {
                off_acc = 0, off_pw = 0, off_g0 = 0, total = 0;
         int blocks = 0, cur = 0, ty = 8, waves = 4, ring_cap = 0;
         double J = 0, seed = 1;
-        hipGraphExec_t seg_graph[2] = {nullptr, nullptr};  // one full segment of the sweep, per adjoint parity
+        // captured graphs of a full segment: its recompute into field buffer b, and its adjoint
+        // sweep (with the reduction) reading buffer b at adjoint parity p
+        hipGraphExec_t rec_graph[2] = {nullptr, nullptr}, adj_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+        // the recompute of the next segment runs on its own stream beside the current adjoint sweep
+        hipStream_t aux = nullptr;
+        hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
         void drop_graphs() {
-            for (auto& g : seg_graph)
+            for (auto& g : rec_graph)
                 if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+            for (auto& row : adj_graph)
+                for (auto& g : row)
+                    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
         }
-        ~Adjoint() { drop_graphs(); }
+        ~Adjoint() {
+            drop_graphs();
+            for (hipEvent_t e : {ev_start, ev_rec[0], ev_rec[1], ev_adj[0], ev_adj[1]})
+                if (e) (void)hipEventDestroy(e);
+            if (aux) (void)hipStreamDestroy(aux);
+        }
         Adjoint() = default;
-        Adjoint& operator=(const Adjoint& o) {  // layout only; the graphs belong to the bound workspace
+        Adjoint& operator=(const Adjoint& o) {  // layout only; graphs, stream and events stay with this one
             drop_graphs();
             dev = o.dev; bound = o.bound; recorded = o.recorded; swept = o.swept;
             n = o.n; seg = o.seg; nckpt = o.nckpt; state = o.state; lam = o.lam; fld = o.fld;
@@ -1165,10 +1178,10 @@ lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm
     size_t o = 0;
     A.off_ckpt = o; o += (size_t)A.nckpt * A.state;
     A.off_pp = o; o += 2 * A.state;               // the recompute's two states
-    A.off_fld = o; o += (size_t)A.seg * A.fld;    // forward fields of each step of a segment
+    A.off_fld = o; o += 2 * (size_t)A.seg * A.fld;  // forward fields of each step of two segments
     A.off_lam[0] = o; o += A.lam;
     A.off_lam[1] = o; o += A.lam;
-    A.off_tw = o; o += align256((size_t)A.seg * 2 * c->nx * sizeof(double));
+    A.off_tw = o; o += align256(2 * (size_t)A.seg * 2 * c->nx * sizeof(double));  // their wall shears
     A.ring_cap = (int)std::max<int64_t>(A.seg, kAdjRing);  // adjoint launches between reductions
     A.off_part = o; o += align256((size_t)A.ring_cap * A.blocks * 4 * sizeof(double));
     A.off_red = o; o += align256((size_t)A.ring_cap * 4 * sizeof(double));
@@ -1242,7 +1255,9 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     double* acc = reinterpret_cast<double*>(A.dev + A.off_acc);
     double* red = reinterpret_cast<double*>(A.dev + A.off_red);
     auto pp = [&](int64_t i) { return A.dev + A.off_pp + (size_t)(i & 1) * A.state; };
-    auto fld = [&](int64_t i) { return A.dev + A.off_fld + (size_t)i * A.fld; };
+    // step i of the segment held in field buffer b: its forward fields and wall shears
+    auto fld = [&](int b, int64_t i) { return A.dev + A.off_fld + ((size_t)b * A.seg + (size_t)i) * A.fld; };
+    auto twp = [&](int b, int64_t i) { return tw + ((size_t)b * A.seg + (size_t)i) * 2 * c->nx; };
     HIP_TRY(c, lbm::launch_fill(reinterpret_cast<double*>(A.dev + A.off_lam[0]), 0.0, (long long)(A.lam / 8), c->stream));
     HIP_TRY(c, lbm::launch_fill(acc, 0.0, 4, c->stream));
     A.cur = 0;
@@ -1254,61 +1269,95 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     aa.nstrip = (c->nx + lbm::kAdjStripOut - 1) / lbm::kAdjStripOut;
     aa.ty = A.ty;
     aa.waves = A.waves;
-    int ring = 0;
-    // One segment, its checkpoint copied to the first recompute state: launch j of
-    // 2 len + 1 recomputes step start + 1 + j (j < len), writing its forward fields
-    // to slot j, then runs the adjoint steps from the segment's last step down, then
-    // (with `reduce_at_end`) the reduction; cur0 is the adjoint parity at the start.
-    auto segment_launch = [&](int64_t len, int cur0, int ring0, int64_t j, hipStream_t s) -> hipError_t {
-        if (j < len) {
-            lbm::StepArgs b = fa;
-            b.fin = pp(j);
-            b.fout = pp(j + 1);
-            b.save = fld(j);
-            b.tau_w = tw + (size_t)j * 2 * c->nx;
-            return lbm::launch_step_save(b, storage, eos, s);
-        }
-        if (j < 2 * len) {
-            const int64_t m = j - len, i = len - 1 - m;  // m-th adjoint launch: step start + 1 + i
-            const int par = (cur0 + (int)m) & 1;
-            lbm::AdjArgs b = aa;
-            b.fld = fld(i);
-            b.lam_in = A.dev + A.off_lam[par];
-            b.lam_out = A.dev + A.off_lam[1 - par];
-            b.tau_w = tw + (size_t)i * 2 * c->nx;
-            b.partial = part + (size_t)(ring0 + m) * A.blocks * 4;
-            return lbm::launch_adjoint(b, storage, eos, s);
-        }
-        return lbm::launch_adjoint_reduce(part, (int)(ring0 + len), A.blocks, red, acc, s);
+    const bool graphs = c->graph_steps() > 0;
+    if (!A.aux) HIP_TRY(c, hipStreamCreateWithFlags(&A.aux, hipStreamNonBlocking));
+    // Below 1M nodes neither kernel fills the chip and the overlap pays (1024x256 FP32: backward sweep 0.456 ->
+    // 0.329 s); on 4096x512 both stream close to the roofline and contend (0.177 -> 0.182 s), so there the
+    // recompute runs on the main stream, in the same order.
+    const hipStream_t rs = (long long)c->nx * c->ny < (1LL << 20) ? A.aux : c->stream;
+    for (hipEvent_t* e : {&A.ev_start, &A.ev_rec[0], &A.ev_rec[1], &A.ev_adj[0], &A.ev_adj[1]})
+        if (!*e) HIP_TRY(c, hipEventCreateWithFlags(e, hipEventDisableTiming));
+    // Recompute launch j of a segment into field buffer b: step start + 1 + j from pp(j) to pp(j + 1).
+    auto rec_launch = [&](int b, int64_t j, hipStream_t s) -> hipError_t {
+        lbm::StepArgs r = fa;
+        r.fin = pp(j);
+        r.fout = pp(j + 1);
+        r.save = fld(b, j);
+        r.tau_w = twp(b, j);
+        return lbm::launch_step_save(r, storage, eos, s);
     };
-    for (int64_t ck = A.nckpt - 1; ck >= 0; --ck) {
-        const int64_t start = ck * A.seg, end = std::min(start + A.seg, A.n), len = end - start;
-        HIP_TRY(c, hipMemcpyAsync(pp(0), A.dev + A.off_ckpt + (size_t)ck * A.state, A.state, hipMemcpyDeviceToDevice,
-                                  c->stream));
-        if (len == A.seg && c->graph_steps() > 0) {
-            // a full segment: replay the captured sweep
+    // Adjoint launch m (m < len) of a segment in buffer b, from its last step down; launch len: the reduction.
+    auto adj_launch = [&](int b, int64_t len, int cur0, int ring0, int64_t m, hipStream_t s) -> hipError_t {
+        if (m == len) return lbm::launch_adjoint_reduce(part, (int)(ring0 + len), A.blocks, red, acc, s);
+        const int64_t i = len - 1 - m;
+        const int par = (cur0 + (int)m) & 1;
+        lbm::AdjArgs r = aa;
+        r.fld = fld(b, i);
+        r.lam_in = A.dev + A.off_lam[par];
+        r.lam_out = A.dev + A.off_lam[1 - par];
+        r.tau_w = twp(b, i);
+        r.partial = part + (size_t)(ring0 + m) * A.blocks * 4;
+        return lbm::launch_adjoint(r, storage, eos, s);
+    };
+    auto seg_len = [&](int64_t k) { return std::min(A.seg, A.n - k * A.seg); };
+    // Segment k's recompute on stream rs, into buffer k & 1, from a copy of its checkpoint.
+    auto recompute = [&](int64_t k) -> lbm_status {
+        const int b = (int)(k & 1);
+        const int64_t len = seg_len(k);
+        HIP_TRY(c, hipMemcpyAsync(pp(0), A.dev + A.off_ckpt + (size_t)k * A.state, A.state, hipMemcpyDeviceToDevice,
+                                  rs));
+        if (len == A.seg && graphs) {
+            if (!A.rec_graph[b]) {
+                auto launch = [&](int j, hipStream_t s) { return rec_launch(b, j, s); };
+                HIP_TRY(c, capture_graph(c->graphs, (int)len, launch, &A.rec_graph[b]));
+            }
+            HIP_TRY(c, hipGraphLaunch(A.rec_graph[b], rs));
+        } else {
+            for (int64_t j = 0; j < len; ++j) HIP_TRY(c, rec_launch(b, j, rs));
+        }
+        HIP_TRY(c, hipEventRecord(A.ev_rec[b], rs));
+        return LBM_OK;
+    };
+    // The recompute stream starts after everything queued so far (the record, the fills).
+    HIP_TRY(c, hipEventRecord(A.ev_start, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(rs, A.ev_start, 0));
+    lbm_status st = recompute(A.nckpt - 1);
+    if (st) return st;
+    int ring = 0;
+    for (int64_t k = A.nckpt - 1; k >= 0; --k) {
+        const int b = (int)(k & 1);
+        const int64_t len = seg_len(k);
+        if (k >= 1) {
+            // segment k - 1 goes to the buffer segment k + 1's sweep read: wait for that sweep
+            if (k + 1 <= A.nckpt - 1) HIP_TRY(c, hipStreamWaitEvent(rs, A.ev_adj[(k + 1) & 1], 0));
+            st = recompute(k - 1);
+            if (st) return st;
+        }
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, A.ev_rec[b], 0));
+        if (len == A.seg && graphs) {
+            // a full segment: the captured sweep (its reduction included)
             if (ring > 0) {
                 HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
                 ring = 0;
             }
-            hipGraphExec_t& ge = A.seg_graph[A.cur];
+            hipGraphExec_t& ge = A.adj_graph[b][A.cur];
             if (!ge) {
                 const int cur0 = A.cur;
-                auto launch = [&](int j, hipStream_t s) { return segment_launch(len, cur0, 0, j, s); };
-                HIP_TRY(c, capture_graph(c->graphs, (int)(2 * len + 1), launch, &ge));
+                auto launch = [&](int m, hipStream_t s) { return adj_launch(b, len, cur0, 0, m, s); };
+                HIP_TRY(c, capture_graph(c->graphs, (int)(len + 1), launch, &ge));
             }
             HIP_TRY(c, hipGraphLaunch(ge, c->stream));
-            A.cur = (A.cur + (int)len) & 1;
-            continue;
+        } else {
+            // the last (shorter) segment, or every segment without graphs: direct launches
+            if (ring + len > A.ring_cap) {
+                HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
+                ring = 0;
+            }
+            for (int64_t m = 0; m < len; ++m) HIP_TRY(c, adj_launch(b, len, A.cur, ring, m, c->stream));
+            ring += (int)len;
         }
-        // the last (shorter) segment, or every segment without graphs: direct launches
-        if (ring + len > A.ring_cap) {
-            HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
-            ring = 0;
-        }
-        for (int64_t j = 0; j < 2 * len; ++j) HIP_TRY(c, segment_launch(len, A.cur, ring, j, c->stream));
         A.cur = (A.cur + (int)len) & 1;
-        ring += (int)len;
+        HIP_TRY(c, hipEventRecord(A.ev_adj[b], c->stream));
     }
     if (ring > 0) HIP_TRY(c, lbm::launch_adjoint_reduce(part, ring, A.blocks, red, acc, c->stream));
     double sums[4];
