@@ -1432,7 +1432,7 @@ struct CkptHeader {
     uint64_t f_bytes;
 };
 struct Fnv64 {
-    uint64_t h = 1469598103934665603ull;
+    uint64_t h = 14695981039346656037ull;  // the 64-bit FNV offset basis
     void add(const void* p, size_t n) {
         const unsigned char* b = static_cast<const unsigned char*>(p);
         for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;

@@ -88,6 +88,31 @@ def test_load_refuses_other_lattices_and_damaged_files(tmp_path):
     assert ok.steps == 10 and os.path.getsize(path) == len(raw)
 
 
+def test_file_layout(tmp_path):
+    """The documented layout: magic, header (nx, ny, tau, ... steps), the distributions, the FP64 fields, and an
+    FNV-1a 64-bit hash of all preceding bytes."""
+    path = str(tmp_path / "run.ckpt")
+    a = make("f64", nx=70, ny=20)
+    a.init_plug(20, 2, math.nan, 1e-3, 4)
+    a.step(13)
+    a.save(path)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"LBMCKPT1"
+    nx, ny = np.frombuffer(raw[8:16], dtype=np.int32)
+    tau = np.frombuffer(raw[16:24], dtype=np.float64)[0]
+    assert (nx, ny, tau) == (70, 20, 0.9)
+    h = 0xCBF29CE484222325
+    for b in raw[:-8]:
+        h = ((h ^ b) * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    assert int.from_bytes(raw[-8:], "little") == h
+    pitch = 128
+    f_bytes = 9 * ny * pitch * 8
+    rho = np.frombuffer(raw[-8 - 3 * nx * ny * 8:-8 - 2 * nx * ny * 8], dtype=np.float64).reshape(ny, nx)
+    assert np.array_equal(rho, a.fields()[0])
+    f = np.frombuffer(raw[-8 - 3 * nx * ny * 8 - f_bytes:-8 - 3 * nx * ny * 8], dtype=np.float64)
+    assert np.array_equal(f.reshape(9, ny, pitch)[:, :, :nx], a.get_f())
+
+
 def test_fields_device_equal_host_fields():
     a = make("f32")
     a.init_plug(36, 4, math.nan, 1e-3, 3)
