@@ -157,7 +157,8 @@ __device__ void wall_step_reduce_body(const WallFlush& f, int t, int64_t first_s
         const double* dtau = slot + (long long)(4 + w) * nx;
         double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
         double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0, wds = 0.0;
-        for (int x = threadIdx.x; x < nx; x += kWallThreads) {
+#pragma unroll 4
+        for (int x = threadIdx.x; x < nx; x += kWallThreads) {  // unrolled: four columns' loads in flight
             const double tv = tau[x], pv = pw[x];
             comb_max(tmax, xtmax, tv, double(x));
             comb_min(tmin, xtmin, tv, double(x));
