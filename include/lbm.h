@@ -270,6 +270,17 @@ lbm_status lbm_launch_config(const lbm_ctx* ctx, int* tile_rows, int* tile_waves
 lbm_status lbm_adjoint_workspace(const lbm_ctx* ctx, int64_t nsteps, int64_t segment, size_t* bytes);
 lbm_status lbm_adjoint_bind(lbm_ctx* ctx, void* device_ptr, size_t bytes, int64_t nsteps, int64_t segment);
 
+/* The objective of the adjoint (after lbm_adjoint_bind, before
+   lbm_adjoint_forward; changing it drops the record).  LBM_J_SUM_TAU2 (the
+   default): J = sum over steps, walls and columns of tau_w^2 (int_tau2).
+   LBM_J_PEAK_TAU2: J = sum over steps of the largest tau_w^2 over both walls
+   and all columns (int_peak_tau2, the time-integrated squared peak wall
+   shear); its gradient takes each step's derivative at the first (wall,
+   column) holding the peak, which is the derivative wherever the peak is
+   unique.  LBM_EINVAL for another value. */
+typedef enum { LBM_J_SUM_TAU2 = 0, LBM_J_PEAK_TAU2 = 1 } lbm_adjoint_objective_kind;
+lbm_status lbm_adjoint_objective(lbm_ctx* ctx, int objective);
+
 /* Runs the next nsteps steps from the lattice's current state (through
    lbm_step, so checks and summaries proceed as usual) and records the
    checkpoints.  *J (may be NULL) receives J over these steps.  Errors of

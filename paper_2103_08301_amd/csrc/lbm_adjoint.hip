@@ -214,7 +214,7 @@ __global__ __launch_bounds__(64 * NW, (adj_min_waves<CD, TYO>())) void adjoint_k
                     vx = buffer_load<C>(rfl, uint32_t(w * a.nx + xe) * esz, uint32_t(kAdjFieldPlanes) * plane_c);
                     inv = recip(rho);
                     const C tw = C(A.tau_w[(bottom ? 0 : a.nx) + xe]);
-                    const C tb = C(2) * tw;
+                    const C tb = A.seed ? C(A.seed[(bottom ? 0 : a.nx) + xe]) : C(2) * tw;  // dJ/dtau_w
                     if (y == yw) {
                         rbw = tb * tw * recip(rw);  // d tau_w / d rho_w = tau_w / rho_w
                         vbx = tb * rw * nu * C(3);
@@ -478,6 +478,44 @@ hipError_t launch_step_save(const StepArgs& a, int storage, int eos, hipStream_t
         case LBM_F32D: return launch_save_c<CodecF32D>(a, eos, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+namespace {
+// One block per step: the largest tau_w^2 over both walls (lane-strided, then wave
+// butterflies, then the waves in order; ties go to the smaller index w nx + x).
+constexpr int kSeedThreads = 256;
+__global__ __launch_bounds__(kSeedThreads) void peak_seed_kernel(const double* __restrict__ tau_w,
+                                                                 double* __restrict__ seed, int nx) {
+    __shared__ double sv[kSeedThreads / 64], si[kSeedThreads / 64];
+    const long long base = (long long)blockIdx.x * 2 * nx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v = -1.0, idx = 1e300;
+    for (int i = threadIdx.x; i < 2 * nx; i += kSeedThreads) {
+        const double t = tau_w[base + i];
+        const double t2 = t * t;
+        if (t2 > v || (t2 == v && double(i) < idx)) { v = t2; idx = double(i); }
+        seed[base + i] = 0.0;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64), oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    if (lane == 0) { sv[wave] = v; si[wave] = idx; }
+    __syncthreads();  // also orders the zero fill before the seed store below
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < kSeedThreads / 64; ++w)
+        if (sv[w] > v || (sv[w] == v && si[w] < idx)) { v = sv[w]; idx = si[w]; }
+    if (!(v >= 0.0)) return;  // every tau_w NaN: no seed
+    const int i = int(idx);
+    seed[base + i] = 2.0 * tau_w[base + i];
+}
+}  // namespace
+
+hipError_t launch_peak_seed(const double* tau_w, double* seed, int nx, int steps, hipStream_t s) {
+    if (steps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(peak_seed_kernel, dim3(steps), dim3(kSeedThreads), 0, s, tau_w, seed, nx);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_reduce(const double* partial, int launches, int blocks, double* red, double* acc,

@@ -313,6 +313,8 @@ struct lbm_ctx {
         size_t off_ckpt = 0, off_pp = 0, off_fld = 0, off_lam[2]{}, off_tw = 0, off_part = 0, off_red = 0,
                off_acc = 0, off_pw = 0, off_g0 = 0, total = 0;
         int blocks = 0, cur = 0, ty = 8, waves = 4, ring_cap = 0;
+        int objective = LBM_J_SUM_TAU2;
+        size_t off_seed = 0;  // peak objective: dJ/dtau_w of each step of two segments
         double J = 0, seed = 1;
         // captured graphs of a full segment: its recompute into field buffer b, and its adjoint
         // sweep (with the reduction) reading buffer b at adjoint parity p
@@ -343,6 +345,7 @@ struct lbm_ctx {
             off_tw = o.off_tw; off_part = o.off_part; off_red = o.off_red; off_acc = o.off_acc; off_pw = o.off_pw;
             off_g0 = o.off_g0; total = o.total; blocks = o.blocks; cur = o.cur; ty = o.ty; waves = o.waves;
             ring_cap = o.ring_cap;
+            objective = o.objective; off_seed = o.off_seed;
             J = o.J; seed = o.seed;
             return *this;
         }
@@ -1182,6 +1185,7 @@ lbm_status adjoint_layout(const lbm_ctx* c, int64_t nsteps, int64_t segment, lbm
     A.off_lam[0] = o; o += A.lam;
     A.off_lam[1] = o; o += A.lam;
     A.off_tw = o; o += align256(2 * (size_t)A.seg * 2 * c->nx * sizeof(double));  // their wall shears
+    A.off_seed = o; o += align256(2 * (size_t)A.seg * 2 * c->nx * sizeof(double));  // and peak-objective seeds
     A.ring_cap = (int)std::max<int64_t>(A.seg, kAdjRing);  // adjoint launches between reductions
     A.off_part = o; o += align256((size_t)A.ring_cap * A.blocks * 4 * sizeof(double));
     A.off_red = o; o += align256((size_t)A.ring_cap * 4 * sizeof(double));
@@ -1218,6 +1222,17 @@ lbm_status lbm_adjoint_bind(lbm_ctx* c, void* device_ptr, size_t bytes, int64_t 
     return LBM_OK;
 }
 
+lbm_status lbm_adjoint_objective(lbm_ctx* c, int objective) {
+    if (!c || (objective != LBM_J_SUM_TAU2 && objective != LBM_J_PEAK_TAU2)) return LBM_EINVAL;
+    if (!c->adj.bound) return fail(c, LBM_ESTATE, "lbm_adjoint_bind must come first");
+    if (c->adj.objective != objective) {
+        c->adj.objective = objective;
+        c->adj.recorded = c->adj.swept = false;  // J of the record was the other objective
+        c->adj.drop_graphs();                    // the recompute graphs include the seeds or not
+    }
+    return LBM_OK;
+}
+
 lbm_status lbm_adjoint_forward(lbm_ctx* c, double* J) {
     if (!c) return LBM_EINVAL;
     if (!c->adj.bound) return fail(c, LBM_ESTATE, "lbm_adjoint_bind must come first");
@@ -1238,7 +1253,8 @@ lbm_status lbm_adjoint_forward(lbm_ctx* c, double* J) {
     }
     HIP_TRY(c, hipMemcpyAsync(acc1, c->dev + c->off_acc, sizeof acc1, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    A.J = acc1[1] - acc0[1];  // time integral of sum tau_w^2 over the recorded steps
+    const int q = A.objective == LBM_J_PEAK_TAU2 ? 0 : 1;  // acc: [0] int peak tau^2, [1] int sum tau^2
+    A.J = acc1[q] - acc0[q];  // the objective over the recorded steps
     A.recorded = true;
     if (J) *J = A.J;
     return LBM_OK;
@@ -1258,6 +1274,9 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
     // step i of the segment held in field buffer b: its forward fields and wall shears
     auto fld = [&](int b, int64_t i) { return A.dev + A.off_fld + ((size_t)b * A.seg + (size_t)i) * A.fld; };
     auto twp = [&](int b, int64_t i) { return tw + ((size_t)b * A.seg + (size_t)i) * 2 * c->nx; };
+    double* seeds = reinterpret_cast<double*>(A.dev + A.off_seed);
+    auto seedp = [&](int b, int64_t i) { return seeds + ((size_t)b * A.seg + (size_t)i) * 2 * c->nx; };
+    const bool peak = A.objective == LBM_J_PEAK_TAU2;
     HIP_TRY(c, lbm::launch_fill(reinterpret_cast<double*>(A.dev + A.off_lam[0]), 0.0, (long long)(A.lam / 8), c->stream));
     HIP_TRY(c, lbm::launch_fill(acc, 0.0, 4, c->stream));
     A.cur = 0;
@@ -1279,6 +1298,7 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
         if (!*e) HIP_TRY(c, hipEventCreateWithFlags(e, hipEventDisableTiming));
     // Recompute launch j of a segment into field buffer b: step start + 1 + j from pp(j) to pp(j + 1).
     auto rec_launch = [&](int b, int64_t j, hipStream_t s) -> hipError_t {
+        if (j == A.seg) return lbm::launch_peak_seed(twp(b, 0), seedp(b, 0), c->nx, (int)A.seg, s);  // graphs only
         lbm::StepArgs r = fa;
         r.fin = pp(j);
         r.fout = pp(j + 1);
@@ -1296,6 +1316,7 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
         r.lam_in = A.dev + A.off_lam[par];
         r.lam_out = A.dev + A.off_lam[1 - par];
         r.tau_w = twp(b, i);
+        r.seed = peak ? seedp(b, i) : nullptr;
         r.partial = part + (size_t)(ring0 + m) * A.blocks * 4;
         return lbm::launch_adjoint(r, storage, eos, s);
     };
@@ -1307,13 +1328,14 @@ lbm_status lbm_adjoint_backward(lbm_ctx* c, double seed, double* grad) {
         HIP_TRY(c, hipMemcpyAsync(pp(0), A.dev + A.off_ckpt + (size_t)k * A.state, A.state, hipMemcpyDeviceToDevice,
                                   rs));
         if (len == A.seg && graphs) {
-            if (!A.rec_graph[b]) {
+            if (!A.rec_graph[b]) {  // the recompute, then (peak objective) the seeds of its steps
                 auto launch = [&](int j, hipStream_t s) { return rec_launch(b, j, s); };
-                HIP_TRY(c, capture_graph(c->graphs, (int)len, launch, &A.rec_graph[b]));
+                HIP_TRY(c, capture_graph(c->graphs, (int)len + (peak ? 1 : 0), launch, &A.rec_graph[b]));
             }
             HIP_TRY(c, hipGraphLaunch(A.rec_graph[b], rs));
         } else {
             for (int64_t j = 0; j < len; ++j) HIP_TRY(c, rec_launch(b, j, rs));
+            if (peak) HIP_TRY(c, lbm::launch_peak_seed(twp(b, 0), seedp(b, 0), c->nx, (int)len, rs));
         }
         HIP_TRY(c, hipEventRecord(A.ev_rec[b], rs));
         return LBM_OK;

@@ -156,12 +156,17 @@ struct AdjArgs {
     const void* lam_in;    // dJ/df of the next step's pulled populations [9][ny][pitch] (arithmetic type)
     void* lam_out;         // the same for this step
     const double* tau_w;   // [2][nx] this step's wall shear (from its forward recompute)
+    const double* seed;    // [2][nx] dJ/dtau_w of this step, or null for J = sum tau_w^2 (seed 2 tau_w)
     double* partial;       // [blocks][4]: sum F~_x, sum phi~ dphi/dRT, dphi/da_eff, dphi/db
     int nstrip;            // 60-column strips
     int ty;                // output rows per tile (adjoint_tile_shape)
     int waves;             // waves per tile block
 };
 hipError_t launch_adjoint(const AdjArgs& A, int storage, int eos, hipStream_t s);
+// Seeds of the peak objective J = sum over steps of max over walls and columns of
+// tau_w^2, for `steps` consecutive steps of [2][nx] wall shears: seed = 2 tau_w at
+// the first (wall, column) where tau_w^2 is largest, 0 elsewhere.
+hipError_t launch_peak_seed(const double* tau_w, double* seed, int nx, int steps, hipStream_t s);
 // acc[0..3] += the parameter sums of `launches` consecutive adjoint launches
 // (partial: [launches][blocks][4]), launch totals added in launch order; red is
 // scratch of launches x 4 doubles.

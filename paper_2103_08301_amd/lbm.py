@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_EOS_CS, LBM_EOS_PR = 0, 1
 LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F32D, LBM_F32S, LBM_F64T, LBM_F16R = 0, 1, 2, 3, 4, 5, 6, 7
+OBJECTIVES = {"sum": 0, "peak": 1}  # lbm_adjoint_objective_kind
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S, "f32d": LBM_F32D,
            "f32s": LBM_F32S, "f64t": LBM_F64T, "f16r": LBM_F16R}
 
@@ -31,7 +32,7 @@ EXPORTED = [
     "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_set_tangent", "lbm_get_f_tangent",
     "lbm_reset_stress_extremes", "lbm_adjoint_workspace", "lbm_adjoint_bind", "lbm_adjoint_forward",
     "lbm_adjoint_backward", "lbm_adjoint_state_gradient", "lbm_autotune", "lbm_batch_autotune",
-    "lbm_fields_device", "lbm_save", "lbm_load", "lbm_launch_config",
+    "lbm_fields_device", "lbm_save", "lbm_load", "lbm_launch_config", "lbm_adjoint_objective",
 ]
 
 
@@ -142,6 +143,7 @@ def library():
             "lbm_adjoint_workspace": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
             "lbm_adjoint_bind": (C.c_int, [_P, _P, C.c_size_t, C.c_int64, C.c_int64]),
             "lbm_adjoint_forward": (C.c_int, [_P, _D]),
+            "lbm_adjoint_objective": (C.c_int, [_P, C.c_int]),
             "lbm_adjoint_backward": (C.c_int, [_P, C.c_double, _D]),
             "lbm_adjoint_state_gradient": (C.c_int, [_P, _D]),
             "lbm_set_tangent": (C.c_int, [_P, _D]),
@@ -509,14 +511,16 @@ class Lattice:
     def launch_config(self) -> dict:
         return lbm_launch_config(self._ctx)
 
-    def adjoint_bind(self, nsteps: int, segment: int = 0):
-        """Device workspace for recording nsteps steps with a checkpoint every `segment` steps."""
+    def adjoint_bind(self, nsteps: int, segment: int = 0, objective: str = "sum"):
+        """Device workspace for recording nsteps steps with a checkpoint every `segment` steps; objective "sum"
+        (J = sum over steps, walls, columns of tau_w^2) or "peak" (J = sum over steps of the peak tau_w^2)."""
         import torch
 
         nbytes = lbm_adjoint_workspace(self._ctx, nsteps, segment)
         self.adjoint_workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         with torch.cuda.device(self.device):
             lbm_adjoint_bind(self._ctx, self.adjoint_workspace.data_ptr(), nbytes, nsteps, segment)
+        _check(self._ctx, library().lbm_adjoint_objective(self._ctx, OBJECTIVES[objective]))
 
     def adjoint_forward(self) -> tuple:
         """Runs and records the bound number of steps; returns (status, J = int of sum tau_w^2)."""
@@ -619,7 +623,8 @@ class WallShearObjective:
     adjoint kernels.
 
     spec: nx, ny, tau, nsteps, rho_init (ny x nx initial density, held fixed), params (other lbm_params
-    fields; give rho_wall to hold the wall density fixed), optional segment and device.
+    fields; give rho_wall to hold the wall density fixed), optional segment, device and objective ("sum", the
+    default, or "peak": the time integral of the squared peak wall shear).
 
         J = WallShearObjective.apply(theta, spec); J.backward()  ->  theta.grad
     """
@@ -636,7 +641,7 @@ class WallShearObjective:
             @staticmethod
             def forward(ctx, theta, spec):
                 lat = _wall_shear_lattice(theta.detach().cpu().tolist(), spec)
-                lat.adjoint_bind(spec["nsteps"], spec.get("segment", 0))
+                lat.adjoint_bind(spec["nsteps"], spec.get("segment", 0), spec.get("objective", "sum"))
                 st, J = lat.adjoint_forward()
                 if st != LBM_OK:
                     raise LbmError(st, "the forward run went unstable")

@@ -149,8 +149,9 @@ def test_batch_create_validates_cases(L):
 
 def test_adjoint_workspace_layout_and_rules(L):
     """Host-side arithmetic of the adjoint workspace (no device needed): ceil(N/S) checkpoints, the recompute's two
-    states, two segments of S steps of forward fields (five planes and four wall rows of the arithmetic type) and of
-    wall shears, two adjoint fields, the per-launch partials and the FP64 state gradient."""
+    states, two segments of S steps of forward fields (five planes and four wall rows of the arithmetic type), of
+    wall shears and of peak-objective seeds, two adjoint fields, the per-launch partials and the FP64 state
+    gradient."""
     def align(v):
         return (v + 255) // 256 * 256
 
@@ -166,7 +167,7 @@ def test_adjoint_workspace_layout_and_rules(L):
             ring = max(s, 64)
             want = (k * align(pitch * ny * 9 * sb) + 2 * align(pitch * ny * 9 * sb)
                     + 2 * s * align((5 * pitch * ny + 4 * nx) * ab) + 2 * align(pitch * ny * 9 * ab)
-                    + align(2 * s * 2 * nx * 8) + align(ring * blocks * 4 * 8) + align(ring * 4 * 8) + 256
+                    + 2 * align(2 * s * 2 * nx * 8) + align(ring * blocks * 4 * 8) + align(ring * 4 * 8) + 256
                     + align(4 * nx * 8) + align(9 * nx * ny * 8))
             assert L.lbm_adjoint_workspace(ctx, n, seg) == want, (storage, n, seg)
         for n, seg in ((0, 0), (10, 11), (10, -1)):

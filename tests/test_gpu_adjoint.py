@@ -66,6 +66,34 @@ def test_adjoint_equals_tangent_and_oracle_differences(cfg):
         assert grad[k] == pytest.approx(fd, rel=1e-6)
 
 
+@pytest.mark.parametrize("segment", [0, 7])
+def test_peak_objective_against_oracle_differences(segment):
+    """J = int_peak_tau2, the time integral of the squared peak wall shear: the seed of each step sits at the
+    (wall, column) of the peak, and the gradient must match the oracle's differences of its own int_peak_tau2
+    (steps of 1e-5 relative, within which the peak keeps its place: the differences at 1e-5 and 3e-6 agree to
+    1e-8)."""
+    P = Problem(CS)
+
+    def J_peak_oracle(theta):
+        dp, a, b, T = theta
+        s = O.Sim(P.nx, P.ny, P.oparams(dp, a, b, T))
+        s.init_density(P.rho_init)
+        assert s.step(P.steps) == 0
+        return s.history()[-1]["int_peak_tau2"]
+
+    lat = P.lattice(P.theta0, "f64")
+    lat.adjoint_bind(P.steps, segment, objective="peak")
+    st, J = lat.adjoint_forward()
+    assert st == 0
+    assert J == pytest.approx(J_peak_oracle(P.theta0), rel=1e-10)
+    grad = lat.adjoint_backward()
+    for k in CS["dirs"]:
+        fd = richardson(J_peak_oracle, P.theta0, k, 1e-5)  # 1e-3 steps move the peak for a, b and T here
+        log(f"peak J, segment {segment}: dJ/d{NAMES[k]}: adjoint {grad[k]:.12e}  oracle FD {fd:.12e}  "
+            f"rel {abs(grad[k] - fd) / abs(fd):.1e}")
+        assert grad[k] == pytest.approx(fd, rel=1e-6)
+
+
 def test_segment_length_does_not_change_the_gradient():
     P = Problem(CS)
     ref = adjoint(P, segment=0)[1]
