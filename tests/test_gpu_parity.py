@@ -160,13 +160,13 @@ def test_c1_fp64_2000_steps():
     assert hg[-1]["int_tau2"] == pytest.approx(hr[-1]["int_tau2"], rel=1e-9)
 
 
-@pytest.mark.parametrize("storage,bound", [("f32d", 1e-5), ("f32", 1e-4)])
+@pytest.mark.parametrize("storage,bound", [("f32d", 1e-5), ("f32", 1e-5)])
 def test_c1_fp32_storage_within_tolerance(storage, bound):
     """FP32 storage against the FP64 oracle over the 2000 pre-rupture steps of
-    the 256x64 plug case.  With FP64 arithmetic (f32d) rel L-inf(rho) stays
-    below 1e-5; with FP32 arithmetic the rounding of the step drifts the moving
-    rear interface by ~3e-4 lu, i.e. up to ~1e-4 in rho at that interface.
-    Interface positions agree within 0.5 lu in both cases."""
+    the 256x64 plug case: rel L-inf(rho) stays below 1e-5 with FP64 arithmetic
+    (f32d; 3.8e-6) and with FP32 arithmetic (9.3e-6; its force sum is formed in
+    FP64, without which the rounding drifted the moving rear interface by
+    ~3e-4 lu, 8.4e-5 in rho).  Interface positions agree within 0.5 lu."""
     lat, ref = pair(256, 64, 1.0, storage=storage, dp=1e-3, check_every=250)
     rho0 = plug_density(ref, 40, 4, 80, 1e-3, 1)
     lat.init_density(rho0)
