@@ -333,14 +333,17 @@ __device__ inline C lap3(const Row3<C>& s, const Row3<C>& m, const Row3<C>& n) {
     return C(2.0 / 3.0) * (m.e + m.w + n.c + s.c) + C(1.0 / 6.0) * (n.e + n.w + s.e + s.w) - C(10.0 / 3.0) * m.c;
 }
 // One component of the force of eq. 2.17, -dphi + kappa rho dL + g.  Near an interface
-// close to equilibrium the two gradient terms almost cancel, so with FP32 arithmetic the
-// sum is formed in FP64 (summed in FP32, its rounding moved a moving interface by ~3e-4
-// lattice units over 2000 steps, 8e-5 of the density; in FP64, 1e-5); other arithmetic
-// types sum in their own precision.  g64 is g in FP64.
-template <class C>
-__device__ inline C force_sum(C gph, C kappa, C rh, C gl, C g, double g64) {
-    if constexpr (std::is_same<C, float>::value)
-        return float(-double(gph) + double(kappa) * double(rh) * double(gl) + g64);
+// close to equilibrium the two gradient terms almost cancel, so with FP32 storage and
+// arithmetic the sum is formed in FP64 (summed in FP32, its rounding moved a moving
+// interface by ~3e-4 lattice units over 2000 steps, 8e-5 of the density; in FP64, 1e-5).
+// FP16/BF16 storage rounds far more than that sum, and FP64 arithmetic needs no help: they
+// sum in their own precision.  g64 is g in FP64.
+template <class CD>
+__device__ inline typename CD::C force_sum(typename CD::C gph, typename CD::C kappa, typename CD::C rh,
+                                           typename CD::C gl, typename CD::C g, double g64) {
+    using C = typename CD::C;
+    if constexpr (std::is_same<C, float>::value && sizeof(typename CD::S) == 4)
+        return float(-double(gph) + double(kappa * rh * gl) + g64);
     else
         return -gph + kappa * rh * gl + g;
 }
@@ -602,8 +605,8 @@ struct Stepper {
             C glx, gly;
             grad3(W.lap3r, W.lap2, lap1, glx, gly);
             const C rh = W.rho2.c;
-            const C Fx = force_sum<C>(W.gphx, kappa, rh, glx, g, a.g);
-            const C Fy = force_sum<C>(W.gphy, kappa, rh, gly, C(0), 0.0);
+            const C Fx = force_sum<CD>(W.gphx, kappa, rh, glx, g, a.g);
+            const C Fy = force_sum<CD>(W.gphy, kappa, rh, gly, C(0), 0.0);
             C* f2 = W.f2;
             const C jx = (f2[1] - f2[3]) + (f2[5] - f2[6]) + (f2[8] - f2[7]);
             const C jy = (f2[2] - f2[4]) + (f2[5] - f2[8]) + (f2[6] - f2[7]);
@@ -861,8 +864,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
             grad3(s, m, n, glx, gly);
         }
         const C rh = sRho[k][lane];
-        const C Fx = force_sum<C>(gphx, kappa, rh, glx, g, a.g);
-        const C Fy = force_sum<C>(gphy, kappa, rh, gly, C(0), 0.0);
+        const C Fx = force_sum<CD>(gphx, kappa, rh, glx, g, a.g);
+        const C Fy = force_sum<CD>(gphy, kappa, rh, gly, C(0), 0.0);
         C* fj = f[j];
         const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
         const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
@@ -1154,8 +1157,8 @@ struct Pipe {
                 grad3(s, m, n, glx, gly);
             }
             const C rh = sRho[k][lane];
-            const C Fx = force_sum<C>(gphx, kappa, rh, glx, gx, a.g);
-            const C Fy = force_sum<C>(gphy, kappa, rh, gly, C(0), 0.0);
+            const C Fx = force_sum<CD>(gphx, kappa, rh, glx, gx, a.g);
+            const C Fy = force_sum<CD>(gphy, kappa, rh, gly, C(0), 0.0);
             C* fj = fc[j];
             const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
             const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
@@ -1342,8 +1345,8 @@ __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v,
             grad3(s, m, n, glx, gly);
         }
         const C rh = sRho[k][lane];
-        const C Fx = force_sum<C>(gphx, kappa, rh, glx, g, a.g);
-        const C Fy = force_sum<C>(gphy, kappa, rh, gly, C(0), 0.0);
+        const C Fx = force_sum<CD>(gphx, kappa, rh, glx, g, a.g);
+        const C Fy = force_sum<CD>(gphy, kappa, rh, gly, C(0), 0.0);
         const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
         const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
         collide<C>(fj, rh, jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
