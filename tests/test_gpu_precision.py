@@ -40,8 +40,8 @@ STEPS = [500, 2000, 5000] + ([20000, 100000] if CAMPAIGN else [])
 # Upper bounds on rel L-inf(rho) and on |mass drift| per storage at each
 # checkpoint: the measured values times about 3 (the runs are deterministic).
 # Measured rel L-inf(rho) at 500 / 2000 / 5000 / 20000 / 100000 steps:
-#   f32    3.5e-6  5.8e-6  8.7e-6  1.9e-5  3.5e-4   (mass drift <= 1.2e-6)
-#   f32s   3.7e-6  5.9e-6  7.6e-6  3.1e-5  3.7e-4   (mass drift <= 1.3e-6)
+#   f32    3.7e-6  5.9e-6  7.2e-6  2.3e-5  3.6e-4   (mass drift <= 1.3e-6)
+#   f32s   3.7e-6  6.4e-6  6.8e-6  2.7e-5  3.7e-4   (mass drift <= 1.4e-6)
 #   f16s   1.2e-3  8.8e-3  7.4e-2  0.70    0.70     (drift -3.4e-4 at 5000, +9.7e-2 at 100000)
 #   bf16s  8.5e-2  0.40    0.70    0.70    0.70     (drift -4.0e-3 at 500)
 #   f16r   1.3e-3  2.5e-3  2.5e-2  0.11    0.42     (mass drift <= 2.3e-4)
