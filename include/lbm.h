@@ -114,7 +114,7 @@ typedef struct {
     int pipe_blocks;     /* schedule 2: blocks launched; 0 = compute units x blocks one unit holds,
                             otherwise >= 8 (every one of the 8 tile ranges needs a block) */
     int graph_steps;     /* schedules 0 and 1 (and batches): steps per captured HIP graph of step launches,
-                            replayed instead of launching kernel by kernel; 0 selects 256, -1 launches every
+                            replayed instead of launching kernel by kernel; 0 selects 64, -1 launches every
                             step directly; otherwise 2, 4, 8, 16, 32, 64, 128 or 256 */
     int fused_steps;     /* schedule 0 (single lattices, not F64T): steps per launch, 0 (= 1), 1 or 2.  2: one
                             launch advances two steps, keeping the intermediate populations in LDS (54 x 14-row

@@ -222,9 +222,9 @@ def test_checkpoint_and_device_fields_need_a_bound_lattice(L, tmp_path):
 def test_launch_config_reports_the_parameters(L):
     """lbm_launch_config reads the host-side launch configuration (no device needed)."""
     lib = L.library()
-    for kw, want in ((dict(), (8, 4, 1, 256)), (dict(storage="f64"), (12, 4, 1, 256)),
-                     (dict(fused_steps=2, graph_steps=-1), (8, 4, 2, 0)), (dict(tile_waves=8), (12, 8, 1, 256)),
-                     (dict(graph_steps=64), (8, 4, 1, 64))):
+    for kw, want in ((dict(), (8, 4, 1, 64)), (dict(storage="f64"), (12, 4, 1, 64)),
+                     (dict(fused_steps=2, graph_steps=-1), (8, 4, 2, 0)), (dict(tile_waves=8), (12, 8, 1, 64)),
+                     (dict(graph_steps=256), (8, 4, 1, 256))):
         ctx = L.lbm_create(64, 16, 1.0, L.lbm_params_default(**kw))
         v = [L.C.c_int() for _ in range(4)]
         assert lib.lbm_launch_config(ctx, *(L.C.byref(x) for x in v)) == L.LBM_OK
