@@ -82,13 +82,19 @@ def test_autotune_rules():
 
 
 def test_autotune_two_steps_per_launch_on_a_small_grid():
-    """A 256x64 grid is far from filling the chip: two steps per launch halve the launches and are chosen
-    (measured 10-25% faster per step there); stochastic-rounding storage has no two-step kernel."""
-    lat = Lattice(256, 64, 1.0, storage="f32", T_over_Tc=0.95, dp=1e-3, check_every=100, v_limit=1.0)
-    lat.init_plug(40, 4, math.nan, 1e-3, 2)
+    """A 256x64 grid is far from filling the chip: two steps per launch halve the launches (measured 10-25% faster
+    per step at such sizes, so the tuner picks them; the choice is timing, so it is logged, not asserted), and the
+    run continues bit for bit whatever the choice; stochastic-rounding storage has no two-step kernel."""
+    kw = dict(storage="f32", T_over_Tc=0.95, dp=1e-3, check_every=100, v_limit=1.0)
+    lat, ref = Lattice(256, 64, 1.0, **kw), Lattice(256, 64, 1.0, **kw)
+    for l in (lat, ref):
+        l.init_plug(40, 4, math.nan, 1e-3, 2)
     pick = lat.autotune(200)
     print("small grid", pick, flush=True)
-    assert pick["fused_steps"] == 2
+    assert pick["fused_steps"] in (1, 2)
+    for l in (lat, ref):
+        assert l.step(333) == 0
+    assert np.array_equal(lat.get_f(), ref.get_f())
     r = Lattice(256, 64, 1.0, storage="f16r", T_over_Tc=0.95, dp=1e-3, check_every=100, v_limit=1.0)
     r.init_plug(40, 4, math.nan, 1e-3, 2)
     assert r.autotune(50)["fused_steps"] == 1
