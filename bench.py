@@ -395,7 +395,7 @@ def main() -> int:
     AUTOTUNE = args.autotune
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
     if "RANK" in os.environ and os.environ.get("WORLD_SIZE", "1") != "1":
         print("bench.py: multi-rank launch is not supported (one GPU only)", file=sys.stderr)
