@@ -193,6 +193,9 @@ def test_calls_before_binding_the_adjoint_are_rejected(L):
     assert L.library().lbm_adjoint_state_gradient(ctx, g) == L.LBM_ESTATE
     assert L.library().lbm_autotune(ctx, 10, None, None, None) == L.LBM_ESTATE
     assert L.library().lbm_adjoint_backward(ctx, math.nan, g) == L.LBM_EINVAL
+    assert L.library().lbm_adjoint_objective(ctx, 1) == L.LBM_ESTATE  # before lbm_adjoint_bind
+    assert L.library().lbm_adjoint_objective(ctx, 2) == L.LBM_EINVAL  # no such objective
+    assert L.library().lbm_adjoint_objective(None, 0) == L.LBM_EINVAL
     L.lbm_destroy(ctx)
 
 
