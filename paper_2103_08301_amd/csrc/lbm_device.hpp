@@ -876,10 +876,12 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
             const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
             if constexpr (stochastic_codec<CD>()) {
                 // 96 random bits per node and step: three hashes of (node, step), 10 bits per
-                // population.  (Deriving two of the words from the first by xorshift steps
-                // leaves only 32 bits of entropy per node; measured on the periodic plug
-                // channel, its interfaces lag the FP64 ones by 1.3-1.7 lattice units after
-                // 20000 steps against 0.9-1.4 with three hashes.)
+                // population, so the nine populations of a node round independently (words
+                // derived from one hash by xorshift steps would carry only 32 bits of entropy
+                // per node).  The interface lag that stochastic rounding leaves on the periodic
+                // plug channel (1-2 lattice units behind FP64 after 20000 steps) does not shrink
+                // with 12 random bits per population instead of 8 or 10: it comes from the
+                // rounding noise itself, not from the dither's resolution.
                 const uint32_t nd = uint32_t(y * a.pitch + x) * 3u;
                 const uint32_t h[3] = {hash32(sr_seed ^ nd), hash32(sr_seed ^ (nd + 1u)), hash32(sr_seed ^ (nd + 2u))};
 #define LBM_SSTORE(I) \
