@@ -3,11 +3,11 @@
 A plug in a 256x64 channel with periodic ends (CS 0.95 Tc, tau 0.8, plug 40 at
 x = 80, film 4, noise 1e-3 seed 1, dp 1e-4) is run with each storage type
 from the same density field as an FP64 oracle run and compared at fixed steps:
-relative L-inf and L2 error of rho, the liquid-column count, and the drift of
-the total mass.  This case stays stable beyond 100000 steps and, with periodic
-ends and bounce-back walls, conserves mass exactly in exact arithmetic (the
-oracle's FP64 drift is ~5e-12 after 100000 steps), so the drift measures what
-the storage rounding does to conservation.
+relative L-inf and L2 error of rho, the interface positions, the liquid-column
+count, and the drift of the total mass.  This case stays stable beyond 100000
+steps and, with periodic ends and bounce-back walls, conserves mass exactly in
+exact arithmetic (the oracle's FP64 drift is ~5e-12 after 100000 steps), so the
+drift measures what the storage rounding does to conservation.
 
 Storage types: f32 (plain FP32), f32s (FP32 of f_i - w_i rho0), f16s and
 bf16s (FP16/BF16 of f_i - w_i rho0, rho0 = rho_g), f16r (FP16 of f_i - w_i rho0
@@ -47,15 +47,24 @@ STEPS = [500, 2000, 5000] + ([20000, 100000] if CAMPAIGN else [])
 #   f16r   1.3e-3  2.5e-3  2.5e-2  0.11    0.42     (mass drift <= 2.3e-4)
 # FP16 storage follows the trajectory for a few thousand steps and then drifts
 # off it (its rounding acts as a mass source); BF16 storage does not follow it.
-# FP16 with stochastic rounding (f16r) keeps the mass to 4e-5 over 20000 steps
-# and the interfaces within 1.2 lattice units of the oracle's (FP16 storage
-# with round-to-nearest: 24).
+# FP16 with stochastic rounding (f16r) keeps the mass to 4e-5 over 20000 steps;
+# its interfaces are 0.25 lattice units behind the oracle's at 5000 steps and
+# 1.2 behind at 20000 (FP16 storage with round-to-nearest: 0.8 and 24 ahead).
 BOUNDS = {
     "f32": {500: 1.2e-5, 2000: 2e-5, 5000: 3e-5, 20000: 6e-5, 100000: 1.2e-3},
     "f32s": {500: 1.2e-5, 2000: 2e-5, 5000: 3e-5, 20000: 1e-4, 100000: 1.2e-3},
     "f16s": {500: 4e-3, 2000: 3e-2, 5000: 0.25},
     "bf16s": {500: 0.3},
     "f16r": {500: 5e-3, 2000: 2e-2, 5000: 8e-2, 20000: 0.35},
+}
+# Upper bounds on the distance (lattice units) of the rear and front interfaces
+# from the oracle's.  FP32 storage matches them to 1e-3.  For f16r the bound is
+# the 0.5 lu interface criterion for reduced-precision storage; over six seeds
+# of the initial noise the measured lag at 5000 steps was 0.17-0.28 lu.
+INTERFACE_BOUNDS = {
+    "f32": {500: 0.01, 2000: 0.01, 5000: 0.01, 20000: 0.01},
+    "f32s": {500: 0.01, 2000: 0.01, 5000: 0.01, 20000: 0.01},
+    "f16r": {500: 0.5, 2000: 0.5, 5000: 0.5},
 }
 MASS_BOUNDS = {
     "f32": {500: 3e-8, 2000: 3e-8, 5000: 3e-8, 20000: 1.5e-7, 100000: 4e-6},
@@ -110,5 +119,8 @@ def test_storage_error_against_oracle(reference, storage):
         assert math.isfinite(e_inf)
         if s in BOUNDS[storage]:
             assert e_inf <= BOUNDS[storage][s], (storage, s, e_inf)
+        if s in INTERFACE_BOUNDS.get(storage, {}):
+            lim = INTERFACE_BOUNDS[storage][s]
+            assert abs(chk["x_rear"] - xr) <= lim and abs(chk["x_front"] - xf) <= lim, (storage, s, chk, xr, xf)
         if s in MASS_BOUNDS[storage]:
             assert abs(drift) <= MASS_BOUNDS[storage][s], (storage, s, drift)
