@@ -172,7 +172,11 @@ lbm_status lbm_workspace(const lbm_ctx* ctx, size_t* bytes);
 
 /* Binds caller-owned device memory (>= lbm_workspace bytes, 256-aligned) on
    the current HIP device and the hipStream_t (NULL = default stream) for all
-   later launches.  Rebinding moves no data: initialise again afterwards. */
+   later launches.  Rebinding moves no data: initialise again afterwards.
+   LBM_ENOMEM if bytes is too small; LBM_EINVAL if the pointer is null or not
+   256-aligned, or if the first or last byte of the workspace is not device
+   memory of the current device (host, pinned-host or unregistered memory,
+   another device), checked on the host before anything is launched. */
 lbm_status lbm_bind(lbm_ctx* ctx, void* device_ptr, size_t bytes, void* hip_stream);
 
 /* Temperature, critical temperature, coexistence densities and wall density
@@ -265,8 +269,8 @@ lbm_status lbm_launch_config(const lbm_ctx* ctx, int* tile_rows, int* tile_waves
    fields (9 x ny x pitch) of the arithmetic type, 2 x segment x 2 x nx FP64
    wall shears and small scratch; it is
    caller-owned device memory like the main workspace, 256-byte aligned, and
-   bound once.  Storage F64, F32 or F32D with the tile schedule; otherwise
-   LBM_EINVAL. */
+   bound once (the same pointer checks as lbm_bind).  Storage F64, F32 or
+   F32D with the tile schedule; otherwise LBM_EINVAL. */
 lbm_status lbm_adjoint_workspace(const lbm_ctx* ctx, int64_t nsteps, int64_t segment, size_t* bytes);
 lbm_status lbm_adjoint_bind(lbm_ctx* ctx, void* device_ptr, size_t bytes, int64_t nsteps, int64_t segment);
 
@@ -404,7 +408,8 @@ lbm_status lbm_batch_create(int n, const int* nx, const int* ny, const double* t
 lbm_status lbm_batch_workspace(const lbm_batch* b, size_t* bytes);
 /* Binds caller-owned device memory (256-byte aligned, at least lbm_batch_workspace
    bytes; the caller keeps ownership) and a stream to the batch and all its
-   cases, and uploads the launch table (synchronises the stream). */
+   cases, and uploads the launch table (synchronises the stream).  The same
+   pointer checks as lbm_bind. */
 lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hip_stream);
 /* Borrowed handle of case k (0 <= k < n), valid until lbm_batch_destroy. */
 lbm_status lbm_batch_case(lbm_batch* b, int k, lbm_ctx** ctx);

@@ -387,6 +387,31 @@ lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
     return s;
 }
 
+// Whether the first and the last byte of [p, p + bytes) are device memory of the current
+// device.  A host pointer handed to a bind call by mistake would otherwise surface only as
+// a memory fault of the first kernel that touches it; this turns it into an error at bind
+// time.  (Memory of another allocation right after the buffer cannot be told apart.)
+// Returns nullptr when the range is usable, else the reason.
+const char* device_range_problem(const void* p, size_t bytes) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "no current HIP device";
+    }
+    const char* ends[2] = {static_cast<const char*>(p), static_cast<const char*>(p) + (bytes ? bytes - 1 : 0)};
+    for (const char* q : ends) {
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, q) != hipSuccess) {
+            (void)hipGetLastError();  // clear it, so that the next HIP call does not report it
+            return "the workspace is not HIP device memory";
+        }
+        if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+            return "the workspace is not HIP device memory (host or unregistered memory)";
+        if (at.device != dev) return "the workspace lies on another device than the current one";
+    }
+    return nullptr;
+}
+
 #define HIP_TRY(ctx, expr)                                                                        \
     do {                                                                                          \
         hipError_t e_ = (expr);                                                                   \
@@ -702,6 +727,7 @@ lbm_status lbm_bind(lbm_ctx* c, void* device_ptr, size_t bytes, void* hip_stream
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return fail(c, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
     if (bytes < c->total) return fail(c, LBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, c->total);
+    if (const char* why = device_range_problem(device_ptr, c->total)) return fail(c, LBM_EINVAL, "%s", why);
     HIP_TRY(c, hipGetDevice(&c->device));
     if (c->schedule == lbm::kSchedulePipe) {
         if (c->p.pipe_blocks > 0)
@@ -1216,6 +1242,7 @@ lbm_status lbm_adjoint_bind(lbm_ctx* c, void* device_ptr, size_t bytes, int64_t 
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return fail(c, LBM_EINVAL, "adjoint workspace pointer must be non-null and 256-byte aligned");
     if (bytes < A.total) return fail(c, LBM_ENOMEM, "adjoint workspace of %zu bytes < %zu needed", bytes, A.total);
+    if (const char* why = device_range_problem(device_ptr, A.total)) return fail(c, LBM_EINVAL, "adjoint: %s", why);
     A.dev = static_cast<char*>(device_ptr);
     A.bound = true;
     c->adj = A;
@@ -1687,6 +1714,7 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return bfail(b, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
     if (bytes < b->total) return bfail(b, LBM_ENOMEM, "workspace too small for the batch");
+    if (const char* why = device_range_problem(device_ptr, b->total)) return bfail(b, LBM_EINVAL, why);
     b->dev = static_cast<char*>(device_ptr);
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->graphs.drop();

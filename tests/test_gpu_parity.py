@@ -10,6 +10,7 @@ grids (FMA contraction and summation order are the only differences) and
 <= 1e-10 on the 256x64, 2000-step plug case; FP32 <= 1e-5 relative L-inf on
 rho and <= 0.5 lattice units on the interface positions before rupture.
 """
+import ctypes as C
 import math
 import sys
 
@@ -23,7 +24,7 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
 import oracle as O  # noqa: E402
-from paper_2103_08301_amd import Lattice, lbm  # noqa: E402
+from paper_2103_08301_amd import Batch, Lattice, lbm  # noqa: E402
 
 ORACLE_KEYS = {  # parameters the oracle shares with the library
 "eos", "a", "b", "R", "omega", "T_over_Tc", "k", "kappa", "s_e", "s_eps", "s_q", "s_j",
@@ -277,6 +278,41 @@ def test_errors_and_state_machine():
         lbm.lbm_bind(ctx, ws.data_ptr(), 1024, torch.cuda.current_stream().cuda_stream)
     assert e.value.status == lbm.LBM_ENOMEM
     lbm.lbm_destroy(ctx)
+
+
+def test_bind_refuses_memory_that_is_not_on_the_device():
+    """Pageable or pinned host memory handed to a bind call is refused on the host
+    (LBM_EINVAL, nothing launched), and the library keeps working afterwards."""
+    stream = torch.cuda.current_stream().cuda_stream
+    lat = Lattice(64, 16, 1.0, storage="f64")
+    need = lbm.lbm_workspace(lat.ctx)
+    aneed = lbm.lbm_adjoint_workspace(lat.ctx, 20)
+    big = max(need, aneed) + 256
+    host = torch.empty(big, dtype=torch.uint8)
+    pinned = torch.empty(big, dtype=torch.uint8, pin_memory=True)
+    batch = Batch([dict(nx=64, ny=16, tau=1.0), dict(nx=48, ny=12, tau=0.9)], storage="f64")
+    size = C.c_size_t()
+    assert lbm.library().lbm_batch_workspace(batch._b, C.byref(size)) == lbm.LBM_OK
+    for buf in (host, pinned):
+        p = (buf.data_ptr() + 255) // 256 * 256
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_bind(lat.ctx, p, need, stream)
+        assert e.value.status == lbm.LBM_EINVAL and "device memory" in str(e.value), str(e.value)
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_adjoint_bind(lat.ctx, p, aneed, 20)
+        assert e.value.status == lbm.LBM_EINVAL and "device memory" in str(e.value), str(e.value)
+    # the batch check, on a host buffer large enough for the batch
+    hb = torch.empty(size.value + 256, dtype=torch.uint8)
+    p = (hb.data_ptr() + 255) // 256 * 256
+    assert lbm.library().lbm_batch_bind(batch._b, C.c_void_p(p), size.value, C.c_void_p(stream)) == lbm.LBM_EINVAL
+    assert b"device memory" in lbm.library().lbm_batch_last_error(batch._b)
+    # the lattice and the batch still run on their own device workspaces
+    lbm.lbm_bind(lat.ctx, lat.workspace.data_ptr(), need, stream)
+    lat.init_plug(20, 2)
+    assert lat.step(20) == lbm.LBM_OK and lat.check()["nan_count"] == 0
+    for k in range(2):
+        batch[k].init_plug(16, 2)
+    assert batch.step(10) == lbm.LBM_OK
 
 
 def test_instability_is_reported_at_a_check():
