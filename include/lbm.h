@@ -213,7 +213,10 @@ lbm_status lbm_fields(lbm_ctx* ctx, double* rho, double* vx, double* vy);
 
 /* The fields of lbm_fields copied to caller-owned device arrays [ny][nx] on the
    bound stream (asynchronously; e.g. torch tensors): FP64 when fp64 != 0, else
-   FP32 (rounded to nearest).  Any pointer may be NULL. */
+   FP32 (rounded to nearest).  Any pointer may be NULL.  LBM_ESTATE before an
+   initialisation; LBM_EINVAL, before anything is copied, if an output is not
+   aligned to its element size or its first or last element is not device
+   memory of the current device. */
 lbm_status lbm_fields_device(lbm_ctx* ctx, void* rho, void* vx, void* vy, int fp64);
 
 /* Wall shear stress and wall pressure of the last step along both walls

@@ -388,7 +388,8 @@ lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
 }
 
 // Whether the first and the last byte of [p, p + bytes) are device memory of the current
-// device.  A host pointer handed to a bind call by mistake would otherwise surface only as
+// device.  A host pointer handed to a bind call (or as a device output) by mistake would
+// otherwise surface only as
 // a memory fault of the first kernel that touches it; this turns it into an error at bind
 // time.  (Memory of another allocation right after the buffer cannot be told apart.)
 // Returns nullptr when the range is usable, else the reason.
@@ -403,11 +404,11 @@ const char* device_range_problem(const void* p, size_t bytes) {
         hipPointerAttribute_t at{};
         if (hipPointerGetAttributes(&at, q) != hipSuccess) {
             (void)hipGetLastError();  // clear it, so that the next HIP call does not report it
-            return "the workspace is not HIP device memory";
+            return "not HIP device memory";
         }
         if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
-            return "the workspace is not HIP device memory (host or unregistered memory)";
-        if (at.device != dev) return "the workspace lies on another device than the current one";
+            return "not HIP device memory (host or unregistered memory)";
+        if (at.device != dev) return "memory of another device than the current one";
     }
     return nullptr;
 }
@@ -727,7 +728,8 @@ lbm_status lbm_bind(lbm_ctx* c, void* device_ptr, size_t bytes, void* hip_stream
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return fail(c, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
     if (bytes < c->total) return fail(c, LBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, c->total);
-    if (const char* why = device_range_problem(device_ptr, c->total)) return fail(c, LBM_EINVAL, "%s", why);
+    if (const char* why = device_range_problem(device_ptr, c->total))
+        return fail(c, LBM_EINVAL, "workspace: %s", why);
     HIP_TRY(c, hipGetDevice(&c->device));
     if (c->schedule == lbm::kSchedulePipe) {
         if (c->p.pipe_blocks > 0)
@@ -1242,7 +1244,8 @@ lbm_status lbm_adjoint_bind(lbm_ctx* c, void* device_ptr, size_t bytes, int64_t 
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return fail(c, LBM_EINVAL, "adjoint workspace pointer must be non-null and 256-byte aligned");
     if (bytes < A.total) return fail(c, LBM_ENOMEM, "adjoint workspace of %zu bytes < %zu needed", bytes, A.total);
-    if (const char* why = device_range_problem(device_ptr, A.total)) return fail(c, LBM_EINVAL, "adjoint: %s", why);
+    if (const char* why = device_range_problem(device_ptr, A.total))
+        return fail(c, LBM_EINVAL, "adjoint workspace: %s", why);
     A.dev = static_cast<char*>(device_ptr);
     A.bound = true;
     c->adj = A;
@@ -1603,6 +1606,14 @@ lbm_status lbm_fields_device(lbm_ctx* c, void* rho, void* vx, void* vy, int fp64
     const long long n = (long long)c->nx * c->ny;
     void* outs[3] = {rho, vx, vy};
     const size_t off_fields[3] = {c->off_rho, c->off_vx, c->off_vy};
+    const size_t elem = fp64 ? sizeof(double) : sizeof(float);
+    for (int q = 0; q < 3; ++q) {
+        if (!outs[q]) continue;
+        if (reinterpret_cast<uintptr_t>(outs[q]) % elem)
+            return fail(c, LBM_EINVAL, "fields_device: output %d is not aligned to its element size", q);
+        if (const char* why = device_range_problem(outs[q], (size_t)n * elem))
+            return fail(c, LBM_EINVAL, "fields_device: output %d: %s", q, why);
+    }
     for (int q = 0; q < 3; ++q) {
         if (!outs[q]) continue;
         const double* src = c->at<double>(off_fields[q]);
@@ -1714,7 +1725,8 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return bfail(b, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
     if (bytes < b->total) return bfail(b, LBM_ENOMEM, "workspace too small for the batch");
-    if (const char* why = device_range_problem(device_ptr, b->total)) return bfail(b, LBM_EINVAL, why);
+    if (const char* why = device_range_problem(device_ptr, b->total))
+        return bfail(b, LBM_EINVAL, std::string("workspace: ") + why);
     b->dev = static_cast<char*>(device_ptr);
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->graphs.drop();

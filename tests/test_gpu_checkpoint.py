@@ -125,3 +125,26 @@ def test_fields_device_equal_host_fields():
         assert d64.dtype == torch.float64 and d64.shape == (40, 150) and d64.device.type == "cuda"
         assert np.array_equal(d64.cpu().numpy(), h)
         assert np.array_equal(d32.cpu().numpy(), h.astype(np.float32))
+
+
+def test_fields_device_refuses_host_outputs():
+    a = make("f32")
+    a.init_plug(36, 4, math.nan, 1e-3, 3)
+    a.step(5)
+    dev = torch.empty((40, 150), dtype=torch.float64, device="cuda")
+    host = torch.empty((40, 150), dtype=torch.float64)
+    pinned = torch.empty((40, 150), dtype=torch.float64, pin_memory=True)
+    for bad in (host, pinned):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_fields_device(a.ctx, dev.data_ptr(), bad.data_ptr(), 0, True)
+        assert e.value.status == lbm.LBM_EINVAL and "device memory" in str(e.value), str(e.value)
+    # (whether a device buffer that is too short is caught depends on what lies after it,
+    # so the remaining case tested is a misaligned output)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_fields_device(a.ctx, dev.data_ptr() + 4, 0, 0, True)
+    assert e.value.status == lbm.LBM_EINVAL and "aligned" in str(e.value)
+    # nothing was copied, and the calls that follow still work
+    assert a.step(5) == lbm.LBM_OK
+    rho = a.fields_device()[0]
+    torch.cuda.synchronize()
+    assert np.array_equal(rho.cpu().numpy(), a.fields()[0])
