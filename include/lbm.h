@@ -176,7 +176,8 @@ lbm_status lbm_workspace(const lbm_ctx* ctx, size_t* bytes);
    LBM_ENOMEM if bytes is too small; LBM_EINVAL if the pointer is null or not
    256-aligned, or if the first or last byte of the workspace is not device
    memory of the current device (host, pinned-host or unregistered memory,
-   another device), checked on the host before anything is launched. */
+   another device), checked on the host before anything is launched;
+   LBM_EDEVICE when there is no current HIP device. */
 lbm_status lbm_bind(lbm_ctx* ctx, void* device_ptr, size_t bytes, void* hip_stream);
 
 /* Temperature, critical temperature, coexistence densities and wall density

@@ -389,28 +389,35 @@ lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
 
 // Whether the first and the last byte of [p, p + bytes) are device memory of the current
 // device.  A host pointer handed to a bind call (or as a device output) by mistake would
-// otherwise surface only as
-// a memory fault of the first kernel that touches it; this turns it into an error at bind
-// time.  (Memory of another allocation right after the buffer cannot be told apart.)
-// Returns nullptr when the range is usable, else the reason.
-const char* device_range_problem(const void* p, size_t bytes) {
+// otherwise surface only as a memory fault of the first kernel that touches it; this turns
+// it into an error before anything is launched.  (Memory of another allocation right after
+// the buffer cannot be told apart.)  LBM_OK when the range is usable; LBM_EDEVICE when there
+// is no current device, LBM_EINVAL for memory that is not on it, with the reason in *why.
+lbm_status device_range_check(const void* p, size_t bytes, const char** why) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) {
         (void)hipGetLastError();
-        return "no current HIP device";
+        *why = "no current HIP device";
+        return LBM_EDEVICE;
     }
     const char* ends[2] = {static_cast<const char*>(p), static_cast<const char*>(p) + (bytes ? bytes - 1 : 0)};
     for (const char* q : ends) {
         hipPointerAttribute_t at{};
         if (hipPointerGetAttributes(&at, q) != hipSuccess) {
             (void)hipGetLastError();  // clear it, so that the next HIP call does not report it
-            return "not HIP device memory";
+            *why = "not HIP device memory";
+            return LBM_EINVAL;
         }
-        if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
-            return "not HIP device memory (host or unregistered memory)";
-        if (at.device != dev) return "memory of another device than the current one";
+        if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) {
+            *why = "not HIP device memory (host or unregistered memory)";
+            return LBM_EINVAL;
+        }
+        if (at.device != dev) {
+            *why = "memory of another device than the current one";
+            return LBM_EINVAL;
+        }
     }
-    return nullptr;
+    return LBM_OK;
 }
 
 #define HIP_TRY(ctx, expr)                                                                        \
@@ -728,8 +735,8 @@ lbm_status lbm_bind(lbm_ctx* c, void* device_ptr, size_t bytes, void* hip_stream
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return fail(c, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
     if (bytes < c->total) return fail(c, LBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, c->total);
-    if (const char* why = device_range_problem(device_ptr, c->total))
-        return fail(c, LBM_EINVAL, "workspace: %s", why);
+    const char* why = nullptr;
+    if (lbm_status st = device_range_check(device_ptr, c->total, &why)) return fail(c, st, "workspace: %s", why);
     HIP_TRY(c, hipGetDevice(&c->device));
     if (c->schedule == lbm::kSchedulePipe) {
         if (c->p.pipe_blocks > 0)
@@ -1244,8 +1251,9 @@ lbm_status lbm_adjoint_bind(lbm_ctx* c, void* device_ptr, size_t bytes, int64_t 
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return fail(c, LBM_EINVAL, "adjoint workspace pointer must be non-null and 256-byte aligned");
     if (bytes < A.total) return fail(c, LBM_ENOMEM, "adjoint workspace of %zu bytes < %zu needed", bytes, A.total);
-    if (const char* why = device_range_problem(device_ptr, A.total))
-        return fail(c, LBM_EINVAL, "adjoint workspace: %s", why);
+    const char* why = nullptr;
+    if (lbm_status st = device_range_check(device_ptr, A.total, &why))
+        return fail(c, st, "adjoint workspace: %s", why);
     A.dev = static_cast<char*>(device_ptr);
     A.bound = true;
     c->adj = A;
@@ -1611,8 +1619,9 @@ lbm_status lbm_fields_device(lbm_ctx* c, void* rho, void* vx, void* vy, int fp64
         if (!outs[q]) continue;
         if (reinterpret_cast<uintptr_t>(outs[q]) % elem)
             return fail(c, LBM_EINVAL, "fields_device: output %d is not aligned to its element size", q);
-        if (const char* why = device_range_problem(outs[q], (size_t)n * elem))
-            return fail(c, LBM_EINVAL, "fields_device: output %d: %s", q, why);
+        const char* why = nullptr;
+        if (lbm_status st = device_range_check(outs[q], (size_t)n * elem, &why))
+            return fail(c, st, "fields_device: output %d: %s", q, why);
     }
     for (int q = 0; q < 3; ++q) {
         if (!outs[q]) continue;
@@ -1725,8 +1734,9 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
     if (!device_ptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255))
         return bfail(b, LBM_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
     if (bytes < b->total) return bfail(b, LBM_ENOMEM, "workspace too small for the batch");
-    if (const char* why = device_range_problem(device_ptr, b->total))
-        return bfail(b, LBM_EINVAL, std::string("workspace: ") + why);
+    const char* why = nullptr;
+    if (lbm_status st = device_range_check(device_ptr, b->total, &why))
+        return bfail(b, st, std::string("workspace: ") + why);
     b->dev = static_cast<char*>(device_ptr);
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->graphs.drop();

@@ -233,3 +233,25 @@ def test_launch_config_reports_the_parameters(L):
         assert lib.lbm_launch_config(ctx, *(L.C.byref(x) for x in v)) == L.LBM_OK
         assert tuple(x.value for x in v) == want, kw
         L.lbm_destroy(ctx)
+
+
+def test_bind_checks_the_workspace_before_any_launch(L):
+    """lbm_bind checks the workspace pointer on the host: without a GPU the call reports
+    LBM_EDEVICE, with one a host buffer is LBM_EINVAL; nothing is launched either way."""
+    import ctypes as C
+
+    import numpy as np
+
+    ctx = L.lbm_create(64, 16, 1.0, L.lbm_params_default())
+    try:
+        need = L.lbm_workspace(ctx)
+        buf = np.zeros(need + 256, dtype=np.uint8)
+        p = (buf.ctypes.data + 255) // 256 * 256
+        st = L.library().lbm_bind(ctx, C.c_void_p(p), need, None)
+        assert st in (L.LBM_EDEVICE, L.LBM_EINVAL), st
+        msg = L.library().lbm_last_error(ctx).decode()
+        assert msg.startswith("workspace: ") and ("no current HIP device" in msg or "device memory" in msg), msg
+        # a step after the refused bind is out of order, not a launch
+        assert L.library().lbm_step(ctx, 1) == L.LBM_ESTATE
+    finally:
+        L.lbm_destroy(ctx)
