@@ -255,3 +255,22 @@ def test_bind_checks_the_workspace_before_any_launch(L):
         assert L.library().lbm_step(ctx, 1) == L.LBM_ESTATE
     finally:
         L.lbm_destroy(ctx)
+
+
+def test_binding_fails_loudly_without_the_library():
+    """With liblbm.so absent the binding raises on first use; there is no CPU fallback."""
+    import subprocess
+    import sys
+
+    code = (
+        "import paper_2103_08301_amd.lbm as L\n"
+        "L.LIB_PATH = '/nonexistent/liblbm.so'\n"
+        "L._lib = None\n"
+        "try:\n"
+        "    L.Lattice(32, 8, 1.0, device='cpu')\n"
+        "except RuntimeError as e:\n"
+        "    assert 'no CPU fallback' in str(e), e\n"
+        "    print('raised')\n"
+    )
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.strip() == "raised", (out.stdout, out.stderr)
