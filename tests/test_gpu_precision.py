@@ -124,3 +124,21 @@ def test_storage_error_against_oracle(reference, storage):
             assert abs(chk["x_rear"] - xr) <= lim and abs(chk["x_front"] - xf) <= lim, (storage, s, chk, xr, xf)
         if s in MASS_BOUNDS[storage]:
             assert abs(drift) <= MASS_BOUNDS[storage][s], (storage, s, drift)
+
+
+@pytest.mark.parametrize("seed", [2, 4, 5])
+def test_f16r_interfaces_within_half_a_lattice_unit_over_noise_seeds(seed):
+    """The 0.5 lu interface bound of F16R storage at 5000 steps for other seeds of the initial noise
+    (measured lags 0.24, 0.24 and 0.18 lu behind the oracle)."""
+    ref = O.Sim(NX, NY, O.params(tau=TAU, v_limit=1.0, check_every=200000, **KW))
+    ref.init_plug(40, 4, 80, 1e-3, seed)
+    rho0 = ref.fields()[0].copy()
+    ref.step(5000)
+    xr, xf, cols = ref.interface()
+    lat = Lattice(NX, NY, TAU, storage="f16r", v_limit=1.0, check_every=200000, **KW)
+    lat.init_density(rho0)
+    assert lat.step(5000) == 0
+    chk = lat.check()
+    log(f"f16r seed {seed} step 5000: rear {chk['x_rear']:.3f}/{xr:.3f}  front {chk['x_front']:.3f}/{xf:.3f}  "
+        f"liquid cols {chk['liquid_columns']}/{cols}")
+    assert abs(chk["x_rear"] - xr) <= 0.5 and abs(chk["x_front"] - xf) <= 0.5, (seed, chk, xr, xf)
