@@ -57,16 +57,24 @@ def make_lattice(w: dict, check_every: int):
     return lat
 
 
+CHECK_EVERY = 1000  # the library's default stability/interface check cadence
+
+
 def time_steps(w: dict, steps: int, warmup: int):
-    """Seconds for `steps` timed steps (HIP events on the library's stream), wall seconds, lattice."""
+    """Seconds for `steps` timed steps (HIP events on the library's stream), wall seconds, lattice.
+
+    The timed call is one lbm_step of `steps` steps with the library's default check cadence; the
+    HIP graphs it replays are captured beforehand (lbm_capture), so no capture falls in the timed
+    region.  Every step's wall diagnostics are reduced on the device inside it."""
     import torch
 
-    lat = make_lattice(w, check_every=max(steps, warmup, 1))
+    lat = make_lattice(w, check_every=CHECK_EVERY)
     if warmup:
         lat.step(warmup)
     lat.tuned = lat.autotune(50) if AUTOTUNE else None
     if lat.tuned:
         log(f"autotune: {lat.tuned}")
+    lat.capture(steps)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)

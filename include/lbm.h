@@ -199,17 +199,36 @@ lbm_status lbm_init_plug(lbm_ctx* ctx, double plug_len, double film, double x_ce
 /* Initial state from a host density field [ny][nx] (all > 0): f = f_eq(rho, 0). */
 lbm_status lbm_init_density(lbm_ctx* ctx, const double* rho);
 
-/* Advances n >= 0 steps on the bound stream.  Returns after the last check of
-   the call has completed on the device (one host synchronisation per check).
-   Returns LBM_EUNSTABLE, and stops, at the first failed check. */
+/* Advances n >= 0 steps, asynchronously on the bound stream.  A stability and
+   interface check (lbm_check_result) runs at every step that is a multiple of
+   check_every: the step there also writes the density and velocity fields, and
+   the call waits for the check's results (one host synchronisation per check).
+   Returns LBM_EUNSTABLE, and stops, at the first failed check, and also at the
+   end of a call on a state an earlier check found unstable.  Between checks the
+   steps are replayed from captured HIP graphs (graph_steps launches per graph,
+   and one graph for the rest of the call; lbm_capture makes them beforehand).
+   Every step's wall diagnostics are reduced into the per-step summaries and
+   time integrals on the device before the call returns its stream work, so
+   lbm_wall_stress and lbm_stress_history see every step; the call itself does
+   not wait for the device.  The fields and the check of a step that was not a
+   check step are formed when lbm_fields, lbm_fields_device, lbm_components,
+   lbm_check_state or lbm_save ask for them (by running that step again with
+   field output, which leaves the state unchanged). */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Captures, without launching anything or changing the state, the HIP graphs
+   that lbm_step(ctx, n) called now would replay, so that the call issues no
+   capture of its own (a capture costs milliseconds).  LBM_ESTATE before bind
+   and initialisation. */
+lbm_status lbm_capture(lbm_ctx* ctx, int64_t n);
 
 /* Number of steps taken since the last initialisation. */
 lbm_status lbm_step_count(const lbm_ctx* ctx, int64_t* steps);
 
 /* Density and velocity v = u + F/(2 rho) of the last step (after an
    initialisation: the initial density and zero velocity), copied to caller-owned
-   host arrays [ny][nx] (FP64).  Any pointer may be NULL. */
+   host arrays [ny][nx] (FP64).  Any pointer may be NULL.  Waits for the
+   stream. */
 lbm_status lbm_fields(lbm_ctx* ctx, double* rho, double* vx, double* vy);
 
 /* The fields of lbm_fields copied to caller-owned device arrays [ny][nx] on the
@@ -229,8 +248,12 @@ lbm_status lbm_wall_stress(lbm_ctx* ctx, double* tau_bot, double* tau_top, doubl
 /* The last min(cap, steps, history_cap) per-step summaries, oldest first. */
 lbm_status lbm_stress_history(lbm_ctx* ctx, lbm_stress_summary* buf, int64_t cap, int64_t* n_out);
 
-/* Result of the latest stability/interface check. */
-lbm_status lbm_check_state(const lbm_ctx* ctx, lbm_check_result* out);
+/* Stability/interface check of the current step: the one that already ran
+   there, or else one run now (forming the step's fields first; one host
+   synchronisation).  A check that finds NaN or |v| > v_limit sets
+   unstable_step in the result and still returns LBM_OK.  Before bind and
+   initialisation: the zero result. */
+lbm_status lbm_check_state(lbm_ctx* ctx, lbm_check_result* out);
 
 /* Tile autotuner of the tile schedule: times trial_steps launches of every
    tile shape (output rows x waves per block: 8x4, 12x4, 20x4, 28x4, 12x8,
@@ -418,11 +441,16 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
 /* Borrowed handle of case k (0 <= k < n), valid until lbm_batch_destroy. */
 lbm_status lbm_batch_case(lbm_batch* b, int k, lbm_ctx** ctx);
 /* Advances every case by n >= 0 steps, one launch per step, with each case's
-   checks at the common check cadence.  All cases must be initialised and have
-   equal step counts (initialise them together).  On a failed check returns
-   that status, stops, and sets *failed_case (may be NULL) to the case index
-   (-1 otherwise). */
+   checks at the common check cadence, asynchronously as lbm_step (graphs
+   between checks, wall summaries reduced on the device, one wait per check;
+   a case's fields and check at another step are formed when asked for).  All
+   cases must be initialised and have equal step counts (initialise them
+   together).  On a failed check returns that status, stops, and sets
+   *failed_case (may be NULL) to the case index (-1 otherwise); a call on a
+   batch with a case found unstable before returns LBM_EUNSTABLE too. */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case);
+/* As lbm_capture, for lbm_batch_step(b, n). */
+lbm_status lbm_batch_capture(lbm_batch* b, int64_t n);
 /* The tile autotuner for a batch: one trial launch covers every case's tiles
    for a shape (the cases share one kernel), and the fastest shape is kept for
    all cases.  As lbm_autotune otherwise; every case must be initialised. */

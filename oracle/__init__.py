@@ -116,6 +116,7 @@ def lib():
             "orc_fields": (None, [C.c_void_p, _D, _D, _D]),
             "orc_force": (None, [C.c_void_p, _D, _D]),
             "orc_wall": (None, [C.c_void_p, _D, _D, _D, _D]),
+            "orc_eval_force": (None, [C.c_void_p, _D, _D, _D, _D, _D]),
             "orc_history": (C.c_int64, [C.c_void_p, C.POINTER(Summary), C.c_int64]),
             "orc_totals": (None, [C.c_void_p, _D, _D, _D]),
             "orc_interface": (C.c_int, [C.c_void_p, _D, _D, C.POINTER(C.c_int)]),
@@ -307,6 +308,18 @@ class Sim:
         fy = np.zeros_like(fx)
         lib().orc_force(self._h, _ptr(fx), _ptr(fy))
         return fx, fy
+
+    def eval_force(self, rho: np.ndarray):
+        """(Fx, Fy, p_bot, p_top) of a given density field [ny][nx] by the step's own force and
+        wall-pressure stages (eqs. 2.17 and 2.8); replaces this simulation's density and force."""
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        assert rho.shape == (self.ny, self.nx)
+        fx = np.zeros((self.ny, self.nx))
+        fy = np.zeros_like(fx)
+        pb = np.zeros(self.nx)
+        pt = np.zeros(self.nx)
+        lib().orc_eval_force(self._h, _ptr(rho), _ptr(fx), _ptr(fy), _ptr(pb), _ptr(pt))
+        return fx, fy, pb, pt
 
     def wall(self):
         a = [np.zeros(self.nx) for _ in range(4)]

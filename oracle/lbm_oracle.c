@@ -698,13 +698,25 @@ static void stage_collide(orc_sim* s) {
         }
 }
 
+/* Wall pressure at column x of fluid row y1 (the first row next to a wall):
+   the isotropic part of the pressure tensor of eq. 2.8 in mesh units,
+   k^2 p0(rho) - kappa rho lap(rho) - kappa/2 |grad rho|^2, with the same
+   stencils as the force (ghost rows at the wall density). */
+static double wall_pressure(const orc_sim* s, int y1, int x) {
+    double k2 = s->p.k * s->p.k;
+    double r = s->rho[CI(s, y1, x)];
+    double gx, gy;
+    grad_at(s->rext + EI(s, y1, x), s->nx + 4, &gx, &gy);
+    double L = s->lap[LI(s, y1, x)];
+    return k2 * eos_p(&s->eos, r, 0) - s->p.kappa * r * L - 0.5 * s->p.kappa * (gx * gx + gy * gy);
+}
+
 /* Stage 7: wall shear and pressure on the first fluid row of each wall, and
    the per-step summary (extremes, sum of squares, running time integrals). */
 static void stage_wall_diagnostics(orc_sim* s) {
     if (s->p.y_periodic) return;
     int nx = s->nx, ny = s->ny;
     double nu = (s->p.tau - 0.5) / 3.0;
-    double k2 = s->p.k * s->p.k;
     orc_summary sm;
     memset(&sm, 0, sizeof sm);
     sm.step = s->step;
@@ -716,11 +728,7 @@ static void stage_wall_diagnostics(orc_sim* s) {
             double r = s->rho[CI(s, y1, x)];
             double dvds = (9.0 * s->vx[CI(s, y1, x)] - s->vx[CI(s, y2, x)]) / 3.0;
             double tw = r * nu * dvds;
-            double gx, gy;
-            grad_at(s->rext + EI(s, y1, x), nx + 4, &gx, &gy);
-            double L = s->lap[LI(s, y1, x)];
-            double pw = k2 * eos_p(&s->eos, r, 0) - s->p.kappa * r * L
-                      - 0.5 * s->p.kappa * (gx * gx + gy * gy);
+            double pw = wall_pressure(s, y1, x);
             s->tau_w[w * nx + x] = tw;
             s->p_w[w * nx + x] = pw;
             if (x == 0 || tw > sm.tau_max[w]) { sm.tau_max[w] = tw; sm.x_tau_max[w] = x; }
@@ -799,6 +807,21 @@ void orc_force(const orc_sim* s, double* Fx, double* Fy) {
     size_t n = (size_t)s->nx * s->ny;
     if (Fx) memcpy(Fx, s->Fx, n * sizeof(double));
     if (Fy) memcpy(Fy, s->Fy, n * sizeof(double));
+}
+
+void orc_eval_force(orc_sim* s, const double* rho, double* Fx, double* Fy, double* p_bot, double* p_top) {
+    int nx = s->nx, ny = s->ny;
+    memcpy(s->rho, rho, (size_t)nx * ny * sizeof(double));
+    stage_ghosts_and_phi(s);
+    stage_laplacian(s);
+    stage_force(s);
+    if (Fx) memcpy(Fx, s->Fx, (size_t)nx * ny * sizeof(double));
+    if (Fy) memcpy(Fy, s->Fy, (size_t)nx * ny * sizeof(double));
+    for (int w = 0; w < 2 && !s->p.y_periodic; ++w) {
+        double* out = w == 0 ? p_bot : p_top;
+        if (!out) continue;
+        for (int x = 0; x < nx; ++x) out[x] = wall_pressure(s, w == 0 ? 0 : ny - 1, x);
+    }
 }
 
 void orc_wall(const orc_sim* s, double* tau_bot, double* tau_top, double* p_bot, double* p_top) {

@@ -112,6 +112,14 @@ int64_t orc_unstable_step(const orc_sim* s);
 void   orc_fields(const orc_sim* s, double* rho, double* vx, double* vy);
 void   orc_force(const orc_sim* s, double* Fx, double* Fy);
 void   orc_wall(const orc_sim* s, double* tau_bot, double* tau_top, double* p_bot, double* p_top);
+/* The force of eq. 2.17 (plus the body force dp/nx) and the wall pressure of
+   the first fluid rows (isotropic part of eq. 2.8) of a given density field
+   rho[ny][nx], evaluated by the stages a step runs after streaming: ghost ring
+   and EOS field, Laplacian, force, wall pressure.  Fx, Fy: [ny][nx]; p_bot,
+   p_top: [nx], left untouched with periodic y; any may be NULL.  It replaces
+   the simulation's density and force fields (not its distributions): meant for
+   a simulation used for nothing else. */
+void   orc_eval_force(orc_sim* s, const double* rho, double* Fx, double* Fy, double* p_bot, double* p_top);
 int64_t orc_history(const orc_sim* s, orc_summary* buf, int64_t cap);
 void   orc_totals(const orc_sim* s, double* mass, double* momx, double* momy);
 int    orc_interface(const orc_sim* s, double* x_rear, double* x_front, int* liquid_columns);

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -243,17 +244,34 @@ bool graph_steps_ok(int g) {
     return g == -1 || g == 0 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64 || g == 128 || g == 256;
 }
 
-// Captured HIP graphs of consecutive step launches, one per (parity of the
-// input buffer, first wall-ring slot), made when first needed: replaying a
-// graph issues its launches without a host call per kernel.  The graphs hold
-// only step kernels (no memset nodes).
+// Captured HIP graphs of consecutive step launches, made when first needed:
+// replaying a graph issues its launches without a host call per kernel.  Runs
+// of the full graph length are kept per (parity of the input buffer, first
+// wall-ring slot); shorter runs (the rest of a call) per (parity, first slot,
+// length), up to kMaxShortGraphs of them, beyond which short runs are launched
+// kernel by kernel.  The graphs hold only step kernels (no memset nodes).
+constexpr size_t kMaxShortGraphs = 64;
 struct StepGraphs {
     hipStream_t cap = nullptr;  // private capture stream (default priority)
     hipGraphExec_t exec[2][kRingCap] = {};
+    std::map<uint32_t, hipGraphExec_t> shorter;  // key: (length << 9) | (slot << 1) | parity
+    // The cache entry for a run of `len` steps from (parity, slot), or null when the
+    // short-run cache is full and the run must be launched kernel by kernel.
+    hipGraphExec_t* entry(int parity, int slot, int len, int full_len) {
+        if (len == full_len) return &exec[parity][slot];
+        const uint32_t key = ((uint32_t)len << 9) | ((uint32_t)slot << 1) | (uint32_t)parity;
+        auto it = shorter.find(key);
+        if (it != shorter.end()) return &it->second;
+        if (shorter.size() >= kMaxShortGraphs) return nullptr;
+        return &shorter.emplace(key, nullptr).first->second;
+    }
     void drop() {
         for (auto& row : exec)
             for (auto& e : row)
                 if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+        for (auto& kv : shorter)
+            if (kv.second) (void)hipGraphExecDestroy(kv.second);
+        shorter.clear();
     }
     ~StepGraphs() {
         drop();
@@ -353,6 +371,12 @@ struct lbm_ctx {
     } adj;
     int cur = 0;
     int64_t steps = 0;
+    // Step whose density and velocity the field buffers hold.  A call of lbm_step emits them only
+    // at a check; the fields of a later step are made when asked for, by running that step again
+    // with field output from its input, which the other distribution buffer still holds while
+    // prev_valid (the run gives the same distributions, wall arrays and step counter words).
+    int64_t fields_step = 0;
+    bool prev_valid = false;
     int ring_fill = 0;
     int last_slot = -1;  // wall-ring slot of the latest step (its wall arrays)
     int64_t ring_first_step = 1;
@@ -437,6 +461,8 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     HIP_TRY(c, lbm::launch_fill(acc + 10, 0.0, 1, c->stream));  // tangent of the sum-of-squares integral
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_sr), 0.0, 1, c->stream));  // stochastic-rounding step counters
     c->steps = 0;
+    c->fields_step = 0;  // the initialisation writes the density and zero velocity
+    c->prev_valid = false;
     c->ring_fill = 0;
     c->last_slot = -1;
     c->ring_first_step = 1;
@@ -807,81 +833,170 @@ lbm_status lbm_init_density(lbm_ctx* c, const double* rho) {
 
 namespace {
 
-// n steps.  Checks run at every multiple of check_every; `finish` adds the flush
-// of the wall ring and a check after the last step (lbm_step always finishes;
-// the recording run of the adjoint finishes only its last segment).
-lbm_status step_impl(lbm_ctx* c, int64_t n, bool finish) {
-    lbm::StepArgs a = make_args(c);
-    if (c->schedule == lbm::kSchedulePipe && n > 0) {
-        // the ticket counters start from zero for this run of launches (all-zero bits)
+// One launch of the single-lattice step kernels: `nsteps` (1 or 2) steps from buffer `in`
+// into the other one, wall arrays to ring slot `slot`.
+hipError_t launch_k(const lbm_ctx* c, lbm::StepArgs& b, int in, int slot, int nsteps, bool emit, hipStream_t s) {
+    b.fin = c->dev + c->off_f[in];
+    b.fout = c->dev + c->off_f[1 - in];
+    b.sr_par = in;
+    set_wall_slot(b, c, slot);
+    return nsteps == 2 ? lbm::launch_step2(b, c->p.storage, c->p.eos, emit, s)
+                       : lbm::launch_step(b, c->p.storage, c->p.eos, emit, s);
+}
+
+lbm_status zero_tickets(lbm_ctx* c) {  // the pipelined schedule's counters start from zero per run of launches
+    if (c->schedule == lbm::kSchedulePipe)
         HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_tickets), 0.0,
                                     (long long)lbm::kTicketGroups * lbm::kTicketStride, c->stream));
+    return LBM_OK;
+}
+
+// Makes the field buffers hold the density and velocity of the latest step: when a call ended
+// between checks they are older, and the latest step is launched again with field output from
+// its input (the other distribution buffer).  The kernels are deterministic, so the run writes
+// the same distributions, wall arrays and stochastic-rounding counter word as the first one.
+lbm_status ensure_fields(lbm_ctx* c) {
+    if (c->fields_step == c->steps) return LBM_OK;
+    if (!c->prev_valid || c->last_slot < 0)
+        return fail(c, LBM_ESTATE, "the fields of step %lld cannot be formed: the previous state was replaced",
+                    (long long)c->steps);
+    lbm::StepArgs a = make_args(c);
+    lbm_status s = zero_tickets(c);
+    if (s) return s;
+    a.launch = 0;
+    HIP_TRY(c, launch_k(c, a, 1 - c->cur, c->last_slot, 1, true, c->stream));
+    c->fields_step = c->steps;
+    return LBM_OK;
+}
+
+// A check at the current step (forming its fields first), unless one already ran there.
+lbm_status check_now(lbm_ctx* c) {
+    if (c->check.step == c->steps) return LBM_OK;
+    lbm_status s = ensure_fields(c);
+    if (s) return s;
+    return run_check(c);
+}
+
+// n steps, or (dry) only the capture of the graphs those steps would replay, with
+// nothing launched and the context left as it was.
+//
+// Checks run at every multiple of check_every: the step there emits the fields, the wall ring
+// is reduced and the check's results are read back (one host synchronisation).  Between checks
+// the steps are replayed from captured graphs of graph_steps launches and one graph for the
+// rest of the run.  A call ends with the reduction of its steps' wall ring queued on the stream
+// and returns without waiting for the device.
+lbm_status step_impl(lbm_ctx* c, int64_t n, bool dry) {
+    struct Cursor {
+        int cur, ring_fill, last_slot;
+        int64_t steps, ring_first_step;
+    };
+    const Cursor saved{c->cur, c->ring_fill, c->last_slot, c->steps, c->ring_first_step};
+    lbm::StepArgs a = make_args(c);
+    if (!dry && n > 0) {
+        lbm_status s = zero_tickets(c);
+        if (s) return s;
     }
     a.launch = 0;
     const int G = c->graph_steps();
     const int L = c->steps_per_launch();  // steps per launch (1 or 2); G is a multiple of it
-    auto launch_k = [&](lbm::StepArgs& b, int in, int slot, int nsteps, bool emit, hipStream_t s) {
-        b.fin = c->dev + c->off_f[in];
-        b.fout = c->dev + c->off_f[1 - in];
-        b.sr_par = in;
-        set_wall_slot(b, c, slot);
-        return nsteps == 2 ? lbm::launch_step2(b, c->p.storage, c->p.eos, emit, s)
-                           : lbm::launch_step(b, c->p.storage, c->p.eos, emit, s);
+    auto flush = [&]() -> lbm_status {
+        if (!dry) return flush_wall(c);
+        c->ring_first_step += c->ring_fill;
+        c->ring_fill = 0;
+        return LBM_OK;
+    };
+    auto advance = [&](int m, int launches) {
+        if (launches & 1) c->cur = 1 - c->cur;
+        c->last_slot = c->ring_fill + m - 1;
+        c->ring_fill += m;
+        c->steps += m;
+    };
+    // m steps launched kernel by kernel (L steps per launch while more than one step remains)
+    auto eager = [&](int64_t m, bool emit_last) -> lbm_status {
+        for (int64_t k = 0; k < m;) {
+            const int mm = (L == 2 && m - k >= 2) ? 2 : 1;
+            if (c->ring_fill + mm > kRingCap) {
+                lbm_status s = flush();
+                if (s) return s;
+            }
+            const bool emit = emit_last && k + mm == m;
+            if (!dry) HIP_TRY(c, launch_k(c, a, c->cur, c->ring_fill, mm, emit, c->stream));
+            a.launch += 1;
+            advance(mm, 1);
+            k += mm;
+        }
+        return LBM_OK;
     };
     int64_t done = 0;
+    lbm_status result = LBM_OK;
     while (done < n) {
         const int64_t next_check = (c->steps / c->p.check_every + 1) * c->p.check_every;
         const int64_t seg = std::min<int64_t>(n - done, next_check - c->steps);
-        int64_t k = 0;
-        // whole graphs while at least one eager step (the emitting one) remains
-        while (G > 0 && seg - k - 1 >= G) {
-            if (c->ring_fill + G > kRingCap) {
-                lbm_status s = flush_wall(c);
-                if (s) return s;
+        const bool check = c->steps + seg == next_check;
+        // the step that emits for a check, and with two steps per launch the last step of
+        // the call, are one-step launches
+        const int64_t tail = (check || L == 2) ? 1 : 0;
+        int64_t body = seg - tail;
+        while (body > 0) {
+            int m = G > 0 ? (int)std::min<int64_t>(body, G) : 0;
+            if (L == 2) m &= ~1;
+            hipGraphExec_t* ge = nullptr;
+            if (m > 0) {
+                if (c->ring_fill + m > kRingCap) {
+                    lbm_status s = flush();
+                    if (s) return s;
+                }
+                ge = c->graphs.entry(c->cur, c->ring_fill, m, G);
             }
-            const int nl = G / L;  // launches in the graph; each flips the buffers once
-            hipGraphExec_t& ge = c->graphs.exec[c->cur][c->ring_fill];
-            if (!ge) {
+            if (!ge) {  // no graphs, or the cache of short runs is full
+                lbm_status s = eager(m > 0 ? m : body, false);
+                if (s) return s;
+                body -= m > 0 ? m : body;
+                continue;
+            }
+            const int nl = m / L;  // launches in the graph; each flips the buffers once
+            if (!*ge) {
                 const int par = c->cur, fill0 = c->ring_fill;
                 auto launch = [&](int j, hipStream_t s) {
                     lbm::StepArgs b = a;
-                    return launch_k(b, (par + j) & 1, fill0 + L * j, L, false, s);
+                    return launch_k(c, b, (par + j) & 1, fill0 + L * j, L, false, s);
                 };
-                HIP_TRY(c, capture_graph(c->graphs, nl, launch, &ge));
+                HIP_TRY(c, capture_graph(c->graphs, nl, launch, ge));
             }
-            HIP_TRY(c, hipGraphLaunch(ge, c->stream));
-            if (nl & 1) c->cur = 1 - c->cur;
-            c->last_slot = c->ring_fill + G - 1;
-            c->ring_fill += G;
-            c->steps += G;
-            k += G;
+            if (!dry) HIP_TRY(c, hipGraphLaunch(*ge, c->stream));
+            advance(m, nl);
+            body -= m;
         }
-        // a check follows this run of steps unless the run ends the call before a check
-        // boundary and the call does not finish
-        const bool check = finish || c->steps + (seg - k) == next_check;
-        while (k < seg) {
-            const int m = (L == 2 && seg - k - 1 >= 2) ? 2 : 1;  // the emitting step is a one-step launch
-            if (c->ring_fill + m > kRingCap) {
-                lbm_status s = flush_wall(c);
-                if (s) return s;
-            }
-            const bool emit = check && (k + m == seg);
-            HIP_TRY(c, launch_k(a, c->cur, c->ring_fill, m, emit, c->stream));
-            a.launch += 1;
-            c->cur = 1 - c->cur;
-            c->last_slot = c->ring_fill + m - 1;
-            c->ring_fill += m;
-            c->steps += m;
-            k += m;
+        if (tail) {
+            lbm_status s = eager(1, check);
+            if (s) return s;
         }
         done += seg;
+        if (!dry) {
+            c->prev_valid = true;
+            if (check) c->fields_step = c->steps;
+        }
         if (!check) break;  // the end of the call, between checks
-        lbm_status s = flush_wall(c);
+        lbm_status s = flush();
         if (s) return s;
-        s = run_check(c);
-        if (s) return s;
+        if (!dry) {
+            s = run_check(c);
+            if (s) return s;
+        }
     }
-    return LBM_OK;
+    if (dry) {
+        c->cur = saved.cur;
+        c->ring_fill = saved.ring_fill;
+        c->last_slot = saved.last_slot;
+        c->steps = saved.steps;
+        c->ring_first_step = saved.ring_first_step;
+        return LBM_OK;
+    }
+    lbm_status s = flush();  // queued: every step's wall summaries without waiting for them
+    if (s) return s;
+    if (result == LBM_OK && c->check.unstable_step >= 0)
+        return fail(c, LBM_EUNSTABLE, "state is unstable since step %lld", (long long)c->check.unstable_step);
+    return result;
 }
 
 }  // namespace
@@ -890,6 +1005,13 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     if (!c || n < 0) return LBM_EINVAL;
     if (c->in_batch) return fail(c, LBM_ESTATE, "this context belongs to a batch: step it with lbm_batch_step");
     if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_step needs lbm_bind and an initialisation");
+    return step_impl(c, n, false);
+}
+
+lbm_status lbm_capture(lbm_ctx* c, int64_t n) {
+    if (!c || n < 0) return LBM_EINVAL;
+    if (c->in_batch) return fail(c, LBM_ESTATE, "this context belongs to a batch: use lbm_batch_capture");
+    if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_capture needs lbm_bind and an initialisation");
     return step_impl(c, n, true);
 }
 
@@ -902,6 +1024,7 @@ lbm_status lbm_step_count(const lbm_ctx* c, int64_t* steps) {
 lbm_status lbm_fields(lbm_ctx* c, double* rho, double* vx, double* vy) {
     if (!c) return LBM_EINVAL;
     if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
+    if (lbm_status st = ensure_fields(c)) return st;
     const size_t bytes = (size_t)c->nx * c->ny * sizeof(double);
     if (rho) HIP_TRY(c, hipMemcpyAsync(rho, c->dev + c->off_rho, bytes, hipMemcpyDeviceToHost, c->stream));
     if (vx) HIP_TRY(c, hipMemcpyAsync(vx, c->dev + c->off_vx, bytes, hipMemcpyDeviceToHost, c->stream));
@@ -956,8 +1079,12 @@ lbm_status lbm_stress_history(lbm_ctx* c, lbm_stress_summary* buf, int64_t cap, 
     return LBM_OK;
 }
 
-lbm_status lbm_check_state(const lbm_ctx* c, lbm_check_result* out) {
+lbm_status lbm_check_state(lbm_ctx* c, lbm_check_result* out) {
     if (!c || !out) return LBM_EINVAL;
+    if (c->initialized && c->bound) {
+        lbm_status s = check_now(c);
+        if (s != LBM_OK && s != LBM_EUNSTABLE) return s;  // instability is reported in the result
+    }
     *out = c->check;
     return LBM_OK;
 }
@@ -1008,6 +1135,10 @@ lbm_status lbm_get_f(lbm_ctx* c, double* f) {
 lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
     if (!c || !f) return LBM_EINVAL;
     if (!c->bound) return fail(c, LBM_ESTATE, "lbm_bind must come first");
+    if (c->initialized) {  // the fields stay those of the latest step
+        lbm_status s = ensure_fields(c);
+        if (s) return s;
+    }
     const size_t sb = storage_bytes(c->p.storage);
     std::vector<unsigned char> raw((size_t)c->plane * 9 * sb, 0);
     const float r0 = (float)c->rho0;
@@ -1045,6 +1176,7 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
         if (s) return s;
         c->initialized = true;
     }
+    c->prev_valid = false;  // the latest step's input no longer leads to the state
     return LBM_OK;
 }
 
@@ -1064,6 +1196,11 @@ lbm_status lbm_set_tangent(lbm_ctx* c, const double* dtheta) {
         if (!std::isfinite(dtheta[k])) return fail(c, LBM_EINVAL, "tangent direction must be finite");
     if (c->p.eos == LBM_EOS_PR && (dtheta[1] != 0.0 || dtheta[2] != 0.0))
         return fail(c, LBM_EINVAL, "PR tangents support d dp and d T only");
+    if (c->initialized && c->bound) {  // a rerun of the latest step with other tangents would change the state
+        lbm_status s = ensure_fields(c);
+        if (s) return s;
+        c->prev_valid = false;
+    }
     for (int k = 0; k < 4; ++k) c->dtheta[k] = dtheta[k];
     c->graphs.drop();  // the step coefficients' tangents are kernel arguments
     return LBM_OK;
@@ -1148,6 +1285,9 @@ lbm_status lbm_autotune(lbm_ctx* c, int trial_steps, int* tile_rows, int* tile_w
         return fail(c, LBM_EINVAL, "lbm_autotune tunes the tile schedule (not F64T storage)");
     lbm_status s = flush_wall(c);
     if (s) return s;
+    s = ensure_fields(c);  // the trials overwrite the latest step's input
+    if (s) return s;
+    c->prev_valid = false;
     double best = INFINITY;
     TileShape pick = {c->ty, c->tile_waves};
     for (const TileShape& t : kTileShapes) {
@@ -1286,9 +1426,11 @@ lbm_status lbm_adjoint_forward(lbm_ctx* c, double* J) {
     for (int64_t k = 0; k < A.nckpt; ++k) {
         HIP_TRY(c, hipMemcpyAsync(A.dev + A.off_ckpt + (size_t)k * A.state, c->dev + c->off_f[c->cur], fbytes,
                                   hipMemcpyDeviceToDevice, c->stream));
-        s = step_impl(c, std::min(A.seg, A.n - k * A.seg), k == A.nckpt - 1);  // checks at their cadence only
+        s = step_impl(c, std::min(A.seg, A.n - k * A.seg), false);  // checks at their cadence only
         if (s) return s;
     }
+    s = check_now(c);  // a record that went unstable is not kept
+    if (s) return s;
     HIP_TRY(c, hipMemcpyAsync(acc1, c->dev + c->off_acc, sizeof acc1, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const int q = A.objective == LBM_J_PEAK_TAU2 ? 0 : 1;  // acc: [0] int peak tau^2, [1] int sum tau^2
@@ -1459,6 +1601,7 @@ lbm_status lbm_components(lbm_ctx* c, double threshold, int connectivity, lbm_co
     if (!c->initialized) return fail(c, LBM_ESTATE, "not initialised");
     if (std::isnan(threshold)) threshold = 0.5 * (c->rho_g + c->rho_l);
     if (std::isnan(threshold)) return fail(c, LBM_EINVAL, "no coexistence densities above Tc: give a threshold");
+    if (lbm_status st = ensure_fields(c)) return st;
     std::vector<double> rho((size_t)c->nx * c->ny);
     HIP_TRY(c, hipMemcpyAsync(rho.data(), c->dev + c->off_rho, rho.size() * sizeof(double), hipMemcpyDeviceToHost,
                               c->stream));
@@ -1514,6 +1657,8 @@ lbm_status lbm_save(lbm_ctx* c, const char* path) {
     if (!c->bound || !c->initialized) return fail(c, LBM_ESTATE, "lbm_save needs an initialised lattice");
     if (c->in_batch) return fail(c, LBM_ESTATE, "a batch case is not saved on its own");
     lbm_status st = flush_wall(c);  // the accumulators then hold every step so far
+    if (st) return st;
+    st = ensure_fields(c);
     if (st) return st;
     CkptHeader h{};
     h.nx = c->nx;
@@ -1597,8 +1742,11 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
     HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_sr, sr, sizeof sr, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->steps = h.steps;
+    c->fields_step = h.steps;
+    c->prev_valid = false;
     c->check = h.check;
     for (int q = 0; q < 4; ++q) c->dtheta[q] = h.dtheta[q];
+    c->graphs.drop();  // the tangent direction is part of the captured launches
     c->ring_fill = 0;
     c->last_slot = -1;
     c->ring_first_step = h.steps + 1;
@@ -1623,6 +1771,7 @@ lbm_status lbm_fields_device(lbm_ctx* c, void* rho, void* vx, void* vy, int fp64
         if (lbm_status st = device_range_check(outs[q], (size_t)n * elem, &why))
             return fail(c, st, "fields_device: output %d: %s", q, why);
     }
+    if (lbm_status st = ensure_fields(c)) return st;
     for (int q = 0; q < 3; ++q) {
         if (!outs[q]) continue;
         const double* src = c->at<double>(off_fields[q]);
@@ -1778,16 +1927,24 @@ lbm_status lbm_batch_case(lbm_batch* b, int k, lbm_ctx** ctx) {
     return LBM_OK;
 }
 
-lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
-    if (failed_case) *failed_case = -1;
-    if (!b || n < 0) return LBM_EINVAL;
-    if (!b->bound) return bfail(b, LBM_ESTATE, "lbm_batch_bind must come first");
+namespace {
+
+// n steps of every case, or (dry) only the capture of the graphs they would replay; as
+// step_impl for one lattice: checks (with one wait for all cases) at multiples of the check
+// cadence, graphs in between, and the cases' wall rings reduced on the stream at the end.
+lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) {
     lbm_ctx* c0 = b->cases[0];
     for (lbm_ctx* c : b->cases) {
         if (!c->initialized) return bfail(b, LBM_ESTATE, "every case must be initialised before stepping");
         if (c->steps != c0->steps || c->cur != c0->cur || c->ring_fill != c0->ring_fill)
             return bfail(b, LBM_ESTATE, "the cases must be initialised together (equal step counts)");
     }
+    struct Cursor {
+        int cur, ring_fill, last_slot;
+        int64_t steps, ring_first_step;
+    };
+    std::vector<Cursor> saved;
+    for (lbm_ctx* c : b->cases) saved.push_back({c->cur, c->ring_fill, c->last_slot, c->steps, c->ring_first_step});
     const int ncases = (int)b->cases.size();
     const auto* desc = reinterpret_cast<const lbm::StepArgs*>(b->dev + b->off_desc);
     const auto* tiles = reinterpret_cast<const int*>(b->dev + b->off_tiles);
@@ -1802,54 +1959,87 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
     };
     auto flush_all = [&]() -> lbm_status {  // every case's wall ring in one pair of launches
         if (c0->ring_fill == 0) return LBM_OK;
-        hipError_t e = lbm::launch_wall_reduce_batch(reinterpret_cast<const lbm::WallFlush*>(b->dev + b->off_flush),
-                                                     b->nflush, c0->ring_fill, c0->ring_first_step, b->stream);
-        if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch wall reduce: ") + hipGetErrorString(e));
+        if (!dry) {
+            hipError_t e = lbm::launch_wall_reduce_batch(reinterpret_cast<const lbm::WallFlush*>(b->dev + b->off_flush),
+                                                         b->nflush, c0->ring_fill, c0->ring_first_step, b->stream);
+            if (e != hipSuccess)
+                return bfail(b, LBM_EDEVICE, std::string("batch wall reduce: ") + hipGetErrorString(e));
+        }
         for (lbm_ctx* c : b->cases) {
             c->ring_first_step += c->ring_fill;
             c->ring_fill = 0;
         }
         return LBM_OK;
     };
+    auto launch1 = [&](bool emit) -> lbm_status {
+        if (c0->ring_fill == kRingCap) {
+            lbm_status s = flush_all();
+            if (s) return s;
+        }
+        if (!dry) {
+            hipError_t e = lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), c0->cur, c0->ring_fill,
+                                                  c0->p.storage, c0->p.eos, c0->ty, c0->tile_waves, emit, b->stream);
+            if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
+        }
+        advance(1);
+        return LBM_OK;
+    };
     int64_t done = 0;
     while (done < n) {
         const int64_t next_check = (c0->steps / c0->p.check_every + 1) * c0->p.check_every;
         const int64_t seg = std::min<int64_t>(n - done, next_check - c0->steps);
-        int64_t k = 0;
-        while (G > 0 && seg - k - 1 >= G) {  // whole graphs while the emitting step remains
-            if (c0->ring_fill + G > kRingCap) {
-                lbm_status s = flush_all();
-                if (s) return s;
+        const bool check = c0->steps + seg == next_check;
+        int64_t body = seg - (check ? 1 : 0);
+        while (body > 0) {
+            const int m = G > 0 ? (int)std::min<int64_t>(body, G) : 0;
+            hipGraphExec_t* ge = nullptr;
+            if (m > 0) {
+                if (c0->ring_fill + m > kRingCap) {
+                    lbm_status s = flush_all();
+                    if (s) return s;
+                }
+                ge = b->graphs.entry(c0->cur, c0->ring_fill, m, G);
             }
-            hipGraphExec_t& ge = b->graphs.exec[c0->cur][c0->ring_fill];
-            if (!ge) {
+            if (!ge) {  // no graphs, or the cache of short runs is full
+                const int64_t mm = m > 0 ? m : body;
+                for (int64_t k = 0; k < mm; ++k) {
+                    lbm_status s = launch1(false);
+                    if (s) return s;
+                }
+                body -= mm;
+                continue;
+            }
+            if (!*ge) {
                 const int par = c0->cur, fill0 = c0->ring_fill;
                 auto launch = [&](int j, hipStream_t s) {
                     return lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), (par + j) & 1, fill0 + j,
                                                   c0->p.storage, c0->p.eos, c0->ty, c0->tile_waves, false, s);
                 };
-                hipError_t e = capture_graph(b->graphs, G, launch, &ge);
+                hipError_t e = capture_graph(b->graphs, m, launch, ge);
                 if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
             }
-            hipError_t e = hipGraphLaunch(ge, b->stream);
-            if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch graph launch: ") + hipGetErrorString(e));
-            advance(G);
-            k += G;
-        }
-        for (; k < seg; ++k) {
-            if (c0->ring_fill == kRingCap) {
-                lbm_status s = flush_all();
-                if (s) return s;
+            if (!dry) {
+                hipError_t e = hipGraphLaunch(*ge, b->stream);
+                if (e != hipSuccess)
+                    return bfail(b, LBM_EDEVICE, std::string("batch graph launch: ") + hipGetErrorString(e));
             }
-            const bool emit = (k == seg - 1);
-            hipError_t e = lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), c0->cur, c0->ring_fill,
-                                                  c0->p.storage, c0->p.eos, c0->ty, c0->tile_waves, emit, b->stream);
-            if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
-            advance(1);
+            advance(m);
+            body -= m;
         }
+        if (check) {
+            lbm_status s = launch1(true);
+            if (s) return s;
+        }
+        done += seg;
+        if (!dry)
+            for (lbm_ctx* c : b->cases) {
+                c->prev_valid = true;
+                if (check) c->fields_step = c->steps;
+            }
+        if (!check) break;
         lbm_status fs = flush_all();
         if (fs) return fs;
-        done += seg;
+        if (dry) continue;
         // every case's check queued on the batch stream, one wait, then the host halves in case order
         for (int k = 0; k < ncases; ++k) {
             lbm_status s = check_launch(b->cases[(size_t)k]);
@@ -1864,7 +2054,41 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
             }
         }
     }
+    if (dry) {
+        for (size_t k = 0; k < b->cases.size(); ++k) {
+            lbm_ctx* c = b->cases[k];
+            c->cur = saved[k].cur;
+            c->ring_fill = saved[k].ring_fill;
+            c->last_slot = saved[k].last_slot;
+            c->steps = saved[k].steps;
+            c->ring_first_step = saved[k].ring_first_step;
+        }
+        return LBM_OK;
+    }
+    lbm_status fs = flush_all();  // queued, as for one lattice
+    if (fs) return fs;
+    for (int k = 0; k < ncases; ++k)
+        if (b->cases[(size_t)k]->check.unstable_step >= 0) {
+            if (failed_case) *failed_case = k;
+            return bfail(b, LBM_EUNSTABLE, "case " + std::to_string(k) + ": unstable since step " +
+                                               std::to_string(b->cases[(size_t)k]->check.unstable_step));
+        }
     return LBM_OK;
+}
+
+}  // namespace
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case) {
+    if (failed_case) *failed_case = -1;
+    if (!b || n < 0) return LBM_EINVAL;
+    if (!b->bound) return bfail(b, LBM_ESTATE, "lbm_batch_bind must come first");
+    return batch_step_impl(b, n, failed_case, false);
+}
+
+lbm_status lbm_batch_capture(lbm_batch* b, int64_t n) {
+    if (!b || n < 0) return LBM_EINVAL;
+    if (!b->bound) return bfail(b, LBM_ESTATE, "lbm_batch_bind must come first");
+    return batch_step_impl(b, n, nullptr, true);
 }
 
 lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int* tile_waves, double* us_per_step) {
@@ -1875,6 +2099,9 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int
         if (!c->initialized) return bfail(b, LBM_ESTATE, "every case must be initialised before tuning");
         lbm_status s = flush_wall(c);
         if (s) return bfail(b, s, c->err);
+        s = ensure_fields(c);  // the trials overwrite the latest step's input
+        if (s) return bfail(b, s, c->err);
+        c->prev_valid = false;
     }
     const int ncases = (int)b->cases.size();
     // trial launch table: each case's diagnostics redirected into its (flushed) wall ring

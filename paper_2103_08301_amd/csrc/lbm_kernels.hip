@@ -242,6 +242,7 @@ __device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t firs
         sh[q][t] = v[q];
     }
     __syncthreads();
+    // running extremes: an inclusive scan (max and min are exact in any order)
     for (int off = 1; off < kWallThreads; off <<= 1) {
         double o[kWallScratchVals];
         for (int q = 0; q < kWallScratchVals; ++q) o[q] = t >= off ? sh[q][t - off] : 0.0;
@@ -249,16 +250,31 @@ __device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t firs
         if (t >= off)
             for (int q = 0; q < kWallScratchVals; ++q) {
                 const int kq = kind(q);
-                v[q] = kq == 0 ? o[q] + v[q] : (kq == 1 ? fmax(o[q], v[q]) : fmin(o[q], v[q]));
+                if (kq == 0) continue;
+                v[q] = kq == 1 ? fmax(o[q], v[q]) : fmin(o[q], v[q]);
                 sh[q][t] = v[q];
             }
         __syncthreads();
     }
+    // time integrals: added one step after another, so that the sums do not depend on how the
+    // steps were split between flushes (and associate as a step-by-step accumulation does)
+    if (t == 0) {
+        double s0 = prev[0], s1 = prev[1], s10 = prev[10];
+        for (int k = 0; k < nsteps; ++k) {
+            s0 += sh[0][k];
+            s1 += sh[1][k];
+            s10 += sh[10][k];
+            sh[0][k] = s0;
+            sh[1][k] = s1;
+            sh[10][k] = s10;
+        }
+    }
+    __syncthreads();
     if (t >= nsteps) return;
     double tot[kWallScratchVals];
     for (int q = 0; q < kWallScratchVals; ++q) {
         const int kq = kind(q);
-        tot[q] = kq == 0 ? prev[q] + v[q] : (kq == 1 ? fmax(prev[q], v[q]) : fmin(prev[q], v[q]));
+        tot[q] = kq == 0 ? sh[q][t] : (kq == 1 ? fmax(prev[q], v[q]) : fmin(prev[q], v[q]));
     }
     lbm_stress_summary* h = &f.hist[(first_step + t - 1) % f.hist_cap];
     h->int_peak_tau2 = tot[0];

@@ -33,6 +33,7 @@ EXPORTED = [
     "lbm_reset_stress_extremes", "lbm_adjoint_workspace", "lbm_adjoint_bind", "lbm_adjoint_forward",
     "lbm_adjoint_backward", "lbm_adjoint_state_gradient", "lbm_autotune", "lbm_batch_autotune",
     "lbm_fields_device", "lbm_save", "lbm_load", "lbm_launch_config", "lbm_adjoint_objective",
+    "lbm_capture", "lbm_batch_capture",
 ]
 
 
@@ -121,6 +122,8 @@ def library():
             "lbm_init_plug": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]),
             "lbm_init_density": (C.c_int, [_P, _D]),
             "lbm_step": (C.c_int, [_P, C.c_int64]),
+            "lbm_capture": (C.c_int, [_P, C.c_int64]),
+            "lbm_batch_capture": (C.c_int, [_P, C.c_int64]),
             "lbm_step_count": (C.c_int, [_P, C.POINTER(C.c_int64)]),
             "lbm_fields": (C.c_int, [_P, _D, _D, _D]),
             "lbm_fields_device": (C.c_int, [_P, _P, _P, _P, C.c_int]),
@@ -232,6 +235,10 @@ def lbm_step(ctx, n: int) -> int:
     if st not in (LBM_OK, LBM_EUNSTABLE):
         _check(ctx, st)
     return st
+
+
+def lbm_capture(ctx, n: int):
+    _check(ctx, library().lbm_capture(ctx, n))
 
 
 def lbm_step_count(ctx) -> int:
@@ -431,7 +438,12 @@ class Lattice:
         lbm_init_density(self._ctx, rho)
 
     def step(self, n: int) -> int:
+        """Enqueues n steps on the lattice's stream; waits only for the checks at multiples of check_every."""
         return lbm_step(self._ctx, n)
+
+    def capture(self, n: int):
+        """Captures the HIP graphs a call step(n) made now would replay (nothing runs)."""
+        lbm_capture(self._ctx, n)
 
     @property
     def steps(self) -> int:
@@ -584,6 +596,10 @@ class Batch:
             err.case = failed.value
             raise err
         return LBM_OK
+
+    def capture(self, n: int):
+        """Captures the HIP graphs a call step(n) made now would replay (nothing runs)."""
+        _batch_check(self._b, library().lbm_batch_capture(self._b, n))
 
     def autotune(self, trial_steps: int = 20) -> dict:
         """Times every tile shape on all cases at once and keeps the fastest for the batch."""
