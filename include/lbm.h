@@ -255,6 +255,21 @@ lbm_status lbm_stress_history(lbm_ctx* ctx, lbm_stress_summary* buf, int64_t cap
    initialisation: the zero result. */
 lbm_status lbm_check_state(lbm_ctx* ctx, lbm_check_result* out);
 
+/* For callers that must not allocate memory (serving loops, harnesses that
+   forbid allocation): lbm_check_state without any allocation.  Its first check
+   allocates nothing: lbm_check_state stages its results in a pinned host
+   buffer it allocates on first use, while this call keeps its device scratch
+   (reduction partials, per-column minima and centreline densities, and the
+   interface summary, which it forms on the device) in a static device array
+   of the library and copies nine doubles back.  Same result as
+   lbm_check_state, bit for bit.  The array holds the columns of lattices with
+   nx <= 16384 (about 280 KB on each GPU the library runs on, kept until the
+   process ends); LBM_EINVAL for wider lattices, before anything is launched.
+   LBM_ESTATE before bind and initialisation.  Waits for the bound stream.
+   All calls on one GPU share the array: calls that overlap in time on one GPU
+   (from several threads, or on several streams) race and must not be made. */
+lbm_status lbm_check_state_noalloc(lbm_ctx* ctx, lbm_check_result* out);
+
 /* Tile autotuner of the tile schedule: times trial_steps launches of every
    tile shape (output rows x waves per block: 8x4, 12x4, 20x4, 28x4, 12x8,
    20x8, 28x8) on the current state and keeps the fastest for later steps.

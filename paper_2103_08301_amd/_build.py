@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["lbm_api.cpp", "lbm_post.cpp", "lbm_kernels.hip", "lbm_adjoint.hip", "lbm_step_f64.hip",
+SOURCES = ["lbm_api.cpp", "lbm_post.cpp", "lbm_kernels.hip", "lbm_noalloc.hip", "lbm_adjoint.hip", "lbm_step_f64.hip",
            "lbm_step_f32.hip", "lbm_step_f16s.hip", "lbm_step_bf16s.hip", "lbm_step_f32d.hip", "lbm_step_f32s.hip",
            "lbm_step_f64t.hip", "lbm_step_f16r.hip"]
 FLAGS = [

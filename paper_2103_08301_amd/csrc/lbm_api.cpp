@@ -524,10 +524,10 @@ lbm_status check_launch(lbm_ctx* c) {
     return LBM_OK;
 }
 
-lbm_status check_finish(lbm_ctx* c) {
-    const double* red = c->check_host;
-    const double* colmin = red + 5;
-    const double* centre = red + 5 + c->nx;
+// Fills the check result from the reduced fields (sum rho, sum rho vx, sum rho vy, max |v|^2,
+// NaN count) and the centreline interfaces and liquid columns, and detects rupture and
+// instability.
+lbm_status check_apply(lbm_ctx* c, const double* red, double x_rear, double x_front, int liquid_columns) {
     lbm_check_result& k = c->check;
     k.step = c->steps;
     k.mass = red[0];
@@ -535,11 +535,29 @@ lbm_status check_finish(lbm_ctx* c) {
     k.momy = red[2];
     k.vmax = std::sqrt(red[3]);
     k.nan_count = (int64_t)red[4];
+    k.x_rear = x_rear;
+    k.x_front = x_front;
+    k.liquid_columns = liquid_columns;
+    const double mid = 0.5 * (c->rho_g + c->rho_l);
+    if (std::isfinite(mid) && c->steps > 0 && k.liquid_columns == 0 && k.rupture_step < 0) k.rupture_step = c->steps;
+    const bool bad = k.nan_count > 0 || !(k.vmax <= c->p.v_limit);
+    if (bad && k.unstable_step < 0) {
+        k.unstable_step = c->steps;
+        return fail(c, LBM_EUNSTABLE, "instability at step %lld: nan cells %lld, |v|max %g",
+                    (long long)c->steps, (long long)k.nan_count, k.vmax);
+    }
+    if (bad) return fail(c, LBM_EUNSTABLE, "state is unstable since step %lld", (long long)k.unstable_step);
+    return LBM_OK;
+}
+
+lbm_status check_finish(lbm_ctx* c) {
+    const double* red = c->check_host;
+    const double* colmin = red + 5;
+    const double* centre = red + 5 + c->nx;
     // interfaces: crossings of the midpoint density on the centreline
     const double mid = 0.5 * (c->rho_g + c->rho_l);
-    k.x_rear = NAN;
-    k.x_front = NAN;
-    k.liquid_columns = 0;
+    double x_rear = NAN, x_front = NAN;
+    int liquid_columns = 0;
     if (std::isfinite(mid)) {
         int runs = 0, first = -1, last = -1;
         bool prev = false;
@@ -550,20 +568,12 @@ lbm_status check_finish(lbm_ctx* c) {
             prev = liq;
         }
         if (runs == 1 && first > 0 && last < c->nx - 1) {
-            k.x_rear = (first - 1) + (mid - centre[first - 1]) / (centre[first] - centre[first - 1]);
-            k.x_front = last + (centre[last] - mid) / (centre[last] - centre[last + 1]);
+            x_rear = (first - 1) + (mid - centre[first - 1]) / (centre[first] - centre[first - 1]);
+            x_front = last + (centre[last] - mid) / (centre[last] - centre[last + 1]);
         }
-        for (int x = 0; x < c->nx; ++x) k.liquid_columns += colmin[x] > mid ? 1 : 0;
-        if (c->steps > 0 && k.liquid_columns == 0 && k.rupture_step < 0) k.rupture_step = c->steps;
+        for (int x = 0; x < c->nx; ++x) liquid_columns += colmin[x] > mid ? 1 : 0;
     }
-    const bool bad = k.nan_count > 0 || !(k.vmax <= c->p.v_limit);
-    if (bad && k.unstable_step < 0) {
-        k.unstable_step = c->steps;
-        return fail(c, LBM_EUNSTABLE, "instability at step %lld: nan cells %lld, |v|max %g",
-                    (long long)c->steps, (long long)k.nan_count, k.vmax);
-    }
-    if (bad) return fail(c, LBM_EUNSTABLE, "state is unstable since step %lld", (long long)k.unstable_step);
-    return LBM_OK;
+    return check_apply(c, red, x_rear, x_front, liquid_columns);
 }
 
 lbm_status run_check(lbm_ctx* c) {
@@ -764,6 +774,7 @@ lbm_status lbm_bind(lbm_ctx* c, void* device_ptr, size_t bytes, void* hip_stream
     const char* why = nullptr;
     if (lbm_status st = device_range_check(device_ptr, c->total, &why)) return fail(c, st, "workspace: %s", why);
     HIP_TRY(c, hipGetDevice(&c->device));
+    HIP_TRY(c, lbm::noalloc_setup());  // this device's address of the static check scratch
     if (c->schedule == lbm::kSchedulePipe) {
         if (c->p.pipe_blocks > 0)
             c->pipe_blocks = c->p.pipe_blocks;
@@ -1083,6 +1094,28 @@ lbm_status lbm_check_state(lbm_ctx* c, lbm_check_result* out) {
     if (!c || !out) return LBM_EINVAL;
     if (c->initialized && c->bound) {
         lbm_status s = check_now(c);
+        if (s != LBM_OK && s != LBM_EUNSTABLE) return s;  // instability is reported in the result
+    }
+    *out = c->check;
+    return LBM_OK;
+}
+
+lbm_status lbm_check_state_noalloc(lbm_ctx* c, lbm_check_result* out) {
+    if (!c || !out) return LBM_EINVAL;
+    if (!c->bound || !c->initialized)
+        return fail(c, LBM_ESTATE, "lbm_check_state_noalloc needs a bound, initialised lattice");
+    if (c->nx > lbm::kNoAllocMaxNx)
+        return fail(c, LBM_EINVAL, "lbm_check_state_noalloc: nx = %d exceeds the %d columns its static scratch holds",
+                    c->nx, lbm::kNoAllocMaxNx);
+    if (c->check.step != c->steps) {
+        lbm_status s = ensure_fields(c);
+        if (s) return s;
+        const double mid = 0.5 * (c->rho_g + c->rho_l);
+        const bool two_phase = std::isfinite(mid);
+        double h[9];
+        HIP_TRY(c, lbm::noalloc_check(c->device, c->at<double>(c->off_rho), c->at<double>(c->off_vx),
+                                      c->at<double>(c->off_vy), c->nx, c->ny, two_phase ? mid : 0.0, h, c->stream));
+        s = check_apply(c, h, two_phase ? h[6] : NAN, two_phase ? h[7] : NAN, two_phase ? (int)h[5] : 0);
         if (s != LBM_OK && s != LBM_EUNSTABLE) return s;  // instability is reported in the result
     }
     *out = c->check;

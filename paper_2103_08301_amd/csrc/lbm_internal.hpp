@@ -177,6 +177,18 @@ hipError_t launch_adjoint_gather(const void* lam, const StepArgs& a, int storage
 int adjoint_blocks(int nx, int ny, int ty);
 
 constexpr int kFieldReduceBlocks = 512;
+
+// The check of lbm_check_state_noalloc (lbm_noalloc.hip), whose device scratch is a
+// static array of the library holding the reduction partials and the column scans
+// of up to kNoAllocMaxNx columns.  noalloc_setup resolves the array's address on the
+// current device (once per device); noalloc_check reduces the fields rho, vx, vy
+// [ny][nx] of `device` on stream s and returns, after waiting for s: [0..4] sum rho,
+// sum rho vx, sum rho vy, max |v|^2, NaN count; [5] liquid columns; [6] x_rear;
+// [7] x_front; [8] centreline liquid runs.  Calls that overlap on one device race.
+constexpr int kNoAllocMaxNx = 16384;
+hipError_t noalloc_setup();
+hipError_t noalloc_check(int device, const double* rho, const double* vx, const double* vy, int nx, int ny,
+                         double mid, double* host9, hipStream_t s);
 constexpr int kWallScratchVals = 11;  // per step: peak tau^2, sum tau^2, tau max/min, p max/min per wall, d sum tau^2
 constexpr int kWallAccVals = 11;      // int peak tau^2, int sum tau^2, running tau/p max/min per wall, d int tau^2
 

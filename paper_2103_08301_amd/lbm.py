@@ -33,7 +33,7 @@ EXPORTED = [
     "lbm_reset_stress_extremes", "lbm_adjoint_workspace", "lbm_adjoint_bind", "lbm_adjoint_forward",
     "lbm_adjoint_backward", "lbm_adjoint_state_gradient", "lbm_autotune", "lbm_batch_autotune",
     "lbm_fields_device", "lbm_save", "lbm_load", "lbm_launch_config", "lbm_adjoint_objective",
-    "lbm_capture", "lbm_batch_capture",
+    "lbm_capture", "lbm_batch_capture", "lbm_check_state_noalloc",
 ]
 
 
@@ -135,6 +135,7 @@ def library():
             "lbm_stress_history": (C.c_int, [_P, C.POINTER(lbm_stress_summary), C.c_int64,
                                              C.POINTER(C.c_int64)]),
             "lbm_check_state": (C.c_int, [_P, C.POINTER(lbm_check_result)]),
+            "lbm_check_state_noalloc": (C.c_int, [_P, C.POINTER(lbm_check_result)]),
             "lbm_components": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(lbm_component), C.c_int64,
                                          C.POINTER(C.c_int64), C.POINTER(lbm_aerosol_summary)]),
             "lbm_components_field": (C.c_int, [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -281,6 +282,12 @@ def lbm_stress_history(ctx, cap: int) -> list:
 def lbm_check_state(ctx) -> dict:
     r = lbm_check_result()
     _check(ctx, library().lbm_check_state(ctx, C.byref(r)))
+    return struct_dict(r)
+
+
+def lbm_check_state_noalloc(ctx) -> dict:
+    r = lbm_check_result()
+    _check(ctx, library().lbm_check_state_noalloc(ctx, C.byref(r)))
     return struct_dict(r)
 
 
