@@ -746,7 +746,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->off_ring = o; o += align256((size_t)kRingCap * lbm::kWallSlotVals * nx * sizeof(double));
     c->off_hist = o; o += align256((size_t)p->history_cap * sizeof(lbm_stress_summary));
     c->off_acc = o; o += 256;
-    c->off_wscr = o; o += align256((size_t)kRingCap * lbm::kWallScratchVals * sizeof(double));
+    c->off_wscr = o; o += align256((size_t)kRingCap * 2 * lbm::kWallPartVals * sizeof(double));
     c->off_red = o; o += align256((size_t)lbm::kFieldReduceBlocks * 5 * sizeof(double));
     c->off_redout = o; o += 256;
     c->off_colmin = o; o += align256((size_t)nx * sizeof(double));

@@ -144,19 +144,30 @@ __device__ inline uint32_t hash32(uint32_t x) {
     return x;
 }
 
-// Stochastic rounding of v to FP16 by dithering: with s the FP16 spacing at |v|
-// (2^-24 below 2^-14), v + D, D = ((2r + 1)/2048 - 1/2) s for 10 uniform random
-// bits r, is rounded to nearest.  When v lies a fraction t of the way from one
-// FP16 neighbour to the next, the result is the upper one for a fraction of the
-// 1024 values of r within 1/2048 of t, so the expected rounding error is zero to
-// within s/2048 (over 10^5 steps a steady value gathers at most ~50 s of bias,
-// against ~160 s of random walk).  v + D is exact in FP32: D is a multiple of
-// s/2048, coarser than the FP32 spacing at v.
+// Stochastic rounding of v to FP16: v goes to one of its two FP16 neighbours,
+// the one above in magnitude with a probability equal to v's fractional position
+// between them (to within 1/2048), so the rounding error has zero mean.
+// For |v| >= 2^-14 (FP16 normals) it acts on v's FP32 bit pattern: the 13
+// mantissa bits below the FP16 cut hold the position t (in 1/8192 of the FP16
+// spacing s); adding an offset o(r) = 8 r + 3 + (r mod 2) for 10 uniform random
+// bits r and clearing the 13 bits rounds the magnitude up exactly when t + o(r) >=
+// 8192.  The offsets are spread over [3, 8188] with mean 4095.5, so the chance of
+// rounding up averages t/8192 over t, and a carry out of the mantissa moves to the
+// next binade exactly: values just above a power of two never drop into the finer
+// binade below, as v + D for a dither D does when D is negative enough.  The
+// cleared pattern has 10 fraction bits and converts to FP16 exactly.  Below 2^-14
+// the FP16 spacing is 2^-24 throughout (subnormals and the lowest normal binade),
+// so there v + D, D = ((2 r + 1)/2048 - 1/2) 2^-24, rounded to nearest does the
+// same.  Both candidates are formed and one is selected (no divergent branch
+// between gas and liquid populations); beyond the FP16 range, inf and NaN round
+// to nearest.
 __device__ inline _Float16 f16_stochastic(float v, uint32_t r) {
-    int e = int((__float_as_uint(v) >> 23) & 0xffu) - 127;  // 2^e <= |v| < 2^(e+1); 0 and FP32 subnormals: -127
-    e = e < -14 ? -14 : e;
-    const float d = __builtin_ldexpf(float(int(2u * r) - 1023), e - 10 - 11);
-    return static_cast<_Float16>(v + d);
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t mag = u & 0x7fffffffu;
+    const float normal = __uint_as_float((u + (r << 3) + 3u + (r & 1u)) & ~0x1fffu);
+    const float tiny = v + float(int(2u * r) - 1023) * 0x1p-35f;
+    const float pick = mag < 0x38800000u ? tiny : (mag < 0x477fe000u ? normal : v);
+    return static_cast<_Float16>(pick);
 }
 
 // 10 random bits for population I: bits 10 (I mod 3) .. of word I / 3.

@@ -118,10 +118,10 @@ hipError_t launch_field_reduce(const double* rho, const double* vx, const double
 // Per column: minimum density over y and the centreline density.
 hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin, double* centre,
                               hipStream_t s);
-// Reduces the first `nsteps` slots of the wall ring (one wave per step: extremes
-// and their columns, sums of squares) into the history ring, then accumulates the running time integrals and
-// running extremes acc[kWallAccVals] in step order.  scratch holds
-// kWallScratchVals doubles per step.
+// Reduces the first `nsteps` slots of the wall ring (a block per step and wall:
+// extremes and their columns, sums of squares) into the history ring, then
+// accumulates the running time integrals and running extremes acc[kWallAccVals]
+// in step order.  scratch holds 2 x kWallPartVals doubles per step.
 hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t first_step,
                               lbm_stress_summary* hist, int hist_cap, double* scratch, double* acc, hipStream_t s);
 // The wall ring, history, scratch and accumulators of one lattice.
@@ -189,7 +189,8 @@ constexpr int kNoAllocMaxNx = 16384;
 hipError_t noalloc_setup();
 hipError_t noalloc_check(int device, const double* rho, const double* vx, const double* vy, int nx, int ny,
                          double mid, double* host9, hipStream_t s);
-constexpr int kWallScratchVals = 11;  // per step: peak tau^2, sum tau^2, tau max/min, p max/min per wall, d sum tau^2
+constexpr int kWallPartVals = 10;  // per step and wall: tau max, its x, tau min, its x, p max, its x, p min, its x,
+                                   // sum tau^2, sum 2 tau dtau (the flush's scratch holds [steps][2][kWallPartVals])
 constexpr int kWallAccVals = 11;      // int peak tau^2, int sum tau^2, running tau/p max/min per wall, d int tau^2
 
 // Liquid components of a host density field (lbm_post.cpp).

@@ -140,115 +140,118 @@ __device__ inline void comb_min(double& v, double& x, double ov, double ox) {
     if (ov < v || (ov == v && ox < x)) { v = ov; x = ox; }
 }
 
-constexpr int kWallThreads = 256;  // threads of the wall reduction blocks (4 waves)
+constexpr int kWallThreads = 256;      // threads of the wall scan block: one per step of a flush (4 waves)
+constexpr int kWallRedThreads = 1024;  // threads of a block that reduces one wall of one step (16 waves)
+constexpr int kWallRedWaves = kWallRedThreads / 64;
 
-// One step of the wall ring (block per step): extremes of tau_w and p_w per wall
-// with their columns (the smallest column on ties) and the sums of tau_w^2 and
+// One wall of one step of the wall ring (block per (step, wall)): extremes of tau_w
+// and p_w with their columns (the smallest column on ties) and the sums of tau_w^2 and
 // of its tangent, reduced lane-strided, then by wave butterflies, then over the
-// 4 waves in order.
-__device__ void wall_step_reduce_body(const WallFlush& f, int t, int64_t first_step) {
-    __shared__ double sh[4][2][10];
+// waves in order.  Writes the ten values to scratch[t][w].
+__device__ void wall_step_reduce_body(const WallFlush& f, int t, int w) {
+    __shared__ double sh[kWallRedWaves][10];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nx = f.nx;
     const double* slot = f.ring + (long long)t * kWallSlotVals * nx;  // tau [2][nx], p [2][nx], dtau [2][nx]
-    for (int w = 0; w < 2; ++w) {
-        const double* tau = slot + (long long)w * nx;
-        const double* pw = slot + (long long)(2 + w) * nx;
-        const double* dtau = slot + (long long)(4 + w) * nx;
-        double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
-        double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0, wds = 0.0;
+    const double* tau = slot + (long long)w * nx;
+    const double* pw = slot + (long long)(2 + w) * nx;
+    const double* dtau = slot + (long long)(4 + w) * nx;
+    double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
+    double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0, wds = 0.0;
 #pragma unroll 4
-        for (int x = threadIdx.x; x < nx; x += kWallThreads) {  // unrolled: four columns' loads in flight
-            const double tv = tau[x], pv = pw[x];
-            comb_max(tmax, xtmax, tv, double(x));
-            comb_min(tmin, xtmin, tv, double(x));
-            comb_max(pmax, xpmax, pv, double(x));
-            comb_min(pmin, xpmin, pv, double(x));
-            ws += tv * tv;
-            wds += 2.0 * tv * dtau[x];
-        }
+    for (int x = threadIdx.x; x < nx; x += kWallRedThreads) {  // unrolled: four columns' loads in flight
+        const double tv = tau[x], pv = pw[x];
+        comb_max(tmax, xtmax, tv, double(x));
+        comb_min(tmin, xtmin, tv, double(x));
+        comb_max(pmax, xpmax, pv, double(x));
+        comb_min(pmin, xpmin, pv, double(x));
+        ws += tv * tv;
+        wds += 2.0 * tv * dtau[x];
+    }
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            comb_max(tmax, xtmax, __shfl_xor(tmax, off, 64), __shfl_xor(xtmax, off, 64));
-            comb_min(tmin, xtmin, __shfl_xor(tmin, off, 64), __shfl_xor(xtmin, off, 64));
-            comb_max(pmax, xpmax, __shfl_xor(pmax, off, 64), __shfl_xor(xpmax, off, 64));
-            comb_min(pmin, xpmin, __shfl_xor(pmin, off, 64), __shfl_xor(xpmin, off, 64));
-            ws += __shfl_xor(ws, off, 64);
-            wds += __shfl_xor(wds, off, 64);
-        }
-        if (lane == 0) {
-            double* o = sh[wave][w];
-            o[0] = tmax; o[1] = xtmax; o[2] = tmin; o[3] = xtmin;
-            o[4] = pmax; o[5] = xpmax; o[6] = pmin; o[7] = xpmin; o[8] = ws; o[9] = wds;
-        }
+    for (int off = 32; off >= 1; off >>= 1) {
+        comb_max(tmax, xtmax, __shfl_xor(tmax, off, 64), __shfl_xor(xtmax, off, 64));
+        comb_min(tmin, xtmin, __shfl_xor(tmin, off, 64), __shfl_xor(xtmin, off, 64));
+        comb_max(pmax, xpmax, __shfl_xor(pmax, off, 64), __shfl_xor(xpmax, off, 64));
+        comb_min(pmin, xpmin, __shfl_xor(pmin, off, 64), __shfl_xor(xpmin, off, 64));
+        ws += __shfl_xor(ws, off, 64);
+        wds += __shfl_xor(wds, off, 64);
+    }
+    if (lane == 0) {
+        double* o = sh[wave];
+        o[0] = tmax; o[1] = xtmax; o[2] = tmin; o[3] = xtmin;
+        o[4] = pmax; o[5] = xpmax; o[6] = pmin; o[7] = xpmin; o[8] = ws; o[9] = wds;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    lbm_stress_summary sm;
-    sm.step = first_step + t;
-    double pk = 0.0, s2 = 0.0, ds2 = 0.0;
-    for (int w = 0; w < 2; ++w) {
-        double r[10];
-        for (int q = 0; q < 10; ++q) r[q] = sh[0][w][q];
-        for (int v = 1; v < 4; ++v) {
-            const double* o = sh[v][w];
-            comb_max(r[0], r[1], o[0], o[1]);
-            comb_min(r[2], r[3], o[2], o[3]);
-            comb_max(r[4], r[5], o[4], o[5]);
-            comb_min(r[6], r[7], o[6], o[7]);
-            r[8] += o[8];
-            r[9] += o[9];
-        }
-        sm.tau_max[w] = r[0]; sm.tau_min[w] = r[2]; sm.p_max[w] = r[4]; sm.p_min[w] = r[6];
-        sm.x_tau_max[w] = int32_t(r[1]); sm.x_tau_min[w] = int32_t(r[3]);
-        sm.x_p_max[w] = int32_t(r[5]); sm.x_p_min[w] = int32_t(r[7]);
-        pk = fmax(pk, fmax(r[0] * r[0], r[2] * r[2]));
-        s2 += r[8];
-        ds2 += r[9];
+    double r[10];
+    for (int q = 0; q < 10; ++q) r[q] = sh[0][q];
+    for (int v = 1; v < kWallRedWaves; ++v) {
+        const double* o = sh[v];
+        comb_max(r[0], r[1], o[0], o[1]);
+        comb_min(r[2], r[3], o[2], o[3]);
+        comb_max(r[4], r[5], o[4], o[5]);
+        comb_min(r[6], r[7], o[6], o[7]);
+        r[8] += o[8];
+        r[9] += o[9];
     }
-    sm.sum_tau2 = s2;
-    sm.d_sum_tau2 = ds2;
-    sm.int_peak_tau2 = 0.0;
-    sm.int_tau2 = 0.0;
-    sm.d_int_tau2 = 0.0;
-    f.hist[(sm.step - 1) % f.hist_cap] = sm;
-    double* o = f.scratch + (long long)t * kWallScratchVals;
-    o[0] = pk;
-    o[1] = s2;
-    for (int w = 0; w < 2; ++w) {
-        o[2 + w] = sm.tau_max[w];
-        o[4 + w] = sm.tau_min[w];
-        o[6 + w] = sm.p_max[w];
-        o[8 + w] = sm.p_min[w];
-    }
-    o[10] = ds2;
+    double* o = f.scratch + ((long long)t * 2 + w) * kWallPartVals;
+    for (int q = 0; q < 10; ++q) o[q] = r[q];
 }
 
-// Running time integrals and running extremes of nsteps <= kWallThreads steps:
-// an inclusive scan over the steps (thread per step, Hillis-Steele in LDS, a
-// fixed tree), added to the totals so far.
+// The per-step summaries and the running time integrals and extremes of nsteps <=
+// kWallThreads steps (thread per step).  A step's summary combines its two walls'
+// partials (peak of tau_w^2 over both walls, sums of squares wall 0 then wall 1); the
+// running extremes are an inclusive scan over the steps (max and min are exact in any
+// order) and the time integrals are added one step after another, so that the sums do
+// not depend on how the steps were split between flushes.
 // acc: [0] int peak tau^2, [1] int sum tau^2, [2 + 2q + w] running extreme q
 // (tau max, tau min, p max, p min) of wall w, [10] tangent of int sum tau^2.
 __device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t first_step) {
-    __shared__ double sh[kWallScratchVals][kWallThreads];
+    constexpr int V = kWallAccVals;
+    __shared__ double sh[V][kWallThreads];
     const int t = threadIdx.x;
-    // per scratch value: 0 sum, 1 max, 2 min
+    // per value: 0 sum, 1 max, 2 min
     auto kind = [](int q) { return (q == 0 || q == 1 || q == 10) ? 0 : ((q - 2) / 2 % 2 == 0 ? 1 : 2); };
-    double v[kWallScratchVals], prev[kWallScratchVals];
-    for (int q = 0; q < kWallScratchVals; ++q) {
-        const int kq = kind(q);
-        v[q] = t < nsteps ? f.scratch[(long long)t * kWallScratchVals + q] : (kq == 0 ? 0.0 : (kq == 1 ? -INFINITY : INFINITY));
-        prev[q] = f.acc[q];  // acc uses the scratch layout's order: 0, 1, 2 + 2q + w, 10
+    double v[V], prev[V];
+    lbm_stress_summary sm;
+    if (t < nsteps) {
+        sm.step = first_step + t;
+        double pk = 0.0, s2 = 0.0, ds2 = 0.0;
+        for (int w = 0; w < 2; ++w) {
+            const double* r = f.scratch + ((long long)t * 2 + w) * kWallPartVals;
+            sm.tau_max[w] = r[0]; sm.tau_min[w] = r[2]; sm.p_max[w] = r[4]; sm.p_min[w] = r[6];
+            sm.x_tau_max[w] = int32_t(r[1]); sm.x_tau_min[w] = int32_t(r[3]);
+            sm.x_p_max[w] = int32_t(r[5]); sm.x_p_min[w] = int32_t(r[7]);
+            pk = fmax(pk, fmax(r[0] * r[0], r[2] * r[2]));
+            s2 += r[8];
+            ds2 += r[9];
+        }
+        sm.sum_tau2 = s2;
+        sm.d_sum_tau2 = ds2;
+        v[0] = pk;
+        v[1] = s2;
+        for (int w = 0; w < 2; ++w) {
+            v[2 + w] = sm.tau_max[w];
+            v[4 + w] = sm.tau_min[w];
+            v[6 + w] = sm.p_max[w];
+            v[8 + w] = sm.p_min[w];
+        }
+        v[10] = ds2;
+    } else {
+        for (int q = 0; q < V; ++q) v[q] = kind(q) == 0 ? 0.0 : (kind(q) == 1 ? -INFINITY : INFINITY);
+    }
+    for (int q = 0; q < V; ++q) {
+        prev[q] = f.acc[q];
         sh[q][t] = v[q];
     }
     __syncthreads();
-    // running extremes: an inclusive scan (max and min are exact in any order)
     for (int off = 1; off < kWallThreads; off <<= 1) {
-        double o[kWallScratchVals];
-        for (int q = 0; q < kWallScratchVals; ++q) o[q] = t >= off ? sh[q][t - off] : 0.0;
+        double o[V];
+        for (int q = 0; q < V; ++q) o[q] = t >= off ? sh[q][t - off] : 0.0;
         __syncthreads();
         if (t >= off)
-            for (int q = 0; q < kWallScratchVals; ++q) {
+            for (int q = 0; q < V; ++q) {
                 const int kq = kind(q);
                 if (kq == 0) continue;
                 v[q] = kq == 1 ? fmax(o[q], v[q]) : fmin(o[q], v[q]);
@@ -256,8 +259,6 @@ __device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t firs
             }
         __syncthreads();
     }
-    // time integrals: added one step after another, so that the sums do not depend on how the
-    // steps were split between flushes (and associate as a step-by-step accumulation does)
     if (t == 0) {
         double s0 = prev[0], s1 = prev[1], s10 = prev[10];
         for (int k = 0; k < nsteps; ++k) {
@@ -271,38 +272,37 @@ __device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t firs
     }
     __syncthreads();
     if (t >= nsteps) return;
-    double tot[kWallScratchVals];
-    for (int q = 0; q < kWallScratchVals; ++q) {
+    double tot[V];
+    for (int q = 0; q < V; ++q) {
         const int kq = kind(q);
         tot[q] = kq == 0 ? sh[q][t] : (kq == 1 ? fmax(prev[q], v[q]) : fmin(prev[q], v[q]));
     }
-    lbm_stress_summary* h = &f.hist[(first_step + t - 1) % f.hist_cap];
-    h->int_peak_tau2 = tot[0];
-    h->int_tau2 = tot[1];
-    h->d_int_tau2 = tot[10];
+    sm.int_peak_tau2 = tot[0];
+    sm.int_tau2 = tot[1];
+    sm.d_int_tau2 = tot[10];
     for (int w = 0; w < 2; ++w) {
-        h->run_tau_max[w] = tot[2 + w];
-        h->run_tau_min[w] = tot[4 + w];
-        h->run_p_max[w] = tot[6 + w];
-        h->run_p_min[w] = tot[8 + w];
+        sm.run_tau_max[w] = tot[2 + w];
+        sm.run_tau_min[w] = tot[4 + w];
+        sm.run_p_max[w] = tot[6 + w];
+        sm.run_p_min[w] = tot[8 + w];
     }
+    f.hist[(sm.step - 1) % f.hist_cap] = sm;
     if (t == nsteps - 1)
-        for (int q = 0; q < kWallScratchVals; ++q) f.acc[q] = tot[q];
+        for (int q = 0; q < V; ++q) f.acc[q] = tot[q];
 }
 
-// One lattice: a block per step, then the scan over the steps.
-__global__ __launch_bounds__(kWallThreads) void wall_step_reduce_kernel(const WallFlush f, int64_t first_step) {
-    wall_step_reduce_body(f, blockIdx.x, first_step);
+// One lattice: a block per (step, wall), then the scan over the steps.
+__global__ __launch_bounds__(kWallRedThreads) void wall_step_reduce_kernel(const WallFlush f) {
+    wall_step_reduce_body(f, blockIdx.x, blockIdx.y);
 }
 __global__ __launch_bounds__(kWallThreads) void wall_integrate_kernel(const WallFlush f, int nsteps, int64_t first_step) {
     wall_integrate_body(f, nsteps, first_step);
 }
 
-// Many lattices stepped together (same steps): blockIdx.y (reduction) or
+// Many lattices stepped together (same steps): blockIdx.y / 2 (reduction) or
 // blockIdx.x (scan) is the case.
-__global__ __launch_bounds__(kWallThreads) void wall_step_reduce_batch_kernel(const WallFlush* __restrict__ tbl,
-                                                                              int64_t first_step) {
-    wall_step_reduce_body(tbl[blockIdx.y], blockIdx.x, first_step);
+__global__ __launch_bounds__(kWallRedThreads) void wall_step_reduce_batch_kernel(const WallFlush* __restrict__ tbl) {
+    wall_step_reduce_body(tbl[blockIdx.y >> 1], blockIdx.x, blockIdx.y & 1);
 }
 __global__ __launch_bounds__(kWallThreads) void wall_integrate_batch_kernel(const WallFlush* __restrict__ tbl,
                                                                             int nsteps, int64_t first_step) {
@@ -416,7 +416,7 @@ hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t fi
     if (nsteps <= 0) return hipSuccess;
     const WallFlush f{ring, nx, hist, hist_cap, scratch, acc};
     if (nsteps > kWallThreads) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps), dim3(kWallThreads), 0, s, f, first_step);
+    hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps, 2), dim3(kWallRedThreads), 0, s, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(wall_integrate_kernel, dim3(1), dim3(kWallThreads), 0, s, f, nsteps, first_step);
@@ -425,8 +425,8 @@ hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t fi
 
 hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, int64_t first_step, hipStream_t s) {
     if (nsteps <= 0 || ncases <= 0) return hipSuccess;
-    if (nsteps > kWallThreads) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(wall_step_reduce_batch_kernel, dim3(nsteps, ncases), dim3(kWallThreads), 0, s, tbl, first_step);
+    if (nsteps > kWallThreads || ncases > 32767) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wall_step_reduce_batch_kernel, dim3(nsteps, 2 * ncases), dim3(kWallRedThreads), 0, s, tbl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(wall_integrate_batch_kernel, dim3(ncases), dim3(kWallThreads), 0, s, tbl, nsteps, first_step);

@@ -71,7 +71,11 @@ MASS_BOUNDS = {
     "f32s": {500: 3e-8, 2000: 3e-8, 5000: 3e-8, 20000: 1.5e-7, 100000: 4e-6},
     "f16s": {500: 4e-5, 2000: 5e-4, 5000: 1e-3},
     "bf16s": {500: 1.5e-2},
-    "f16r": {500: 2e-5, 2000: 5e-5, 5000: 1e-4, 20000: 2e-4, 100000: 7e-4},
+    # stochastic rounding is unbiased, but its errors still move the total mass as a random walk:
+    # ~4600 liquid nodes with rounding noise of ~2.8e-5 each give ~1.2e-6 of the mass per step,
+    # sigma ~2.6e-5, 5.2e-5, 8.2e-5 and 1.6e-4 after 500, 2000, 5000 and 20000 steps; the bounds
+    # are about 3 sigma (one realisation measured +5.9e-5 at 2000 steps)
+    "f16r": {500: 8e-5, 2000: 1.6e-4, 5000: 2.5e-4, 20000: 5e-4, 100000: 1.2e-3},
 }
 
 

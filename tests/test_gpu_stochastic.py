@@ -94,3 +94,39 @@ def test_runs_are_reproducible_and_steps_draw_new_bits():
     d = np.count_nonzero(a.get_f() != c.get_f())
     log(f"values that rounded differently with another step counter: {d} of {f.size}")
     assert d > 1000
+
+
+def test_values_just_above_powers_of_two_round_to_a_neighbour_without_bias():
+    """Populations placed just above powers of two: at rho = 9/16 the rest populations w_i rho are 1/4,
+    1/16 and 1/64.  A periodic state of FP16 values f_i = fp16(w_i rho(x)), rho(x) = 9/16 plus noise of
+    1.5e-3 (a few FP16 spacings), gives post-collision values on both sides of those powers of two; the
+    ones at most a quarter
+    of the FP16 spacing above one must round to that power of two or the FP16 value above it (never
+    into the finer binade below), and their mean rounding error must vanish."""
+    rng = np.random.default_rng(17)
+    nx, ny = 256, 128
+    kw = dict(T_over_Tc=0.9, dp=0.0, rho0_shift=0.0, check_every=10 ** 6, v_limit=1.0, x_periodic=1, y_periodic=1)
+    rho = 0.5625 + 1.5e-3 * (2 * rng.random((ny, nx)) - 1)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    f0 = (w[:, None, None] * rho[None]).astype(np.float16).astype(np.float64)
+    lats = {}
+    for storage in ("f16r", "f32"):
+        lat = Lattice(nx, ny, 0.9, storage=storage, **kw)
+        lat.set_f(f0)
+        assert lat.step(1) == 0
+        lats[storage] = lat
+    v = lats["f32"].get_f().astype(np.float32)
+    h = lats["f16r"].get_f()
+    lo, hi = neighbours(v)
+    assert np.all((h == lo) | (h == hi))
+    p2 = 2.0 ** np.floor(np.log2(v.astype(np.float64)))
+    spacing = hi - lo
+    t = np.where(spacing > 0, (v - lo) / np.where(spacing > 0, spacing, 1), 0)
+    near = (lo == p2) & (spacing > 0) & (t <= 0.25)  # within a quarter spacing above a power of two
+    k = int(near.sum())
+    err = (h[near] - v[near]) / spacing[near]
+    sigma = math.sqrt(float(np.mean(t[near] * (1 - t[near]))) / k)
+    log(f"{k} values within s/4 above a power of two: mean position {t[near].mean():.4f}, "
+        f"rounded up {np.mean(h[near] == hi[near]):.4f}, mean error {err.mean():+.2e} ulp (sigma {sigma:.1e})")
+    assert k > 5000
+    assert abs(err.mean()) < 5 * sigma + 1e-3
