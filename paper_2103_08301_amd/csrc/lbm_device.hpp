@@ -144,36 +144,30 @@ __device__ inline uint32_t hash32(uint32_t x) {
     return x;
 }
 
-// Stochastic rounding of v to FP16: v goes to one of its two FP16 neighbours,
-// the one above in magnitude with a probability equal to v's fractional position
-// between them (to within 1/2048), so the rounding error has zero mean.
-// For |v| >= 2^-14 (FP16 normals) it acts on v's FP32 bit pattern: the 13
-// mantissa bits below the FP16 cut hold the position t (in 1/8192 of the FP16
-// spacing s); adding an offset o(r) = 8 r + 3 + (r mod 2) for 10 uniform random
-// bits r and clearing the 13 bits rounds the magnitude up exactly when t + o(r) >=
-// 8192.  The offsets are spread over [3, 8188] with mean 4095.5, so the chance of
-// rounding up averages t/8192 over t, and a carry out of the mantissa moves to the
-// next binade exactly: values just above a power of two never drop into the finer
-// binade below, as v + D for a dither D does when D is negative enough.  The
-// cleared pattern has 10 fraction bits and converts to FP16 exactly.  Below 2^-14
-// the FP16 spacing is 2^-24 throughout (subnormals and the lowest normal binade),
-// so there v + D, D = ((2 r + 1)/2048 - 1/2) 2^-24, rounded to nearest does the
-// same.  Both candidates are formed and one is selected (no divergent branch
-// between gas and liquid populations); beyond the FP16 range, inf and NaN round
-// to nearest.
+// Stochastic rounding of v to FP16 with gfx950's conversion instruction
+// (v_cvt_sr_f16_f32): it rounds |v| up to the next FP16 value when t + r/2^32 >= 1,
+// t the fraction of the FP16 spacing by which |v| exceeds the FP16 value below it
+// and r the random operand, so with r uniform over 32 bits the chance of rounding
+// up is t and the expected rounding error is zero.  (Measured on the device with
+// the top 13 bits of r swept exhaustively: the fraction rounded up equals t for
+// normals, values just above and below powers of two, negative values and FP16
+// subnormals, every result is one of v's two FP16 neighbours, and the low 13 bits
+// of r decide only near-ties.)
 __device__ inline _Float16 f16_stochastic(float v, uint32_t r) {
-    const uint32_t u = __float_as_uint(v);
-    const uint32_t mag = u & 0x7fffffffu;
-    const float normal = __uint_as_float((u + (r << 3) + 3u + (r & 1u)) & ~0x1fffu);
-    const float tiny = v + float(int(2u * r) - 1023) * 0x1p-35f;
-    const float pick = mag < 0x38800000u ? tiny : (mag < 0x477fe000u ? normal : v);
-    return static_cast<_Float16>(pick);
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    half2_t z = {};
+    z = __builtin_amdgcn_cvt_sr_f16_f32(z, v, r, false);
+    return z[0];
 }
 
-// 10 random bits for population I: bits 10 (I mod 3) .. of word I / 3.
+// The random word of population I: word I / 3 of the node's three hash words,
+// rotated so that its bits 10 (I mod 3) .. 10 (I mod 3) + 9, drawn for this
+// population alone, are the top bits that decide the rounding.  Every rotated word
+// is uniform over 32 bits; populations sharing a hash word share only the low bits,
+// which decide near-ties.
 template <int I>
-__device__ inline uint32_t sr_bits(const uint32_t (&h)[3]) {
-    return (h[I / 3] >> (10 * (I % 3))) & 1023u;
+__device__ inline uint32_t sr_word(const uint32_t (&h)[3]) {
+    return __builtin_amdgcn_alignbit(h[I / 3], h[I / 3], 10u * (I % 3) + 10u);
 }
 
 // FP16 storage of f_i - w_i rho0 with stochastic rounding (the step kernel
@@ -886,17 +880,14 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
         if (out_lane) {
             const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
             if constexpr (stochastic_codec<CD>()) {
-                // 96 random bits per node and step: three hashes of (node, step), 10 bits per
-                // population, so the nine populations of a node round independently (words
-                // derived from one hash by xorshift steps would carry only 32 bits of entropy
-                // per node).  The interface lag that stochastic rounding leaves on the periodic
-                // plug channel (1-2 lattice units behind FP64 after 20000 steps) does not shrink
-                // with 12 random bits per population instead of 8 or 10: it comes from the
-                // rounding noise itself, not from the dither's resolution.
+                // 96 random bits per node and step: three hashes of (node, step), 10 bits of
+                // its own per population in the top bits of its random word, so the nine
+                // populations of a node round independently (words derived from one hash by
+                // xorshift steps would carry only 32 bits of entropy per node).
                 const uint32_t nd = uint32_t(y * a.pitch + x) * 3u;
                 const uint32_t h[3] = {hash32(sr_seed ^ nd), hash32(sr_seed ^ (nd + 1u)), hash32(sr_seed ^ (nd + 2u))};
 #define LBM_SSTORE(I) \
-    buffer_store(CD::template encode_sr<I>(f[j][I], rho0, sr_bits<I>(h)), rout, o, uint32_t(I) * plane_bytes);
+    buffer_store(CD::template encode_sr<I>(f[j][I], rho0, sr_word<I>(h)), rout, o, uint32_t(I) * plane_bytes);
                 LBM_SSTORE(0) LBM_SSTORE(1) LBM_SSTORE(2) LBM_SSTORE(3) LBM_SSTORE(4) LBM_SSTORE(5) LBM_SSTORE(6)
                 LBM_SSTORE(7) LBM_SSTORE(8)
 #undef LBM_SSTORE
