@@ -625,6 +625,16 @@ class Batch:
 
 # ---- autograd ------------------------------------------------------------------
 
+def _check_wall_shear_spec(spec: dict):
+    """The adjoint holds the wall ghost density fixed.  Without an explicit rho_wall the library
+    sets it to rho_l(T) of each theta, so the forward J would depend on theta through the wall
+    density and the returned gradient would not be the gradient of J: such a spec is refused."""
+    rw = spec.get("params", {}).get("rho_wall")
+    if rw is None or not math.isfinite(float(rw)):
+        raise ValueError("WallShearObjective needs spec['params']['rho_wall'] (a finite wall density): the "
+                         "gradient holds the wall density fixed, and by default it would follow rho_l(theta)")
+
+
 def _wall_shear_lattice(theta, spec: dict):
     """A lattice at theta = (dp, a, b, T) with T absolute, initialised with spec['rho_init']."""
     dp, a, b, T = (float(v) for v in theta)
@@ -646,8 +656,9 @@ class WallShearObjective:
     adjoint kernels.
 
     spec: nx, ny, tau, nsteps, rho_init (ny x nx initial density, held fixed), params (other lbm_params
-    fields; give rho_wall to hold the wall density fixed), optional segment, device and objective ("sum", the
-    default, or "peak": the time integral of the squared peak wall shear).
+    fields; rho_wall is required: the gradient holds the wall density fixed, so it must not follow theta),
+    optional segment, device and objective ("sum", the default, or "peak": the time integral of the squared
+    peak wall shear).
 
         J = WallShearObjective.apply(theta, spec); J.backward()  ->  theta.grad
     """
@@ -663,6 +674,7 @@ class WallShearObjective:
         class _Fn(torch.autograd.Function):
             @staticmethod
             def forward(ctx, theta, spec):
+                _check_wall_shear_spec(spec)
                 lat = _wall_shear_lattice(theta.detach().cpu().tolist(), spec)
                 lat.adjoint_bind(spec["nsteps"], spec.get("segment", 0), spec.get("objective", "sum"))
                 st, J = lat.adjoint_forward()

@@ -68,3 +68,20 @@ def test_limits_and_errors():
         lbm.lbm_components_field(rho, 0.1, 0.05, 5)
     with pytest.raises(lbm.LbmError):
         lbm.lbm_components_field(rho, float("nan"), 0.05, 4)
+
+
+def test_wall_shear_objective_requires_a_fixed_wall_density():
+    """The adjoint holds rho_wall fixed; a spec that leaves it to follow rho_l(theta) is refused before any
+    device work (so this runs without a GPU)."""
+    import math
+
+    import pytest
+    import torch
+
+    from paper_2103_08301_amd.lbm import WallShearObjective
+
+    theta = torch.tensor([1e-3, 1.0, 4.0, 0.08], dtype=torch.float64, requires_grad=True)
+    base = dict(nx=32, ny=16, tau=1.0, nsteps=10, rho_init=None)
+    for params in ({}, {"rho_wall": None}, {"rho_wall": math.nan}):
+        with pytest.raises(ValueError, match="rho_wall"):
+            WallShearObjective.apply(theta, dict(base, params=params))

@@ -346,3 +346,59 @@ def test_reset_stress_extremes_restarts_the_running_spans():
         assert last["run_p_max"][w] == max(h["p_max"][w] for h in window)
         assert last["run_p_min"][w] == min(h["p_min"][w] for h in window)
     assert last["int_tau2"] > int_before  # the integral is not restarted
+
+
+def test_fp32_headline_grid_2000_steps_against_oracle():
+    """The timed workload itself (4096x512, CS 0.95 Tc, tau 0.8, plug 300, film 16, noise 1e-3 seed 2,
+    dp drawn from seed 2), element by element against the FP64 oracle over 2000 steps from the same
+    initial state, with both FP32-storage variants run beside one oracle run (about half a minute on
+    16 host threads):
+
+      * f32d (FP32 storage, FP64 arithmetic) holds rel L-inf(rho) <= 1e-5 throughout (measured
+        3.7e-7 at 250 steps, 8.8e-7 at 2000);
+      * f32 (FP32 storage and arithmetic, the timed kernel) meets 1e-5 to about step 1000 (measured
+        5.2e-6 at 250, 6.4e-6 at 500, 1.05e-5 at 1000, 1.9e-5 at 2000).  Its error grows linearly: in
+        the steady films and the moving plug the FP32 rounding of the arithmetic (not of the storage,
+        which f32d shares) repeats every step, and the plug thins by ~2.5e-4 lattice units over 2000
+        steps.  Evaluating the EOS in FP64 halves it (1.1e-5 at 2000) at 1.8% of the step, the whole
+        collision in FP64 as well reaches 6e-6 at 15%; neither is in the timed kernel.
+
+    Both keep the interfaces within 0.5 lattice units (measured 1.4e-4), the wall stresses within 1e-3
+    and the time integral of the squared wall shear within 1e-3."""
+    from paper_2103_08301_amd import workloads
+
+    w = workloads.plug_large_stable("f32")
+    nx, ny, tau = w["nx"], w["ny"], w["tau"]
+    kw = dict(check_every=500, v_limit=1.0, **w["params"])
+    ref = O.Sim(nx, ny, O.params(tau=tau, **{k: v for k, v in kw.items() if k in ORACLE_KEYS}))
+    pl = w["plug"]
+    rho0 = plug_density(ref, pl["plug_len"], pl["film"], pl["x_center"], pl["noise_amp"], pl["seed"])
+    ref.init_density(rho0)
+    bounds = {"f32d": {250: 1e-5, 500: 1e-5, 1000: 1e-5, 2000: 1e-5},
+              "f32": {250: 1e-5, 500: 1e-5, 1000: 1.2e-5, 2000: 2.2e-5}}
+    lats = {}
+    for storage in bounds:
+        lat = Lattice(nx, ny, tau, storage=storage, **kw)
+        lat.init_density(rho0)
+        lats[storage] = lat
+    for target in (250, 500, 1000, 2000):
+        ref.step(target - ref.steps)
+        rr, _, _ = ref.fields()
+        xr, xf, cols = ref.interface()
+        assert cols > 0  # before rupture
+        for storage, lat in lats.items():
+            assert lat.step(target - lat.steps) == 0
+            rg, _, _ = lat.fields()
+            e = relinf(rg, rr)
+            chk = lat.check()
+            log(f"4096x512 {storage} step {target}: rel Linf rho {e:.3e}, rear {chk['x_rear']:.5f}/{xr:.5f}, "
+                f"front {chk['x_front']:.5f}/{xf:.5f}, liquid columns {chk['liquid_columns']}/{cols}")
+            assert e <= bounds[storage][target], (storage, target, e)
+            assert abs(chk["x_rear"] - xr) <= 0.5 and abs(chk["x_front"] - xf) <= 0.5
+    wr = ref.wall()
+    hr = ref.history()[-1]
+    for storage, lat in lats.items():
+        wg, _ = lat.wall()
+        for key in ("tau_bot", "tau_top", "p_bot", "p_top"):
+            assert np.abs(wg[key] - wr[key]).max() <= 1e-3 * np.abs(wr[key]).max(), (storage, key)
+        assert lat.history(1)[-1]["int_tau2"] == pytest.approx(hr["int_tau2"], rel=1e-3)
