@@ -43,6 +43,7 @@ def kernel_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
+METRIC = "MLUPS and % HBM roofline, D2Q9 4096\u00d7512 FP32 vs FP16-store; adjoint/fwd time"
 GRAPH_STEPS = 0  # steps per captured HIP graph (--graph-steps)
 AUTOTUNE = False  # time every tile shape after the warm-up and keep the fastest (--autotune; always for --batch)
 
@@ -234,7 +235,7 @@ def tangent_cost(steps: int, warmup: int) -> int:
     return 0
 
 
-def adjoint_cost(storage: str, steps: int, segment: int, large: bool) -> int:
+def adjoint_measure(storage: str, steps: int, segment: int, large: bool) -> dict:
     """Time of one gradient of J = int sum tau_w^2 (recorded forward run with checkpoints + one reverse sweep)
     against a plain forward run of the same steps, on the 1024x256 adjoint workload (or 4096x512)."""
     import torch
@@ -278,17 +279,21 @@ def adjoint_cost(storage: str, steps: int, segment: int, large: bool) -> int:
     recompute_steps = steps  # every step is recomputed once from its segment's checkpoint
     t_adj_kernel = max(t_bwd - recompute_steps * t_fwd / steps, 0.0) / steps
     bpn = 23 * (4 if storage == "f32" else 8)  # 5 forward fields and 9 adjoint reads, 9 adjoint writes
-    out = {"metric": "adjoint/fwd time (gradient of int sum tau_w^2 w.r.t. dp, a, b, T)", "workload": w["name"],
-           "storage": storage, "steps": steps, "segment": seg, "checkpoints": math.ceil(steps / seg),
-           "forward_s": round(t_fwd, 4), "record_s": round(t_rec, 4), "backward_s": round(t_bwd, 4),
-           "adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3),
-           "forward_us_per_step": round(t_fwd / steps * 1e6, 2),
-           "adjoint_kernel_us_per_step_est": round(t_adj_kernel * 1e6, 2),
-           "adjoint_kernel_GBps_est": round(bpn * nodes / t_adj_kernel / 1e9, 1) if t_adj_kernel > 0 else None,
-           "adjoint_bytes_per_node": bpn,
-           "status": [st, st2], "J": J, "J_plain_forward": J_fwd,
-           "dJ_ddp": grad[0], "dJ_da": grad[1], "dJ_db": grad[2], "dJ_dT": grad[3]}
-    print(json.dumps(finite(out)), flush=True)
+    del lat
+    return {"metric": "adjoint/fwd time (gradient of int sum tau_w^2 w.r.t. dp, a, b, T)", "workload": w["name"],
+            "storage": storage, "steps": steps, "segment": seg, "checkpoints": math.ceil(steps / seg),
+            "forward_s": round(t_fwd, 4), "record_s": round(t_rec, 4), "backward_s": round(t_bwd, 4),
+            "adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3),
+            "forward_us_per_step": round(t_fwd / steps * 1e6, 2),
+            "adjoint_kernel_us_per_step_est": round(t_adj_kernel * 1e6, 2),
+            "adjoint_kernel_GBps_est": round(bpn * nodes / t_adj_kernel / 1e9, 1) if t_adj_kernel > 0 else None,
+            "adjoint_bytes_per_node": bpn,
+            "status": [st, st2], "J": J, "J_plain_forward": J_fwd,
+            "dJ_ddp": grad[0], "dJ_da": grad[1], "dJ_db": grad[2], "dJ_dT": grad[3]}
+
+
+def adjoint_cost(storage: str, steps: int, segment: int, large: bool) -> int:
+    print(json.dumps(finite(adjoint_measure(storage, steps, segment, large))), flush=True)
     return 0
 
 
@@ -306,36 +311,26 @@ def _time_lattice(lat, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3, None, lat
 
 
-def sweep_cases() -> list:
-    """48 uneven cases shaped like the sweeps of Sec. 3.3 (Figs 10-12): channels of
-    radius 32, 48 and 64 cells (nx = 8 R), pressure drops, plug and film
-    thicknesses varied around a droplet-forming state point (CS 0.90 Tc, tau 1)."""
-    cases = []
-    for R in (32, 48, 64):
-        for dp in (2e-4, 4e-4):
-            for b in (0.6, 1.0):
-                for h in (0.1, 0.15, 0.2, 0.25):
-                    cases.append(dict(nx=8 * R, ny=2 * R, tau=1.0, T_over_Tc=0.90, dp=dp * 4 * R / 256,
-                                      x_periodic=1, plug=b * R, film=h * R))
-    return cases
-
-
 def batch_sweep(storage: str, steps: int, warmup: int) -> int:
-    """Aggregate throughput of the 48 sweep cases as one batch (one launch per
-    step for all cases) and one after another (one launch per case and step)."""
+    """Aggregate throughput of the 48 sweep cases drawn from seed 4 (workloads.c4_cases: nx 1024-4096,
+    ny 128-512, dp, plug and film drawn per case; 42.3 M nodes) advanced as one batch (one launch per step for
+    all cases, autotuned tiles, graphs captured beforehand) against the same cases stepped one after another
+    (one launch per case and step), with each case's stability check after the timed steps."""
     import numpy as np
     import torch
 
-    from paper_2103_08301_amd import Batch, Lattice
+    from paper_2103_08301_amd import Batch, Lattice, workloads
 
-    cases = sweep_cases()
+    cases = workloads.c4_cases()
     nodes = sum(c["nx"] * c["ny"] for c in cases)
-    spec = [{k: v for k, v in c.items() if k not in ("plug", "film")} for c in cases]
-    batch = Batch(spec, storage=storage, check_every=max(steps, warmup, 1), v_limit=0.5, graph_steps=GRAPH_STEPS)
+    init = ("plug", "film", "noise_amp", "seed")
+    spec = [{k: v for k, v in c.items() if k not in init} for c in cases]
+    batch = Batch(spec, storage=storage, check_every=CHECK_EVERY, v_limit=0.5, graph_steps=GRAPH_STEPS)
     for k, c in enumerate(cases):
-        batch[k].init_plug(c["plug"], c["film"], float("nan"), 1e-3, k + 1)
+        batch[k].init_plug(c["plug"], c["film"], float("nan"), c["noise_amp"], c["seed"])
     batch.step(warmup)
     tuned = batch.autotune(20)
+    batch.capture(steps)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(batch.stream)
@@ -343,13 +338,15 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
     e1.record(batch.stream)
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / 1e3
+    checks = [batch[k].check() for k in range(len(cases))]
     lats = []
     for k, (c, s) in enumerate(zip(cases, spec)):
         s = dict(s)
-        lat = Lattice(s.pop("nx"), s.pop("ny"), s.pop("tau"), storage=storage, check_every=max(steps, warmup, 1),
+        lat = Lattice(s.pop("nx"), s.pop("ny"), s.pop("tau"), storage=storage, check_every=CHECK_EVERY,
                       v_limit=0.5, graph_steps=GRAPH_STEPS, **s)
-        lat.init_plug(c["plug"], c["film"], float("nan"), 1e-3, k + 1)
+        lat.init_plug(c["plug"], c["film"], float("nan"), c["noise_amp"], c["seed"])
         lat.step(warmup)
+        lat.capture(steps)
         lats.append(lat)
     torch.cuda.synchronize()
     e0.record(lats[0].stream)
@@ -359,13 +356,19 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
     torch.cuda.synchronize()
     t_seq = e0.elapsed_time(e1) / 1e3
     same = all(np.array_equal(batch[k].fields()[0], lats[k].fields()[0]) for k in range(len(cases)))
-    out = {"metric": "aggregate MLUPS, 48 uneven sweep cases", "unit": "MLUPS", "storage": storage,
-           "cases": len(cases), "nodes": nodes, "steps": steps,
-           "batch": {"MLUPS": round(nodes * steps / t_batch / 1e6, 1), "us_per_step": round(t_batch / steps * 1e6, 2)},
-           "sequential": {"MLUPS": round(nodes * steps / t_seq / 1e6, 1), "us_per_step": round(t_seq / steps * 1e6, 2)},
-           "speedup": round(t_seq / t_batch, 2), "batch_equals_sequential": bool(same), "batch_tiles": tuned,
-           "graph_steps": GRAPH_STEPS}
-    print(json.dumps(out), flush=True)
+    bpn = BYTES_PER_NODE[storage]
+    out = {"metric": "aggregate MLUPS, 48 sweep cases drawn from seed 4", "unit": "MLUPS", "storage": storage,
+           "cases": len(cases), "nodes": nodes, "steps": steps, "warmup": warmup,
+           "batch": {"MLUPS": round(nodes * steps / t_batch / 1e6, 1), "us_per_step": round(t_batch / steps * 1e6, 2),
+                     "roofline_frac": round(bpn * nodes / (t_batch / steps) / 1e9 / HBM_PEAK_GBS, 4)},
+           "sequential": {"MLUPS": round(nodes * steps / t_seq / 1e6, 1), "us_per_step": round(t_seq / steps * 1e6, 2),
+                          "roofline_frac": round(bpn * nodes / (t_seq / steps) / 1e9 / HBM_PEAK_GBS, 4)},
+           "speedup": round(t_seq / t_batch, 3), "batch_equals_sequential": bool(same), "batch_tiles": tuned,
+           "graph_steps": GRAPH_STEPS,
+           "unstable_cases": [[k, ch["unstable_step"]] for k, ch in enumerate(checks) if ch["unstable_step"] >= 0],
+           "ruptured_cases": [[k, ch["rupture_step"]] for k, ch in enumerate(checks) if ch["rupture_step"] >= 0],
+           "max_vmax": max(ch["vmax"] for ch in checks)}
+    print(json.dumps(finite(out)), flush=True)
     return 0
 
 
@@ -467,7 +470,7 @@ def main() -> int:
         h = hist[-1]
         peak = max(abs(h["tau_max"][0]), abs(h["tau_min"][0]), abs(h["tau_max"][1]), abs(h["tau_min"][1]))
     out = {
-        "metric": "MLUPS (D2Q9 EOS-multiphase step, 4096x512 plug-in-channel)",
+        "metric": METRIC if args.workload == "large-stable" else f"MLUPS, D2Q9 {w['nx']}x{w['ny']} ({args.workload})",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -483,7 +486,7 @@ def main() -> int:
                    **{k: v for k, v in w["plug"].items() if k != "x_center"}, "storage": args.storage,
                    "schedule": (f"tile 60x{lat.tuned['tile_rows']}, {lat.tuned['tile_waves']} waves (autotuned)"
                                 if lat.tuned else ("tile 60x8" if args.storage not in ("f64", "f32d") else "tile 60x12")),
-                   "graph_steps": GRAPH_STEPS},
+                   "graph_steps": GRAPH_STEPS, "check_every": CHECK_EVERY},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_node": bpn,
@@ -505,6 +508,24 @@ def main() -> int:
                         "unstable_step": hc["unstable_step"]}
             log(f"{key}: {out[key]}")
             del wh, hl
+        # the same physics on 16384x2048: 2 x 1.2 GB of FP32 distributions, beyond the 256 MB Infinity Cache
+        wo = workloads.plug_out_of_cache(args.storage)
+        no = wo["nx"] * wo["ny"]
+        os_, _, ol = time_steps(wo, args.steps, args.warmup)
+        oc = ol.check()
+        out["out_of_cache"] = {"workload": wo["name"], "value": round(no * args.steps / os_ / 1e6, 1),
+                               "unit": "MLUPS", "ms_per_step": round(os_ * 1e3 / args.steps, 4),
+                               "roofline_frac": round(bpn * no / (os_ / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+                               "unstable_step": oc["unstable_step"]}
+        log(f"out_of_cache: {out['out_of_cache']}")
+        del ol
+        # the gradient's cost: one reverse-mode gradient of int tau_w^2 over the 1024x256, 20000-step run
+        # against a plain forward run of the same steps
+        adj = adjoint_measure("f32", 20000, 0, False)
+        out["adjoint"] = {k: adj[k] for k in ("workload", "steps", "checkpoints", "forward_s", "record_s",
+                                              "backward_s", "adjoint_over_forward", "dJ_ddp", "dJ_da", "dJ_db",
+                                              "dJ_dT")}
+        log(f"adjoint: {out['adjoint']}")
         lit = workloads.plug_large(args.storage)
         ll = make_lattice(lit, check_every=50)
         ll.step(400)

@@ -62,9 +62,14 @@ def plug_large_stable(storage: str = "f32") -> dict:
 
 
 def plug_out_of_cache(storage: str = "f32") -> dict:
-    """16384x2048 control whose distributions (2 x 1.2 GB in FP32) exceed the 256 MB Infinity Cache."""
+    """16384x2048 control whose distributions (2 x 1.2 GB in FP32) exceed the 256 MB Infinity Cache: the
+    4096x512 workload scaled by 4 in both directions (plug 1200, films 64 rows), with the pressure drop
+    scaled with the length so that the body force density dp/nx is the same."""
     w = plug_large_stable(storage)
-    w.update(nx=16384, ny=2048, name=w["name"].replace("4096x512", "16384x2048"))
+    dp = 4 * w["params"]["dp"]
+    w.update(nx=16384, ny=2048,
+             name=f"plug-channel 16384x2048 {storage.upper()} (CS 0.95 Tc, tau 0.8, plug 1200, film 64, dp {dp:.6g})")
+    w["params"] = dict(w["params"], dp=dp)
     w["plug"] = dict(w["plug"], plug_len=1200, film=64)
     return w
 
@@ -81,3 +86,21 @@ def plug_adjoint(storage: str = "f32") -> dict:
         params=dict(T_over_Tc=0.95, dp=5e-4),
         plug=dict(plug_len=120, film=8, x_center=math.nan, noise_amp=1e-3, seed=5),
     )
+
+
+def c4_cases(n: int = 48, seed: int = 4) -> list:
+    """The sweep of Sec. 3.3 (Figs 10-12: pressure drop, plug and film thickness varied) as n independent
+    channels drawn from SplitMix64(seed): per case, in this order, nx uniform in [1024, 4096], ny uniform in
+    [128, 512] (integers), dp uniform in [5e-4, 3e-3], plug length / ny uniform in [0.3, 1.2] and film
+    thickness / ny uniform in [0.01, 0.08] (plug rounded to whole cells, films to whole rows, at least one).
+    The state point is the 4096x512 workload's (CS 0.95 Tc, tau 0.8; the plug's rear interface at nx/4) and
+    the initial noise 1e-3 with seed `seed`."""
+    cases = []
+    for k in range(n):
+        u = [uniform(seed, 5 * k + j) for j in range(5)]
+        nx = 1024 + int(u[0] * 3073)
+        ny = 128 + int(u[1] * 385)
+        cases.append(dict(nx=nx, ny=ny, tau=0.8, T_over_Tc=0.95, dp=5e-4 + 2.5e-3 * u[2],
+                          plug=float(round((0.3 + 0.9 * u[3]) * ny)),
+                          film=float(max(1, round((0.01 + 0.07 * u[4]) * ny))), noise_amp=1e-3, seed=seed))
+    return cases

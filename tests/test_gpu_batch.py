@@ -128,3 +128,41 @@ def test_batch_reports_the_unstable_case():
         b.step(30)
     assert e.value.status == lbm.LBM_EUNSTABLE and e.value.case == 1
     assert b[0].check()["unstable_step"] == -1 and b[1].check()["unstable_step"] == 10
+
+
+@pytest.mark.parametrize("storage,bound", [("f64", 1e-10), ("f32", 1e-5)])
+def test_drawn_sweep_cases_in_a_batch_match_the_oracle(storage, bound):
+    """The three smallest of the 48 sweep cases drawn from seed 4 (workloads.c4_cases; 1113x242 and the
+    next two), as one batch, each against its own FP64 oracle run over 200 steps from the same initial
+    state: rel L-inf(rho) <= 1e-10 with FP64 storage and <= 1e-5 with FP32, interfaces within 0.5 lattice
+    units, the wall stresses alongside."""
+    from paper_2103_08301_amd import workloads
+
+    cases = sorted(workloads.c4_cases(), key=lambda c: c["nx"] * c["ny"])[:3]
+    init = ("plug", "film", "noise_amp", "seed")
+    spec = [{k: v for k, v in c.items() if k not in init} for c in cases]
+    b = Batch(spec, storage=storage, check_every=1000, v_limit=1.0)
+    refs = []
+    for k, c in enumerate(cases):
+        b[k].init_plug(c["plug"], c["film"], math.nan, c["noise_amp"], c["seed"])
+        ref = O.Sim(c["nx"], c["ny"], O.params(tau=c["tau"], T_over_Tc=c["T_over_Tc"], dp=c["dp"], v_limit=1.0,
+                                               check_every=1000))
+        ref.init_plug(c["plug"], c["film"], math.nan, c["noise_amp"], c["seed"])
+        refs.append(ref)
+    b.step(200)
+    for k, (c, ref) in enumerate(zip(cases, refs)):
+        ref.step(200)
+        rg, _, _ = b[k].fields()
+        rr, _, _ = ref.fields()
+        e = float(np.abs(rg - rr).max() / np.abs(rr).max())
+        chk = b[k].check()
+        xr, xf, cols = ref.interface()
+        print(f"sweep case {c['nx']}x{c['ny']} {storage}: rel Linf rho {e:.2e}, rear {chk['x_rear']:.4f}/{xr:.4f}, "
+              f"front {chk['x_front']:.4f}/{xf:.4f}", flush=True)
+        assert e <= bound
+        assert chk["liquid_columns"] == cols
+        assert abs(chk["x_rear"] - xr) <= 0.5 and abs(chk["x_front"] - xf) <= 0.5
+        wg, _ = b[k].wall()
+        wr = ref.wall()
+        for key in ("tau_bot", "tau_top", "p_bot", "p_top"):
+            assert np.abs(wg[key] - wr[key]).max() <= 1e3 * bound * np.abs(wr[key]).max(), key
