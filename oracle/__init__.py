@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("s_eps", C.c_double), ("s_q", C.c_double), ("s_j", C.c_double),
         ("rho_wall", C.c_double), ("dp", C.c_double), ("x_periodic", C.c_int),
         ("y_periodic", C.c_int), ("check_every", C.c_int), ("v_limit", C.c_double),
+        ("forcing", C.c_int),
     ]
 
 

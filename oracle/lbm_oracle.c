@@ -341,6 +341,7 @@ void orc_lap_field(const double* a, int w, int h, double* lap) {
 typedef struct {
     double S[9];     /* diagonal relaxation rates */
     double tau;
+    int forcing;     /* ORC_FORCING_* */
     double Minv[9][9];
 } collide_t;
 
@@ -350,10 +351,14 @@ static void collide_setup(const orc_params* p, collide_t* c) {
     double S[9] = {0.0, p->s_e, p->s_eps, sj, p->s_q, sj, p->s_q, sv, sv};
     memcpy(c->S, S, sizeof S);
     c->tau = p->tau;
+    c->forcing = p->forcing;
     inverse_moment_matrix(c->Minv);
 }
 
-/* f -> f* for one node given the force; also returns rho and v = u + F/(2 rho). */
+/* f -> f* for one node given the force; also returns rho and v = u + F/(2 rho).
+   Velocity shift (the method): the equilibrium is taken at u + tau F/rho.
+   Exact difference (comparison only): the equilibrium is taken at u and the
+   difference f_eq(rho, u + F/rho) - f_eq(rho, u) is added after the collision. */
 static void collide(const collide_t* c, const double* f, double Fx, double Fy,
                     double* fout, double* rho_out, double* vx, double* vy) {
     double rho = 0.0, jx = 0.0, jy = 0.0;
@@ -363,7 +368,8 @@ static void collide(const collide_t* c, const double* f, double Fx, double Fy,
         jy += f[i] * EY[i];
     }
     double ux = jx / rho, uy = jy / rho;
-    double uex = ux + c->tau * Fx / rho, uey = uy + c->tau * Fy / rho;
+    const int edm = c->forcing == ORC_FORCING_EXACT_DIFFERENCE;
+    double uex = edm ? ux : ux + c->tau * Fx / rho, uey = edm ? uy : uy + c->tau * Fy / rho;
     *vx = ux + Fx / (2.0 * rho);
     *vy = uy + Fy / (2.0 * rho);
     *rho_out = rho;
@@ -381,6 +387,11 @@ static void collide(const collide_t* c, const double* f, double Fx, double Fy,
     for (int i = 0; i < 9; ++i) {
         fout[i] = 0.0;
         for (int k = 0; k < 9; ++k) fout[i] += c->Minv[i][k] * ms[k];
+    }
+    if (edm) {
+        double f1[9];
+        orc_equilibrium(rho, ux + Fx / rho, uy + Fy / rho, f1);
+        for (int i = 0; i < 9; ++i) fout[i] += f1[i] - feq[i];
     }
 }
 
@@ -453,11 +464,14 @@ void orc_params_default(orc_params* p) {
     p->y_periodic = 0;
     p->check_every = 1000;
     p->v_limit = 0.5;
+    p->forcing = ORC_FORCING_VELOCITY_SHIFT;
 }
 
 int orc_create(int nx, int ny, const orc_params* p, orc_sim** out) {
     *out = NULL;
-    if (nx < 3 || ny < 3 || !(p->tau > 0.5) || p->check_every < 1) return ORC_EINVAL;
+    if (nx < 3 || ny < 3 || !(p->tau > 0.5) || p->check_every < 1 ||
+        (p->forcing != ORC_FORCING_VELOCITY_SHIFT && p->forcing != ORC_FORCING_EXACT_DIFFERENCE))
+        return ORC_EINVAL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof *s);
     if (!s) return ORC_ENOMEM;
     s->nx = nx;

@@ -47,7 +47,17 @@ typedef struct {
     int y_periodic;     /* 1: periodic in y (no walls); 0: halfway bounce-back walls */
     int check_every;    /* stability check cadence in steps (>= 1) */
     double v_limit;     /* |v| above this (or a NaN) at a check is an instability */
+    int forcing;        /* ORC_FORCING_VELOCITY_SHIFT (Sec. 2.2, the method) or, for comparison
+                           only, ORC_FORCING_EXACT_DIFFERENCE */
 } orc_params;
+
+/* How the force enters the collision.  The method of the paper shifts the
+   equilibrium velocity (Sec. 2.2).  The exact difference method of Kupershtokh,
+   Medvedev & Karpov (Comput. Math. Appl. 58, 2009) relaxes towards the
+   equilibrium at u = j/rho and then adds f_eq(rho, u + F/rho) - f_eq(rho, u),
+   which leaves the steady state independent of tau; it is here only to compare
+   the two, and the GPU library implements the velocity shift alone. */
+enum { ORC_FORCING_VELOCITY_SHIFT = 0, ORC_FORCING_EXACT_DIFFERENCE = 1 };
 
 typedef struct {
     int64_t step;                       /* 1-based index of the step these values belong to */
