@@ -61,15 +61,15 @@ typedef enum {
 typedef enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 } lbm_eos_kind;
 
 /* Storage of the distributions in device memory and arithmetic of the step:
-   F64: FP64 / FP64.  F32: FP32 / FP32.  F16S, BF16S: f_i - w_i rho0_shift in
-   FP16 / BF16, FP32 arithmetic.  F32D: FP32 storage, FP64 arithmetic.
-   F32S: f_i - w_i rho0_shift in FP32, FP32 arithmetic. */
+   F64: FP64 / FP64.  F32: FP32 / FP32.  F16S, BF16S: f_i - 9 w_i q in
+   FP16 / BF16, FP32 arithmetic (q: see rho0_shift).  F32D: FP32 storage, FP64
+   arithmetic.  F32S: f_i - 9 w_i q in FP32, FP32 arithmetic. */
 /* Storage of the distributions.  F64T keeps each population as an FP64 value
    and its FP64 tangent along a direction of the parameters (lbm_set_tangent):
    the step then runs in tangent-linear arithmetic and the wall summaries carry
    the derivative of the squared wall shear (forward-mode sensitivities).  F64T
    runs on the tile schedule with 12-row, 8-wave tiles, CS or PR.
-   F16R: f_i - w_i rho0_shift in FP16 with stochastic rounding, FP32
+   F16R: f_i - 9 w_i q in FP16 with stochastic rounding, FP32
    arithmetic: each stored value rounds up or down to a neighbouring FP16 value
    with probabilities that make the expected rounding error zero, the random
    bits coming from an integer hash of (step counter, node, direction), so runs
@@ -97,7 +97,11 @@ typedef struct {
     int x_periodic;      /* 1: periodic ends; 0: extrapolated (zero-gradient) ends */
     int y_periodic;      /* 1: no walls, periodic in y (test mode; no wall diagnostics) */
     int storage;         /* lbm_storage */
-    double rho0_shift;   /* shift of F16S/BF16S storage; NaN selects rho_g(T) */
+    double rho0_shift;   /* density shift rho0 of the shifted storages (F32S, F16S, F16R, BF16S);
+                            NaN selects rho_g(T).  They store f_i - 9 w_i q with q = rho0 / 9
+                            rounded to a multiple of 2^-24, so that the shift constants
+                            9 w_i q (w_i = 4/9, 1/9, 1/36) have few bits and an FP16 value
+                            plus its shift is exact in FP32 (below 1/4) */
     int check_every;     /* stability/interface check cadence in steps (>= 1) */
     double v_limit;      /* a check fails when |v| exceeds this or a NaN appears */
     int history_cap;     /* capacity (steps) of the device ring of per-step wall summaries (>= 1) */

@@ -308,13 +308,14 @@ struct lbm_ctx {
     double tau = 1.0;
     lbm_params p{};
     Eos eos{};
-    double rho_c = 0, rho_g = NAN, rho_l = NAN, rho_w = 0, rho0 = 0;
+    double rho_c = 0, rho_g = NAN, rho_l = NAN, rho_w = 0;
+    double shift_q = 0;  // shifted storage: f_i - 9 w_i q is stored, q = rho0_shift / 9 on a 2^-24 grid
     int pitch = 0;
     long long plane = 0;
     int nstrip = 0, nchunk = 0, ty = 0, schedule = 0, tile_waves = 4, pipe_blocks = 0;
     // workspace layout (byte offsets)
     size_t off_f[2]{}, off_rho = 0, off_vx = 0, off_vy = 0, off_ring = 0, off_hist = 0,
-           off_acc = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, off_tickets = 0,
+           off_acc = 0, off_wparts = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, off_tickets = 0,
            off_sr = 0, total = 0;
     char* dev = nullptr;
     hipStream_t stream = nullptr;
@@ -450,6 +451,13 @@ lbm_status device_range_check(const void* p, size_t bytes, const char** why) {
         if (e_ != hipSuccess) return fail(ctx, LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// The single-lattice wall flush counts its finished blocks in acc[kFlushTicket] (the
+// accumulator block holds 32 doubles, kWallAccVals of them accumulators); the last
+// block clears it, so it is zero between flushes.
+constexpr int kFlushTicket = 16;
+static_assert(lbm::kWallAccVals <= kFlushTicket, "ticket after the accumulators");
+unsigned* flush_ticket(lbm_ctx* c) { return reinterpret_cast<unsigned*>(c->at<double>(c->off_acc) + kFlushTicket); }
+
 lbm_status reset_diagnostics(lbm_ctx* c) {
     const long long nxy = (long long)c->nx * c->ny;
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_vx), 0.0, nxy, c->stream));
@@ -459,6 +467,7 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     for (int q = 0; q < 4; ++q)  // running maxima start at -inf, minima at +inf
         HIP_TRY(c, lbm::launch_fill(acc + 2 + 2 * q, (q % 2 == 0) ? -INFINITY : INFINITY, 2, c->stream));
     HIP_TRY(c, lbm::launch_fill(acc + 10, 0.0, 1, c->stream));  // tangent of the sum-of-squares integral
+    HIP_TRY(c, lbm::launch_fill(acc + kFlushTicket, 0.0, 1, c->stream));  // the wall flush's ticket
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_sr), 0.0, 1, c->stream));  // stochastic-rounding step counters
     c->steps = 0;
     c->fields_step = 0;  // the initialisation writes the density and zero velocity
@@ -479,7 +488,7 @@ lbm_status run_check(lbm_ctx* c);
 
 lbm_status init_from_device_rho(lbm_ctx* c) {
     HIP_TRY(c, lbm::launch_init(c->at<double>(c->off_rho), c->dev + c->off_f[0], c->nx, c->ny, c->pitch, c->plane,
-                                c->p.storage, c->rho0, c->stream));
+                                c->p.storage, c->shift_q, c->stream));
     c->cur = 0;
     lbm_status s = reset_diagnostics(c);
     if (s) return s;
@@ -492,7 +501,8 @@ lbm_status flush_wall(lbm_ctx* c) {
     if (!c->p.y_periodic) {
         HIP_TRY(c, lbm::launch_wall_reduce(c->at<double>(c->off_ring), c->ring_fill, c->nx, c->ring_first_step,
                                            c->at<lbm_stress_summary>(c->off_hist), c->p.history_cap,
-                                           c->at<double>(c->off_wscr), c->at<double>(c->off_acc), c->stream));
+                                           c->at<double>(c->off_wparts), c->at<double>(c->off_wscr),
+                                           c->at<double>(c->off_acc), flush_ticket(c), c->stream));
     }
     c->ring_first_step += c->ring_fill;
     c->ring_fill = 0;
@@ -618,7 +628,7 @@ lbm::StepArgs make_args(const lbm_ctx* c) {
     a.a_eff = c->eos.a * c->eos.alpha;
     a.b = c->eos.b;
     a.rho_w = c->rho_w;
-    a.rho0 = c->rho0;
+    a.rho0 = c->shift_q;
     a.cf = lbm::CoefF32{float(a.tau), float(a.s_e), float(a.s_eps), float(a.s_q), float(a.s_j), float(a.s_v),
                         float(a.k2), float(a.kappa), float(a.g), float(a.nu), float(a.RT), float(a.a_eff),
                         float(a.b), float(a.rho_w), float(a.rho0)};
@@ -716,7 +726,9 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     }
     const double liquid = std::isnan(c->rho_l) ? c->rho_c : c->rho_l;
     c->rho_w = std::isnan(p->rho_wall) ? liquid : p->rho_wall;
-    c->rho0 = std::isnan(p->rho0_shift) ? (std::isnan(c->rho_g) ? c->rho_c : c->rho_g) : p->rho0_shift;
+    const double rho0 = std::isnan(p->rho0_shift) ? (std::isnan(c->rho_g) ? c->rho_c : c->rho_g) : p->rho0_shift;
+    // the shift constants 9 w_i q = {4, 1, 1/4} q are then dyadic with few bits (exact in FP32)
+    c->shift_q = std::ldexp(std::nearbyint(std::ldexp(rho0 / 9.0, 24)), -24);
     c->pitch = pitch;
     c->plane = (long long)pitch * ny;
     c->nstrip = (nx + lbm::kStripOut - 1) / lbm::kStripOut;
@@ -746,6 +758,7 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->off_ring = o; o += align256((size_t)kRingCap * lbm::kWallSlotVals * nx * sizeof(double));
     c->off_hist = o; o += align256((size_t)p->history_cap * sizeof(lbm_stress_summary));
     c->off_acc = o; o += 256;
+    c->off_wparts = o; o += align256((size_t)kRingCap * 2 * lbm::wall_segments(nx) * lbm::kWallPartVals * sizeof(double));
     c->off_wscr = o; o += align256((size_t)kRingCap * 2 * lbm::kWallPartVals * sizeof(double));
     c->off_red = o; o += align256((size_t)lbm::kFieldReduceBlocks * 5 * sizeof(double));
     c->off_redout = o; o += 256;
@@ -1122,8 +1135,8 @@ lbm_status lbm_check_state_noalloc(lbm_ctx* c, lbm_check_result* out) {
     return LBM_OK;
 }
 
-// Same shift arithmetic as the device codecs (fused multiply-add with the FP32 weight).
-static float host_weight(int i) { return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
+// Same shift arithmetic as the device codecs: one fused multiply-add with 9 w_i and the shift unit q.
+static float host_k(int i) { return i == 0 ? 4.0f : (i < 5 ? 1.0f : 0.25f); }
 
 lbm_status lbm_get_f(lbm_ctx* c, double* f) {
     if (!c || !f) return LBM_EINVAL;
@@ -1132,7 +1145,7 @@ lbm_status lbm_get_f(lbm_ctx* c, double* f) {
     std::vector<unsigned char> raw((size_t)c->plane * 9 * sb);
     HIP_TRY(c, hipMemcpyAsync(raw.data(), c->dev + c->off_f[c->cur], raw.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    const float r0 = (float)c->rho0;
+    const float r0 = (float)c->shift_q;
     for (int i = 0; i < 9; ++i)
         for (int y = 0; y < c->ny; ++y)
             for (int x = 0; x < c->nx; ++x) {
@@ -1143,12 +1156,12 @@ lbm_status lbm_get_f(lbm_ctx* c, double* f) {
                     case LBM_F64T: std::memcpy(&v, raw.data() + src * 16, 8); break;
                     case LBM_F32:
                     case LBM_F32D: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = t; break; }
-                    case LBM_F32S: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = (double)std::fmaf(host_weight(i), r0, t); break; }
+                    case LBM_F32S: { float t; std::memcpy(&t, raw.data() + src * 4, 4); v = (double)std::fmaf(host_k(i), r0, t); break; }
                     case LBM_F16S:
                     case LBM_F16R: {
                         _Float16 h;
                         std::memcpy(&h, raw.data() + src * 2, 2);
-                        v = (double)std::fmaf(host_weight(i), r0, (float)h);
+                        v = (double)std::fmaf(host_k(i), r0, (float)h);
                         break;
                     }
                     default: {
@@ -1157,7 +1170,7 @@ lbm_status lbm_get_f(lbm_ctx* c, double* f) {
                         uint32_t u = (uint32_t)h << 16;
                         float t;
                         std::memcpy(&t, &u, 4);
-                        v = (double)std::fmaf(host_weight(i), r0, t);
+                        v = (double)std::fmaf(host_k(i), r0, t);
                     }
                 }
                 f[((size_t)i * c->ny + y) * c->nx + x] = v;
@@ -1174,7 +1187,7 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
     }
     const size_t sb = storage_bytes(c->p.storage);
     std::vector<unsigned char> raw((size_t)c->plane * 9 * sb, 0);
-    const float r0 = (float)c->rho0;
+    const float r0 = (float)c->shift_q;
     for (int i = 0; i < 9; ++i)
         for (int y = 0; y < c->ny; ++y)
             for (int x = 0; x < c->nx; ++x) {
@@ -1185,15 +1198,15 @@ lbm_status lbm_set_f(lbm_ctx* c, const double* f) {
                     case LBM_F64T: std::memcpy(raw.data() + dst * 16, &v, 8); break;  // tangent zero
                     case LBM_F32:
                     case LBM_F32D: { const float t = (float)v; std::memcpy(raw.data() + dst * 4, &t, 4); break; }
-                    case LBM_F32S: { const float t = std::fmaf(-host_weight(i), r0, (float)v); std::memcpy(raw.data() + dst * 4, &t, 4); break; }
+                    case LBM_F32S: { const float t = std::fmaf(-host_k(i), r0, (float)v); std::memcpy(raw.data() + dst * 4, &t, 4); break; }
                     case LBM_F16S:
                     case LBM_F16R: {
-                        const _Float16 h = (_Float16)std::fmaf(-host_weight(i), r0, (float)v);
+                        const _Float16 h = (_Float16)std::fmaf(-host_k(i), r0, (float)v);
                         std::memcpy(raw.data() + dst * 2, &h, 2);
                         break;
                     }
                     default: {
-                        const float t = std::fmaf(-host_weight(i), r0, (float)v);
+                        const float t = std::fmaf(-host_k(i), r0, (float)v);
                         uint32_t u;
                         std::memcpy(&u, &t, 4);
                         u += 0x7FFFu + ((u >> 16) & 1u);
@@ -1772,6 +1785,7 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
         HIP_TRY(c, hipMemcpyAsync(c->dev + off_fields[q], fields.data() + q * nxy, nxy * sizeof(double),
                                   hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_acc, h.acc, sizeof h.acc, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_acc) + kFlushTicket, 0.0, 1, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_sr, sr, sizeof sr, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->steps = h.steps;
@@ -1834,6 +1848,7 @@ struct lbm_batch {
     std::vector<int> tile_start;  // ncases + 1
     size_t off_desc = 0, off_tiles = 0, off_flush = 0, total = 0;
     int nflush = 0;  // cases with walls (their wall rings are reduced together)
+    int max_nseg = 1;  // the most wall segments of a case
     std::vector<size_t> off_case;
     char* dev = nullptr;
     hipStream_t stream = nullptr;
@@ -1937,9 +1952,13 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
     std::vector<lbm::WallFlush> flush;
     for (lbm_ctx* c : b->cases)
         if (!c->p.y_periodic)
-            flush.push_back(lbm::WallFlush{c->at<double>(c->off_ring), c->nx, c->at<lbm_stress_summary>(c->off_hist),
-                                           c->p.history_cap, c->at<double>(c->off_wscr), c->at<double>(c->off_acc)});
+            flush.push_back(lbm::WallFlush{c->at<double>(c->off_ring), c->nx, lbm::wall_segments(c->nx),
+                                           c->at<lbm_stress_summary>(c->off_hist), c->p.history_cap,
+                                           c->at<double>(c->off_wparts), c->at<double>(c->off_wscr),
+                                           c->at<double>(c->off_acc), flush_ticket(c)});
     b->nflush = (int)flush.size();
+    b->max_nseg = 1;
+    for (const lbm::WallFlush& f : flush) b->max_nseg = std::max(b->max_nseg, f.nseg);
     hipError_t e = hipMemcpyAsync(b->dev + b->off_desc, desc.data(), desc.size() * sizeof(lbm::StepArgs),
                                   hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && !flush.empty())
@@ -1994,7 +2013,8 @@ lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) 
         if (c0->ring_fill == 0) return LBM_OK;
         if (!dry) {
             hipError_t e = lbm::launch_wall_reduce_batch(reinterpret_cast<const lbm::WallFlush*>(b->dev + b->off_flush),
-                                                         b->nflush, c0->ring_fill, c0->ring_first_step, b->stream);
+                                                         b->nflush, b->max_nseg, c0->ring_fill, c0->ring_first_step,
+                                                         b->stream);
             if (e != hipSuccess)
                 return bfail(b, LBM_EDEVICE, std::string("batch wall reduce: ") + hipGetErrorString(e));
         }

@@ -50,6 +50,11 @@ template <class C>
 __host__ __device__ constexpr C wgt(int i) {
     return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
 }
+// 9 w_i: the shifted codecs' multipliers of the shift unit (powers of two, exact).
+template <class C>
+__host__ __device__ constexpr C kwt(int i) {
+    return i == 0 ? C(4) : (i < 5 ? C(1) : C(0.25));
+}
 
 __device__ inline int wrapi(int v, int n) {
     v %= n;
@@ -100,35 +105,41 @@ struct CodecF32D {
     __device__ static void store(S* p, C v, C r) { *p = encode<I>(v, r); }
 };
 
-// The shifted codecs below add and subtract w_i rho0 with explicit FMAs, so
-// both directions use the same exact product: a load/store round trip carries
-// no systematic offset (with one side contracted and the other not, every step
-// would add the product's rounding error to each population, a mass drift).
+// The shifted codecs below store f_i - k_i q, with k_i = 9 w_i in {4, 1, 1/4} and
+// the shift unit q = rho0 / 9 on a grid of 2^-24 (the host rounds it), passed in
+// place of rho0.  The shift constants k_i q are then short dyadic numbers: adding
+// one back to an FP16 value (a multiple of 2^-24) is exact in FP32 below 1/4, so
+// loading a stored value carries no rounding.  A shift by the exact product
+// w_i rho0 would not be: the decode would round away the same low bits of
+// w_i rho0 at every node whose stored value is small, every step, a systematic
+// mass source (+1.4e-9 per gas node and step at rho0 = rho_g in FP16).  Both
+// directions take k_i q in one explicit FMA, so neither side is contracted
+// differently from the other.
 
-// FP32 storage of f_i - w_i rho0, FP32 arithmetic.
+// FP32 storage of f_i - k_i q, FP32 arithmetic.
 struct CodecF32S {
     using S = float;
     using C = float;
     template <int I>
-    __device__ static C decode(S s, C rho0) { return __builtin_fmaf(wgt<float>(I), rho0, s); }
+    __device__ static C decode(S s, C q) { return __builtin_fmaf(kwt<float>(I), q, s); }
     template <int I>
     __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
     template <int I>
-    __device__ static S encode(C v, C rho0) { return __builtin_fmaf(-wgt<float>(I), rho0, v); }
+    __device__ static S encode(C v, C q) { return __builtin_fmaf(-kwt<float>(I), q, v); }
     template <int I>
     __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
 };
 
-// FP16 storage of f_i - w_i rho0, FP32 arithmetic, round-to-nearest-even.
+// FP16 storage of f_i - k_i q, FP32 arithmetic, round-to-nearest-even.
 struct CodecF16S {
     using S = _Float16;
     using C = float;
     template <int I>
-    __device__ static C decode(S s, C rho0) { return __builtin_fmaf(wgt<float>(I), rho0, static_cast<float>(s)); }
+    __device__ static C decode(S s, C q) { return __builtin_fmaf(kwt<float>(I), q, static_cast<float>(s)); }
     template <int I>
     __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
     template <int I>
-    __device__ static S encode(C v, C rho0) { return static_cast<_Float16>(__builtin_fmaf(-wgt<float>(I), rho0, v)); }
+    __device__ static S encode(C v, C q) { return static_cast<_Float16>(__builtin_fmaf(-kwt<float>(I), q, v)); }
     template <int I>
     __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
 };
@@ -170,15 +181,15 @@ __device__ inline uint32_t sr_word(const uint32_t (&h)[3]) {
     return __builtin_amdgcn_alignbit(h[I / 3], h[I / 3], 10u * (I % 3) + 10u);
 }
 
-// FP16 storage of f_i - w_i rho0 with stochastic rounding (the step kernel
+// FP16 storage of f_i - k_i q with stochastic rounding (the step kernel
 // passes the random bits).  Round-to-nearest repeats the same error every step
 // wherever the populations are steady, which adds up to a mass source; rounding
 // up or down at random makes the errors average out instead.  encode (used by
 // the initialisation) rounds to nearest.
 struct CodecF16R : CodecF16S {
     template <int I>
-    __device__ static S encode_sr(C v, C rho0, uint32_t r) {
-        return f16_stochastic(__builtin_fmaf(-wgt<float>(I), rho0, v), r);
+    __device__ static S encode_sr(C v, C q, uint32_t r) {
+        return f16_stochastic(__builtin_fmaf(-kwt<float>(I), q, v), r);
     }
 };
 template <class CD>
@@ -186,19 +197,19 @@ constexpr bool stochastic_codec() { return false; }
 template <>
 constexpr bool stochastic_codec<CodecF16R>() { return true; }
 
-// BF16 storage of f_i - w_i rho0, FP32 arithmetic, round-to-nearest-even.
+// BF16 storage of f_i - k_i q, FP32 arithmetic, round-to-nearest-even.
 struct CodecBF16S {
     using S = uint16_t;
     using C = float;
     template <int I>
-    __device__ static C decode(S s, C rho0) {
-        return __builtin_fmaf(wgt<float>(I), rho0, __uint_as_float(static_cast<uint32_t>(s) << 16));
+    __device__ static C decode(S s, C q) {
+        return __builtin_fmaf(kwt<float>(I), q, __uint_as_float(static_cast<uint32_t>(s) << 16));
     }
     template <int I>
     __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
     template <int I>
-    __device__ static S encode(C v, C rho0) {
-        uint32_t u = __float_as_uint(__builtin_fmaf(-wgt<float>(I), rho0, v));
+    __device__ static S encode(C v, C q) {
+        uint32_t u = __float_as_uint(__builtin_fmaf(-kwt<float>(I), q, v));
         u += 0x7FFFu + ((u >> 16) & 1u);
         return static_cast<uint16_t>(u >> 16);
     }

@@ -52,7 +52,7 @@ struct StepArgs {
     double k2, kappa, g, nu;
     double RT, a_eff, b;      // EOS: R T, a * alpha(T), b
     double rho_w;             // wall ghost density
-    double rho0;              // storage shift (F16S/BF16S)
+    double rho0;              // shifted storage (F32S/F16S/F16R/BF16S): the shift unit q, rho0 / 9 on a 2^-24 grid
     CoefF32 cf;               // the coefficients above, rounded to FP32
     CoefTangent ct;           // their tangents (tangent-linear storage)
     double* tau_w;            // [2][nx] wall shear of this step (its slot of the wall ring)
@@ -107,7 +107,7 @@ hipError_t launch_step_batch(const StepArgs* cases, const int* tile_start, int n
 // blocks one CU holds at once.
 hipError_t pipe_grid(int storage, int eos, int ty, int waves, int* blocks);
 hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, long long plane,
-                       int storage, double rho0, hipStream_t s);
+                       int storage, double q, hipStream_t s);
 hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
 // out[i] = (float)in[i], i < n.
 hipError_t launch_to_f32(const double* in, float* out, long long n, hipStream_t s);
@@ -118,24 +118,35 @@ hipError_t launch_field_reduce(const double* rho, const double* vx, const double
 // Per column: minimum density over y and the centreline density.
 hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin, double* centre,
                               hipStream_t s);
-// Reduces the first `nsteps` slots of the wall ring (a block per step and wall:
-// extremes and their columns, sums of squares) into the history ring, then
-// accumulates the running time integrals and running extremes acc[kWallAccVals]
-// in step order.  scratch holds 2 x kWallPartVals doubles per step.
+// Reduces the first `nsteps` slots of the wall ring into the history ring, then
+// accumulates the running time integrals and running extremes acc[kWallAccVals] in
+// step order.  Each (step, wall, segment of kWallSegCols columns) is one block's
+// reduction (extremes with their smallest column, sums of squares); the segments
+// are then combined in column order per step, and the per-step values integrated
+// in step order.  The single-lattice flush is one launch: the last block to finish
+// (a ticket counter, zero between flushes) combines and integrates.
+// parts holds [steps][2][nseg][kWallPartVals] doubles, scratch [steps][2][kWallPartVals].
+constexpr int kWallSegCols = 1024;
+inline int wall_segments(int nx) { return (nx + kWallSegCols - 1) / kWallSegCols; }
 hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t first_step,
-                              lbm_stress_summary* hist, int hist_cap, double* scratch, double* acc, hipStream_t s);
+                              lbm_stress_summary* hist, int hist_cap, double* parts, double* scratch, double* acc,
+                              unsigned* ticket, hipStream_t s);
 // The wall ring, history, scratch and accumulators of one lattice.
 struct WallFlush {
     const double* ring;
     int nx;
+    int nseg;                 // wall_segments(nx)
     lbm_stress_summary* hist;
     int hist_cap;
-    double* scratch;
+    double* parts;            // per-segment partials
+    double* scratch;          // per-step, per-wall values
     double* acc;
+    unsigned* ticket;         // single-lattice flush: blocks done
 };
 // launch_wall_reduce for the ncases lattices of tbl (device array) at once;
 // they have stepped together, so nsteps and first_step are shared.
-hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, int64_t first_step, hipStream_t s);
+hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int max_nseg, int nsteps, int64_t first_step,
+                                    hipStream_t s);
 
 // Reverse-mode (adjoint) step (lbm_adjoint.hip).  Tiles of 64 columns give 60
 // outputs (a 2-column halo on each side) and ty output rows.

@@ -8,7 +8,7 @@ namespace {
 
 template <class CD>
 __global__ void init_kernel(const double* __restrict__ rho, void* fv, int nx, int ny, int pitch, long long plane,
-                            double rho0) {
+                            double q) {  // q: the shifted codecs' shift unit
     using S = typename CD::S;
     using C = typename CD::C;
     S* f = static_cast<S*>(fv);
@@ -17,15 +17,15 @@ __global__ void init_kernel(const double* __restrict__ rho, void* fv, int nx, in
         const int y = int(c / nx), x = int(c - (long long)y * nx);
         const C r = C(rho[c]);
         S* p = f + (long long)y * pitch + x;
-        CD::template store<0>(p + 0 * plane, wgt<C>(0) * r, C(rho0));
-        CD::template store<1>(p + 1 * plane, wgt<C>(1) * r, C(rho0));
-        CD::template store<2>(p + 2 * plane, wgt<C>(2) * r, C(rho0));
-        CD::template store<3>(p + 3 * plane, wgt<C>(3) * r, C(rho0));
-        CD::template store<4>(p + 4 * plane, wgt<C>(4) * r, C(rho0));
-        CD::template store<5>(p + 5 * plane, wgt<C>(5) * r, C(rho0));
-        CD::template store<6>(p + 6 * plane, wgt<C>(6) * r, C(rho0));
-        CD::template store<7>(p + 7 * plane, wgt<C>(7) * r, C(rho0));
-        CD::template store<8>(p + 8 * plane, wgt<C>(8) * r, C(rho0));
+        CD::template store<0>(p + 0 * plane, wgt<C>(0) * r, C(q));
+        CD::template store<1>(p + 1 * plane, wgt<C>(1) * r, C(q));
+        CD::template store<2>(p + 2 * plane, wgt<C>(2) * r, C(q));
+        CD::template store<3>(p + 3 * plane, wgt<C>(3) * r, C(q));
+        CD::template store<4>(p + 4 * plane, wgt<C>(4) * r, C(q));
+        CD::template store<5>(p + 5 * plane, wgt<C>(5) * r, C(q));
+        CD::template store<6>(p + 6 * plane, wgt<C>(6) * r, C(q));
+        CD::template store<7>(p + 7 * plane, wgt<C>(7) * r, C(q));
+        CD::template store<8>(p + 8 * plane, wgt<C>(8) * r, C(q));
     }
 }
 
@@ -130,9 +130,8 @@ __global__ __launch_bounds__(64 * kColScanWaves) void column_scan_kernel(const d
         centre[x] = rho[(long long)(ny / 2) * nx + x];
 }
 
-// One wave per step reduces that step's per-strip partials: lanes take strips
-// lane, lane + 64, ... in x order (strict comparisons keep the smallest x),
-// then a fixed butterfly combines the lanes (ties again to the smaller x).
+// Extremes with their columns: a strictly better value wins, an equal one keeps the
+// smaller column, so any fixed combination order yields the smallest column on ties.
 __device__ inline void comb_max(double& v, double& x, double ov, double ox) {
     if (ov > v || (ov == v && ox < x)) { v = ov; x = ox; }
 }
@@ -140,26 +139,27 @@ __device__ inline void comb_min(double& v, double& x, double ov, double ox) {
     if (ov < v || (ov == v && ox < x)) { v = ov; x = ox; }
 }
 
-constexpr int kWallThreads = 256;      // threads of the wall scan block: one per step of a flush (4 waves)
-constexpr int kWallRedThreads = 1024;  // threads of a block that reduces one wall of one step (16 waves)
-constexpr int kWallRedWaves = kWallRedThreads / 64;
+constexpr int kWallThreads = 256;  // threads of a flush block; the integration takes one per step (4 waves)
+constexpr int kWallWaves = kWallThreads / 64;
 
-// One wall of one step of the wall ring (block per (step, wall)): extremes of tau_w
-// and p_w with their columns (the smallest column on ties) and the sums of tau_w^2 and
-// of its tangent, reduced lane-strided, then by wave butterflies, then over the
-// waves in order.  Writes the ten values to scratch[t][w].
-__device__ void wall_step_reduce_body(const WallFlush& f, int t, int w) {
-    __shared__ double sh[kWallRedWaves][10];
+// One segment of one wall of one step of the wall ring: extremes of tau_w and p_w
+// with their columns (the smallest column on ties) and the sums of tau_w^2 and of its
+// tangent over columns seg * kWallSegCols ... (seg + 1) * kWallSegCols - 1, reduced
+// lane-strided, then by wave butterflies, then over the waves in order.  Thread 0
+// writes the ten values to parts[t][w][seg].  Every thread returns.
+__device__ void wall_segment_reduce(const WallFlush& f, int t, int w, int seg) {
+    __shared__ double sh[kWallWaves][kWallPartVals];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nx = f.nx;
     const double* slot = f.ring + (long long)t * kWallSlotVals * nx;  // tau [2][nx], p [2][nx], dtau [2][nx]
     const double* tau = slot + (long long)w * nx;
     const double* pw = slot + (long long)(2 + w) * nx;
     const double* dtau = slot + (long long)(4 + w) * nx;
+    const int x1 = min(nx, (seg + 1) * kWallSegCols);
     double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
     double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0, wds = 0.0;
 #pragma unroll 4
-    for (int x = threadIdx.x; x < nx; x += kWallRedThreads) {  // unrolled: four columns' loads in flight
+    for (int x = seg * kWallSegCols + threadIdx.x; x < x1; x += kWallThreads) {  // four columns' loads in flight
         const double tv = tau[x], pv = pw[x];
         comb_max(tmax, xtmax, tv, double(x));
         comb_min(tmin, xtmin, tv, double(x));
@@ -183,20 +183,44 @@ __device__ void wall_step_reduce_body(const WallFlush& f, int t, int w) {
         o[4] = pmax; o[5] = xpmax; o[6] = pmin; o[7] = xpmin; o[8] = ws; o[9] = wds;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double r[10];
-    for (int q = 0; q < 10; ++q) r[q] = sh[0][q];
-    for (int v = 1; v < kWallRedWaves; ++v) {
-        const double* o = sh[v];
-        comb_max(r[0], r[1], o[0], o[1]);
-        comb_min(r[2], r[3], o[2], o[3]);
-        comb_max(r[4], r[5], o[4], o[5]);
-        comb_min(r[6], r[7], o[6], o[7]);
-        r[8] += o[8];
-        r[9] += o[9];
+    if (threadIdx.x == 0) {
+        double r[kWallPartVals];
+        for (int q = 0; q < kWallPartVals; ++q) r[q] = sh[0][q];
+        for (int v = 1; v < kWallWaves; ++v) {
+            const double* o = sh[v];
+            comb_max(r[0], r[1], o[0], o[1]);
+            comb_min(r[2], r[3], o[2], o[3]);
+            comb_max(r[4], r[5], o[4], o[5]);
+            comb_min(r[6], r[7], o[6], o[7]);
+            r[8] += o[8];
+            r[9] += o[9];
+        }
+        double* o = f.parts + (((long long)t * 2 + w) * f.nseg + seg) * kWallPartVals;
+        for (int q = 0; q < kWallPartVals; ++q) o[q] = r[q];
     }
-    double* o = f.scratch + ((long long)t * 2 + w) * kWallPartVals;
-    for (int q = 0; q < 10; ++q) o[q] = r[q];
+}
+
+// The segments of each step and wall combined in column order (thread per step):
+// scratch[t][w] from parts[t][w][0 .. nseg - 1].
+__device__ void wall_combine_segments(const WallFlush& f, int nsteps) {
+    const int t = threadIdx.x;
+    if (t >= nsteps) return;
+    for (int w = 0; w < 2; ++w) {
+        const double* p = f.parts + ((long long)t * 2 + w) * f.nseg * kWallPartVals;
+        double r[kWallPartVals];
+        for (int q = 0; q < kWallPartVals; ++q) r[q] = p[q];
+        for (int g = 1; g < f.nseg; ++g) {
+            const double* o = p + (long long)g * kWallPartVals;
+            comb_max(r[0], r[1], o[0], o[1]);
+            comb_min(r[2], r[3], o[2], o[3]);
+            comb_max(r[4], r[5], o[4], o[5]);
+            comb_min(r[6], r[7], o[6], o[7]);
+            r[8] += o[8];
+            r[9] += o[9];
+        }
+        double* d = f.scratch + ((long long)t * 2 + w) * kWallPartVals;
+        for (int q = 0; q < kWallPartVals; ++q) d[q] = r[q];
+    }
 }
 
 // The per-step summaries and the running time integrals and extremes of nsteps <=
@@ -291,22 +315,38 @@ __device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t firs
         for (int q = 0; q < V; ++q) f.acc[q] = tot[q];
 }
 
-// One lattice: a block per (step, wall), then the scan over the steps.
-__global__ __launch_bounds__(kWallRedThreads) void wall_step_reduce_kernel(const WallFlush f) {
-    wall_step_reduce_body(f, blockIdx.x, blockIdx.y);
-}
-__global__ __launch_bounds__(kWallThreads) void wall_integrate_kernel(const WallFlush f, int nsteps, int64_t first_step) {
+// One lattice, one launch: a block per (segment, wall, step); the last block to finish
+// combines the segments and integrates over the steps, then clears the ticket.
+__global__ __launch_bounds__(kWallThreads) void wall_flush_kernel(const WallFlush f, int nsteps, int64_t first_step) {
+    __shared__ int last;
+    wall_segment_reduce(f, blockIdx.z, blockIdx.y, blockIdx.x);
+    if (threadIdx.x == 0) {
+        __threadfence();  // this block's partials before its ticket
+        const unsigned total = gridDim.x * gridDim.y * gridDim.z;
+        last = atomicAdd(f.ticket, 1u) == total - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // every other block's partials after their tickets
+    wall_combine_segments(f, nsteps);
+    __syncthreads();
     wall_integrate_body(f, nsteps, first_step);
+    if (threadIdx.x == 0) atomicExch(f.ticket, 0u);
 }
 
-// Many lattices stepped together (same steps): blockIdx.y / 2 (reduction) or
-// blockIdx.x (scan) is the case.
-__global__ __launch_bounds__(kWallRedThreads) void wall_step_reduce_batch_kernel(const WallFlush* __restrict__ tbl) {
-    wall_step_reduce_body(tbl[blockIdx.y >> 1], blockIdx.x, blockIdx.y & 1);
+// Many lattices stepped together (same steps), in two launches with the same
+// arithmetic: blockIdx.y / 2 (reduction) or blockIdx.x (integration) is the case.
+__global__ __launch_bounds__(kWallThreads) void wall_segment_reduce_batch_kernel(const WallFlush* __restrict__ tbl) {
+    const WallFlush& f = tbl[blockIdx.y >> 1];
+    if ((int)blockIdx.x >= f.nseg) return;
+    wall_segment_reduce(f, blockIdx.z, blockIdx.y & 1, blockIdx.x);
 }
 __global__ __launch_bounds__(kWallThreads) void wall_integrate_batch_kernel(const WallFlush* __restrict__ tbl,
                                                                             int nsteps, int64_t first_step) {
-    wall_integrate_body(tbl[blockIdx.x], nsteps, first_step);
+    const WallFlush& f = tbl[blockIdx.x];
+    wall_combine_segments(f, nsteps);
+    __syncthreads();
+    wall_integrate_body(f, nsteps, first_step);
 }
 
 }  // namespace
@@ -365,18 +405,18 @@ hipError_t pipe_grid(int storage, int eos, int ty, int waves, int* blocks) {
 }
 
 hipError_t launch_init(const double* rho, void* f, int nx, int ny, int pitch, long long plane, int storage,
-                       double rho0, hipStream_t s) {
+                       double q, hipStream_t s) {
     const long long n = (long long)nx * ny;
     const int blocks = int((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
     switch (storage) {
-        case LBM_F64: hipLaunchKernelGGL(init_kernel<CodecF64>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
-        case LBM_F32: hipLaunchKernelGGL(init_kernel<CodecF32>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
-        case LBM_F16S: hipLaunchKernelGGL(init_kernel<CodecF16S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
-        case LBM_BF16S: hipLaunchKernelGGL(init_kernel<CodecBF16S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
-        case LBM_F32D: hipLaunchKernelGGL(init_kernel<CodecF32D>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
-        case LBM_F32S: hipLaunchKernelGGL(init_kernel<CodecF32S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
-        case LBM_F64T: hipLaunchKernelGGL(init_kernel<CodecF64T>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
-        case LBM_F16R: hipLaunchKernelGGL(init_kernel<CodecF16R>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, rho0); break;
+        case LBM_F64: hipLaunchKernelGGL(init_kernel<CodecF64>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, q); break;
+        case LBM_F32: hipLaunchKernelGGL(init_kernel<CodecF32>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, q); break;
+        case LBM_F16S: hipLaunchKernelGGL(init_kernel<CodecF16S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, q); break;
+        case LBM_BF16S: hipLaunchKernelGGL(init_kernel<CodecBF16S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, q); break;
+        case LBM_F32D: hipLaunchKernelGGL(init_kernel<CodecF32D>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, q); break;
+        case LBM_F32S: hipLaunchKernelGGL(init_kernel<CodecF32S>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, q); break;
+        case LBM_F64T: hipLaunchKernelGGL(init_kernel<CodecF64T>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, q); break;
+        case LBM_F16R: hipLaunchKernelGGL(init_kernel<CodecF16R>, dim3(blocks), dim3(256), 0, s, rho, f, nx, ny, pitch, plane, q); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -412,21 +452,21 @@ hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin,
 }
 
 hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t first_step, lbm_stress_summary* hist,
-                              int hist_cap, double* scratch, double* acc, hipStream_t s) {
+                              int hist_cap, double* parts, double* scratch, double* acc, unsigned* ticket,
+                              hipStream_t s) {
     if (nsteps <= 0) return hipSuccess;
-    const WallFlush f{ring, nx, hist, hist_cap, scratch, acc};
     if (nsteps > kWallThreads) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(wall_step_reduce_kernel, dim3(nsteps, 2), dim3(kWallRedThreads), 0, s, f);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(wall_integrate_kernel, dim3(1), dim3(kWallThreads), 0, s, f, nsteps, first_step);
+    const WallFlush f{ring, nx, wall_segments(nx), hist, hist_cap, parts, scratch, acc, ticket};
+    hipLaunchKernelGGL(wall_flush_kernel, dim3(f.nseg, 2, nsteps), dim3(kWallThreads), 0, s, f, nsteps, first_step);
     return hipGetLastError();
 }
 
-hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, int64_t first_step, hipStream_t s) {
+hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int max_nseg, int nsteps, int64_t first_step,
+                                    hipStream_t s) {
     if (nsteps <= 0 || ncases <= 0) return hipSuccess;
-    if (nsteps > kWallThreads || ncases > 32767) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(wall_step_reduce_batch_kernel, dim3(nsteps, 2 * ncases), dim3(kWallRedThreads), 0, s, tbl);
+    if (nsteps > kWallThreads || ncases > 32767 || max_nseg < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wall_segment_reduce_batch_kernel, dim3(max_nseg, 2 * ncases, nsteps), dim3(kWallThreads), 0, s,
+                       tbl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(wall_integrate_batch_kernel, dim3(ncases), dim3(kWallThreads), 0, s, tbl, nsteps, first_step);
