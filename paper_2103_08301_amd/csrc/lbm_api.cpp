@@ -247,19 +247,21 @@ bool graph_steps_ok(int g) {
 // Captured HIP graphs of consecutive step launches, made when first needed:
 // replaying a graph issues its launches without a host call per kernel.  Runs
 // of the full graph length are kept per (parity of the input buffer, first
-// wall-ring slot); shorter runs (the rest of a call) per (parity, first slot,
-// length), up to kMaxShortGraphs of them, beyond which short runs are launched
-// kernel by kernel.  The graphs hold only step kernels (no memset nodes).
+// wall-ring slot); shorter runs, and the last run of a call, which ends with the
+// wall flush of the ring so far, per (parity, first slot, length, flush), up to
+// kMaxShortGraphs of them, beyond which such runs are launched kernel by kernel.
+// The graphs hold only step and flush kernels (no memset nodes).
 constexpr size_t kMaxShortGraphs = 64;
 struct StepGraphs {
     hipStream_t cap = nullptr;  // private capture stream (default priority)
     hipGraphExec_t exec[2][kRingCap] = {};
-    std::map<uint32_t, hipGraphExec_t> shorter;  // key: (length << 9) | (slot << 1) | parity
-    // The cache entry for a run of `len` steps from (parity, slot), or null when the
-    // short-run cache is full and the run must be launched kernel by kernel.
-    hipGraphExec_t* entry(int parity, int slot, int len, int full_len) {
-        if (len == full_len) return &exec[parity][slot];
-        const uint32_t key = ((uint32_t)len << 9) | ((uint32_t)slot << 1) | (uint32_t)parity;
+    std::map<uint32_t, hipGraphExec_t> shorter;  // key: (length << 10) | (flush << 9) | (slot << 1) | parity
+    // The cache entry for a run of `len` steps from (parity, slot), followed by the
+    // wall flush if `flush`, or null when the cache of other runs is full and the run
+    // must be launched kernel by kernel.
+    hipGraphExec_t* entry(int parity, int slot, int len, int full_len, bool flush) {
+        if (len == full_len && !flush) return &exec[parity][slot];
+        const uint32_t key = ((uint32_t)len << 10) | ((uint32_t)flush << 9) | ((uint32_t)slot << 1) | (uint32_t)parity;
         auto it = shorter.find(key);
         if (it != shorter.end()) return &it->second;
         if (shorter.size() >= kMaxShortGraphs) return nullptr;
@@ -315,7 +317,7 @@ struct lbm_ctx {
     int nstrip = 0, nchunk = 0, ty = 0, schedule = 0, tile_waves = 4, pipe_blocks = 0;
     // workspace layout (byte offsets)
     size_t off_f[2]{}, off_rho = 0, off_vx = 0, off_vy = 0, off_ring = 0, off_hist = 0,
-           off_acc = 0, off_wparts = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, off_tickets = 0,
+           off_acc = 0, off_wscr = 0, off_red = 0, off_redout = 0, off_colmin = 0, off_centre = 0, off_tickets = 0,
            off_sr = 0, total = 0;
     char* dev = nullptr;
     hipStream_t stream = nullptr;
@@ -451,13 +453,6 @@ lbm_status device_range_check(const void* p, size_t bytes, const char** why) {
         if (e_ != hipSuccess) return fail(ctx, LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-// The single-lattice wall flush counts its finished blocks in acc[kFlushTicket] (the
-// accumulator block holds 32 doubles, kWallAccVals of them accumulators); the last
-// block clears it, so it is zero between flushes.
-constexpr int kFlushTicket = 16;
-static_assert(lbm::kWallAccVals <= kFlushTicket, "ticket after the accumulators");
-unsigned* flush_ticket(lbm_ctx* c) { return reinterpret_cast<unsigned*>(c->at<double>(c->off_acc) + kFlushTicket); }
-
 lbm_status reset_diagnostics(lbm_ctx* c) {
     const long long nxy = (long long)c->nx * c->ny;
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_vx), 0.0, nxy, c->stream));
@@ -467,7 +462,8 @@ lbm_status reset_diagnostics(lbm_ctx* c) {
     for (int q = 0; q < 4; ++q)  // running maxima start at -inf, minima at +inf
         HIP_TRY(c, lbm::launch_fill(acc + 2 + 2 * q, (q % 2 == 0) ? -INFINITY : INFINITY, 2, c->stream));
     HIP_TRY(c, lbm::launch_fill(acc + 10, 0.0, 1, c->stream));  // tangent of the sum-of-squares integral
-    HIP_TRY(c, lbm::launch_fill(acc + kFlushTicket, 0.0, 1, c->stream));  // the wall flush's ticket
+    HIP_TRY(c, lbm::launch_fill(acc + lbm::kAccTicket, 0.0, 1, c->stream));  // the wall flush's ticket
+    HIP_TRY(c, lbm::launch_fill(acc + lbm::kAccNextStep, 1.0, 1, c->stream));  // the first step to flush
     HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_sr), 0.0, 1, c->stream));  // stochastic-rounding step counters
     c->steps = 0;
     c->fields_step = 0;  // the initialisation writes the density and zero velocity
@@ -499,10 +495,9 @@ lbm_status init_from_device_rho(lbm_ctx* c) {
 lbm_status flush_wall(lbm_ctx* c) {
     if (c->ring_fill == 0) return LBM_OK;
     if (!c->p.y_periodic) {
-        HIP_TRY(c, lbm::launch_wall_reduce(c->at<double>(c->off_ring), c->ring_fill, c->nx, c->ring_first_step,
+        HIP_TRY(c, lbm::launch_wall_reduce(c->at<double>(c->off_ring), c->ring_fill, c->nx,
                                            c->at<lbm_stress_summary>(c->off_hist), c->p.history_cap,
-                                           c->at<double>(c->off_wparts), c->at<double>(c->off_wscr),
-                                           c->at<double>(c->off_acc), flush_ticket(c), c->stream));
+                                           c->at<double>(c->off_wscr), c->at<double>(c->off_acc), c->stream));
     }
     c->ring_first_step += c->ring_fill;
     c->ring_fill = 0;
@@ -758,7 +753,6 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     c->off_ring = o; o += align256((size_t)kRingCap * lbm::kWallSlotVals * nx * sizeof(double));
     c->off_hist = o; o += align256((size_t)p->history_cap * sizeof(lbm_stress_summary));
     c->off_acc = o; o += 256;
-    c->off_wparts = o; o += align256((size_t)kRingCap * 2 * lbm::wall_segments(nx) * lbm::kWallPartVals * sizeof(double));
     c->off_wscr = o; o += align256((size_t)kRingCap * 2 * lbm::kWallPartVals * sizeof(double));
     c->off_red = o; o += align256((size_t)lbm::kFieldReduceBlocks * 5 * sizeof(double));
     c->off_redout = o; o += 256;
@@ -929,6 +923,7 @@ lbm_status step_impl(lbm_ctx* c, int64_t n, bool dry) {
         c->ring_fill = 0;
         return LBM_OK;
     };
+    const bool walls = !c->p.y_periodic;
     auto advance = [&](int m, int launches) {
         if (launches & 1) c->cur = 1 - c->cur;
         c->last_slot = c->ring_fill + m - 1;
@@ -965,12 +960,14 @@ lbm_status step_impl(lbm_ctx* c, int64_t n, bool dry) {
             int m = G > 0 ? (int)std::min<int64_t>(body, G) : 0;
             if (L == 2) m &= ~1;
             hipGraphExec_t* ge = nullptr;
+            // the call's last run (no check, no one-step launch after it) ends with the flush
+            const bool with_flush = walls && !check && tail == 0 && m == body;
             if (m > 0) {
                 if (c->ring_fill + m > kRingCap) {
                     lbm_status s = flush();
                     if (s) return s;
                 }
-                ge = c->graphs.entry(c->cur, c->ring_fill, m, G);
+                ge = c->graphs.entry(c->cur, c->ring_fill, m, G, with_flush);
             }
             if (!ge) {  // no graphs, or the cache of short runs is full
                 lbm_status s = eager(m > 0 ? m : body, false);
@@ -982,14 +979,22 @@ lbm_status step_impl(lbm_ctx* c, int64_t n, bool dry) {
             if (!*ge) {
                 const int par = c->cur, fill0 = c->ring_fill;
                 auto launch = [&](int j, hipStream_t s) {
+                    if (j == nl)  // the flush of every ring slot written so far
+                        return lbm::launch_wall_reduce(c->at<double>(c->off_ring), fill0 + m, c->nx,
+                                                       c->at<lbm_stress_summary>(c->off_hist), c->p.history_cap,
+                                                       c->at<double>(c->off_wscr), c->at<double>(c->off_acc), s);
                     lbm::StepArgs b = a;
                     return launch_k(c, b, (par + j) & 1, fill0 + L * j, L, false, s);
                 };
-                HIP_TRY(c, capture_graph(c->graphs, nl, launch, ge));
+                HIP_TRY(c, capture_graph(c->graphs, nl + (with_flush ? 1 : 0), launch, ge));
             }
             if (!dry) HIP_TRY(c, hipGraphLaunch(*ge, c->stream));
             advance(m, nl);
             body -= m;
+            if (with_flush) {  // flushed inside the graph
+                c->ring_first_step += c->ring_fill;
+                c->ring_fill = 0;
+            }
         }
         if (tail) {
             lbm_status s = eager(1, check);
@@ -1785,7 +1790,8 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
         HIP_TRY(c, hipMemcpyAsync(c->dev + off_fields[q], fields.data() + q * nxy, nxy * sizeof(double),
                                   hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_acc, h.acc, sizeof h.acc, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_acc) + kFlushTicket, 0.0, 1, c->stream));
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_acc) + lbm::kAccTicket, 0.0, 1, c->stream));
+    HIP_TRY(c, lbm::launch_fill(c->at<double>(c->off_acc) + lbm::kAccNextStep, double(h.steps + 1), 1, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->dev + c->off_sr, sr, sizeof sr, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->steps = h.steps;
@@ -1848,7 +1854,6 @@ struct lbm_batch {
     std::vector<int> tile_start;  // ncases + 1
     size_t off_desc = 0, off_tiles = 0, off_flush = 0, total = 0;
     int nflush = 0;  // cases with walls (their wall rings are reduced together)
-    int max_nseg = 1;  // the most wall segments of a case
     std::vector<size_t> off_case;
     char* dev = nullptr;
     hipStream_t stream = nullptr;
@@ -1952,13 +1957,9 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
     std::vector<lbm::WallFlush> flush;
     for (lbm_ctx* c : b->cases)
         if (!c->p.y_periodic)
-            flush.push_back(lbm::WallFlush{c->at<double>(c->off_ring), c->nx, lbm::wall_segments(c->nx),
-                                           c->at<lbm_stress_summary>(c->off_hist), c->p.history_cap,
-                                           c->at<double>(c->off_wparts), c->at<double>(c->off_wscr),
-                                           c->at<double>(c->off_acc), flush_ticket(c)});
+            flush.push_back(lbm::WallFlush{c->at<double>(c->off_ring), c->nx, c->at<lbm_stress_summary>(c->off_hist),
+                                           c->p.history_cap, c->at<double>(c->off_wscr), c->at<double>(c->off_acc)});
     b->nflush = (int)flush.size();
-    b->max_nseg = 1;
-    for (const lbm::WallFlush& f : flush) b->max_nseg = std::max(b->max_nseg, f.nseg);
     hipError_t e = hipMemcpyAsync(b->dev + b->off_desc, desc.data(), desc.size() * sizeof(lbm::StepArgs),
                                   hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && !flush.empty())
@@ -2013,8 +2014,7 @@ lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) 
         if (c0->ring_fill == 0) return LBM_OK;
         if (!dry) {
             hipError_t e = lbm::launch_wall_reduce_batch(reinterpret_cast<const lbm::WallFlush*>(b->dev + b->off_flush),
-                                                         b->nflush, b->max_nseg, c0->ring_fill, c0->ring_first_step,
-                                                         b->stream);
+                                                         b->nflush, c0->ring_fill, b->stream);
             if (e != hipSuccess)
                 return bfail(b, LBM_EDEVICE, std::string("batch wall reduce: ") + hipGetErrorString(e));
         }
@@ -2051,7 +2051,7 @@ lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) 
                     lbm_status s = flush_all();
                     if (s) return s;
                 }
-                ge = b->graphs.entry(c0->cur, c0->ring_fill, m, G);
+                ge = b->graphs.entry(c0->cur, c0->ring_fill, m, G, false);
             }
             if (!ge) {  // no graphs, or the cache of short runs is full
                 const int64_t mm = m > 0 ? m : body;

@@ -120,33 +120,29 @@ hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin,
                               hipStream_t s);
 // Reduces the first `nsteps` slots of the wall ring into the history ring, then
 // accumulates the running time integrals and running extremes acc[kWallAccVals] in
-// step order.  Each (step, wall, segment of kWallSegCols columns) is one block's
-// reduction (extremes with their smallest column, sums of squares); the segments
-// are then combined in column order per step, and the per-step values integrated
-// in step order.  The single-lattice flush is one launch: the last block to finish
-// (a ticket counter, zero between flushes) combines and integrates.
-// parts holds [steps][2][nseg][kWallPartVals] doubles, scratch [steps][2][kWallPartVals].
-constexpr int kWallSegCols = 1024;
-inline int wall_segments(int nx) { return (nx + kWallSegCols - 1) / kWallSegCols; }
-hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t first_step,
-                              lbm_stress_summary* hist, int hist_cap, double* parts, double* scratch, double* acc,
-                              unsigned* ticket, hipStream_t s);
+// step order.  A block per (wall, step) reduces that wall's columns (extremes with
+// their smallest column, sums of squares) into scratch[step][wall][kWallPartVals];
+// the last block to finish (a ticket counter in the accumulator block, zero between
+// flushes) integrates over the steps.  The history takes its step numbers from the
+// accumulator block (acc[kAccNextStep], the first step not yet flushed), which the
+// flush advances, so a flush launch does not depend on the step count and can be
+// captured in a graph.
+constexpr int kAccTicket = 16;    // acc index holding the flush's ticket (an unsigned)
+constexpr int kAccNextStep = 17;  // acc index holding the next step to flush (an integer in a double)
+hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, lbm_stress_summary* hist, int hist_cap,
+                              double* scratch, double* acc, hipStream_t s);
 // The wall ring, history, scratch and accumulators of one lattice.
 struct WallFlush {
     const double* ring;
     int nx;
-    int nseg;                 // wall_segments(nx)
     lbm_stress_summary* hist;
     int hist_cap;
-    double* parts;            // per-segment partials
-    double* scratch;          // per-step, per-wall values
+    double* scratch;
     double* acc;
-    unsigned* ticket;         // single-lattice flush: blocks done
 };
 // launch_wall_reduce for the ncases lattices of tbl (device array) at once;
 // they have stepped together, so nsteps and first_step are shared.
-hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int max_nseg, int nsteps, int64_t first_step,
-                                    hipStream_t s);
+hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, hipStream_t s);
 
 // Reverse-mode (adjoint) step (lbm_adjoint.hip).  Tiles of 64 columns give 60
 // outputs (a 2-column halo on each side) and ty output rows.
@@ -203,6 +199,7 @@ hipError_t noalloc_check(int device, const double* rho, const double* vx, const 
 constexpr int kWallPartVals = 10;  // per step and wall: tau max, its x, tau min, its x, p max, its x, p min, its x,
                                    // sum tau^2, sum 2 tau dtau (the flush's scratch holds [steps][2][kWallPartVals])
 constexpr int kWallAccVals = 11;      // int peak tau^2, int sum tau^2, running tau/p max/min per wall, d int tau^2
+static_assert(kWallAccVals <= kAccTicket && kAccNextStep < 32, "the accumulator block holds 32 doubles");
 
 // Liquid components of a host density field (lbm_post.cpp).
 lbm_status label_components(const double* rho, int nx, int ny, bool xper, bool yper, double threshold, double rho_g,

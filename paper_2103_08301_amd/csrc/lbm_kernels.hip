@@ -142,12 +142,12 @@ __device__ inline void comb_min(double& v, double& x, double ov, double ox) {
 constexpr int kWallThreads = 256;  // threads of a flush block; the integration takes one per step (4 waves)
 constexpr int kWallWaves = kWallThreads / 64;
 
-// One segment of one wall of one step of the wall ring: extremes of tau_w and p_w
-// with their columns (the smallest column on ties) and the sums of tau_w^2 and of its
-// tangent over columns seg * kWallSegCols ... (seg + 1) * kWallSegCols - 1, reduced
-// lane-strided, then by wave butterflies, then over the waves in order.  Thread 0
-// writes the ten values to parts[t][w][seg].  Every thread returns.
-__device__ void wall_segment_reduce(const WallFlush& f, int t, int w, int seg) {
+// One wall of one step of the wall ring: extremes of tau_w and p_w with their columns
+// (the smallest column on ties) and the sums of tau_w^2 and of its tangent, reduced
+// lane-strided (sixteen columns' loads in flight per thread), then by wave butterflies,
+// then over the waves in order.  Thread 0 writes the ten values to scratch[t][w].
+// Every thread returns.
+__device__ void wall_step_reduce(const WallFlush& f, int t, int w) {
     __shared__ double sh[kWallWaves][kWallPartVals];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nx = f.nx;
@@ -155,11 +155,10 @@ __device__ void wall_segment_reduce(const WallFlush& f, int t, int w, int seg) {
     const double* tau = slot + (long long)w * nx;
     const double* pw = slot + (long long)(2 + w) * nx;
     const double* dtau = slot + (long long)(4 + w) * nx;
-    const int x1 = min(nx, (seg + 1) * kWallSegCols);
     double tmax = -INFINITY, xtmax = 1e300, tmin = INFINITY, xtmin = 1e300;
     double pmax = -INFINITY, xpmax = 1e300, pmin = INFINITY, xpmin = 1e300, ws = 0.0, wds = 0.0;
-#pragma unroll 4
-    for (int x = seg * kWallSegCols + threadIdx.x; x < x1; x += kWallThreads) {  // four columns' loads in flight
+#pragma unroll 16
+    for (int x = threadIdx.x; x < nx; x += kWallThreads) {
         const double tv = tau[x], pv = pw[x];
         comb_max(tmax, xtmax, tv, double(x));
         comb_min(tmin, xtmin, tv, double(x));
@@ -195,31 +194,8 @@ __device__ void wall_segment_reduce(const WallFlush& f, int t, int w, int seg) {
             r[8] += o[8];
             r[9] += o[9];
         }
-        double* o = f.parts + (((long long)t * 2 + w) * f.nseg + seg) * kWallPartVals;
+        double* o = f.scratch + ((long long)t * 2 + w) * kWallPartVals;
         for (int q = 0; q < kWallPartVals; ++q) o[q] = r[q];
-    }
-}
-
-// The segments of each step and wall combined in column order (thread per step):
-// scratch[t][w] from parts[t][w][0 .. nseg - 1].
-__device__ void wall_combine_segments(const WallFlush& f, int nsteps) {
-    const int t = threadIdx.x;
-    if (t >= nsteps) return;
-    for (int w = 0; w < 2; ++w) {
-        const double* p = f.parts + ((long long)t * 2 + w) * f.nseg * kWallPartVals;
-        double r[kWallPartVals];
-        for (int q = 0; q < kWallPartVals; ++q) r[q] = p[q];
-        for (int g = 1; g < f.nseg; ++g) {
-            const double* o = p + (long long)g * kWallPartVals;
-            comb_max(r[0], r[1], o[0], o[1]);
-            comb_min(r[2], r[3], o[2], o[3]);
-            comb_max(r[4], r[5], o[4], o[5]);
-            comb_min(r[6], r[7], o[6], o[7]);
-            r[8] += o[8];
-            r[9] += o[9];
-        }
-        double* d = f.scratch + ((long long)t * 2 + w) * kWallPartVals;
-        for (int q = 0; q < kWallPartVals; ++q) d[q] = r[q];
     }
 }
 
@@ -231,10 +207,11 @@ __device__ void wall_combine_segments(const WallFlush& f, int nsteps) {
 // not depend on how the steps were split between flushes.
 // acc: [0] int peak tau^2, [1] int sum tau^2, [2 + 2q + w] running extreme q
 // (tau max, tau min, p max, p min) of wall w, [10] tangent of int sum tau^2.
-__device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t first_step) {
+__device__ void wall_integrate_body(const WallFlush& f, int nsteps) {
     constexpr int V = kWallAccVals;
     __shared__ double sh[V][kWallThreads];
     const int t = threadIdx.x;
+    const int64_t first_step = (int64_t)f.acc[kAccNextStep];
     // per value: 0 sum, 1 max, 2 min
     auto kind = [](int q) { return (q == 0 || q == 1 || q == 10) ? 0 : ((q - 2) / 2 % 2 == 0 ? 1 : 2); };
     double v[V], prev[V];
@@ -311,42 +288,37 @@ __device__ void wall_integrate_body(const WallFlush& f, int nsteps, int64_t firs
         sm.run_p_min[w] = tot[8 + w];
     }
     f.hist[(sm.step - 1) % f.hist_cap] = sm;
-    if (t == nsteps - 1)
+    if (t == nsteps - 1) {
         for (int q = 0; q < V; ++q) f.acc[q] = tot[q];
+        f.acc[kAccNextStep] = double(first_step + nsteps);
+    }
 }
 
-// One lattice, one launch: a block per (segment, wall, step); the last block to finish
-// combines the segments and integrates over the steps, then clears the ticket.
-__global__ __launch_bounds__(kWallThreads) void wall_flush_kernel(const WallFlush f, int nsteps, int64_t first_step) {
+// One lattice, one launch: a block per (wall, step); the last block to finish
+// integrates over the steps, then clears the ticket.
+__global__ __launch_bounds__(kWallThreads) void wall_flush_kernel(const WallFlush f, int nsteps) {
     __shared__ int last;
-    wall_segment_reduce(f, blockIdx.z, blockIdx.y, blockIdx.x);
+    wall_step_reduce(f, blockIdx.y, blockIdx.x);
     if (threadIdx.x == 0) {
-        __threadfence();  // this block's partials before its ticket
-        const unsigned total = gridDim.x * gridDim.y * gridDim.z;
-        last = atomicAdd(f.ticket, 1u) == total - 1;
+        __threadfence();  // this block's values before its ticket
+        const unsigned total = gridDim.x * gridDim.y;
+        last = atomicAdd(reinterpret_cast<unsigned*>(f.acc + kAccTicket), 1u) == total - 1;
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();  // every other block's partials after their tickets
-    wall_combine_segments(f, nsteps);
-    __syncthreads();
-    wall_integrate_body(f, nsteps, first_step);
-    if (threadIdx.x == 0) atomicExch(f.ticket, 0u);
+    __threadfence();  // every other block's values after their tickets
+    wall_integrate_body(f, nsteps);
+    if (threadIdx.x == 0) atomicExch(reinterpret_cast<unsigned*>(f.acc + kAccTicket), 0u);
 }
 
 // Many lattices stepped together (same steps), in two launches with the same
-// arithmetic: blockIdx.y / 2 (reduction) or blockIdx.x (integration) is the case.
-__global__ __launch_bounds__(kWallThreads) void wall_segment_reduce_batch_kernel(const WallFlush* __restrict__ tbl) {
-    const WallFlush& f = tbl[blockIdx.y >> 1];
-    if ((int)blockIdx.x >= f.nseg) return;
-    wall_segment_reduce(f, blockIdx.z, blockIdx.y & 1, blockIdx.x);
+// arithmetic: blockIdx.x / 2 (reduction) or blockIdx.x (integration) is the case.
+__global__ __launch_bounds__(kWallThreads) void wall_step_reduce_batch_kernel(const WallFlush* __restrict__ tbl) {
+    wall_step_reduce(tbl[blockIdx.x >> 1], blockIdx.y, blockIdx.x & 1);
 }
 __global__ __launch_bounds__(kWallThreads) void wall_integrate_batch_kernel(const WallFlush* __restrict__ tbl,
-                                                                            int nsteps, int64_t first_step) {
-    const WallFlush& f = tbl[blockIdx.x];
-    wall_combine_segments(f, nsteps);
-    __syncthreads();
-    wall_integrate_body(f, nsteps, first_step);
+                                                                            int nsteps) {
+    wall_integrate_body(tbl[blockIdx.x], nsteps);
 }
 
 }  // namespace
@@ -451,25 +423,22 @@ hipError_t launch_column_scan(const double* rho, int nx, int ny, double* colmin,
     return hipGetLastError();
 }
 
-hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, int64_t first_step, lbm_stress_summary* hist,
-                              int hist_cap, double* parts, double* scratch, double* acc, unsigned* ticket,
-                              hipStream_t s) {
+hipError_t launch_wall_reduce(const double* ring, int nsteps, int nx, lbm_stress_summary* hist, int hist_cap,
+                              double* scratch, double* acc, hipStream_t s) {
     if (nsteps <= 0) return hipSuccess;
     if (nsteps > kWallThreads) return hipErrorInvalidValue;
-    const WallFlush f{ring, nx, wall_segments(nx), hist, hist_cap, parts, scratch, acc, ticket};
-    hipLaunchKernelGGL(wall_flush_kernel, dim3(f.nseg, 2, nsteps), dim3(kWallThreads), 0, s, f, nsteps, first_step);
+    const WallFlush f{ring, nx, hist, hist_cap, scratch, acc};
+    hipLaunchKernelGGL(wall_flush_kernel, dim3(2, nsteps), dim3(kWallThreads), 0, s, f, nsteps);
     return hipGetLastError();
 }
 
-hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int max_nseg, int nsteps, int64_t first_step,
-                                    hipStream_t s) {
+hipError_t launch_wall_reduce_batch(const WallFlush* tbl, int ncases, int nsteps, hipStream_t s) {
     if (nsteps <= 0 || ncases <= 0) return hipSuccess;
-    if (nsteps > kWallThreads || ncases > 32767 || max_nseg < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(wall_segment_reduce_batch_kernel, dim3(max_nseg, 2 * ncases, nsteps), dim3(kWallThreads), 0, s,
-                       tbl);
+    if (nsteps > kWallThreads || ncases > (1 << 30)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wall_step_reduce_batch_kernel, dim3(2 * ncases, nsteps), dim3(kWallThreads), 0, s, tbl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(wall_integrate_batch_kernel, dim3(ncases), dim3(kWallThreads), 0, s, tbl, nsteps, first_step);
+    hipLaunchKernelGGL(wall_integrate_batch_kernel, dim3(ncases), dim3(kWallThreads), 0, s, tbl, nsteps);
     return hipGetLastError();
 }
 
