@@ -61,18 +61,19 @@ def make_lattice(w: dict, check_every: int):
 CHECK_EVERY = 1000  # the library's default stability/interface check cadence
 
 
-def time_steps(w: dict, steps: int, warmup: int):
+def time_steps(w: dict, steps: int, warmup: int, tune: bool = False):
     """Seconds for `steps` timed steps (HIP events on the library's stream), wall seconds, lattice.
 
     The timed call is one lbm_step of `steps` steps with the library's default check cadence; the
     HIP graphs it replays are captured beforehand (lbm_capture), so no capture falls in the timed
-    region.  Every step's wall diagnostics are reduced on the device inside it."""
+    region.  Every step's wall diagnostics are reduced on the device inside it.  With `tune` (or
+    --autotune) the library's autotuner picks the launch configuration after the warm-up."""
     import torch
 
     lat = make_lattice(w, check_every=CHECK_EVERY)
     if warmup:
         lat.step(warmup)
-    lat.tuned = lat.autotune(50) if AUTOTUNE else None
+    lat.tuned = lat.autotune(50) if (AUTOTUNE or tune) else None
     if lat.tuned:
         log(f"autotune: {lat.tuned}")
     lat.capture(steps)
@@ -508,17 +509,32 @@ def main() -> int:
                         "unstable_step": hc["unstable_step"]}
             log(f"{key}: {out[key]}")
             del wh, hl
-        # the same physics on 16384x2048: 2 x 1.2 GB of FP32 distributions, beyond the 256 MB Infinity Cache
+        # the same physics on 16384x2048: 2 x 1.2 GB of FP32 distributions, beyond the 256 MB Infinity Cache,
+        # with the default one-step launch (its HBM roofline) and with the launch the library's autotuner picks
+        # (two steps per launch there: half the HBM bytes per step)
         wo = workloads.plug_out_of_cache(args.storage)
         no = wo["nx"] * wo["ny"]
         os_, _, ol = time_steps(wo, args.steps, args.warmup)
         oc = ol.check()
-        out["out_of_cache"] = {"workload": wo["name"], "value": round(no * args.steps / os_ / 1e6, 1),
-                               "unit": "MLUPS", "ms_per_step": round(os_ * 1e3 / args.steps, 4),
-                               "roofline_frac": round(bpn * no / (os_ / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
-                               "unstable_step": oc["unstable_step"]}
-        log(f"out_of_cache: {out['out_of_cache']}")
         del ol
+        ts_, _, tl = time_steps(wo, args.steps, args.warmup, tune=True)
+        lc = tl.launch_config()
+        tc = tl.check()
+        del tl
+        moved = bpn // lc["fused_steps"]  # HBM bytes per node and step of the chosen launch
+        out["out_of_cache"] = {
+            "workload": wo["name"], "value": round(no * args.steps / ts_ / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(ts_ * 1e3 / args.steps, 4),
+            "launch": {"tile_rows": lc["tile_rows"], "tile_waves": lc["tile_waves"],
+                       "steps_per_launch": lc["fused_steps"], "autotuned": True},
+            "hbm_bytes_per_node_step": moved,
+            "roofline_frac": round(moved * no / (ts_ / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+            "unstable_step": tc["unstable_step"],
+            "one_step_launch": {"value": round(no * args.steps / os_ / 1e6, 1),
+                                "ms_per_step": round(os_ * 1e3 / args.steps, 4), "hbm_bytes_per_node_step": bpn,
+                                "roofline_frac": round(bpn * no / (os_ / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+                                "unstable_step": oc["unstable_step"]}}
+        log(f"out_of_cache: {out['out_of_cache']}")
         # the gradient's cost: one reverse-mode gradient of int tau_w^2 over the 1024x256, 20000-step run
         # against a plain forward run of the same steps
         adj = adjoint_measure("f32", 20000, 0, False)
