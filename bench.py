@@ -314,9 +314,11 @@ def _time_lattice(lat, steps: int, warmup: int):
 
 def batch_sweep(storage: str, steps: int, warmup: int) -> int:
     """Aggregate throughput of the 48 sweep cases drawn from seed 4 (workloads.c4_cases: nx 1024-4096,
-    ny 128-512, dp, plug and film drawn per case; 42.3 M nodes) advanced as one batch (one launch per step for
-    all cases, autotuned tiles, graphs captured beforehand) against the same cases stepped one after another
-    (one launch per case and step), with each case's stability check after the timed steps."""
+    ny 128-512, dp, plug and film drawn per case; 42.3 M nodes) advanced as one batch (one launch for all cases
+    per step or per two steps, as the autotuner picks; graphs captured beforehand) against the same cases
+    stepped one after another (each case autotuned on its own), with each case's stability check after the
+    timed steps.  The roofline fractions count the HBM bytes the chosen launches move per node and step (72 B
+    in FP32 for one step per launch, 36 B for two)."""
     import numpy as np
     import torch
 
@@ -347,6 +349,7 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
                       v_limit=0.5, graph_steps=GRAPH_STEPS, **s)
         lat.init_plug(c["plug"], c["film"], float("nan"), c["noise_amp"], c["seed"])
         lat.step(warmup)
+        lat.autotune(20)
         lat.capture(steps)
         lats.append(lat)
     torch.cuda.synchronize()
@@ -357,13 +360,19 @@ def batch_sweep(storage: str, steps: int, warmup: int) -> int:
     torch.cuda.synchronize()
     t_seq = e0.elapsed_time(e1) / 1e3
     same = all(np.array_equal(batch[k].fields()[0], lats[k].fields()[0]) for k in range(len(cases)))
-    bpn = BYTES_PER_NODE[storage]
+    L = batch[0].launch_config()["fused_steps"]
+    bpn = BYTES_PER_NODE[storage] // L
+    seq_launch = [lat.launch_config()["fused_steps"] for lat in lats]
+    # bytes moved by the sequential runs: each case at its own launch's rate
+    seq_bytes = sum(BYTES_PER_NODE[storage] // f * c["nx"] * c["ny"] for f, c in zip(seq_launch, cases))
     out = {"metric": "aggregate MLUPS, 48 sweep cases drawn from seed 4", "unit": "MLUPS", "storage": storage,
            "cases": len(cases), "nodes": nodes, "steps": steps, "warmup": warmup,
            "batch": {"MLUPS": round(nodes * steps / t_batch / 1e6, 1), "us_per_step": round(t_batch / steps * 1e6, 2),
+                     "steps_per_launch": L, "hbm_bytes_per_node_step": bpn,
                      "roofline_frac": round(bpn * nodes / (t_batch / steps) / 1e9 / HBM_PEAK_GBS, 4)},
            "sequential": {"MLUPS": round(nodes * steps / t_seq / 1e6, 1), "us_per_step": round(t_seq / steps * 1e6, 2),
-                          "roofline_frac": round(bpn * nodes / (t_seq / steps) / 1e9 / HBM_PEAK_GBS, 4)},
+                          "cases_with_two_steps_per_launch": sum(f == 2 for f in seq_launch),
+                          "roofline_frac": round(seq_bytes / (t_seq / steps) / 1e9 / HBM_PEAK_GBS, 4)},
            "speedup": round(t_seq / t_batch, 3), "batch_equals_sequential": bool(same), "batch_tiles": tuned,
            "graph_steps": GRAPH_STEPS,
            "unstable_cases": [[k, ch["unstable_step"]] for k, ch in enumerate(checks) if ch["unstable_step"] >= 0],

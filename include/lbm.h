@@ -120,11 +120,13 @@ typedef struct {
     int graph_steps;     /* schedules 0 and 1 (and batches): steps per captured HIP graph of step launches,
                             replayed instead of launching kernel by kernel; 0 selects 64, -1 launches every
                             step directly; otherwise 2, 4, 8, 16, 32, 64, 128 or 256 */
-    int fused_steps;     /* schedule 0 (single lattices, not F64T): steps per launch, 0 (= 1), 1 or 2.  2: one
-                            launch advances two steps, keeping the intermediate populations in LDS (54 x 14-row
-                            tiles, 54 x 6 with FP64 arithmetic), bit-identical to two one-step launches; it halves
-                            the HBM traffic per step but is slower on MI355X (latency of the longer tile chain),
-                            so it is not the default.  The step that emits fields is always a one-step launch */
+    int fused_steps;     /* schedule 0 (single lattices and batches, not F64T or F16R): steps per launch, 0
+                            (= 1), 1 or 2.  2: one launch advances two steps, keeping the intermediate
+                            populations in LDS (54 x 14-row tiles, 54 x 6 with FP64 arithmetic), bit-identical to
+                            two one-step launches; it halves the HBM traffic per step, which pays when the
+                            distributions do not fit the Infinity Cache, while on smaller lattices the longer tile
+                            chain's latency makes it slower, so it is not the default (lbm_autotune times both).
+                            The step that emits fields, and the last step of a call, are one-step launches */
 } lbm_params;
 
 /* Per-step wall summary ([0] bottom wall, [1] top wall).  FP64. */
@@ -459,7 +461,9 @@ lbm_status lbm_batch_workspace(const lbm_batch* b, size_t* bytes);
 lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hip_stream);
 /* Borrowed handle of case k (0 <= k < n), valid until lbm_batch_destroy. */
 lbm_status lbm_batch_case(lbm_batch* b, int k, lbm_ctx** ctx);
-/* Advances every case by n >= 0 steps, one launch per step, with each case's
+/* Advances every case by n >= 0 steps, one launch per step (two steps per
+   launch when the cases were created with fused_steps = 2 or the autotuner
+   chose it; checks and the last step of a call are one-step launches), with each case's
    checks at the common check cadence, asynchronously as lbm_step (graphs
    between checks, wall summaries reduced on the device, one wait per check;
    a case's fields and check at another step are formed when asked for).  All
@@ -471,8 +475,10 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n, int* failed_case);
 /* As lbm_capture, for lbm_batch_step(b, n). */
 lbm_status lbm_batch_capture(lbm_batch* b, int64_t n);
 /* The tile autotuner for a batch: one trial launch covers every case's tiles
-   for a shape (the cases share one kernel), and the fastest shape is kept for
-   all cases.  As lbm_autotune otherwise; every case must be initialised. */
+   for a shape (the cases share one kernel), then two steps per launch are timed
+   as well (storage types with the two-step kernel), and the fastest is kept for
+   all cases (lbm_launch_config of a case reports it).  As lbm_autotune
+   otherwise; every case must be initialised. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int* tile_waves, double* us_per_step);
 
 void lbm_batch_destroy(lbm_batch* b);

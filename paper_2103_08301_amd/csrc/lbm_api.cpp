@@ -1848,11 +1848,28 @@ const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null
 // ---------------------------------------------------------------------------
 // Batches: many independent lattices advanced by one kernel launch per step.
 
+namespace {
+// Output rows of the two-step tiles for a storage type, 0 where it has no two-step kernel.
+int batch_tile2_rows(int storage) {
+    switch (storage) {
+        case LBM_F64:
+        case LBM_F32D: return lbm::kTile2RowsF64;
+        case LBM_F32:
+        case LBM_F16S:
+        case LBM_BF16S:
+        case LBM_F32S: return lbm::kTile2Rows;
+        default: return 0;
+    }
+}
+}  // namespace
+
 struct lbm_batch {
     StepGraphs graphs;
     std::vector<lbm_ctx*> cases;
-    std::vector<int> tile_start;  // ncases + 1
-    size_t off_desc = 0, off_tiles = 0, off_flush = 0, total = 0;
+    std::vector<int> tile_start;   // ncases + 1
+    std::vector<int> tile_start2;  // the same for the two-step tiles
+    int L = 1;                     // steps per launch (2: the two-step kernel)
+    size_t off_desc = 0, off_tiles = 0, off_tiles2 = 0, off_flush = 0, total = 0;
     int nflush = 0;  // cases with walls (their wall rings are reduced together)
     std::vector<size_t> off_case;
     char* dev = nullptr;
@@ -1889,7 +1906,7 @@ lbm_status lbm_batch_create(int n, const int* nx, const int* ny, const double* t
         // cases are checked together
         if (p.storage != p0.storage || p.storage == LBM_F64T || p.eos != p0.eos || p.schedule != lbm::kScheduleTile ||
             p.tile_rows != p0.tile_rows || p.tile_waves != p0.tile_waves || p.check_every != p0.check_every ||
-            p.graph_steps != p0.graph_steps) {
+            p.graph_steps != p0.graph_steps || p.fused_steps != p0.fused_steps) {
             delete b;
             return LBM_EINVAL;
         }
@@ -1905,21 +1922,28 @@ lbm_status lbm_batch_create(int n, const int* nx, const int* ny, const double* t
     size_t o = 0;
     b->off_desc = o; o += align256((size_t)n * sizeof(lbm::StepArgs));
     b->off_tiles = o; o += align256((size_t)(n + 1) * sizeof(int));
+    b->off_tiles2 = o; o += align256((size_t)(n + 1) * sizeof(int));
     b->off_flush = o; o += align256((size_t)n * sizeof(lbm::WallFlush));
+    const int rows2 = batch_tile2_rows(p0.storage);
+    b->L = (rows2 > 0 && p0.fused_steps == 2) ? 2 : 1;
+    long long tiles2 = 0;
     int tiles = 0;
     for (int k = 0; k < n; ++k) {
         lbm_ctx* c = b->cases[k];
         b->off_case.push_back(o);
         o += align256(c->total);
         b->tile_start.push_back(tiles);
+        b->tile_start2.push_back((int)tiles2);
         const long long t = (long long)tiles + (long long)c->nstrip * ((c->ny + c->ty - 1) / c->ty);
-        if (t > (1LL << 30)) {
+        tiles2 += rows2 > 0 ? lbm::tiles2(c->nx, c->ny, rows2) : 0;
+        if (t > (1LL << 30) || tiles2 > (1LL << 30)) {
             delete b;
             return LBM_EINVAL;
         }
         tiles = (int)t;
     }
     b->tile_start.push_back(tiles);
+    b->tile_start2.push_back((int)tiles2);
     b->total = o;
     *out = b;
     return LBM_OK;
@@ -1968,6 +1992,9 @@ lbm_status lbm_batch_bind(lbm_batch* b, void* device_ptr, size_t bytes, void* hi
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->dev + b->off_tiles, b->tile_start.data(), b->tile_start.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dev + b->off_tiles2, b->tile_start2.data(), b->tile_start2.size() * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch descriptors: ") + hipGetErrorString(e));
     b->bound = true;
@@ -2001,14 +2028,24 @@ lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) 
     const int ncases = (int)b->cases.size();
     const auto* desc = reinterpret_cast<const lbm::StepArgs*>(b->dev + b->off_desc);
     const auto* tiles = reinterpret_cast<const int*>(b->dev + b->off_tiles);
+    const auto* tiles2 = reinterpret_cast<const int*>(b->dev + b->off_tiles2);
     const int G = c0->graph_steps();
-    auto advance = [&](int nsteps) {
+    const int L = b->L;  // steps per launch; G is a multiple of it
+    auto advance = [&](int nsteps, int launches) {  // each launch flips the buffers once
         for (lbm_ctx* c : b->cases) {
-            c->cur = (c->cur + nsteps) & 1;
+            c->cur = (c->cur + launches) & 1;
             c->last_slot = c->ring_fill + nsteps - 1;
             c->ring_fill += nsteps;
             c->steps += nsteps;
         }
+    };
+    // one launch of `steps` (1 or 2) steps of every case from buffer parity `par`, wall arrays from ring slot `slot`
+    auto launch_any = [&](int steps, int par, int slot, bool emit, hipStream_t s) -> hipError_t {
+        if (steps == 2)
+            return lbm::launch_step2_batch(desc, tiles2, ncases, b->tile_start2.back(), par, slot, c0->p.storage,
+                                           c0->p.eos, emit, s);
+        return lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), par, slot, c0->p.storage, c0->p.eos,
+                                      c0->ty, c0->tile_waves, emit, s);
     };
     auto flush_all = [&]() -> lbm_status {  // every case's wall ring in one pair of launches
         if (c0->ring_fill == 0) return LBM_OK;
@@ -2024,17 +2061,16 @@ lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) 
         }
         return LBM_OK;
     };
-    auto launch1 = [&](bool emit) -> lbm_status {
-        if (c0->ring_fill == kRingCap) {
+    auto launch_direct = [&](int steps, bool emit) -> lbm_status {
+        if (c0->ring_fill + steps > kRingCap) {
             lbm_status s = flush_all();
             if (s) return s;
         }
         if (!dry) {
-            hipError_t e = lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), c0->cur, c0->ring_fill,
-                                                  c0->p.storage, c0->p.eos, c0->ty, c0->tile_waves, emit, b->stream);
+            hipError_t e = launch_any(steps, c0->cur, c0->ring_fill, emit, b->stream);
             if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
         }
-        advance(1);
+        advance(steps, 1);
         return LBM_OK;
     };
     int64_t done = 0;
@@ -2042,9 +2078,13 @@ lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) 
         const int64_t next_check = (c0->steps / c0->p.check_every + 1) * c0->p.check_every;
         const int64_t seg = std::min<int64_t>(n - done, next_check - c0->steps);
         const bool check = c0->steps + seg == next_check;
-        int64_t body = seg - (check ? 1 : 0);
+        // the step that emits for a check, and with two steps per launch the last step of
+        // the call, are one-step launches
+        const int64_t tail = (check || L == 2) ? 1 : 0;
+        int64_t body = seg - tail;
         while (body > 0) {
-            const int m = G > 0 ? (int)std::min<int64_t>(body, G) : 0;
+            int m = G > 0 ? (int)std::min<int64_t>(body, G) : 0;
+            if (L == 2) m &= ~1;
             hipGraphExec_t* ge = nullptr;
             if (m > 0) {
                 if (c0->ring_fill + m > kRingCap) {
@@ -2053,22 +2093,22 @@ lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) 
                 }
                 ge = b->graphs.entry(c0->cur, c0->ring_fill, m, G, false);
             }
-            if (!ge) {  // no graphs, or the cache of short runs is full
+            if (!ge) {  // no graphs, or the cache of short runs is full: L steps per launch while they fit
                 const int64_t mm = m > 0 ? m : body;
-                for (int64_t k = 0; k < mm; ++k) {
-                    lbm_status s = launch1(false);
+                for (int64_t k = 0; k < mm;) {
+                    const int st = (L == 2 && mm - k >= 2) ? 2 : 1;
+                    lbm_status s = launch_direct(st, false);
                     if (s) return s;
+                    k += st;
                 }
                 body -= mm;
                 continue;
             }
+            const int nl = m / L;  // launches in the graph
             if (!*ge) {
                 const int par = c0->cur, fill0 = c0->ring_fill;
-                auto launch = [&](int j, hipStream_t s) {
-                    return lbm::launch_step_batch(desc, tiles, ncases, b->tile_start.back(), (par + j) & 1, fill0 + j,
-                                                  c0->p.storage, c0->p.eos, c0->ty, c0->tile_waves, false, s);
-                };
-                hipError_t e = capture_graph(b->graphs, m, launch, ge);
+                auto launch = [&](int j, hipStream_t s) { return launch_any(L, (par + j) & 1, fill0 + L * j, false, s); };
+                hipError_t e = capture_graph(b->graphs, nl, launch, ge);
                 if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
             }
             if (!dry) {
@@ -2076,11 +2116,11 @@ lbm_status batch_step_impl(lbm_batch* b, int64_t n, int* failed_case, bool dry) 
                 if (e != hipSuccess)
                     return bfail(b, LBM_EDEVICE, std::string("batch graph launch: ") + hipGetErrorString(e));
             }
-            advance(m);
+            advance(m, nl);
             body -= m;
         }
-        if (check) {
-            lbm_status s = launch1(true);
+        if (tail) {
+            lbm_status s = launch_direct(1, check);
             if (s) return s;
         }
         done += seg;
@@ -2193,6 +2233,22 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int
         }, &us);
         if (e == hipSuccess && us < best) { best = us; pick = t; }
     }
+    // two steps per launch, where the storage has the two-step kernel (its own tile table);
+    // the two wall arrays go to two consecutive ring slots, neither of them the latest step's
+    int fused = 1;
+    if (e == hipSuccess && batch_tile2_rows(c0->p.storage) > 0) {
+        double us = 0;
+        const int slot = c0->last_slot + 1 <= kRingCap - 2 ? c0->last_slot + 1 : 0;
+        const auto* tiles2 = reinterpret_cast<const int*>(b->dev + b->off_tiles2);
+        e = time_launches(b->stream, (trial_steps + 1) / 2, [&] {
+            return lbm::launch_step2_batch(desc, tiles2, ncases, b->tile_start2.back(), c0->cur, slot, c0->p.storage,
+                                           c0->p.eos, false, b->stream);
+        }, &us);
+        if (e == hipSuccess && 0.5 * us < best) {
+            best = 0.5 * us;
+            fused = 2;
+        }
+    }
     // the chosen shape's tile table and the real launch table
     starts.emplace_back(1, 0);
     std::vector<int>& start = starts.back();
@@ -2204,9 +2260,11 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* tile_rows, int
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch autotune: ") + hipGetErrorString(e));
     b->tile_start = start;
+    b->L = fused;
     for (lbm_ctx* c : b->cases) {
         c->ty = c->p.tile_rows = pick.rows;
         c->tile_waves = c->p.tile_waves = pick.waves;
+        c->p.fused_steps = fused;
         c->nchunk = std::max(1, c->ny / c->ty);
     }
     b->graphs.drop();

@@ -1285,8 +1285,8 @@ __global__ __launch_bounds__(64 * NW) void pipe_kernel(const StepArgs a) {
 // the state crosses HBM once per two steps.  Both steps write their wall
 // arrays: step 1 to tau_w/p_w/dtau_w, step 2 to the next wall-ring slot
 // (kWallSlotVals * nx further on).
-constexpr int kStrip2Out = 54;
 constexpr int kHalo2 = 5;
+static_assert(kStrip2Out + 2 * kHalo2 == 64, "a two-step tile is one wave wide");
 
 template <class CD, int EOS, bool EMIT, int T, int NW>
 __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v, void* fout_v, double* tau_w,
@@ -1303,8 +1303,9 @@ __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v,
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int tile = bid / a.nstrip;
-    const int strip = bid - tile * a.nstrip;
+    const int nstrip = (a.nx + kStrip2Out - 1) / kStrip2Out;
+    const int tile = bid / nstrip;
+    const int strip = bid - tile * nstrip;
     const int y0 = (a.ny >= T) ? min(tile * T, a.ny - T) : 0;
     const int x0 = strip * kStrip2Out;
     const int x = x0 - kHalo2 + lane;
@@ -1534,6 +1535,26 @@ __global__ __launch_bounds__(64 * NW) void tile2_kernel(const StepArgs a) {
     tile2_body<CD, EOS, EMIT, T, NW>(a, a.fin, a.fout, a.tau_w, a.p_w, a.dtau_w, xcd_remap(blockIdx.x, gridDim.x));
 }
 
+// Two steps of many lattices in one launch: tile_batch_kernel's layout with the
+// two-step tiles (tile_start counts them), the two steps' wall arrays in ring
+// slots slot and slot + 1.
+template <class CD, int EOS, bool EMIT, int T, int NW>
+__global__ __launch_bounds__(64 * NW) void tile2_batch_kernel(const StepArgs* __restrict__ cases,
+                                                              const int* __restrict__ tile_start, int ncases,
+                                                              int parity, int slot) {
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = ncases - 1;  // last case whose first tile is <= bid (uniform search)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= bid) lo = mid; else hi = mid - 1;
+    }
+    const StepArgs& a = cases[lo];
+    const void* fin = parity ? a.fout : a.fin;
+    void* fout = parity ? const_cast<void*>(a.fin) : a.fout;
+    double* w = a.ring + (long long)slot * kWallSlotVals * a.nx;
+    tile2_body<CD, EOS, EMIT, T, NW>(a, fin, fout, w, w + 2 * a.nx, w + 4 * a.nx, bid - tile_start[lo]);
+}
+
 template <class CD, int EOS, int TYO, int NW>
 hipError_t launch_tile(const StepArgs& a, bool emit, hipStream_t s) {
     const dim3 grid(a.nstrip * ((a.ny + TYO - 1) / TYO)), block(64 * NW);
@@ -1544,16 +1565,14 @@ hipError_t launch_tile(const StepArgs& a, bool emit, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Two steps in one launch (tile2_kernel); a.nstrip is replaced by the 54-column strips.
+// Two steps in one launch (tile2_kernel) over 54-column strips.
 template <class CD, int EOS, int T, int NW>
 hipError_t launch_tile2(const StepArgs& a, bool emit, hipStream_t s) {
-    StepArgs b = a;
-    b.nstrip = (a.nx + kStrip2Out - 1) / kStrip2Out;
-    const dim3 grid(b.nstrip * ((a.ny + T - 1) / T)), block(64 * NW);
+    const dim3 grid(tiles2(a.nx, a.ny, T)), block(64 * NW);
     if (emit)
-        hipLaunchKernelGGL((tile2_kernel<CD, EOS, true, T, NW>), grid, block, 0, s, b);
+        hipLaunchKernelGGL((tile2_kernel<CD, EOS, true, T, NW>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((tile2_kernel<CD, EOS, false, T, NW>), grid, block, 0, s, b);
+        hipLaunchKernelGGL((tile2_kernel<CD, EOS, false, T, NW>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
@@ -1563,7 +1582,29 @@ template <class CD>
 hipError_t launch_step2_c(const StepArgs& a, int eos, bool emit, hipStream_t s) {
     constexpr bool f64 = sizeof(typename CD::C) == 8;
     constexpr int T = f64 ? 6 : 14, NW = f64 ? 4 : 8;
+    static_assert(T == (f64 ? kTile2RowsF64 : kTile2Rows), "two-step tile rows");
     return eos == LBM_EOS_CS ? launch_tile2<CD, LBM_EOS_CS, T, NW>(a, emit, s) : launch_tile2<CD, LBM_EOS_PR, T, NW>(a, emit, s);
+}
+
+template <class CD, int EOS>
+hipError_t launch_batch2_e(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                           int slot, bool emit, hipStream_t s) {
+    constexpr bool f64 = sizeof(typename CD::C) == 8;
+    constexpr int T = f64 ? 6 : 14, NW = f64 ? 4 : 8;
+    const dim3 grid(total_tiles), block(64 * NW);
+    if (emit)
+        hipLaunchKernelGGL((tile2_batch_kernel<CD, EOS, true, T, NW>), grid, block, 0, s, cases, tile_start, ncases,
+                           parity, slot);
+    else
+        hipLaunchKernelGGL((tile2_batch_kernel<CD, EOS, false, T, NW>), grid, block, 0, s, cases, tile_start, ncases,
+                           parity, slot);
+    return hipGetLastError();
+}
+template <class CD>
+hipError_t launch_batch2_c(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                           int slot, int eos, bool emit, hipStream_t s) {
+    return eos == LBM_EOS_CS ? launch_batch2_e<CD, LBM_EOS_CS>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s)
+                             : launch_batch2_e<CD, LBM_EOS_PR>(cases, tile_start, ncases, total_tiles, parity, slot, emit, s);
 }
 
 template <class CD, int EOS, int TYO, int NW>
@@ -1705,5 +1746,9 @@ hipError_t pipe_grid_c(int eos, int ty, int waves, int* blocks) {
     }                                                                                                          \
     hipError_t launch_step2_##NAME(const StepArgs& a, int eos, bool emit, hipStream_t s) {                    \
         return launch_step2_c<CODEC>(a, eos, emit, s);                                                         \
+    }                                                                                                          \
+    hipError_t launch_batch2_##NAME(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, \
+                                    int parity, int slot, int eos, bool emit, hipStream_t s) {                \
+        return launch_batch2_c<CODEC>(cases, tile_start, ncases, total_tiles, parity, slot, eos, emit, s);     \
     }                                                                                                          \
     }

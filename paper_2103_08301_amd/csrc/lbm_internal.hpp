@@ -79,7 +79,9 @@ hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipSt
     hipError_t launch_batch_##NAME(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, \
                                    int parity, int slot, int eos, int ty, int waves, bool emit, hipStream_t s); \
     hipError_t pipe_grid_##NAME(int eos, int ty, int waves, int* blocks);                                     \
-    hipError_t launch_step2_##NAME(const StepArgs& a, int eos, bool emit, hipStream_t s);
+    hipError_t launch_step2_##NAME(const StepArgs& a, int eos, bool emit, hipStream_t s);                    \
+    hipError_t launch_batch2_##NAME(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, \
+                                    int parity, int slot, int eos, bool emit, hipStream_t s);
 LBM_DECLARE_STORAGE_LAUNCHERS(f64)
 LBM_DECLARE_STORAGE_LAUNCHERS(f32)
 LBM_DECLARE_STORAGE_LAUNCHERS(f16s)
@@ -98,6 +100,16 @@ hipError_t launch_batch_f16r(const StepArgs* cases, const int* tile_start, int n
 // go to a.tau_w/p_w/dtau_w and those of the second kWallSlotVals * nx further on.
 // Not for F64T storage.
 hipError_t launch_step2(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s);
+// Tiles of the two-step kernel: 54 output columns (a 5-column halo each side) by
+// kTile2Rows rows (kTile2RowsF64 with FP64 arithmetic).
+constexpr int kStrip2Out = 54;
+constexpr int kTile2Rows = 14, kTile2RowsF64 = 6;
+inline int tiles2(int nx, int ny, int rows) { return ((nx + kStrip2Out - 1) / kStrip2Out) * ((ny + rows - 1) / rows); }
+// Two steps of many lattices in one launch (as launch_step_batch, with the
+// two-step tiles: tile_start counts tiles2 per case); the two steps' wall arrays
+// go to ring slots slot and slot + 1.  Not for F64T or F16R storage.
+hipError_t launch_step2_batch(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                              int slot, int storage, int eos, bool emit, hipStream_t s);
 // One step of many lattices in one launch (tile schedule): cases[c] holds case
 // c's arguments with both distribution buffers (f[0] as fin, f[1] as fout) and
 // the base of its wall ring; tile_start[c] is its first tile (device arrays).

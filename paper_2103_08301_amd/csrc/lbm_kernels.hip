@@ -335,6 +335,20 @@ hipError_t launch_step2(const StepArgs& a, int storage, int eos, bool emit, hipS
     }
 }
 
+hipError_t launch_step2_batch(const StepArgs* cases, const int* tile_start, int ncases, int total_tiles, int parity,
+                              int slot, int storage, int eos, bool emit, hipStream_t s) {
+    if (ncases < 1 || total_tiles < 1) return hipErrorInvalidValue;
+    switch (storage) {
+        case LBM_F64: return launch_batch2_f64(cases, tile_start, ncases, total_tiles, parity, slot, eos, emit, s);
+        case LBM_F32: return launch_batch2_f32(cases, tile_start, ncases, total_tiles, parity, slot, eos, emit, s);
+        case LBM_F16S: return launch_batch2_f16s(cases, tile_start, ncases, total_tiles, parity, slot, eos, emit, s);
+        case LBM_BF16S: return launch_batch2_bf16s(cases, tile_start, ncases, total_tiles, parity, slot, eos, emit, s);
+        case LBM_F32D: return launch_batch2_f32d(cases, tile_start, ncases, total_tiles, parity, slot, eos, emit, s);
+        case LBM_F32S: return launch_batch2_f32s(cases, tile_start, ncases, total_tiles, parity, slot, eos, emit, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_step(const StepArgs& a, int storage, int eos, bool emit, hipStream_t s) {
     switch (storage) {
         case LBM_F64: return launch_step_f64(a, eos, emit, s);

@@ -59,7 +59,7 @@ def test_batch_autotune_keeps_results():
     ref, bat = make(), make()
     f0 = [bat[k].get_f() for k in range(4)]
     pick = bat.autotune(10)
-    print("batch chosen", pick, flush=True)
+    print("batch chosen", pick, bat[0].launch_config(), flush=True)
     assert (pick["tile_rows"], pick["tile_waves"]) in SHAPES
     for k in range(4):
         assert np.array_equal(bat[k].get_f(), f0[k])

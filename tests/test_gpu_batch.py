@@ -87,6 +87,39 @@ def test_batch_matches_single_runs_bitwise(storage, check_every):
         del lat
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+def test_two_step_batch_matches_one_step_single_runs_bitwise(storage):
+    """Batches with two steps per launch (the two-step tiles of every case in one launch, the first step's
+    populations kept in LDS) against each case run on its own with one step per launch, launched kernel by
+    kernel: distributions, fields, checks and wall histories equal bit for bit.  The calls of 1, 149 and 330
+    steps exercise the one-step launches of a call's last step and of the check steps, graphs of two-step
+    launches and several wall-ring flushes."""
+    cases = [c for i, c in enumerate(CASES) if i != 4]
+    calls = (1, 149, 330)
+    b = Batch(cases, storage=storage, v_limit=1.0, check_every=300, fused_steps=2)
+    assert b[0].launch_config()["fused_steps"] == 2
+    for k, c in enumerate(cases):
+        pl, fl = plug(c)
+        b[k].init_plug(pl, fl, math.nan, 1e-3, k + 1)
+    for n in calls:
+        b.step(n)
+    for k, c in enumerate(cases):
+        spec = dict(c)
+        nx, ny, tau = spec.pop("nx"), spec.pop("ny"), spec.pop("tau")
+        lat = Lattice(nx, ny, tau, storage=storage, v_limit=1.0, check_every=300, graph_steps=-1, **spec)
+        pl, fl = plug(c)
+        lat.init_plug(pl, fl, math.nan, 1e-3, k + 1)
+        for n in calls:
+            lat.step(n)
+        assert np.array_equal(b[k].get_f(), lat.get_f()), k
+        assert np.array_equal(b[k].fields()[0], lat.fields()[0]), k
+        same_dict(b[k].check(), lat.check())
+        if not c.get("y_periodic"):
+            assert b[k].history() == lat.history(), k
+        log(f"case {k} {nx}x{ny} {storage}: two-step batch identical to its one-step single run")
+        del lat
+
+
 def test_batch_case_against_oracle():
     cases = [dict(nx=96, ny=20, tau=1.0, T_over_Tc=0.85, dp=1e-3), dict(nx=150, ny=40, tau=0.9, T_over_Tc=0.9, dp=1e-3)]
     b = Batch(cases, storage="f64", v_limit=1.0)
