@@ -173,8 +173,9 @@ void lbm_params_default(lbm_params* p);
    then lbm_init_plug is rejected. */
 lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx** out);
 
-/* Device bytes the caller must allocate and bind (alignment 256). */
-lbm_status lbm_workspace(const lbm_ctx* ctx, size_t* bytes);
+/* Device bytes the caller must allocate and bind, and their alignment (256
+   bytes; align may be NULL). */
+lbm_status lbm_workspace(const lbm_ctx* ctx, size_t* bytes, size_t* align);
 
 /* Binds caller-owned device memory (>= lbm_workspace bytes, 256-aligned) on
    the current HIP device and the hipStream_t (NULL = default stream) for all

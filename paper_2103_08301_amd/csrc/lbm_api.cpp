@@ -767,9 +767,10 @@ lbm_status lbm_create(int nx, int ny, double tau, const lbm_params* p, lbm_ctx**
     return LBM_OK;
 }
 
-lbm_status lbm_workspace(const lbm_ctx* c, size_t* bytes) {
+lbm_status lbm_workspace(const lbm_ctx* c, size_t* bytes, size_t* align) {
     if (!c || !bytes) return LBM_EINVAL;
     *bytes = c->total;
+    if (align) *align = 256;
     return LBM_OK;
 }
 

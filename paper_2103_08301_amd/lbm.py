@@ -116,7 +116,7 @@ def library():
         sig = {
             "lbm_params_default": (None, [PP]),
             "lbm_create": (C.c_int, [C.c_int, C.c_int, C.c_double, PP, C.POINTER(_P)]),
-            "lbm_workspace": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+            "lbm_workspace": (C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
             "lbm_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
             "lbm_state": (C.c_int, [_P, _D, _D, _D, _D, _D]),
             "lbm_init_plug": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]),
@@ -206,10 +206,11 @@ def lbm_create(nx: int, ny: int, tau: float, p: lbm_params):
     return h
 
 
-def lbm_workspace(ctx) -> int:
-    n = C.c_size_t()
-    _check(ctx, library().lbm_workspace(ctx, C.byref(n)))
-    return n.value
+def lbm_workspace(ctx, with_align: bool = False):
+    """Device bytes to allocate and bind (and, with_align, their required alignment)."""
+    n, a = C.c_size_t(), C.c_size_t()
+    _check(ctx, library().lbm_workspace(ctx, C.byref(n), C.byref(a)))
+    return (n.value, a.value) if with_align else n.value
 
 
 def lbm_bind(ctx, device_ptr: int, nbytes: int, stream: int):
@@ -405,9 +406,11 @@ class Lattice:
         self.params = lbm_params_default(**params)
         self._ctx = lbm_create(nx, ny, tau, self.params)
         self._owner = None
-        nbytes = lbm_workspace(self._ctx)
+        nbytes, align = lbm_workspace(self._ctx, with_align=True)
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % align:
+            raise RuntimeError(f"torch returned a workspace not aligned to {align} bytes")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
             lbm_bind(self._ctx, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)

@@ -103,6 +103,11 @@ def test_calls_before_bind_are_rejected(L):
     assert e.value.status == L.LBM_ESTATE
     assert L.library().lbm_step(ctx, 1) == L.LBM_ESTATE
     assert L.lbm_workspace(ctx) > 2 * 9 * 64 * 32 * 4
+    assert L.lbm_workspace(ctx, with_align=True)[1] == 256
+    import ctypes as C
+
+    n = C.c_size_t()
+    assert L.library().lbm_workspace(ctx, C.byref(n), None) == L.LBM_OK and n.value > 0  # align may be NULL
     L.lbm_destroy(ctx)
 
 
