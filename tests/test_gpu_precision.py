@@ -244,3 +244,29 @@ def test_shifted_values_load_without_rounding(reference, storage):
     small = np.abs(f) < 0.25
     assert np.array_equal(s[small], s[small].astype(np.float16).astype(np.float64))
     log(f"{storage}: {int(small.sum())} of {f.size} loaded populations are their stored value plus 9 w_i q exactly")
+
+
+def test_f16r_interfaces_on_the_timed_workload_at_20000_steps():
+    """The 4096x512 workload (CS 0.95 Tc, tau 0.8, plug 300, film 16, dp drawn from seed 2) over 20000 steps, too
+    long for the oracle at this size: FP16 storage with stochastic rounding against FP32 storage with FP64
+    arithmetic (f32d, within 9e-7 of the oracle over the first 2000 steps).  The interfaces and the liquid-column
+    count of F16R must stay within 0.5 lattice units and one column; round-to-nearest FP16 is logged beside it."""
+    from paper_2103_08301_amd import workloads
+
+    w = workloads.plug_large_stable("f32")
+    pl = w["plug"]
+    out = {}
+    for storage in ("f32d", "f16r", "f16s"):
+        lat = Lattice(w["nx"], w["ny"], w["tau"], storage=storage, check_every=20000, v_limit=1.0, **w["params"])
+        lat.init_plug(pl["plug_len"], pl["film"], pl["x_center"], pl["noise_amp"], pl["seed"])
+        assert lat.step(20000) == 0
+        out[storage] = lat.check()
+        del lat
+    ref = out["f32d"]
+    for storage in ("f16r", "f16s"):
+        c = out[storage]
+        log(f"4096x512, 20000 steps, {storage} against f32d: rear {c['x_rear'] - ref['x_rear']:+.3f} lu, "
+            f"front {c['x_front'] - ref['x_front']:+.3f} lu, liquid columns {c['liquid_columns']}/{ref['liquid_columns']}")
+    c = out["f16r"]
+    assert abs(c["x_rear"] - ref["x_rear"]) <= 0.5 and abs(c["x_front"] - ref["x_front"]) <= 0.5
+    assert abs(c["liquid_columns"] - ref["liquid_columns"]) <= 1
