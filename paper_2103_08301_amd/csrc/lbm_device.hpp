@@ -310,21 +310,57 @@ __device__ inline C shfl_next(C v) { return dpp_move<kDppWaveShl1>(v); }
 template <class C>
 __device__ inline C shfl_prev(C v) { return dpp_move<kDppWaveShr1>(v); }
 
+// FP64 reciprocal from the hardware estimate refined by two Newton steps: for the
+// EOS denominators, which lie in (0, 1], as accurate as the division for what the
+// FP32 kernels keep of it, at a fraction of its cost.
+__device__ inline double recip_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
 // phi = k^2 p0(rho) - rho/3: the nonideal part of the pressure in mesh units (eq. 2.17).
-template <int EOS, class C>
+// NR: the denominator through recip_nr (FP64 only) instead of a division.
+template <int EOS, class C, bool NR = false>
 __device__ inline C phi_of(C rho, C RT, C a_eff, C b, C k2) {
+    auto inv = [](C v) {
+        if constexpr (NR) return recip_nr(v);
+        else return recip(v);
+    };
     C p0;
     if (EOS == LBM_EOS_CS) {
         const C eta = C(0.25) * b * rho;
         const C num = C(1) + eta * (C(1) + eta * (C(1) - eta));
         const C d = C(1) - eta;
-        p0 = rho * RT * num * recip(d * d * d) - a_eff * rho * rho;
+        p0 = rho * RT * num * inv(d * d * d) - a_eff * rho * rho;
     } else {
         const C d = C(1) - b * rho;
         const C q = C(1) + b * rho * (C(2) - b * rho);
-        p0 = rho * (RT * q - a_eff * rho * d) * recip(d * q);
+        p0 = rho * (RT * q - a_eff * rho * d) * inv(d * q);
     }
     return k2 * p0 - rho * C(1.0 / 3.0);
+}
+
+// The type in which the EOS field phi is evaluated, kept between the phases and
+// differentiated: the arithmetic type, except with FP32 storage and FP32 arithmetic,
+// where it is FP64.  At an interface grad phi is ~1e-2 while the pressure-drop force is
+// ~1e-7 per node; phi rounded to FP32 (|phi| up to ~0.07) puts ~5e-9 of noise into
+// every gradient, fixed in time while the flow is steady, and on the 4096 x 512 channel
+// that drifted rho from the FP64 solution by 1.9e-5 over 2000 steps.  In FP64 the same run
+// stays at 7.3e-6, for 2.8% of the step.  FP16/BF16 storage rounds far more than that.
+template <class CD>
+using PhiT = std::conditional_t<std::is_same<typename CD::C, float>::value && sizeof(typename CD::S) == 4, double,
+                                typename CD::C>;
+
+// phi of one node for storage CD, in PhiT<CD>: in FP64 from the FP64 coefficients
+// where PhiT is FP64 and the arithmetic FP32.
+template <class CD, int EOS>
+__device__ inline PhiT<CD> phi_field(typename CD::C rho, const StepArgs& a) {
+    using C = typename CD::C;
+    if constexpr (std::is_same<PhiT<CD>, C>::value)
+        return phi_of<EOS, C>(rho, LBM_COEF(C, RT), LBM_COEF(C, a_eff), LBM_COEF(C, b), LBM_COEF(C, k2));
+    else
+        return phi_of<EOS, double, true>(double(rho), a.RT, a.a_eff, a.b, a.k2);
 }
 
 template <int EOS, class C>
@@ -348,18 +384,17 @@ template <class C>
 __device__ inline C lap3(const Row3<C>& s, const Row3<C>& m, const Row3<C>& n) {
     return C(2.0 / 3.0) * (m.e + m.w + n.c + s.c) + C(1.0 / 6.0) * (n.e + n.w + s.e + s.w) - C(10.0 / 3.0) * m.c;
 }
-// One component of the force of eq. 2.17, -dphi + kappa rho dL + g.  Near an interface
-// close to equilibrium the two gradient terms almost cancel, so with FP32 storage and
-// arithmetic the sum is formed in FP64 (summed in FP32, its rounding moved a moving
-// interface by ~3e-4 lattice units over 2000 steps, 8e-5 of the density; in FP64, 1e-5).
-// FP16/BF16 storage rounds far more than that sum, and FP64 arithmetic needs no help: they
-// sum in their own precision.  g64 is g in FP64.
+// One component of the force of eq. 2.17, -dphi + kappa rho dL + g, from dphi in PhiT.
+// Near an interface close to equilibrium the two gradient terms almost cancel, so where
+// phi is FP64 and the arithmetic FP32 the sum is formed in FP64 and rounded once (summed
+// in FP32, its rounding moved a moving interface by ~3e-4 lattice units over 2000 steps,
+// 8e-5 of the density).  Otherwise it is summed in the arithmetic type.  g64 is g in FP64.
 template <class CD>
-__device__ inline typename CD::C force_sum(typename CD::C gph, typename CD::C kappa, typename CD::C rh,
+__device__ inline typename CD::C force_sum(PhiT<CD> gph, typename CD::C kappa, typename CD::C rh,
                                            typename CD::C gl, typename CD::C g, double g64) {
     using C = typename CD::C;
-    if constexpr (std::is_same<C, float>::value && sizeof(typename CD::S) == 4)
-        return float(-double(gph) + double(kappa * rh * gl) + g64);
+    if constexpr (!std::is_same<PhiT<CD>, C>::value)
+        return C(-gph + double(kappa * rh * gl) + g64);
     else
         return -gph + kappa * rh * gl + g;
 }
@@ -562,11 +597,14 @@ __device__ inline void issue_row(const typename CD::S* __restrict__ fin, const S
 }
 
 // Per-wave register window of the row march.  Suffix 1 is row r-1, suffix 2
-// row r-2 (the row being collided); lap3r is the Laplacian of row r-3.
-template <class C>
+// row r-2 (the row being collided); lap3r is the Laplacian of row r-3.  P is the
+// type of phi and its gradient.
+template <class C, class P>
 struct Window {
-    Row3<C> rho1, rho2, phi1, phi2, lap2, lap3r;
-    C gphx, gphy, grx, gry;   // grad phi and grad rho of row r-2
+    Row3<C> rho1, rho2, lap2, lap3r;
+    Row3<P> phi1, phi2;
+    P gphx, gphy;             // grad phi of row r-2
+    C grx, gry;               // grad rho of row r-2
     C f1[9], f2[9];           // pulled populations of rows r-1 and r-2
     C fn[9];                  // prefetched populations of row r
     C wall_rho, wall_vx, wall_p;
@@ -585,7 +623,8 @@ struct Stepper {
     uint32_t dir_off[9];  // byte offset of population i's pull source: i*plane - e_i (in elements) times sizeof(S)
     uint32_t plane_bytes;
 
-    __device__ void prefetch(Window<C>& W, int r) const { issue_row<CD>(fin, a, xe, strip_inner, dir_off, r, rho0, W.fn); }
+    using P = PhiT<CD>;
+    __device__ void prefetch(Window<C, P>& W, int r) const { issue_row<CD>(fin, a, xe, strip_inner, dir_off, r, rho0, W.fn); }
 
     // One row of the march: takes the prefetched populations of row r, issues
     // the loads of row r+1, forms rho/phi of row r and lap/grad of row r-1, and
@@ -593,7 +632,7 @@ struct Stepper {
     // FAST: row r is a fluid row and row r+1 is an interior row of an interior
     // strip, so the prefetch is nine straight loads with no boundary logic.
     template <bool COLLIDE, bool WALL, bool EMIT, bool FAST>
-    __device__ __forceinline__ void row(Window<C>& W, int r, bool prefetch_next) const {
+    __device__ __forceinline__ void row(Window<C, P>& W, int r, bool prefetch_next) const {
         C f0[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) f0[i] = W.fn[i];
@@ -609,9 +648,9 @@ struct Stepper {
         const C rho = fluid_row ? ((f0[0] + f0[1]) + (f0[2] + f0[3])) + ((f0[4] + f0[5]) + (f0[6] + f0[7])) + f0[8]
                                 : rho_w;
         const Row3<C> rho0r = with_neighbours(rho);
-        const Row3<C> phi0 = with_neighbours(phi_of<EOS, C>(rho, RT, a_eff, bb, k2));
+        const Row3<P> phi0 = with_neighbours(phi_field<CD, EOS>(rho, a));
         const Row3<C> lap1 = with_neighbours(lap3(W.rho2, W.rho1, rho0r));
-        C gphx1, gphy1;
+        P gphx1, gphy1;
         grad3(W.phi2, W.phi1, phi0, gphx1, gphy1);
         C grx1 = 0, gry1 = 0;
         if (WALL && !a.yper && (r - 1 == 0 || r - 1 == a.ny - 1)) grad3(W.rho2, W.rho1, rho0r, grx1, gry1);
@@ -656,7 +695,7 @@ struct Stepper {
 
     // Wall shear and wall pressure on the first two fluid rows of each wall
     // (FP64, into this step's slot of the wall ring).
-    __device__ void wall_row(Window<C>& W, int y, C rh, C vx) const {
+    __device__ void wall_row(Window<C, P>& W, int y, C rh, C vx) const {
         if (a.yper) return;
         const bool bottom_p = (y == 0), top_p = (y == a.ny - 1);
         if (bottom_p || top_p) {
@@ -718,9 +757,11 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
     const int ya = (walls && chunk == 0) ? y0 + 2 : y0;
     const int yb = (walls && last) ? y1 - 2 : y1;
 
-    Window<C> W;
-    W.rho1 = W.rho2 = W.phi1 = W.phi2 = W.lap2 = W.lap3r = Row3<C>{0, 0, 0};
-    W.gphx = W.gphy = W.grx = W.gry = 0;
+    Window<C, PhiT<CD>> W;
+    W.rho1 = W.rho2 = W.lap2 = W.lap3r = Row3<C>{0, 0, 0};
+    W.phi1 = W.phi2 = Row3<PhiT<CD>>{0, 0, 0};
+    W.gphx = W.gphy = 0;
+    W.grx = W.gry = 0;
     W.wall_rho = W.wall_vx = W.wall_p = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) { W.f1[i] = 0; W.f2[i] = 0; }
@@ -772,7 +813,9 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
     constexpr int H = TYO + 4;    // tile rows including the halo
     constexpr int RPT = H / NW;   // rows per thread
     static_assert(H % NW == 0, "tile height must be a multiple of the waves per block");
-    __shared__ C sRho[H][64], sPhi[H][64], sLap[H][64];
+    using P = PhiT<CD>;
+    __shared__ C sRho[H][64], sLap[H][64];
+    __shared__ P sPhi[H][64];
     __shared__ C sWv[4][64], sWr[2][64], sWp[2][64];  // wall rows: vx (0, 1, ny-2, ny-1), rho and p_w (0, ny-1)
 
     const int lane = threadIdx.x & 63;
@@ -840,7 +883,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
         const C rho = fluid ? ((f[j][0] + f[j][1]) + (f[j][2] + f[j][3])) + ((f[j][4] + f[j][5]) + (f[j][6] + f[j][7])) + f[j][8]
                             : rho_w;
         sRho[k][lane] = rho;
-        sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+        sPhi[k][lane] = phi_field<CD, EOS>(rho, a);
     }
     __syncthreads();
 
@@ -866,11 +909,12 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
         const int k = wave + NW * j;
         const int y = y0 - 2 + k;
         if (k < 2 || k > H - 3 || y >= a.ny) continue;  // halo row (wave-uniform)
-        C gphx, gphy, glx, gly;
+        P gphx, gphy;
+        C glx, gly;
         {
-            const Row3<C> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
-            const Row3<C> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
-            const Row3<C> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
+            const Row3<P> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
+            const Row3<P> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
+            const Row3<P> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
             grad3(s, m, n, gphx, gphy);
         }
         {
@@ -1031,7 +1075,8 @@ struct Pipe {
     static_assert(TYO % NW == 0 && NW >= 4, "tile rows must be a multiple of the waves, at least 4 waves");
 
     struct Smem {
-        C rho[2][H][64], phi[2][H][64], lap[H][64];
+        C rho[2][H][64], lap[H][64];
+        PhiT<CD> phi[2][H][64];
         C wv[4][64], wr[2][64], wp[2][64];  // wall rows: vx (0, 1, ny-2, ny-1), rho and p_w (0, ny-1)
         int first, next;                    // broadcast tickets
     };
@@ -1119,13 +1164,13 @@ struct Pipe {
             const int k = 2 + w + NW * j;
             const C rho = density(g, a, g.y0 - 2 + k, fc[j], rho_w);
             sRho[k][lane] = rho;
-            sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+            sPhi[k][lane] = phi_field<CD, EOS>(rho, a);
         }
         if (w < 4) {
             const int k = halo_k(w);
             const C rho = density(g, a, g.y0 - 2 + k, fh, rho_w);
             sRho[k][lane] = rho;
-            sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+            sPhi[k][lane] = phi_field<CD, EOS>(rho, a);
         }
         if (threadIdx.x == 0) sm.next = int(tk - base);
         __syncthreads();
@@ -1158,11 +1203,12 @@ struct Pipe {
             const int k = 2 + w + NW * j;
             const int y = g.y0 + w + NW * j;
             const bool row_ok = g.inner || y < a.ny;  // false only when ny < TYO (wave-uniform)
-            C gphx, gphy, glx, gly;
+            PhiT<CD> gphx, gphy;
+            C glx, gly;
             {
-                const Row3<C> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
-                const Row3<C> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
-                const Row3<C> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
+                const Row3<PhiT<CD>> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
+                const Row3<PhiT<CD>> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
+                const Row3<PhiT<CD>> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
                 grad3(s, m, n, gphx, gphy);
             }
             {
@@ -1297,7 +1343,9 @@ __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v,
     constexpr int H1 = H - 4;          // tile rows 2 .. H-3: step 1's collided nodes
     constexpr int RPT = H / NW;
     static_assert(H % NW == 0, "tile height must be a multiple of the waves per block");
-    __shared__ C sRho[H][64], sPhi[H][64], sLap[H][64];
+    using P = PhiT<CD>;
+    __shared__ C sRho[H][64], sLap[H][64];
+    __shared__ P sPhi[H][64];
     __shared__ S sF[9][H1][64];
     __shared__ C sWv[2][4][64], sWr[2][2][64], sWp[2][2][64];  // wall rows of step 1 and step 2
 
@@ -1347,11 +1395,12 @@ __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v,
     // Force and collision of the node at tile row k, pulled populations in fj (tile_body's
     // phase C); wall rows of output lanes record v_x, rho and p_w of step st.
     auto collide_at = [&](int k, int y, C (&fj)[9], int st, bool wall_lane, C& vx, C& vy) {
-        C gphx, gphy, glx, gly;
+        P gphx, gphy;
+        C glx, gly;
         {
-            const Row3<C> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
-            const Row3<C> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
-            const Row3<C> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
+            const Row3<P> s{sPhi[k - 1][lane], sPhi[k - 1][lp], sPhi[k - 1][lm]};
+            const Row3<P> m{sPhi[k][lane], sPhi[k][lp], sPhi[k][lm]};
+            const Row3<P> n{sPhi[k + 1][lane], sPhi[k + 1][lp], sPhi[k + 1][lm]};
             grad3(s, m, n, gphx, gphy);
         }
         {
@@ -1438,7 +1487,7 @@ __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v,
             const bool fluid = tile_inner || a.yper || (r >= 0 && r < a.ny);
             const C rho = fluid ? density(f[j]) : rho_w;
             sRho[k][lane] = rho;
-            sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+            sPhi[k][lane] = phi_field<CD, EOS>(rho, a);
         }
         __syncthreads();
         // ---- step 1, phase B: Laplacian on rows 1 .. H-2 -------------------------------
@@ -1495,7 +1544,7 @@ __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v,
         }
         const C rho = fluid ? density(f2[j]) : rho_w;
         sRho[k][lane] = rho;
-        sPhi[k][lane] = phi_of<EOS, C>(rho, RT, a_eff, bb, k2);
+        sPhi[k][lane] = phi_field<CD, EOS>(rho, a);
     }
     __syncthreads();
     // ---- step 2, phase B: Laplacian on rows 4 .. H-5 -------------------------------------

@@ -14,6 +14,11 @@ checks the rounding itself against an FP32 lattice run of the same step:
     sampling error of tens of thousands of independent draws;
   * the random bits depend on the step counter, node and direction only:
     two runs are bitwise equal, the next step draws other bits.
+
+The FP32 lattice evaluates the EOS field phi and its gradient in FP64, the FP16
+storages in FP32, so v can differ by ~1e-9 from the FP32 value the FP16 kernels
+round.  The exact checks therefore accept the FP16 neighbours (F16R) and the
+nearest FP16 value (F16S) of any value within TIE of v; the statistics use v.
 """
 import math
 
@@ -44,10 +49,27 @@ def start(storage, f0=None):
     return lat
 
 
+TIE = 1e-7
+
+
+def is_neighbour_within_tie(h, v):
+    """h is an FP16 neighbour of v - TIE or of v + TIE."""
+    v = v.astype(np.float64)
+    lo_m, hi_m = neighbours(v - TIE)
+    lo_p, hi_p = neighbours(v + TIE)
+    return (h == lo_m) | (h == hi_m) | (h == lo_p) | (h == hi_p)
+
+
+def is_nearest_within_tie(n, v):
+    """n is the FP16 value nearest to v - TIE or to v + TIE."""
+    v = v.astype(np.float64)
+    return (n == (v - TIE).astype(np.float16).astype(np.float64)) | (n == (v + TIE).astype(np.float16).astype(np.float64))
+
+
 def neighbours(v):
-    """FP16 values just below and just above each FP32 value of v (equal when v is an FP16 value)."""
+    """FP16 values just below and just above each value of v (equal when v is an FP16 value)."""
     h = v.astype(np.float16)
-    hd = h.astype(np.float32)
+    hd = h.astype(v.dtype)
     lo = np.where(hd <= v, h, np.nextafter(h, np.float16(-np.inf)))
     hi = np.where(hd >= v, h, np.nextafter(h, np.float16(np.inf)))
     return lo.astype(np.float64), hi.astype(np.float64)
@@ -64,8 +86,10 @@ def test_one_step_rounds_to_a_neighbour_without_bias():
     v = s.get_f().astype(np.float32)
     h = r.get_f()
     lo, hi = neighbours(v)
-    assert np.all((h == lo) | (h == hi))
-    assert np.array_equal(n.get_f(), v.astype(np.float16).astype(np.float64))  # round to nearest
+    exact = (h == lo) | (h == hi)
+    log(f"{int((~exact).sum())} of {v.size} values not rounded to a neighbour of the FP32 lattice's value")
+    assert np.all(exact | is_neighbour_within_tie(h, v))
+    assert np.all(is_nearest_within_tie(n.get_f(), v))  # round to nearest
     m = hi > lo
     t = (v[m].astype(np.float64) - lo[m]) / (hi[m] - lo[m])  # position of v between its neighbours
     up = (h[m] == hi[m]).astype(np.float64)
@@ -118,7 +142,7 @@ def test_values_just_above_powers_of_two_round_to_a_neighbour_without_bias():
     v = lats["f32"].get_f().astype(np.float32)
     h = lats["f16r"].get_f()
     lo, hi = neighbours(v)
-    assert np.all((h == lo) | (h == hi))
+    assert np.all((h == lo) | (h == hi) | is_neighbour_within_tie(h, v))
     p2 = 2.0 ** np.floor(np.log2(v.astype(np.float64)))
     spacing = hi - lo
     t = np.where(spacing > 0, (v - lo) / np.where(spacing > 0, spacing, 1), 0)
