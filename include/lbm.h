@@ -61,9 +61,11 @@ typedef enum {
 typedef enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 } lbm_eos_kind;
 
 /* Storage of the distributions in device memory and arithmetic of the step:
-   F64: FP64 / FP64.  F32: FP32 / FP32.  F16S, BF16S: f_i - 9 w_i q in
-   FP16 / BF16, FP32 arithmetic (q: see rho0_shift).  F32D: FP32 storage, FP64
-   arithmetic.  F32S: f_i - 9 w_i q in FP32, FP32 arithmetic. */
+   F64: FP64 / FP64.  F32: FP32 / FP32, with the EOS field phi of eq. 2.17 and
+   its gradient in FP64.  F16S, BF16S: f_i - 9 w_i q in FP16 / BF16, FP32
+   arithmetic on those deviations (q: see rho0_shift).  F32D: FP32 storage, FP64
+   arithmetic.  F32S: f_i - 9 w_i q in FP32, FP32 arithmetic on the deviations,
+   phi in FP64. */
 /* Storage of the distributions.  F64T keeps each population as an FP64 value
    and its FP64 tangent along a direction of the parameters (lbm_set_tangent):
    the step then runs in tangent-linear arithmetic and the wall summaries carry
